@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Throughput of the SSN kernel-OT solver on one MI355X.
+
+A step is one full solve of one synthetic problem with inputs resident in HBM: setup (Gram matrices, mean
+embeddings, q^2, Cholesky factor) and Algorithm 2 to |R(w)| <= 1e-6.  The workload is ``mix1000`` (n = 5000
+samples per side, d = 10, two 4-component Gaussian mixtures, l = 1000 filling points), one instance per
+seed.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--arm fp64] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "fp64_tflops": 78.6,
+    "fp32_tflops": 157.3,
+    "bf16_tflops": 2500.0,
+    "hbm_gbs": 8000.0,
+}
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(workload: str):
+    """Time the CPU oracle (as it stands) on one full solve of instance 0 of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import kot_oracle as ko
+    from paper_2310_14087_amd.inputs import make_problem
+
+    p = make_problem(workload, 0)
+    t0 = time.perf_counter()
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    res = ko.solve(core, ko.Params(tol=p.tol))
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return dict(value=1.0 / dt, unit="solves/s", cores=threads, kind="oracle",
+                sample=f"1 full oracle solve (setup + Algorithm 2, {res['iters']} iterations, status "
+                       f"{res['status']}) of {workload} instance 0, {dt:.1f} s wall, numpy/OpenBLAS FP64",
+                cpu=_cpu_model())
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mix1000")
+    ap.add_argument("--arm", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    a = ap.parse_args()
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (a multi-GPU run would only "
+                                   "repeat independent solves per GPU and is not part of this build)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2310_14087_amd import kotssn
+    from paper_2310_14087_amd.inputs import make_problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n_inst = max(1, a.steps)
+    _log(f"generating {n_inst} {a.workload} instances")
+    probs = [make_problem(a.workload, s) for s in range(n_inst)]
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    dev_inputs = [(t(p.xs), t(p.ys), t(p.xf), t(p.yf)) for p in probs]
+    torch.cuda.synchronize()
+
+    ctx = kotssn.Context(0)
+    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol) for p in probs]
+
+    for w in range(a.warmup):
+        _log(f"warmup {w}")
+        _, _, r = ctx.solve(*dev_inputs[w % n_inst], prms[w % n_inst])
+    torch.cuda.synchronize()
+
+    if not a.no_profile:
+        ctx.profile_start()
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        i = k % n_inst
+        _, _, r = ctx.solve(*dev_inputs[i], prms[i])
+        results.append(r)
+        _log(f"step {k}: instance {i} status={r.status} iters={r.iters} residual={r.residual:.2e} "
+             f"ot={r.ot:.8g} device_ms={r.time_ms:.1f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_stop() if not a.no_profile else None
+    ctx.close()
+
+    elapsed = t1 - t0
+    converged = sum(1 for r in results if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
+    value = a.steps / elapsed
+    out = {
+        "metric": "SSN solves/s to residual<=1e-6 at l=1000: plain FP64 vs warm-start+mixed",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: n=5000/side, d=10, two 4-component mixtures, l=1000, "
+                               f"sigma^2=0.005 on unit-cube data, lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
+                   "arm": a.arm, "instances": n_inst, "converged": converged,
+                   "iters": [r.iters for r in results], "eig_sweeps": [r.eig_sweeps_total for r in results],
+                   "cg_iters": [r.cg_iters_total for r in results]},
+    }
+    if prof:
+        dom = max(prof, key=lambda c: prof[c]["ms"])
+        pc = prof[dom]
+        ach = pc["flops"] / (pc["ms"] * 1e-3) / 1e12 if pc["ms"] > 0 else 0.0
+        out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
+                           "frac": ach / PEAK["fp64_tflops"], "traffic": None, "kernel": dom,
+                           "launches": pc["launches"], "avg_launch_us": 1e3 * pc["ms"] / max(1, pc["launches"]),
+                           "share_of_step": pc["ms"] * 1e-3 / elapsed}
+        out["profile"] = {c: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                              "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0}
+                          for c, v in prof.items()}
+    if not a.no_cpu_baseline:
+        _log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(a.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

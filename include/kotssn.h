@@ -1,0 +1,171 @@
+/*
+ * kotssn — semismooth Newton (SSN) solver for the kernel-based optimal-transport estimator of
+ * Lin, Cuturi & Jordan, "A Specialized Semismooth Newton Method for Kernel-Based Optimal Transport" (2023),
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments named in a "device" comment are device pointers (HIP memory on the context's device);
+ *    arrays named "host" are host pointers.  Matrices are row-major, FP64, leading dimension = number of
+ *    columns (l for l x l matrices, d for point sets), contiguous.
+ *  - The caller owns every input and output buffer.  The library owns the context's workspace, which it
+ *    sizes lazily from the largest l it has seen and frees in kot_destroy.
+ *  - All work is enqueued on the context's stream; every call returns after that stream has drained, so
+ *    outputs are ready on return.
+ *  - Errors are returned as kot_status; a message for the last error of a context is available from
+ *    kot_last_error.  Nothing throws across this boundary.  Inputs are validated before any kernel is
+ *    launched: l, n, d >= 1, sigma, lambda1, lambda2 > 0, pointers non-null (KOT_ERR_ARG otherwise).
+ *  - Not thread-safe per context: calls that share a context must not overlap.
+ */
+#ifndef KOTSSN_H
+#define KOTSSN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kot_ctx kot_ctx;
+
+typedef enum {
+  KOT_OK = 0,
+  KOT_NOT_CONVERGED = 1,   /* outputs valid; tolerance not met within max_iter */
+  KOT_ERR_ARG = -1,        /* invalid argument; nothing was launched */
+  KOT_ERR_HIP = -2,        /* HIP runtime error */
+  KOT_ERR_OOM = -3,        /* workspace allocation failed */
+  KOT_ERR_FACTOR = -4,     /* K + eps I is not numerically positive definite */
+  KOT_ERR_NUMERIC = -5,    /* NaN/Inf in the residual */
+  KOT_ERR_EIG = -6         /* eigensolver did not reach its off-diagonal tolerance */
+} kot_status;
+
+typedef enum { KOT_FP64 = 0, KOT_FP32 = 1, KOT_MIXED_BF16 = 2 } kot_precision;
+typedef enum { KOT_SAFEGUARD_EG = 0, KOT_SAFEGUARD_NONE = 1 } kot_safeguard;
+
+/* Parameters of Algorithm 2 and the inexactness rule Eq. (4.5).  kot_params_default fills the values
+ * used throughout: tol 1e-6, max_iter 200, cg_max_iter 20 (Remark 4.5), tau = kappa = 0.5,
+ * alpha1 = 1e-6, alpha2 = 1, beta0 = 0.5, beta1 = 1/1.2, beta2 = 5 (Section 5 constants, with beta1 < 1
+ * as Algorithm 2's input requires), theta0 = 1, theta in [1e-6, 1e6], eg_step = 0 (=> 0.5 / Lhat with
+ * Lhat = |Q|_inf/(2 lambda2) + sqrt(|K o K|_inf)), null_step = 1 (keep w_k when it beats both the SSN trial
+ * and the extragradient iterate), eps_jitter = 1e-10 (R^T R = K + eps I). */
+typedef struct kot_params {
+  double sigma;        /* Gaussian bandwidth: k(a,b) = exp(-|a-b|^2 / (2 sigma^2)) */
+  double lambda1;      /* trace penalty (Eq. 3.2) */
+  double lambda2;      /* RKHS-norm penalty (Eq. 3.2) */
+  double eps_jitter;
+  double tol;          /* stop when |r1|_2 + |r2|_F <= tol */
+  int max_iter;
+  int cg_max_iter;
+  double tau, kappa;
+  double alpha1, alpha2, beta0, beta1, beta2;
+  double theta0, theta_min, theta_max;
+  double eg_step;
+  int precision;       /* kot_precision: arithmetic of the CG matvec GEMMs */
+  int safeguard;       /* kot_safeguard */
+  int null_step;
+  int eig_max_sweeps;  /* Jacobi sweep cap (default 30) */
+  int warm_eig;        /* 1: start each eigendecomposition from the previous eigenbasis (default 1) */
+} kot_params;
+
+/* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:
+ * xs n_src x d, ys n_tgt x d, xf l x d, yf l x d. */
+typedef struct kot_problem {
+  int n_src, n_tgt, d, l;
+  const double* xs;
+  const double* ys;
+  const double* xf;
+  const double* yf;
+} kot_problem;
+
+/* Solver outputs.  gamma (device, length l) receives the dual vector; X (device, l x l, may be NULL)
+ * receives the PSD multiplier; res_hist / res_v_hist (host, hist_cap entries each, may be NULL) receive
+ * |R(w_k)| and |R(v_k)| for k = 0..iters; the scalars are filled on return. */
+typedef struct kot_result {
+  double* gamma;
+  double* X;
+  double* res_hist;
+  double* res_v_hist;
+  int hist_cap;
+  double ot;           /* estimator: (q2 - gamma^T (w_mu + w_nu)) / (2 lambda2), Section 3 */
+  double residual;     /* |R(w)| at the returned iterate */
+  int iters;           /* outer iterations performed */
+  int cg_iters_total;
+  int eg_accepts;      /* iterations whose w_{k+1} is the extragradient iterate */
+  int null_steps;      /* iterations that kept w_k */
+  int eig_sweeps_total;
+  int alpha_last;      /* number of positive eigenvalues of Z at the returned iterate */
+  double time_ms;      /* wall time of the solve on the device stream */
+} kot_result;
+
+/* Fills *p with the defaults listed above (sigma, lambda1, lambda2 set to 1, 1e-3, 1e-3). */
+void kot_params_default(kot_params* p);
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t (NULL = the context creates and
+ * owns its own stream); the caller keeps ownership of a stream it passes in. */
+kot_status kot_create(kot_ctx** out, int device, void* hip_stream);
+kot_status kot_destroy(kot_ctx* ctx);
+/* Message of the last error on this context ("" if none).  Valid until the next call on the context. */
+const char* kot_last_error(const kot_ctx* ctx);
+
+/* Dual data of Eq. (3.4) (Section 3): Q = K_X + K_Y (l x l), z (l), the upper-triangular factor R with
+ * R^T R = K + eps I where K = K_X o K_Y (l x l), wsum = w_mu + w_nu at the filling points (l), and q2
+ * (host scalar).  Q, z, R, wsum are device pointers; R's strictly lower triangle is written as 0.
+ * Returns KOT_ERR_FACTOR if the Cholesky factorization meets a non-positive pivot. */
+kot_status kot_setup(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm,
+                     double* Q, double* z, double* R, double* wsum, double* q2);
+
+/* Full solve: setup (as kot_setup) then Algorithm 2 from gamma0 (device, length l; NULL = cold start
+ * gamma = 0), X0 = 0. */
+kot_status kot_solve(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm, const double* gamma0,
+                     kot_result* res);
+
+/* Algorithm 2 on given dual data (Eq. 3.4): Q, z, R (any factor with R^T R = K), wsum (device) and q2
+ * (host).  prm->sigma is ignored. */
+kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, double q2,
+                          const double* wsum, const kot_params* prm, const double* gamma0, kot_result* res);
+
+/* Symmetric eigendecomposition (Eq. 4.4): Z = P diag(w) P^T with w ascending.  Z, P (l x l) and w (l) are
+ * device pointers; P's columns are the eigenvectors.  Z is not modified.  Returns KOT_ERR_EIG if the
+ * Jacobi sweeps do not reach the off-diagonal tolerance within prm->eig_max_sweeps (P, w still written). */
+kot_status kot_eigh(kot_ctx* ctx, int l, const double* Z, double* P, double* w, const kot_params* prm);
+
+/* Residual map Eq. (4.2) at w = (gamma, X): r1 = (Q gamma - z)/(2 lambda2) - Phi(X),
+ * r2 = X - Pi(X - Phi*(gamma) - lambda1 I), with Phi(X)_i = R[:,i]^T X R[:,i], Phi*(gamma) = R diag(gamma) R^T.
+ * Q, z, R, gamma, X, r1, r2 are device pointers; norms (host, 3 entries) receives |r1|_2, |r2|_F and
+ * the number of positive eigenvalues of Z (as a double). */
+kot_status kot_residual(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R,
+                        const double* gamma, const double* X, const kot_params* prm,
+                        double* r1, double* r2, double* norms);
+
+/* One regularized SSN direction (Eq. 4.3) by Algorithm 1 at w = (gamma, X) with regularization mu:
+ * writes dgamma (device, l) and dX (device, l x l).  info (host, 4 entries): CG iterations, CG residual
+ * norm, |alpha|, |r|. */
+kot_status kot_ssn_direction(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R,
+                             const double* gamma, const double* X, double mu, const kot_params* prm,
+                             double* dgamma, double* dX, double* info);
+
+/* One extragradient step (Section 4.4) on the min-max form Eq. (4.1) with step eta: (gamma, X) ->
+ * (gamma_out, X_out), projection onto R^l x S^l_+.  All arrays device pointers. */
+kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R,
+                       const double* gamma, const double* X, double eta, const kot_params* prm,
+                       double* gamma_out, double* X_out);
+
+/* Upper Cholesky factor R (device, l x l) of the symmetric positive definite A (device, l x l) + eps I:
+ * R^T R = A + eps I; strictly lower triangle written as 0.  Returns KOT_ERR_FACTOR on a non-positive
+ * pivot. */
+kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double* R);
+
+/* General FP64 product on the device (MFMA): C = alpha op(A) diag(s) op(B) + beta C, op = transpose if
+ * trans* != 0; s (device, length k) may be NULL.  C is m x n with leading dimension ldc. */
+kot_status kot_gemm(kot_ctx* ctx, int transa, int transb, int m, int n, int k, double alpha,
+                    const double* A, int lda, const double* s, const double* B, int ldb, double beta,
+                    double* C, int ldc);
+
+/* Launch profiler for measurement.  enable = 1 clears and starts recording HIP events around every launch
+ * of the instrumented kernel classes on the context's stream; enable = 0 stops, waits for the stream, and
+ * writes 4 values per class into out (host, 4 * nclass doubles; may be NULL): launches, total milliseconds
+ * between the events, algorithmic flops and algorithmic bytes.  Classes: 0 = FP64 GEMM (2mnk flops),
+ * 1 = one Jacobi round (pair solves + tile updates; flops of the 16x16 tile products), 2 = reserved. */
+kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KOTSSN_H */

@@ -1,0 +1,265 @@
+// Elementwise kernels, deterministic reductions and the Hadamard weight Psi of Section 4.3.
+#include "kot_internal.h"
+
+namespace kot {
+namespace {
+
+__global__ void fill_kernel(long long n, double v, double* __restrict__ x) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void fill2d_kernel(int rows, int cols, double v, double* __restrict__ C, int ldc) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)rows * cols) return;
+  C[(u / cols) * ldc + (u % cols)] = v;
+}
+__global__ void axpby_kernel(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+__global__ void lincomb_kernel(long long n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                               double* __restrict__ z) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = a * x[i] + b * y[i];
+}
+__global__ void add_diag_kernel(int l, double a, double* __restrict__ X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < l) X[(long long)i * l + i] += a;
+}
+__global__ void symmetrize_kernel(int l, double* __restrict__ Z) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)l * l) return;
+  const int i = (int)(u / l), j = (int)(u % l);
+  if (j <= i) return;
+  const double v = 0.5 * (Z[u] + Z[(long long)j * l + i]);
+  Z[u] = v;
+  Z[(long long)j * l + i] = v;
+}
+__global__ __launch_bounds__(256) void dot_part_kernel(long long n, const double* __restrict__ x, const double* __restrict__ y,
+                                                       double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) acc += x[i] * y[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void sum_final_kernel(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = (threadIdx.x < nb) ? part[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+__global__ __launch_bounds__(256) void rowsum_abs_kernel(int l, const double* __restrict__ A, int sq, double* __restrict__ rows) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < l; j += 256) {
+    const double v = A[(long long)i * l + j];
+    acc += sq ? v * v : fabs(v);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rows[i] = red[0];
+}
+__global__ __launch_bounds__(256) void max_kernel(int n, const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, v[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+__global__ __launch_bounds__(256) void count_pos_kernel(int l, const double* __restrict__ w, int* __restrict__ out) {
+  __shared__ int red[256];
+  int c = 0;
+  for (int i = threadIdx.x; i < l; i += 256) c += (w[i] > 0.0) ? 1 : 0;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Psi weights (Section 4.3), eigenvalues w ascending so alpha = [l-a, l).
+//   non-complement, row r in alpha:  j in alpha -> diag_scale/mu ;  j not in alpha -> off_scale * xi(r, j)
+//   complement, row r not in alpha:  j not in alpha -> diag_scale/mu ; j in alpha -> off_scale * (1/mu - xi(j, r))
+// with eta(i, j) = w_i/(w_i - w_j) (i in alpha, j not), 1 - eta = |w_j|/(w_i + |w_j|), xi = eta/(mu + 1 - eta),
+// and 1/mu - xi = (1 - eta)(1 + mu) / (mu (mu + 1 - eta)).
+__global__ void psi_kernel(int l, int a, int r0, int m, double mu, const double* __restrict__ w, double* __restrict__ C, int ldc,
+                           int complement, double diag_scale, double off_scale) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)m * l) return;
+  const int rr = (int)(u / l), j = (int)(u % l);
+  const int r = r0 + rr;
+  const int split = l - a;  // first alpha index
+  const bool r_in = r >= split, j_in = j >= split;
+  double wt;
+  if (r_in == j_in) {
+    wt = diag_scale / mu;
+  } else {
+    const int ia = r_in ? r : j;   // alpha member
+    const int ib = r_in ? j : r;   // alpha-bar member
+    const double sa = w[ia], sb = -w[ib];       // sa > 0, sb >= 0
+    const double one_m_eta = sb / (sa + sb);
+    const double eta = sa / (sa + sb);
+    if (!complement) wt = off_scale * (eta / (mu + one_m_eta));
+    else wt = off_scale * (one_m_eta * (1.0 + mu) / (mu * (mu + one_m_eta)));
+  }
+  C[(long long)rr * ldc + j] *= wt;
+}
+
+__global__ void sub_kernel(long long n, const double* __restrict__ X, const double* __restrict__ Y, double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = X[i] - Y[i];
+}
+__global__ void transpose_kernel(int l, const double* __restrict__ A, double* __restrict__ At) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads = 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int i = by + k, j = bx + tx;
+    if (i < l && j < l) tile[k][tx] = A[(long long)i * l + j];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int i = bx + k, j = by + tx;
+    if (i < l && j < l) At[(long long)i * l + j] = tile[tx][k];
+  }
+}
+__global__ void hsq_kernel(long long n, const double* __restrict__ A, double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = A[i] * A[i];
+}
+__global__ void sym_plus_kernel(int l, const double* __restrict__ G, double a, const double* __restrict__ S, double b,
+                                double* __restrict__ out) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // tile holds G^T block: rows of the output block (by..), cols (bx..) need G[j][i]
+  for (int k = ty; k < 32; k += 8) {
+    const int i = bx + k, j = by + tx;  // read G[i][j] with i in col-range, j in row-range
+    if (i < l && j < l) tile[tx][k] = G[(long long)i * l + j];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int i = by + k, j = bx + tx;
+    if (i < l && j < l) {
+      const long long u = (long long)i * l + j;
+      const double g = G[u] + tile[k][tx];
+      out[u] = (b == 0.0 || S == nullptr) ? a * g : a * g + b * S[u];
+    }
+  }
+}
+__global__ void scale_cols_kernel(int rows, int cols, const double* __restrict__ A, int lda, const double* __restrict__ s,
+                                  double* __restrict__ out, int ldo) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)rows * cols) return;
+  const int i = (int)(u / cols), j = (int)(u % cols);
+  out[(long long)i * ldo + j] = A[(long long)i * lda + j] * s[j];
+}
+
+inline int nblk(long long n, int b = 256) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t vec_fill(int n, double v, double* x, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(n)), dim3(256), 0, st, (long long)n, v, x);
+  return hipGetLastError();
+}
+hipError_t mat_fill(int rows, int cols, double v, double* C, int ldc, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill2d_kernel, dim3(nblk((long long)rows * cols)), dim3(256), 0, st, rows, cols, v, C, ldc);
+  return hipGetLastError();
+}
+hipError_t vec_copy(int n, const double* x, double* y, hipStream_t st) {
+  if (n <= 0 || x == y) return hipSuccess;
+  return hipMemcpyAsync(y, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st);
+}
+hipError_t vec_axpby(int n, double a, const double* x, double b, double* y, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3(nblk(n)), dim3(256), 0, st, (long long)n, a, x, b, y);
+  return hipGetLastError();
+}
+hipError_t vec_lincomb(int n, double a, const double* x, double b, const double* y, double* z, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n)), dim3(256), 0, st, (long long)n, a, x, b, y, z);
+  return hipGetLastError();
+}
+hipError_t add_diag(int l, double a, double* X, hipStream_t st) {
+  hipLaunchKernelGGL(add_diag_kernel, dim3(nblk(l)), dim3(256), 0, st, l, a, X);
+  return hipGetLastError();
+}
+hipError_t symmetrize(int l, double* Z, hipStream_t st) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk((long long)l * l)), dim3(256), 0, st, l, Z);
+  return hipGetLastError();
+}
+hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st) {
+  int nb = nblk(n);
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(dot_part_kernel, dim3(nb), dim3(256), 0, st, (long long)n, x, y, part);
+  KOT_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(256), 0, st, nb, part, out);
+  return hipGetLastError();
+}
+hipError_t rowsum_abs_max(int l, const double* A, bool square_entries, double* out, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(rowsum_abs_kernel, dim3(l), dim3(256), 0, st, l, A, square_entries ? 1 : 0, part);
+  KOT_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, l, part, out);
+  return hipGetLastError();
+}
+hipError_t count_positive(int l, const double* w, int* out_int, hipStream_t st) {
+  hipLaunchKernelGGL(count_pos_kernel, dim3(1), dim3(256), 0, st, l, w, out_int);
+  return hipGetLastError();
+}
+hipError_t psi_hadamard(int l, int a, int r0, int m, double mu, const double* w, double* C, int ldc, bool complement,
+                        double diag_scale, double off_scale, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psi_kernel, dim3(nblk((long long)m * l)), dim3(256), 0, st, l, a, r0, m, mu, w, C, ldc,
+                     complement ? 1 : 0, diag_scale, off_scale);
+  return hipGetLastError();
+}
+hipError_t mat_sub(int n, const double* X, const double* Y, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sub_kernel, dim3(nblk(n)), dim3(256), 0, st, (long long)n, X, Y, out);
+  return hipGetLastError();
+}
+hipError_t transpose(int l, const double* A, double* At, hipStream_t st) {
+  dim3 grid((l + 31) / 32, (l + 31) / 32);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, l, A, At);
+  return hipGetLastError();
+}
+hipError_t hadamard_square(int n, const double* A, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(hsq_kernel, dim3(nblk(n)), dim3(256), 0, st, (long long)n, A, out);
+  return hipGetLastError();
+}
+hipError_t sym_plus(int l, const double* G, double a, const double* S, double b, double* out, hipStream_t st) {
+  dim3 grid((l + 31) / 32, (l + 31) / 32);
+  hipLaunchKernelGGL(sym_plus_kernel, grid, dim3(256), 0, st, l, G, a, S, b, out);
+  return hipGetLastError();
+}
+hipError_t scale_cols(int rows, int cols, const double* A, int lda, const double* s, double* out, int ldo, hipStream_t st) {
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(nblk((long long)rows * cols)), dim3(256), 0, st, rows, cols, A, lda, s, out, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace kot

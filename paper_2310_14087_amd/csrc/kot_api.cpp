@@ -1,0 +1,795 @@
+// C-ABI of libkotssn and the host orchestration of the SSN method (Algorithms 1 and 2).
+// Every arithmetic step runs in the HIP kernels of this library; the host only sequences launches and reads
+// back the scalars that the algorithm branches on (norms, inner products, the eigenvalue count).
+#include "kotssn.h"
+#include "kot_internal.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace kot;
+
+namespace {
+
+struct State {  // an iterate w = (gamma, X) with its residual and the spectral data of Z
+  double* g = nullptr;
+  double* X = nullptr;
+  double* r1 = nullptr;
+  double* r2 = nullptr;
+  double* P = nullptr;
+  double* s = nullptr;
+  int a = 0;
+  double r1n = 0.0, r2n = 0.0, rn = 0.0;
+  bool has_eig = false;
+};
+
+struct CoreView {  // dual data of Eq. (3.4) on the device
+  int l = 0;
+  const double* Q = nullptr;
+  const double* z = nullptr;
+  const double* R = nullptr;
+  const double* wsum = nullptr;
+  double q2 = 0.0;
+  double lam1 = 0.0, lam2 = 0.0;
+  double* KK = nullptr;  // (R^T R) o (R^T R)
+};
+
+}  // namespace
+
+struct kot_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  EigWork* eig = nullptr;
+  int cap = 0;  // workspace l capacity
+  std::vector<void*> bufs;
+  // scalar exchange
+  double* dsc = nullptr;
+  double* hsc = nullptr;
+  int* dint = nullptr;
+  int* hint = nullptr;
+  double* part = nullptr;      // reduction partials (>= max(kRedBlocks, kDiagParts*l, n))
+  size_t part_cap = 0;
+  // matrices (cap x cap)
+  double *Qb, *Rb, *Kb, *KKb, *Z, *T1, *T2, *T3, *T4, *Bm, *dX, *Mr, *eigtmp, *Pe1, *Pe2, *Xh;
+  // vectors (cap)
+  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *vtmp, *gh, *s_e1, *s_e2, *r1h;
+  State S[4];  // 0: w, 1: trial, 2: v, 3: scratch
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  Profiler prof;
+};
+
+namespace {
+
+kot_status fail(kot_ctx* c, kot_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(ctx, KOT_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), \
+                  __FILE__, __LINE__);                                                      \
+  } while (0)
+
+#define KCHK(expr)                  \
+  do {                              \
+    kot_status _s = (expr);         \
+    if (_s < 0) return _s;          \
+  } while (0)
+
+void free_ws(kot_ctx* c) {
+  for (void* p : c->bufs) hipFree(p);
+  c->bufs.clear();
+  if (c->eig) { eig_work_destroy(c->eig); c->eig = nullptr; }
+  c->cap = 0;
+}
+
+kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t need_part = std::max<size_t>({(size_t)kRedBlocks, (size_t)kDiagParts * l + 64, (size_t)nmax + 64,
+                                             (size_t)l + 64});
+  if (l <= ctx->cap && need_part <= ctx->part_cap) return KOT_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  free_ws(ctx);
+  const int cap = std::max(l, ctx->cap);
+  const size_t mm = (size_t)cap * cap * sizeof(double);
+  const size_t vv = (size_t)cap * sizeof(double);
+  auto alloc = [&](size_t bytes) -> double* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    ctx->bufs.push_back(p);
+    return (double*)p;
+  };
+  double** mats[] = {&ctx->Qb, &ctx->Rb, &ctx->Kb, &ctx->KKb, &ctx->Z, &ctx->T1, &ctx->T2, &ctx->T3, &ctx->T4,
+                     &ctx->Bm, &ctx->dX, &ctx->Mr, &ctx->Pe1, &ctx->Pe2, &ctx->Xh};
+  for (double** m : mats)
+    if (!(*m = alloc(mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed (l=%d)", cap);
+  if (!(ctx->eigtmp = alloc(2 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  double** vecs[] = {&ctx->zb, &ctx->wsumb, &ctx->wmu, &ctx->wnu, &ctx->dg, &ctx->a1, &ctx->cx, &ctx->cr, &ctx->cp,
+                     &ctx->cAp, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h};
+  for (double** v : vecs)
+    if (!(*v = alloc(vv))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  for (auto& s : ctx->S) {
+    if (!(s.g = alloc(vv)) || !(s.X = alloc(mm)) || !(s.r1 = alloc(vv)) || !(s.r2 = alloc(mm)) ||
+        !(s.P = alloc(mm)) || !(s.s = alloc(vv)))
+      return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+    s.has_eig = false;
+  }
+  if (!(ctx->part = alloc(need_part * sizeof(double)))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  ctx->part_cap = need_part;
+  ctx->eig = eig_work_create(cap);
+  if (!ctx->eig) return fail(ctx, KOT_ERR_OOM, "eigensolver workspace allocation failed");
+  ctx->cap = cap;
+  return KOT_OK;
+}
+
+kot_status sync_read(kot_ctx* ctx, int nd, int ni) {
+  if (nd > 0) HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->dsc, sizeof(double) * nd, hipMemcpyDeviceToHost, ctx->stream));
+  if (ni > 0) HIPCHK(hipMemcpyAsync(ctx->hint, ctx->dint, sizeof(int) * ni, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
+// ---- GEMM helpers ------------------------------------------------------------------------------------------
+hipError_t mm(hipStream_t st, int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda,
+              const double* s, const double* B, int ldb, double beta, double* C, int ldc) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (k <= 0) {
+    if (beta != 0.0) return hipErrorInvalidValue;  // not needed by callers
+    return mat_fill(m, n, 0.0, C, ldc, st);
+  }
+  GemmArgs g{};
+  g.transa = ta; g.transb = tb; g.m = m; g.n = n; g.k = k; g.alpha = alpha; g.beta = beta;
+  g.A = A; g.lda = lda; g.s = s; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.batch = 1;
+  return gemm_f64(g, st);
+}
+
+// out = Phi*(g) = R diag(g) R^T
+kot_status phi_star(kot_ctx* ctx, const CoreView& cv, const double* g, double* out) {
+  const int l = cv.l;
+  HIPCHK(mm(ctx->stream, 0, 1, l, l, l, 1.0, cv.R, l, g, cv.R, l, 0.0, out, l));
+  return KOT_OK;
+}
+
+// y = alpha*Phi(X) + beta*y, Phi(X)_i = R[:,i]^T X R[:,i]; uses tmp (l x l)
+kot_status phi_op(kot_ctx* ctx, const CoreView& cv, const double* X, double alpha, double beta, double* y, double* tmp) {
+  const int l = cv.l;
+  HIPCHK(mm(ctx->stream, 0, 0, l, l, l, 1.0, X, l, nullptr, cv.R, l, 0.0, tmp, l));
+  HIPCHK(diag_dot(0, l, l, alpha, cv.R, l, tmp, l, beta, y, ctx->part, ctx->stream));
+  return KOT_OK;
+}
+
+// r1 = (Q g - z)/(2 lam2) - Phi(X)
+kot_status r1_op(kot_ctx* ctx, const CoreView& cv, const double* g, const double* X, double* r1, double* tmp) {
+  const int l = cv.l;
+  // r1 = Q g  (as an l x 1 product)
+  HIPCHK(mm(ctx->stream, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, g, 1, 0.0, r1, 1));
+  HIPCHK(vec_axpby(l, -1.0 / (2.0 * cv.lam2), cv.z, 1.0 / (2.0 * cv.lam2), r1, ctx->stream));
+  KCHK(phi_op(ctx, cv, X, -1.0, 1.0, r1, tmp));
+  return KOT_OK;
+}
+
+kot_status eig_run(kot_ctx* ctx, int l, const double* Z, const double* P0, double* P, double* w, const kot_params* p,
+                   int* sweeps_acc) {
+  int sw = 0;
+  double rel = 0.0;
+  const int max_sw = p->eig_max_sweeps > 0 ? p->eig_max_sweeps : 30;
+  HIPCHK(eigh_jacobi(ctx->eig, l, Z, P0, P, w, ctx->eigtmp, max_sw, 1e-14, &sw, &rel, ctx->stream));
+  if (sweeps_acc) *sweeps_acc += sw;
+  if (!(rel <= 1e-14)) {
+    if (!std::isfinite(rel)) return fail(ctx, KOT_ERR_NUMERIC, "non-finite matrix in eigensolver");
+    return fail(ctx, KOT_ERR_EIG, "Jacobi did not converge in %d sweeps (off/norm = %.3e)", sw, rel);
+  }
+  return KOT_OK;
+}
+
+// Pi(Z) = P_alpha diag(w_alpha) P_alpha^T given ascending spectral data with a positives.
+kot_status proj_from_eig(kot_ctx* ctx, int l, const double* P, const double* w, int a, double* out) {
+  HIPCHK(mm(ctx->stream, 0, 1, l, l, a, 1.0, P + (l - a), l, w + (l - a), P + (l - a), l, 0.0, out, l));
+  return KOT_OK;
+}
+
+// Residual map Eq. (4.2) at state s (g, X set); fills r1, r2, P, s, a, norms.  P0: warm basis or null.
+kot_status residual_state(kot_ctx* ctx, const CoreView& cv, State& s, const double* P0, const kot_params* p,
+                          int* sweeps_acc) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  KCHK(phi_star(ctx, cv, s.g, ctx->T1));
+  HIPCHK(mat_sub(l * l, s.X, ctx->T1, ctx->Z, st));
+  HIPCHK(add_diag(l, -cv.lam1, ctx->Z, st));
+  HIPCHK(symmetrize(l, ctx->Z, st));
+  KCHK(eig_run(ctx, l, ctx->Z, P0, s.P, s.s, p, sweeps_acc));
+  HIPCHK(count_positive(l, s.s, ctx->dint, st));
+  KCHK(sync_read(ctx, 0, 1));
+  s.a = ctx->hint[0];
+  KCHK(proj_from_eig(ctx, l, s.P, s.s, s.a, ctx->T1));
+  HIPCHK(mat_sub(l * l, s.X, ctx->T1, s.r2, st));
+  KCHK(r1_op(ctx, cv, s.g, s.X, s.r1, ctx->T2));
+  HIPCHK(dot(l, s.r1, s.r1, ctx->dsc + 0, ctx->part, st));
+  HIPCHK(dot(l * l, s.r2, s.r2, ctx->dsc + 1, ctx->part, st));
+  KCHK(sync_read(ctx, 2, 0));
+  s.r1n = std::sqrt(ctx->hsc[0]);
+  s.r2n = std::sqrt(ctx->hsc[1]);
+  s.rn = s.r1n + s.r2n;
+  s.has_eig = true;
+  return KOT_OK;
+}
+
+// ---- operator T (Section 4.3) via the G + G^T decomposition -----------------------------------------------
+struct TPlan {
+  int l, a;
+  bool comp;   // complement form (|alpha| > l/2)
+  int r0, m;   // eigen-index set of the rows used: alpha, or alpha-bar in the complement form
+  double mu;
+  const double* P;
+  const double* w;
+};
+
+TPlan make_tplan(int l, int a, double mu, const double* P, const double* w) {
+  TPlan t;
+  t.l = l; t.a = a; t.mu = mu; t.P = P; t.w = w;
+  t.comp = (a > l - a);
+  if (!t.comp) { t.r0 = l - a; t.m = a; }
+  else { t.r0 = 0; t.m = l - a; }
+  return t;
+}
+
+// out = T[S]; uses T3, T4 (and out must differ from S and from T3/T4)
+kot_status t_apply(kot_ctx* ctx, const TPlan& tp, const double* S, double* out) {
+  const int l = tp.l;
+  hipStream_t st = ctx->stream;
+  if (tp.m == 0) {
+    if (!tp.comp) HIPCHK(vec_fill(l * l, 0.0, out, st));               // alpha empty: T = 0
+    else HIPCHK(vec_lincomb(l * l, 1.0 / tp.mu, S, 0.0, S, out, st));  // alpha-bar empty: T = S/mu
+    return KOT_OK;
+  }
+  double* U = ctx->T3;   // m x l
+  double* Y = ctx->T4;   // m x l
+  // U = P_set^T S
+  HIPCHK(mm(st, 1, 0, tp.m, l, l, 1.0, tp.P + tp.r0, l, nullptr, S, l, 0.0, U, l));
+  // Y = U P  (= P_set^T S P)
+  HIPCHK(mm(st, 0, 0, tp.m, l, l, 1.0, U, l, nullptr, tp.P, l, 0.0, Y, l));
+  // Y <- W (weights with 1/2 on the within-set block)
+  HIPCHK(psi_hadamard(l, tp.a, tp.r0, tp.m, tp.mu, tp.w, Y, l, tp.comp, 0.5, 1.0, st));
+  // U = W P^T
+  HIPCHK(mm(st, 0, 1, tp.m, l, l, 1.0, Y, l, nullptr, tp.P, l, 0.0, U, l));
+  // G = P_set U   (l x l) into Y? Y is only m x l sized conceptually but buffers are l x l
+  HIPCHK(mm(st, 0, 0, l, l, tp.m, 1.0, tp.P + tp.r0, l, nullptr, U, l, 0.0, Y, l));
+  if (!tp.comp) HIPCHK(sym_plus(l, Y, 1.0, nullptr, 0.0, out, st));
+  else HIPCHK(sym_plus(l, Y, -1.0, S, 1.0 / tp.mu, out, st));
+  return KOT_OK;
+}
+
+// y = (Q/(2 lam2) + mu I + Phi T Phi*) v  with the B = P^T R chain (Bm holds B)
+kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const double* v, double* y) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  // y = Q v / (2 lam2) + mu v
+  HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / (2.0 * cv.lam2), cv.Q, l, nullptr, v, 1, 0.0, y, 1));
+  HIPCHK(vec_axpby(l, tp.mu, v, 1.0, y, st));
+  if (tp.comp) {  // + (1/mu) (K o K) v
+    HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / tp.mu, cv.KK, l, nullptr, v, 1, 1.0, y, 1));
+  }
+  if (tp.m == 0) return KOT_OK;
+  const double* Bs = ctx->Bm + (long long)tp.r0 * l;
+  double* C = ctx->T3;
+  double* E = ctx->T4;
+  // C = B_set diag(v) B^T   (m x l)
+  HIPCHK(mm(st, 0, 1, tp.m, l, l, 1.0, Bs, l, v, ctx->Bm, l, 0.0, C, l));
+  // H = [Psi o C] with the cross block doubled
+  HIPCHK(psi_hadamard(l, tp.a, tp.r0, tp.m, tp.mu, tp.w, C, l, tp.comp, 1.0, 2.0, st));
+  // E = H B
+  HIPCHK(mm(st, 0, 0, tp.m, l, l, 1.0, C, l, nullptr, ctx->Bm, l, 0.0, E, l));
+  // y_i += (+/-) sum_{r in set} B_ri E_ri
+  HIPCHK(diag_dot(0, tp.m, l, tp.comp ? -1.0 : 1.0, Bs, l, E, l, 1.0, y, ctx->part, st));
+  return KOT_OK;
+}
+
+struct DirInfo {
+  int cg_iters = 0;
+  double cg_res = 0.0;
+};
+
+// Algorithm 1 at state s with regularization mu: writes ctx->dg, ctx->dX.
+kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, double mu, const kot_params* p, DirInfo* info) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  TPlan tp = make_tplan(l, s.a, mu, s.P, s.s);
+  // B = P^T R
+  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, s.P, l, nullptr, cv.R, l, 0.0, ctx->Bm, l));
+  // M = r2 + T[r2]  (kept in Mr), a1 = -r1 - Phi(M)/(mu+1)
+  KCHK(t_apply(ctx, tp, s.r2, ctx->T1));
+  HIPCHK(vec_lincomb(l * l, 1.0, s.r2, 1.0, ctx->T1, ctx->Mr, st));
+  HIPCHK(vec_copy(l, s.r1, ctx->a1, st));
+  KCHK(phi_op(ctx, cv, ctx->Mr, -1.0 / (mu + 1.0), -1.0, ctx->a1, ctx->T2));
+  // CG on the Schur system from x = 0 (Eq. 4.5 on the CG residual)
+  double* x = ctx->cx;
+  double* r = ctx->cr;
+  double* pp = ctx->cp;
+  double* Ap = ctx->cAp;
+  HIPCHK(vec_fill(l, 0.0, x, st));
+  HIPCHK(vec_copy(l, ctx->a1, r, st));
+  HIPCHK(vec_copy(l, ctx->a1, pp, st));
+  HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
+  KCHK(sync_read(ctx, 1, 0));
+  double rr = ctx->hsc[0];
+  double xx = 0.0;
+  int it = 0;
+  const double rnorm = s.rn;
+  while (it < p->cg_max_iter) {
+    const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
+    if (std::sqrt(rr) <= thr) break;
+    KCHK(schur_matvec(ctx, cv, tp, pp, Ap));
+    HIPCHK(dot(l, pp, Ap, ctx->dsc + 0, ctx->part, st));
+    KCHK(sync_read(ctx, 1, 0));
+    const double pAp = ctx->hsc[0];
+    if (!(pAp > 0.0)) break;
+    const double alpha = rr / pAp;
+    HIPCHK(vec_axpby(l, alpha, pp, 1.0, x, st));
+    HIPCHK(vec_axpby(l, -alpha, Ap, 1.0, r, st));
+    HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
+    HIPCHK(dot(l, x, x, ctx->dsc + 1, ctx->part, st));
+    KCHK(sync_read(ctx, 2, 0));
+    const double rr_new = ctx->hsc[0];
+    xx = ctx->hsc[1];
+    HIPCHK(vec_axpby(l, 1.0, r, rr_new / rr, pp, st));
+    rr = rr_new;
+    ++it;
+  }
+  info->cg_iters = it;
+  info->cg_res = std::sqrt(rr);
+  // dgamma = x;  dX = a~2 - T[Phi*(x)],  a~2 = (a2 + T[a2])/(mu+1) = -M/(mu+1)
+  HIPCHK(vec_copy(l, x, ctx->dg, st));
+  KCHK(phi_star(ctx, cv, x, ctx->T1));
+  KCHK(t_apply(ctx, tp, ctx->T1, ctx->T2));
+  HIPCHK(vec_lincomb(l * l, -1.0 / (mu + 1.0), ctx->Mr, -1.0, ctx->T2, ctx->dX, st));
+  return KOT_OK;
+}
+
+// Pi(Y) into out via an eigendecomposition warm-started from Pbasis (updated in place); ws: w buffer.
+kot_status proj_psd(kot_ctx* ctx, int l, double* Y, double* Pbasis, double* wbuf, bool warm, double* out,
+                    const kot_params* p, int* sweeps_acc) {
+  HIPCHK(symmetrize(l, Y, ctx->stream));
+  KCHK(eig_run(ctx, l, Y, warm ? Pbasis : nullptr, ctx->T2, wbuf, p, sweeps_acc));
+  HIPCHK(vec_copy(l * l, ctx->T2, Pbasis, ctx->stream));
+  HIPCHK(count_positive(l, wbuf, ctx->dint, ctx->stream));
+  KCHK(sync_read(ctx, 0, 1));
+  KCHK(proj_from_eig(ctx, l, Pbasis, wbuf, ctx->hint[0], out));
+  return KOT_OK;
+}
+
+// One extragradient step on Eq. (4.1) from (g, X) with r1(g, X) given; writes (gn, Xn).
+kot_status eg_step_impl(kot_ctx* ctx, const CoreView& cv, const double* g, const double* X, const double* r1,
+                        double eta, double* gn, double* Xn, bool warm, const kot_params* p, int* sweeps_acc) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  // half step: gh = g - eta r1(g,X);  Xh = Pi(X - eta (Phi*(g) + lam1 I))
+  HIPCHK(vec_lincomb(l, 1.0, g, -eta, r1, ctx->gh, st));
+  KCHK(phi_star(ctx, cv, g, ctx->T1));
+  HIPCHK(vec_lincomb(l * l, 1.0, X, -eta, ctx->T1, ctx->Z, st));
+  HIPCHK(add_diag(l, -eta * cv.lam1, ctx->Z, st));
+  KCHK(proj_psd(ctx, l, ctx->Z, ctx->Pe1, ctx->s_e1, warm, ctx->Xh, p, sweeps_acc));
+  // full step with F at the half point
+  KCHK(r1_op(ctx, cv, ctx->gh, ctx->Xh, ctx->r1h, ctx->T1));
+  HIPCHK(vec_lincomb(l, 1.0, g, -eta, ctx->r1h, gn, st));
+  KCHK(phi_star(ctx, cv, ctx->gh, ctx->T1));
+  HIPCHK(vec_lincomb(l * l, 1.0, X, -eta, ctx->T1, ctx->Z, st));
+  HIPCHK(add_diag(l, -eta * cv.lam1, ctx->Z, st));
+  KCHK(proj_psd(ctx, l, ctx->Z, ctx->Pe2, ctx->s_e2, warm, Xn, p, sweeps_acc));
+  return KOT_OK;
+}
+
+kot_status copy_state(kot_ctx* ctx, int l, const State& from, State& to) {
+  hipStream_t st = ctx->stream;
+  HIPCHK(vec_copy(l, from.g, to.g, st));
+  HIPCHK(vec_copy(l * l, from.X, to.X, st));
+  HIPCHK(vec_copy(l, from.r1, to.r1, st));
+  HIPCHK(vec_copy(l * l, from.r2, to.r2, st));
+  HIPCHK(vec_copy(l * l, from.P, to.P, st));
+  HIPCHK(vec_copy(l, from.s, to.s, st));
+  to.a = from.a; to.r1n = from.r1n; to.r2n = from.r2n; to.rn = from.rn; to.has_eig = from.has_eig;
+  return KOT_OK;
+}
+
+kot_status prepare_core(kot_ctx* ctx, CoreView& cv) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  // KK = (R^T R) o (R^T R)
+  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, cv.R, l, nullptr, cv.R, l, 0.0, ctx->Kb, l));
+  HIPCHK(hadamard_square(l * l, ctx->Kb, ctx->KKb, st));
+  cv.KK = ctx->KKb;
+  return KOT_OK;
+}
+
+kot_status default_eta(kot_ctx* ctx, const CoreView& cv, double* eta) {
+  const int l = cv.l;
+  HIPCHK(rowsum_abs_max(l, cv.Q, false, ctx->dsc + 0, ctx->part, ctx->stream));
+  HIPCHK(rowsum_abs_max(l, cv.KK, false, ctx->dsc + 1, ctx->part, ctx->stream));
+  KCHK(sync_read(ctx, 2, 0));
+  *eta = 0.5 / (ctx->hsc[0] / (2.0 * cv.lam2) + std::sqrt(ctx->hsc[1]));
+  return KOT_OK;
+}
+
+kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
+  if (!p) return fail(ctx, KOT_ERR_ARG, "params is NULL");
+  if (need_sigma && !(p->sigma > 0.0)) return fail(ctx, KOT_ERR_ARG, "sigma must be > 0");
+  if (!(p->lambda1 > 0.0) || !(p->lambda2 > 0.0)) return fail(ctx, KOT_ERR_ARG, "lambda1, lambda2 must be > 0");
+  if (p->max_iter < 0 || p->cg_max_iter < 0) return fail(ctx, KOT_ERR_ARG, "negative iteration cap");
+  if (p->precision != KOT_FP64) return fail(ctx, KOT_ERR_ARG, "precision %d is not available in this build", p->precision);
+  if (p->safeguard != KOT_SAFEGUARD_EG && p->safeguard != KOT_SAFEGUARD_NONE)
+    return fail(ctx, KOT_ERR_ARG, "unknown safeguard %d", p->safeguard);
+  return KOT_OK;
+}
+
+// Algorithm 2 on a prepared core.
+kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const double* gamma0, kot_result* res) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipEventRecord(ctx->ev0, st));
+  KCHK(prepare_core(ctx, cv));
+  double eta = p->eg_step;
+  if (!(eta > 0.0)) KCHK(default_eta(ctx, cv, &eta));
+  State* W = &ctx->S[0];
+  State* T = &ctx->S[1];
+  State* V = &ctx->S[2];
+  if (gamma0) HIPCHK(vec_copy(l, gamma0, W->g, st));
+  else HIPCHK(vec_fill(l, 0.0, W->g, st));
+  HIPCHK(vec_fill(l * l, 0.0, W->X, st));
+  int sweeps = 0;
+  KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+  const bool use_eg = p->safeguard == KOT_SAFEGUARD_EG;
+  if (use_eg) KCHK(copy_state(ctx, l, *W, *V));
+  double theta = p->theta0;
+  int k = 0, cg_total = 0, eg_acc = 0, nulls = 0;
+  kot_status status = KOT_NOT_CONVERGED;
+  bool warm_e = false;
+  for (k = 0;; ++k) {
+    if (res->res_hist && k < res->hist_cap) res->res_hist[k] = W->rn;
+    if (res->res_v_hist && k < res->hist_cap) res->res_v_hist[k] = use_eg ? V->rn : W->rn;
+    if (!std::isfinite(W->rn)) { status = KOT_ERR_NUMERIC; break; }
+    if (W->rn <= p->tol) { status = KOT_OK; break; }
+    if (k >= p->max_iter) break;
+    // (1) safeguard: one EG step on v, then R(v_{k+1})
+    if (use_eg) {
+      State* H = &ctx->S[3];
+      KCHK(eg_step_impl(ctx, cv, V->g, V->X, V->r1, eta, H->g, H->X, warm_e && p->warm_eig, p, &sweeps));
+      warm_e = true;
+      std::swap(H->g, V->g);
+      std::swap(H->X, V->X);
+      KCHK(residual_state(ctx, cv, *V, p->warm_eig ? V->P : nullptr, p, &sweeps));
+    }
+    // (2) regularized SSN trial
+    const double mu = theta * W->rn;
+    DirInfo di;
+    KCHK(ssn_direction(ctx, cv, *W, mu, p, &di));
+    cg_total += di.cg_iters;
+    HIPCHK(vec_lincomb(l, 1.0, W->g, 1.0, ctx->dg, T->g, st));
+    HIPCHK(vec_lincomb(l * l, 1.0, W->X, 1.0, ctx->dX, T->X, st));
+    KCHK(residual_state(ctx, cv, *T, p->warm_eig ? W->P : nullptr, p, &sweeps));
+    // theta rule (Section 4.3): rho = -<R(w + dw), dw>
+    HIPCHK(dot(l, T->r1, ctx->dg, ctx->dsc + 0, ctx->part, st));
+    HIPCHK(dot(l * l, T->r2, ctx->dX, ctx->dsc + 1, ctx->part, st));
+    HIPCHK(dot(l, ctx->dg, ctx->dg, ctx->dsc + 2, ctx->part, st));
+    HIPCHK(dot(l * l, ctx->dX, ctx->dX, ctx->dsc + 3, ctx->part, st));
+    KCHK(sync_read(ctx, 4, 0));
+    const double rho = -(ctx->hsc[0] + ctx->hsc[1]);
+    const double dwn = std::sqrt(ctx->hsc[2]) + std::sqrt(ctx->hsc[3]);
+    const double dw2 = dwn * dwn;
+    if (rho >= p->alpha2 * dw2) theta = std::max(p->theta_min, p->beta0 * theta);
+    else if (rho >= p->alpha1 * dw2) theta = p->beta1 * theta;
+    else theta = std::min(p->theta_max, p->beta2 * theta);
+    // (3) accept test
+    const double rv = use_eg ? V->rn : INFINITY;
+    if (p->null_step && T->rn > W->rn && (!use_eg || W->rn <= rv)) {
+      ++nulls;
+    } else if (!use_eg || T->rn <= rv) {
+      std::swap(ctx->S[0], ctx->S[1]);
+      W = &ctx->S[0];
+      T = &ctx->S[1];
+    } else {
+      KCHK(copy_state(ctx, l, *V, *W));
+      ++eg_acc;
+    }
+  }
+  res->iters = k;
+  res->cg_iters_total = cg_total;
+  res->eg_accepts = eg_acc;
+  res->null_steps = nulls;
+  res->eig_sweeps_total = sweeps;
+  res->alpha_last = W->a;
+  res->residual = W->rn;
+  // outputs
+  if (res->gamma) HIPCHK(vec_copy(l, W->g, res->gamma, st));
+  if (res->X) HIPCHK(vec_copy(l * l, W->X, res->X, st));
+  HIPCHK(dot(l, W->g, cv.wsum, ctx->dsc + 0, ctx->part, st));
+  HIPCHK(hipEventRecord(ctx->ev1, st));
+  KCHK(sync_read(ctx, 1, 0));
+  res->ot = (cv.q2 - ctx->hsc[0]) / (2.0 * cv.lam2);
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  res->time_ms = ms;
+  if (status == KOT_ERR_NUMERIC) return fail(ctx, KOT_ERR_NUMERIC, "non-finite residual at iteration %d", k);
+  return status;
+}
+
+kot_status setup_impl(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, double* Q, double* z, double* R,
+                      double* wsum, double* q2) {
+  const int l = pb->l, d = pb->d;
+  hipStream_t st = ctx->stream;
+  HIPCHK(gram_build(l, d, pb->xf, pb->yf, p->sigma, Q, ctx->Kb, st));
+  HIPCHK(mean_embedding(pb->n_src, l, d, pb->xs, pb->xf, p->sigma, ctx->wmu, st));
+  HIPCHK(mean_embedding(pb->n_tgt, l, d, pb->ys, pb->yf, p->sigma, ctx->wnu, st));
+  HIPCHK(mean_gram(pb->n_src, d, pb->xs, p->sigma, ctx->dsc + 0, ctx->part, st));
+  HIPCHK(mean_gram(pb->n_tgt, d, pb->ys, p->sigma, ctx->dsc + 1, ctx->part, st));
+  HIPCHK(build_z(l, d, pb->xf, pb->yf, ctx->wmu, ctx->wnu, p->lambda2, z, wsum, st));
+  HIPCHK(cholesky_upper(l, ctx->Kb, p->eps_jitter, R, ctx->T1, ctx->dint, st));
+  KCHK(sync_read(ctx, 2, 1));
+  *q2 = ctx->hsc[0] + ctx->hsc[1];
+  if (ctx->hint[0] != 0)
+    return fail(ctx, KOT_ERR_FACTOR, "K + eps I is not positive definite (pivot %d)", ctx->hint[0]);
+  return KOT_OK;
+}
+
+kot_status check_problem(kot_ctx* ctx, const kot_problem* pb) {
+  if (!pb) return fail(ctx, KOT_ERR_ARG, "problem is NULL");
+  if (pb->l < 1 || pb->d < 1 || pb->n_src < 1 || pb->n_tgt < 1)
+    return fail(ctx, KOT_ERR_ARG, "sizes must be >= 1 (l=%d d=%d n_src=%d n_tgt=%d)", pb->l, pb->d, pb->n_src, pb->n_tgt);
+  if (pb->d > 64) return fail(ctx, KOT_ERR_ARG, "d must be <= 64");
+  if (pb->l > 4096) return fail(ctx, KOT_ERR_ARG, "l must be <= 4096");
+  if (!pb->xs || !pb->ys || !pb->xf || !pb->yf) return fail(ctx, KOT_ERR_ARG, "null point array");
+  return KOT_OK;
+}
+
+kot_status check_ctx(kot_ctx* ctx) {
+  if (!ctx) return KOT_ERR_ARG;
+  ctx->err.clear();
+  g_prof = &ctx->prof;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, KOT_ERR_HIP, "hipSetDevice failed");
+  return KOT_OK;
+}
+
+}  // namespace
+
+// ================================================================================================
+extern "C" {
+
+void kot_params_default(kot_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->sigma = 1.0;
+  p->lambda1 = 1e-3;
+  p->lambda2 = 1e-3;
+  p->eps_jitter = 1e-10;
+  p->tol = 1e-6;
+  p->max_iter = 200;
+  p->cg_max_iter = 20;
+  p->tau = 0.5;
+  p->kappa = 0.5;
+  p->alpha1 = 1e-6;
+  p->alpha2 = 1.0;
+  p->beta0 = 0.5;
+  p->beta1 = 1.0 / 1.2;
+  p->beta2 = 5.0;
+  p->theta0 = 1.0;
+  p->theta_min = 1e-6;
+  p->theta_max = 1e6;
+  p->eg_step = 0.0;
+  p->precision = KOT_FP64;
+  p->safeguard = KOT_SAFEGUARD_EG;
+  p->null_step = 1;
+  p->eig_max_sweeps = 30;
+  p->warm_eig = 1;
+}
+
+kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {
+  if (!out) return KOT_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KOT_ERR_ARG;
+  kot_ctx* ctx = new kot_ctx();
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) { delete ctx; return KOT_ERR_HIP; }
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return KOT_ERR_HIP; }
+    ctx->own_stream = true;
+  }
+  bool ok = hipMalloc(&ctx->dsc, 64 * sizeof(double)) == hipSuccess &&
+            hipHostMalloc(&ctx->hsc, 64 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&ctx->dint, 16 * sizeof(int)) == hipSuccess &&
+            hipHostMalloc(&ctx->hint, 16 * sizeof(int)) == hipSuccess &&
+            hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
+  if (!ok) { kot_destroy(ctx); return KOT_ERR_HIP; }
+  *out = ctx;
+  return KOT_OK;
+}
+
+kot_status kot_destroy(kot_ctx* ctx) {
+  if (!ctx) return KOT_ERR_ARG;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  free_ws(ctx);
+  hipFree(ctx->dsc);
+  hipHostFree(ctx->hsc);
+  hipFree(ctx->dint);
+  hipHostFree(ctx->hint);
+  if (ctx->ev0) hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) hipEventDestroy(ctx->ev1);
+  if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return KOT_OK;
+}
+
+const char* kot_last_error(const kot_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+kot_status kot_setup(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, double* Q, double* z, double* R,
+                     double* wsum, double* q2) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_problem(ctx, pb));
+  KCHK(check_params(ctx, p, true));
+  if (!Q || !z || !R || !wsum || !q2) return fail(ctx, KOT_ERR_ARG, "null output");
+  KCHK(ensure_ws(ctx, pb->l, std::max(pb->n_src, pb->n_tgt)));
+  return setup_impl(ctx, pb, p, Q, z, R, wsum, q2);
+}
+
+kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, const double* gamma0, kot_result* res) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_problem(ctx, pb));
+  KCHK(check_params(ctx, p, true));
+  if (!res || !res->gamma) return fail(ctx, KOT_ERR_ARG, "result or result->gamma is NULL");
+  KCHK(ensure_ws(ctx, pb->l, std::max(pb->n_src, pb->n_tgt)));
+  double q2 = 0.0;
+  KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2));
+  CoreView cv;
+  cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb; cv.q2 = q2;
+  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  return run_alg2(ctx, cv, p, gamma0, res);
+}
+
+kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, double q2,
+                          const double* wsum, const kot_params* p, const double* gamma0, kot_result* res) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_params(ctx, p, false));
+  if (l < 1 || l > 4096) return fail(ctx, KOT_ERR_ARG, "l must be in [1, 4096]");
+  if (!Q || !z || !R || !wsum || !res || !res->gamma) return fail(ctx, KOT_ERR_ARG, "null pointer argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  CoreView cv;
+  cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.wsum = wsum; cv.q2 = q2; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  return run_alg2(ctx, cv, p, gamma0, res);
+}
+
+kot_status kot_eigh(kot_ctx* ctx, int l, const double* Z, double* P, double* w, const kot_params* p) {
+  KCHK(check_ctx(ctx));
+  if (l < 1 || l > 4096 || !Z || !P || !w || !p) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  HIPCHK(vec_copy(l * l, Z, ctx->Z, ctx->stream));
+  HIPCHK(symmetrize(l, ctx->Z, ctx->stream));
+  int sw = 0;
+  kot_status s = eig_run(ctx, l, ctx->Z, nullptr, P, w, p, &sw);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return s;
+}
+
+kot_status kot_residual(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, const double* gamma,
+                        const double* X, const kot_params* p, double* r1, double* r2, double* norms) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_params(ctx, p, false));
+  if (l < 1 || l > 4096 || !Q || !z || !R || !gamma || !X || !r1 || !r2 || !norms)
+    return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  CoreView cv;
+  cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  State& s = ctx->S[3];
+  HIPCHK(vec_copy(l, gamma, s.g, ctx->stream));
+  HIPCHK(vec_copy(l * l, X, s.X, ctx->stream));
+  KCHK(residual_state(ctx, cv, s, nullptr, p, nullptr));
+  HIPCHK(vec_copy(l, s.r1, r1, ctx->stream));
+  HIPCHK(vec_copy(l * l, s.r2, r2, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  norms[0] = s.r1n;
+  norms[1] = s.r2n;
+  norms[2] = (double)s.a;
+  return KOT_OK;
+}
+
+kot_status kot_ssn_direction(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, const double* gamma,
+                             const double* X, double mu, const kot_params* p, double* dgamma, double* dX, double* info) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_params(ctx, p, false));
+  if (l < 1 || l > 4096 || !Q || !z || !R || !gamma || !X || !dgamma || !dX || !info || !(mu > 0.0))
+    return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  CoreView cv;
+  cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  KCHK(prepare_core(ctx, cv));
+  State& s = ctx->S[0];
+  HIPCHK(vec_copy(l, gamma, s.g, ctx->stream));
+  HIPCHK(vec_copy(l * l, X, s.X, ctx->stream));
+  KCHK(residual_state(ctx, cv, s, nullptr, p, nullptr));
+  DirInfo di;
+  KCHK(ssn_direction(ctx, cv, s, mu, p, &di));
+  HIPCHK(vec_copy(l, ctx->dg, dgamma, ctx->stream));
+  HIPCHK(vec_copy(l * l, ctx->dX, dX, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  info[0] = di.cg_iters;
+  info[1] = di.cg_res;
+  info[2] = s.a;
+  info[3] = s.rn;
+  return KOT_OK;
+}
+
+kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, const double* gamma,
+                       const double* X, double eta, const kot_params* p, double* gamma_out, double* X_out) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_params(ctx, p, false));
+  if (l < 1 || l > 4096 || !Q || !z || !R || !gamma || !X || !gamma_out || !X_out || !(eta > 0.0))
+    return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  CoreView cv;
+  cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  KCHK(r1_op(ctx, cv, gamma, X, ctx->vtmp, ctx->T2));
+  KCHK(eg_step_impl(ctx, cv, gamma, X, ctx->vtmp, eta, gamma_out, X_out, false, p, nullptr));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
+kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double* R) {
+  KCHK(check_ctx(ctx));
+  if (l < 1 || l > 4096 || !A || !R || !(eps >= 0.0)) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  HIPCHK(cholesky_upper(l, A, eps, R, ctx->T1, ctx->dint, ctx->stream));
+  KCHK(sync_read(ctx, 0, 1));
+  if (ctx->hint[0] != 0) return fail(ctx, KOT_ERR_FACTOR, "matrix is not positive definite (pivot %d)", ctx->hint[0]);
+  return KOT_OK;
+}
+
+kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass) {
+  KCHK(check_ctx(ctx));
+  if (enable) {
+    ctx->prof.clear();
+    ctx->prof.on = true;
+    return KOT_OK;
+  }
+  ctx->prof.on = false;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (out) {
+    for (int c = 0; c < nclass * 4; ++c) out[c] = 0.0;
+    for (const auto& r : ctx->prof.recs) {
+      if (r.cls >= nclass || !r.a || !r.b) continue;
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+      out[4 * r.cls + 0] += 1.0;
+      out[4 * r.cls + 1] += ms;
+      out[4 * r.cls + 2] += r.flops;
+      out[4 * r.cls + 3] += r.bytes;
+    }
+  }
+  ctx->prof.clear();
+  return KOT_OK;
+}
+
+kot_status kot_gemm(kot_ctx* ctx, int transa, int transb, int m, int n, int k, double alpha, const double* A, int lda,
+                    const double* s, const double* B, int ldb, double beta, double* C, int ldc) {
+  KCHK(check_ctx(ctx));
+  if (m < 0 || n < 0 || k < 1 || !A || !B || !C) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  HIPCHK(mm(ctx->stream, transa ? 1 : 0, transb ? 1 : 0, m, n, k, alpha, A, lda, s, B, ldb, beta, C, ldc));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
+}  // extern "C"

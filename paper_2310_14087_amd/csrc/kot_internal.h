@@ -1,0 +1,110 @@
+// Internal declarations shared by the HIP kernels and the host orchestration of libkotssn.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <vector>
+
+namespace kot {
+
+// ---- optional launch profiler (events around kernel launches on the issuing stream) -----------------------
+enum ProfClass { PROF_GEMM_F64 = 0, PROF_EIG_ROUND = 1, PROF_EIG_OTHER = 2, PROF_NCLASS = 3 };
+struct Profiler {
+  bool on = false;
+  struct Rec { int cls; double flops; double bytes; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  hipEvent_t get();
+  // begin/end bracket one launch (or a fixed group of launches) of class cls
+  void begin(hipStream_t st, int cls, double flops, double bytes);
+  void end(hipStream_t st);
+  void clear();
+  ~Profiler();
+};
+extern thread_local Profiler* g_prof;
+
+// ---- GEMM (FP64 MFMA): C = alpha * op(A) * diag(s) * op(B) + beta * C, row-major --------------------------
+// Batched over grid.z with element strides sA, sB, sS, sC (0 for a shared operand).
+struct GemmArgs {
+  int transa, transb, m, n, k;
+  double alpha, beta;
+  const double* A; int lda; long long sA;
+  const double* s; long long sS;      // may be null
+  const double* B; int ldb; long long sB;
+  double* C; int ldc; long long sC;
+  int batch;
+};
+hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
+
+// y[j] = alpha * sum_{r in [r0, r1)} A[r*lda + j] * B[r*ldb + j] + beta * y[j], j < n (column dots).
+// part: workspace of at least kDiagParts * n doubles.
+constexpr int kDiagParts = 16;
+hipError_t diag_dot(int r0, int r1, int n, double alpha, const double* A, int lda, const double* B, int ldb,
+                    double beta, double* y, double* part, hipStream_t st);
+
+// ---- setup ------------------------------------------------------------------------------------------------
+hipError_t gram_build(int l, int d, const double* xf, const double* yf, double sigma, double* Q, double* K,
+                      hipStream_t st);
+hipError_t mean_embedding(int n, int l, int d, const double* samples, const double* pts, double sigma,
+                          double* w, hipStream_t st);
+// sum_{i,j} k(x_i, x_j) / n^2 written to out[0]; part: workspace of at least n doubles.
+hipError_t mean_gram(int n, int d, const double* x, double sigma, double* out, double* part, hipStream_t st);
+hipError_t build_z(int l, int d, const double* xf, const double* yf, const double* wmu, const double* wnu,
+                   double lam2, double* z, double* wsum, hipStream_t st);
+
+// ---- Cholesky: R^T R = A + eps I (R upper). info[0] != 0 on a non-positive pivot. ----------------------------
+hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double* work, int* info, hipStream_t st);
+
+// ---- symmetric eigensolver (block Jacobi) ------------------------------------------------------------------
+struct EigWork;
+EigWork* eig_work_create(int lmax);
+void eig_work_destroy(EigWork* w);
+// Z (l x l) -> P (columns eigenvectors), wv ascending.  If P0 is non-null, starts from the basis P0
+// (columns orthonormal).  Returns the sweep count through *sweeps and off/norm through *rel_off.
+// tmp: workspace of at least 2*l*l doubles.
+hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
+                       int max_sweeps, double tol, int* sweeps, double* rel_off, hipStream_t st);
+
+// ---- vector kernels -----------------------------------------------------------------------------------------
+hipError_t vec_fill(int n, double v, double* x, hipStream_t st);
+hipError_t mat_fill(int rows, int cols, double v, double* C, int ldc, hipStream_t st);
+hipError_t vec_copy(int n, const double* x, double* y, hipStream_t st);
+// y = a*x + b*y
+hipError_t vec_axpby(int n, double a, const double* x, double b, double* y, hipStream_t st);
+// z = a*x + b*y
+hipError_t vec_lincomb(int n, double a, const double* x, double b, const double* y, double* z, hipStream_t st);
+// X += a * I  (l x l)
+hipError_t add_diag(int l, double a, double* X, hipStream_t st);
+// Z = 0.5 * (Z + Z^T)
+hipError_t symmetrize(int l, double* Z, hipStream_t st);
+// Deterministic reductions: out[slot] = sum x*y (or sum x^2); partials in part (>= kRedBlocks doubles).
+constexpr int kRedBlocks = 256;
+hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st);
+// out[0] = max_i sum_j |A_ij| (row-sum norm)
+hipError_t rowsum_abs_max(int l, const double* A, bool square_entries, double* out, double* part, hipStream_t st);
+// count of w[i] > 0 (ascending w): out_int[0]
+hipError_t count_positive(int l, const double* w, int* out_int, hipStream_t st);
+// Psi rows for the eigen-index range [r0, r0 + m): H[r][j] = weight(r, j) * C[r][j] (in place), with
+// weight per Section 4.3; 'complement' selects the complement form used when |alpha| > l/2; 'half_diag'
+// scales the within-set block by 1/2 (for G + G^T) and 'double_off' doubles the cross block (CG chain).
+hipError_t psi_hadamard(int l, int a, int r0, int m, double mu, const double* w, double* C, int ldc,
+                        bool complement, double diag_scale, double off_scale, hipStream_t st);
+// out = P_S diag(w_S) P_S^T restricted to eigen-index set S = [r0, r0+m): via gemm (helper in host code)
+// X_out = X - Y ; also norm
+hipError_t mat_sub(int n, const double* X, const double* Y, double* out, hipStream_t st);
+hipError_t transpose(int l, const double* A, double* At, hipStream_t st);
+hipError_t hadamard_square(int n, const double* A, double* out, hipStream_t st);
+// G + G^T into out (l x l): out[i][j] = a*(G[i][j] + G[j][i]) + b*S[i][j]
+hipError_t sym_plus(int l, const double* G, double a, const double* S, double b, double* out, hipStream_t st);
+// scale columns: out[i][j] = A[i][j] * s[j]
+hipError_t scale_cols(int rows, int cols, const double* A, int lda, const double* s, double* out, int ldo,
+                      hipStream_t st);
+
+}  // namespace kot
+
+#define KOT_HIP_TRY(expr)                                   \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return _e;                        \
+  } while (0)

@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI library and the input generator (no GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_14087_amd.inputs import make_problem, WORKLOADS
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kotssn.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(kot_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2310_14087_amd import kotssn
+    path = kotssn._LIBPATH
+    if not path.exists():
+        from paper_2310_14087_amd import build
+        build.build()
+    return kotssn.load()
+
+
+def test_header_exports_every_symbol(lib):
+    from paper_2310_14087_amd import kotssn
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in kotssn.h but not exported"
+    assert sorted(kotssn.EXPORTED) == names
+
+
+def test_params_default_host_only(lib):
+    from paper_2310_14087_amd import kotssn
+    p = kotssn.default_params()
+    assert p.tol == 1e-6 and p.max_iter == 200 and p.cg_max_iter == 20
+    assert p.tau == 0.5 and p.kappa == 0.5
+    assert p.alpha1 == 1e-6 and p.alpha2 == 1.0 and p.beta0 == 0.5 and p.beta2 == 5.0
+    assert p.beta1 == pytest.approx(1 / 1.2)
+    assert p.null_step == 1 and p.safeguard == kotssn.KOT_SAFEGUARD_EG and p.precision == kotssn.KOT_FP64
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the C structs have the sizes the header implies (field order / padding)."""
+    from paper_2310_14087_amd import kotssn
+    assert C.sizeof(kotssn.KotParams) == 8 * 3 + 8 + 8 + 4 + 4 + 8 * 11 + 4 * 5 + 4
+    assert C.sizeof(kotssn.KotProblem) == 16 + 4 * 8
+    assert C.sizeof(kotssn.KotResult) == 8 * 4 + 8 + 8 + 8 + 4 * 6 + 8
+
+
+def test_null_arguments_are_rejected_without_a_device(lib):
+    from paper_2310_14087_amd import kotssn
+    assert lib.kot_create(None, 0, None) == kotssn.KOT_ERR_ARG
+    assert lib.kot_destroy(None) == kotssn.KOT_ERR_ARG
+    assert lib.kot_last_error(None) == b"null context"
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_generator_is_seeded(name):
+    a = make_problem(name, 1, l=30, n=60)
+    b = make_problem(name, 1, l=30, n=60)
+    c = make_problem(name, 2, l=30, n=60)
+    for f in ("xs", "ys", "xf", "yf"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
+        assert getattr(a, f).dtype == np.float64 and getattr(a, f).flags.c_contiguous
+    assert not np.array_equal(a.xs, c.xs)
+    assert a.sigma == b.sigma and a.sigma > 0 and a.lam1 > 0 and a.lam2 > 0
+
+
+def test_generator_shapes():
+    p = make_problem("mix1000", 0, l=40, n=50)
+    assert p.xs.shape == (50, 10) and p.xf.shape == (40, 10) and p.lam1 == 1 / 40
+    t = make_problem("tiny", 0)
+    assert t.xs.shape == (100, 2) and t.l == 50 and t.sigma == 1.0 and t.lam1 == t.lam2 == 1e-3 and t.tol == 1e-8

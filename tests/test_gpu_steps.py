@@ -1,0 +1,176 @@
+"""GPU parity of the individual steps of the hot path, through the C-ABI, against the CPU FP64 oracle.
+
+Each test prints the case (entry point, shape, seed) before its GPU call so a failure names it.
+"""
+import numpy as np
+import pytest
+
+from oracle import kot_oracle as ko
+from paper_2310_14087_amd.inputs import make_problem, make_custom
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("m,n,k", [(64, 64, 16), (1, 1, 1), (37, 129, 70), (200, 3, 65), (130, 257, 300)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("scaled", [False, True])
+def test_gemm_f64(gpu_ctx, m, n, k, ta, tb, scaled):
+    _case(f"kot_gemm m={m} n={n} k={k} ta={ta} tb={tb} scaled={scaled}")
+    rng = np.random.default_rng(m * 1000 + n + k)
+    A = rng.standard_normal((k, m) if ta else (m, k))
+    B = rng.standard_normal((n, k) if tb else (k, n))
+    s = rng.standard_normal(k) if scaled else None
+    C0 = rng.standard_normal((m, n))
+    opA = A.T if ta else A
+    opB = B.T if tb else B
+    ref = 0.5 * (opA * (s if scaled else 1.0)) @ opB - 1.5 * C0
+    out = gpu_ctx.gemm(_t(A), _t(B), transa=bool(ta), transb=bool(tb), s=_t(s) if scaled else None,
+                       alpha=0.5, beta=-1.5, Cm=_t(C0))
+    np.testing.assert_allclose(_n(out), ref, rtol=1e-12, atol=1e-12 * k)
+
+
+@pytest.mark.parametrize("name,l,n", [("tiny", None, None), ("gauss500", 120, 400), ("mix1000", 200, 700),
+                                      ("mix256", 97, 300)])
+def test_setup(gpu_ctx, name, l, n):
+    from paper_2310_14087_amd import kotssn
+    p = make_problem(name, 0, l=l, n=n)
+    _case(f"kot_setup {name} l={p.l} n={p.n_src} d={p.d}")
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2)
+    Q, z, R, wsum, q2 = gpu_ctx.setup(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm)
+    np.testing.assert_allclose(_n(Q), core.Q, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(_n(z), core.z, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(_n(wsum), core.wsum, rtol=1e-12, atol=1e-14)
+    assert abs(q2 - core.q2) <= 1e-12 * abs(core.q2)
+    Rg = _n(R)
+    assert np.all(np.tril(Rg, -1) == 0.0)
+    K = core.extra["K"] + 1e-10 * np.eye(p.l)
+    np.testing.assert_allclose(Rg.T @ Rg, K, atol=1e-13)
+    np.testing.assert_allclose(Rg, core.R, atol=1e-9)
+
+
+@pytest.mark.parametrize("l", [1, 2, 7, 16, 33, 64, 100, 257])
+def test_eigh(gpu_ctx, l):
+    from paper_2310_14087_amd import kotssn
+    _case(f"kot_eigh random symmetric l={l}")
+    rng = np.random.default_rng(l)
+    A = rng.standard_normal((l, l))
+    Z = A + A.T
+    w, P = gpu_ctx.eigh(_t(Z), kotssn.default_params())
+    w, P = _n(w), _n(P)
+    wref = np.linalg.eigvalsh(Z)
+    scale = np.abs(wref).max()
+    assert np.all(np.diff(w) >= 0)
+    np.testing.assert_allclose(w, wref, atol=1e-13 * scale * max(1, l ** 0.5))
+    assert np.abs(Z @ P - P * w).max() <= 1e-13 * scale * max(1, l ** 0.5)
+    assert np.abs(P.T @ P - np.eye(l)).max() <= 1e-13 * max(1, l ** 0.5)
+
+
+def test_eigh_degenerate(gpu_ctx):
+    """Repeated and zero eigenvalues: invariants still hold."""
+    from paper_2310_14087_amd import kotssn
+    _case("kot_eigh degenerate l=48")
+    rng = np.random.default_rng(5)
+    Qm, _ = np.linalg.qr(rng.standard_normal((48, 48)))
+    lam = np.repeat([-2.0, 0.0, 0.0, 1.0, 3.0, 3.0], 8)
+    Z = (Qm * lam) @ Qm.T
+    w, P = gpu_ctx.eigh(_t(Z), kotssn.default_params())
+    w, P = _n(w), _n(P)
+    np.testing.assert_allclose(w, np.sort(lam), atol=1e-13 * 3 * 7)
+    assert np.abs(Z @ P - P * w).max() <= 1e-12
+    assert np.abs(P.T @ P - np.eye(48)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("l", [1, 31, 100])
+def test_cholesky(gpu_ctx, l):
+    _case(f"kot_cholesky l={l}")
+    rng = np.random.default_rng(l + 7)
+    A = rng.standard_normal((l, l))
+    S = A @ A.T + l * np.eye(l)
+    R = _n(gpu_ctx.cholesky(_t(S), 0.0))
+    np.testing.assert_allclose(R, np.linalg.cholesky(S).T, rtol=1e-12, atol=1e-12)
+
+
+def test_cholesky_not_pd(gpu_ctx):
+    from paper_2310_14087_amd import kotssn
+    _case("kot_cholesky indefinite l=10")
+    S = np.eye(10)
+    S[3, 3] = -1.0
+    with pytest.raises(kotssn.KotError) as e:
+        gpu_ctx.cholesky(_t(S), 0.0)
+    assert e.value.status == kotssn.KOT_ERR_FACTOR
+
+
+def _core_case(name, l, n, seed=0):
+    p = make_problem(name, seed, l=l, n=n)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    return p, core
+
+
+def _random_iterate(l, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    g = scale * rng.standard_normal(l) * 1e-2
+    B = rng.standard_normal((l, l))
+    X = scale * (B @ B.T) / l
+    return g, X
+
+
+@pytest.mark.parametrize("name,l,n", [("tiny", None, None), ("mix1000", 130, 400), ("gauss500", 90, 300)])
+def test_residual(gpu_ctx, name, l, n):
+    from paper_2310_14087_amd import kotssn
+    p, core = _core_case(name, l, n)
+    _case(f"kot_residual {name} l={core.l}")
+    g, X = _random_iterate(core.l, 11)
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2)
+    r1, r2, (n1, n2, a) = gpu_ctx.residual(_t(core.Q), _t(core.z), _t(core.R), _t(g), _t(X), prm)
+    o1, o2, on, (s, P) = ko.residual(core, g, X)
+    np.testing.assert_allclose(_n(r1), o1, rtol=1e-10, atol=1e-10 * np.abs(o1).max())
+    np.testing.assert_allclose(_n(r2), o2, atol=1e-11 * max(1.0, np.abs(X).max()))
+    assert a == int(np.sum(s > 0))
+    assert abs(n1 + n2 - on) <= 1e-10 * on
+
+
+@pytest.mark.parametrize("name,l,n,mu", [("tiny", None, None, 0.3), ("mix1000", 120, 400, 0.05),
+                                         ("gauss500", 80, 300, 1.0), ("tiny", None, None, 1e-3)])
+def test_ssn_direction(gpu_ctx, name, l, n, mu):
+    """Algorithm 1 with the B-chain / G+G^T forms on the GPU vs the plain dense oracle; CG run to a tight
+    tolerance on both sides so the comparison is of the direction, not of the CG stopping point."""
+    from paper_2310_14087_amd import kotssn
+    p, core = _core_case(name, l, n)
+    _case(f"kot_ssn_direction {name} l={core.l} mu={mu}")
+    g, X = _random_iterate(core.l, 23)
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2, cg_max_iter=400, tau=1e-13, kappa=1e-13)
+    dg, dX, info = gpu_ctx.ssn_direction(_t(core.Q), _t(core.z), _t(core.R), _t(g), _t(X), mu, prm)
+    o1, o2, on, eig = ko.residual(core, g, X)
+    oprm = ko.Params(cg_max_iter=400, tau=1e-13, kappa=1e-13)
+    odg, odX, oinfo = ko.ssn_direction(core, o1, o2, eig, mu, oprm)
+    assert info["alpha"] == oinfo["alpha"]
+    np.testing.assert_allclose(_n(dg), odg, atol=1e-7 * np.abs(odg).max())
+    np.testing.assert_allclose(_n(dX), odX, atol=1e-7 * np.abs(odX).max())
+
+
+@pytest.mark.parametrize("name,l,n", [("tiny", None, None), ("mix1000", 100, 300)])
+def test_eg_step(gpu_ctx, name, l, n):
+    from paper_2310_14087_amd import kotssn
+    p, core = _core_case(name, l, n)
+    _case(f"kot_eg_step {name} l={core.l}")
+    g, X = _random_iterate(core.l, 31)
+    eta = ko.default_eg_step(core)
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2)
+    gn, Xn = gpu_ctx.eg_step(_t(core.Q), _t(core.z), _t(core.R), _t(g), _t(X), eta, prm)
+    ogn, oXn = ko.eg_step(core, g, X, eta)
+    np.testing.assert_allclose(_n(gn), ogn, rtol=1e-11, atol=1e-12 * np.abs(ogn).max())
+    np.testing.assert_allclose(_n(Xn), oXn, atol=1e-11 * max(1.0, np.abs(oXn).max()))
