@@ -68,7 +68,7 @@ def main():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mix1000")
-    ap.add_argument("--arm", default="fp64", choices=["fp64"])
+    ap.add_argument("--arm", default="both", choices=["fp64", "warm", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     a = ap.parse_args()
@@ -93,31 +93,56 @@ def main():
     torch.cuda.synchronize()
 
     ctx = kotssn.Context(0)
-    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol) for p in probs]
+    base = [dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol) for p in probs]
+    arms = ["fp64", "warm"] if a.arm == "both" else [a.arm]
+    theta_dev, H = None, 0
+    if "warm" in arms:
+        from paper_2310_14087_amd import warmstart
+        theta, F, H, meta = warmstart.load()
+        theta_dev = torch.from_numpy(theta).to(dev)
 
-    for w in range(a.warmup):
-        _log(f"warmup {w}")
-        _, _, r = ctx.solve(*dev_inputs[w % n_inst], prms[w % n_inst])
-    torch.cuda.synchronize()
+    def params(i, arm):
+        kw = dict(base[i])
+        if arm == "warm":
+            kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
+        return kotssn.default_params(**kw)
 
-    if not a.no_profile:
-        ctx.profile_start()
-    results = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        i = k % n_inst
-        _, _, r = ctx.solve(*dev_inputs[i], prms[i])
-        results.append(r)
-        _log(f"step {k}: instance {i} status={r.status} iters={r.iters} residual={r.residual:.2e} "
-             f"ot={r.ot:.8g} device_ms={r.time_ms:.1f}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_stop() if not a.no_profile else None
+    def run_arm(arm, profile):
+        for w in range(a.warmup):
+            _log(f"{arm} warmup {w}")
+            ctx.solve(*dev_inputs[w % n_inst], params(w % n_inst, arm))
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile_start()
+        results = []
+        t0 = time.perf_counter()
+        for k in range(a.steps):
+            i = k % n_inst
+            _, _, r = ctx.solve(*dev_inputs[i], params(i, arm))
+            results.append(r)
+            _log(f"{arm} step {k}: instance {i} status={r.status} iters={r.iters} warm_used={r.warm_used} "
+                 f"residual={r.residual:.2e} ot={r.ot:.10g} device_ms={r.time_ms:.1f}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_stop() if profile else None
+        return results, t1 - t0, prof
+
+    out_arms = {}
+    prof = None
+    elapsed = None
+    for arm in arms:
+        results, el, pr = run_arm(arm, not a.no_profile)
+        conv = sum(1 for r in results if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
+        out_arms[arm] = dict(solves_per_s=a.steps / el, ms_per_solve=1e3 * el / a.steps, converged=conv,
+                             iters=[r.iters for r in results], eig_sweeps=[r.eig_sweeps_total for r in results],
+                             cg_iters=[r.cg_iters_total for r in results], ot=[r.ot for r in results])
+        if arm == arms[-1]:
+            elapsed, prof, final = el, pr, arm
     ctx.close()
-
-    elapsed = t1 - t0
-    converged = sum(1 for r in results if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
+    if "fp64" in out_arms and "warm" in out_arms:
+        ot_dev = max(abs(x - y) / abs(y) for x, y in zip(out_arms["warm"]["ot"], out_arms["fp64"]["ot"]))
+        out_arms["warm"]["ot_rel_dev_vs_fp64"] = ot_dev
+        out_arms["speedup_warm_vs_fp64"] = out_arms["warm"]["solves_per_s"] / out_arms["fp64"]["solves_per_s"]
     value = a.steps / elapsed
     out = {
         "metric": "SSN solves/s to residual<=1e-6 at l=1000: plain FP64 vs warm-start+mixed",
@@ -134,9 +159,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: n=5000/side, d=10, two 4-component mixtures, l=1000, "
                                f"sigma^2=0.005 on unit-cube data, lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
-                   "arm": a.arm, "instances": n_inst, "converged": converged,
-                   "iters": [r.iters for r in results], "eig_sweeps": [r.eig_sweeps_total for r in results],
-                   "cg_iters": [r.cg_iters_total for r in results]},
+                   "arm": final, "instances": n_inst, "arms": out_arms},
     }
     if prof:
         dom = max(prof, key=lambda c: prof[c]["ms"])

@@ -62,6 +62,11 @@ typedef struct kot_params {
   int null_step;
   int eig_max_sweeps;  /* Jacobi sweep cap (default 30) */
   int warm_eig;        /* 1: start each eigendecomposition from the previous eigenbasis (default 1) */
+  int lift_x0;         /* with a start gamma0: 1 (default) = X0 = R^-T diag(y) R^-1 with y_i = (Q gamma0 - z)_i/(2 lambda2)
+                          on constraints predicted active (gamma0_i <= -0.9 lambda1, y_i > 0), entries below
+                          0.02 x the mean positive y_i set to 0; 0 = X0 = 0 */
+  int ws_F, ws_H;      /* warm-start network sizes (features, width) when ws_theta is set */
+  const float* ws_theta; /* device, kot_mlp layout; non-NULL: kot_solve predicts gamma0 with the network */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:
@@ -91,6 +96,7 @@ typedef struct kot_result {
   int null_steps;      /* iterations that kept w_k */
   int eig_sweeps_total;
   int alpha_last;      /* number of positive eigenvalues of Z at the returned iterate */
+  int warm_used;       /* 1 if the start from gamma0 was kept (it had |R(w0)| <= |R(0,0)|), else 0 */
   double time_ms;      /* wall time of the solve on the device stream */
 } kot_result;
 
@@ -157,6 +163,30 @@ kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double
 kot_status kot_gemm(kot_ctx* ctx, int transa, int transb, int m, int n, int k, double alpha,
                     const double* A, int lda, const double* s, const double* B, int ldb, double beta,
                     double* C, int ldc);
+
+/* ---- Learned warm start (not in the paper: a network predicting the start dual) ----------------------------
+ * Network: f(x) = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3 applied to each row x of a feature matrix.
+ * Parameters are one flat FP32 device vector theta of kot_mlp_params(F, H) entries laid out W1 (F x H,
+ * row-major), b1 (H), W2 (H x H), b2 (H), W3 (H), b3 (1).  The prediction for filling point i is
+ * gamma0_i = lambda1 * f(x_i).  Features (F = 12 per filling point, FP32, row-major l x 12), bounded and free of
+ * the problem's scale, with f0 = z_i/(lambda1 Q_ii) and K = R^T R: max(f0,-2), max(f0,-1), (Q 1)_i/Q_ii - 1,
+ * (K 1)_i/K_ii - 1, ((K o K) 1)_i/K_ii^2 - 1, Q_ii - 2, K_ii - 1, min(wsum_i/|z_i|, 10), the fraction of points
+ * with f0 < -1, the mean of max(f0,-1), 0, 1.
+ * Callers: training and inference of the warm start.  All matrices FP64 device, features/theta FP32 device. */
+int kot_mlp_params(int F, int H);
+kot_status kot_features(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, const double* wsum,
+                        double q2, const kot_params* prm, float* X);
+/* out (device, n) = f(X) for X (device, n x F). */
+kot_status kot_mlp_forward(kot_ctx* ctx, int n, int F, int H, const float* X, const float* theta, float* out);
+/* loss (host) = mean((f(X) - y)^2); grad (device, same layout as theta) = its gradient. */
+kot_status kot_mlp_loss_grad(kot_ctx* ctx, int n, int F, int H, const float* X, const float* y, const float* theta,
+                             float* grad, double* loss);
+/* One Adam step on theta with moments m, v (device, P entries each); t = step count after this update (>= 1). */
+kot_status kot_mlp_adam(kot_ctx* ctx, int P, float* theta, const float* grad, float* m, float* v, int t, float lr,
+                        float beta1, float beta2, float eps);
+/* gamma0 (device, l) predicted for the problem: runs the setup, the features and the network. */
+kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm, int F, int H,
+                         const float* theta, double* gamma0);
 
 /* Launch profiler for measurement.  enable = 1 clears and starts recording HIP events around every launch
  * of the instrumented kernel classes on the context's stream; enable = 0 stops, waits for the stream, and

@@ -1,6 +1,7 @@
 // FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64) with LDS-staged 64x64x16 tiles, and the
 // column-dot reduction used for Phi(X)_i = R[:,i]^T (X R)[:,i] and the diagonal extract of the CG matvec.
 #include "kot_internal.h"
+#include <algorithm>
 
 namespace kot {
 
@@ -8,26 +9,111 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int PAD = 4;  // row pad (doubles) of the LDS tiles
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int KM_S = BM + 2;   // k-major tile [BK][KM_S] (operand loaded along m / n)
+constexpr int MK_S = BK + 1;   // m-major tile [BM][MK_S] (operand loaded along k)
+constexpr int TILE_D = BK * KM_S;  // == BM * MK_S == 2112 doubles either way
+static_assert(BK * KM_S == BM * MK_S, "tile sizes");
 
 // One 64x64 output tile per workgroup of 256 threads = 4 waves in a 2x2 grid; each wave owns 32x32 =
 // 2x2 MFMA blocks of 16x16.  MFMA operand layout (16x16x4 f64): lane L supplies A[L%16][L/16] and
 // B[L/16][L%16]; the accumulator lane L holds D[L/16 + 4*v][L%16], v = 0..3.
+// Each operand is staged in LDS along the dimension it is contiguous in (global loads and LDS stores both
+// run along that dimension; the odd row stride of the m-major layout keeps the 16-row MFMA reads
+// conflict-free).  The next 32-deep K slice is prefetched into registers while the current one feeds the
+// matrix cores.
 template <bool TA, bool TB, bool SC>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
-  __shared__ double As[BK][BM + PAD];
-  __shared__ double Bs[BK][BN + PAD];
-  const int bz = blockIdx.z;
+struct Tile {
+  double a[8], b[8];
+  __device__ __forceinline__ void load(const GemmArgs& g, const double* __restrict__ A, const double* __restrict__ B,
+                                       const double* __restrict__ S, int m0, int n0, int k0, int t) {
+    const int M = g.m, N = g.n, K = g.k;
+    if (!TA) {  // A[m*lda + k]: lanes along k (32), 8 rows per pass
+      const int kk = t & 31, mm = t >> 5;
+      const int gk = k0 + kk;
+      const double sc = (SC && gk < K) ? S[gk] : 1.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gm = m0 + mm + 8 * u;
+        const double v = (gm < M && gk < K) ? A[(long long)gm * g.lda + gk] : 0.0;
+        a[u] = SC ? v * sc : v;
+      }
+    } else {    // A[k*lda + m]: lanes along m (64), 4 k-rows per pass
+      const int mm = t & 63, kk = t >> 6;
+      const int gm = m0 + mm;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gk = k0 + kk + 4 * u;
+        const double v = (gm < M && gk < K) ? A[(long long)gk * g.lda + gm] : 0.0;
+        a[u] = SC ? ((gk < K) ? v * S[gk] : 0.0) : v;
+      }
+    }
+    if (!TB) {  // B[k*ldb + n]: lanes along n
+      const int nn = t & 63, kk = t >> 6;
+      const int gn = n0 + nn;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gk = k0 + kk + 4 * u;
+        b[u] = (gn < N && gk < K) ? B[(long long)gk * g.ldb + gn] : 0.0;
+      }
+    } else {    // B[n*ldb + k]: lanes along k
+      const int kk = t & 31, nn = t >> 5;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gn = n0 + nn + 8 * u;
+        b[u] = (gn < N && gk < K) ? B[(long long)gn * g.ldb + gk] : 0.0;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(double* __restrict__ As, double* __restrict__ Bs, int t) const {
+    if (!TA) {  // m-major
+      const int kk = t & 31, mm = t >> 5;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) As[(mm + 8 * u) * MK_S + kk] = a[u];
+    } else {    // k-major
+      const int mm = t & 63, kk = t >> 6;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) As[(kk + 4 * u) * KM_S + mm] = a[u];
+    }
+    if (!TB) {  // k-major
+      const int nn = t & 63, kk = t >> 6;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Bs[(kk + 4 * u) * KM_S + nn] = b[u];
+    } else {    // n-major
+      const int kk = t & 31, nn = t >> 5;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Bs[(nn + 8 * u) * MK_S + kk] = b[u];
+    }
+  }
+  // op(A)[m][k] and op(B)[k][n] from the staged tiles
+  static __device__ __forceinline__ double ga(const double* As, int m, int k) {
+    return TA ? As[k * KM_S + m] : As[m * MK_S + k];
+  }
+  static __device__ __forceinline__ double gb(const double* Bs, int k, int n) {
+    return TB ? Bs[n * MK_S + k] : Bs[k * KM_S + n];
+  }
+};
+
+// blockIdx.z = batch * splits + split.  With splits > 1 the workgroup covers K slices
+// [split*kchunk, (split+1)*kchunk) and writes its raw partial tile to part (layout [batch][split][m][n]).
+template <bool TA, bool TB, bool SC>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, int kchunk, double* __restrict__ part) {
+  __shared__ double As[TILE_D];
+  __shared__ double Bs[TILE_D];
+  const int bz = blockIdx.z / splits, sp = blockIdx.z % splits;
   const double* __restrict__ A = g.A + bz * g.sA;
   const double* __restrict__ B = g.B + bz * g.sB;
   const double* __restrict__ S = SC ? g.s + bz * g.sS : nullptr;
   double* __restrict__ C = g.C + bz * g.sC;
-  const int M = g.m, N = g.n, K = g.k;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  const int kbeg = sp * kchunk;
+  const int kend = min(g.k, kbeg + kchunk);
+  const int nk = (kend - kbeg + BK - 1) / BK;
+  using T = Tile<TA, TB, SC>;
 
   dbl4 acc[2][2];
 #pragma unroll
@@ -35,78 +121,69 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // ---- stage op(A)[m0:m0+64, k0:k0+16] into As[k][m] ----
-    if (!TA) {  // A[m*lda + k]: 4 consecutive k per thread
-      const int mm = t >> 2, kq = (t & 3) * 4;
-      const int gm = m0 + mm;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gk = k0 + kq + u;
-        double v = (gm < M && gk < K) ? A[(long long)gm * g.lda + gk] : 0.0;
-        if (SC) v *= (gk < K) ? S[gk] : 0.0;
-        As[kq + u][mm] = v;
-      }
-    } else {    // A[k*lda + m]: 4 consecutive m per thread
-      const int kk = t >> 4, mq = (t & 15) * 4;
-      const int gk = k0 + kk;
-      const double sc = (SC && gk < K) ? S[gk] : 1.0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gm = m0 + mq + u;
-        double v = (gm < M && gk < K) ? A[(long long)gk * g.lda + gm] : 0.0;
-        As[kk][mq + u] = SC ? v * sc : v;
-      }
-    }
-    // ---- stage op(B)[k0:k0+16, n0:n0+64] into Bs[k][n] ----
-    if (!TB) {  // B[k*ldb + n]
-      const int kk = t >> 4, nq = (t & 15) * 4;
-      const int gk = k0 + kk;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gn = n0 + nq + u;
-        Bs[kk][nq + u] = (gn < N && gk < K) ? B[(long long)gk * g.ldb + gn] : 0.0;
-      }
-    } else {    // B[n*ldb + k]
-      const int nn = t >> 2, kq = (t & 3) * 4;
-      const int gn = n0 + nn;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gk = k0 + kq + u;
-        Bs[kq + u][nn] = (gn < N && gk < K) ? B[(long long)gn * g.ldb + gk] : 0.0;
-      }
-    }
-    __syncthreads();
+  T tile;
+  GemmArgs gk = g;
+  gk.k = kend;  // bounds for the loads of this split
+  tile.load(gk, A, B, S, m0, n0, kbeg, t);
+  tile.store(As, Bs, t);
+  __syncthreads();
+  const int r16 = lane & 15, k4 = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const bool more = kt + 1 < nk;
+    if (more) tile.load(gk, A, B, S, m0, n0, kbeg + (kt + 1) * BK, t);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[ks + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = T::ga(As, wm * 32 + i * 16 + r16, ks + k4);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[ks + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = T::gb(Bs, ks + k4, wn * 32 + j * 16 + r16);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
+    if (more) {
+      __syncthreads();
+      tile.store(As, Bs, t);
+      __syncthreads();
+    }
   }
   // ---- epilogue ----
+  const int M = g.m, N = g.n;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
-        const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+        const int row = m0 + wm * 32 + i * 16 + k4 + 4 * v;
+        const int col = n0 + wn * 32 + j * 16 + r16;
         if (row < M && col < N) {
-          double* p = C + (long long)row * g.ldc + col;
-          const double r = g.alpha * acc[i][j][v];
-          *p = (g.beta == 0.0) ? r : r + g.beta * (*p);
+          if (splits > 1) {
+            part[(((long long)bz * splits + sp) * M + row) * N + col] = acc[i][j][v];
+          } else {
+            double* p = C + (long long)row * g.ldc + col;
+            const double r = g.alpha * acc[i][j][v];
+            *p = (g.beta == 0.0) ? r : r + g.beta * (*p);
+          }
         }
       }
+}
+
+// C = alpha * sum_s part[b][s] + beta * C, summed in split order.
+__global__ void splitk_reduce_kernel(GemmArgs g, int splits, const double* __restrict__ part) {
+  const long long mn = (long long)g.m * g.n;
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int bz = blockIdx.y;
+  if (u >= mn) return;
+  const double* p = part + (long long)bz * splits * mn + u;
+  double s = 0.0;
+  for (int q = 0; q < splits; ++q) s += p[q * mn];
+  const int row = (int)(u / g.n), col = (int)(u % g.n);
+  double* c = g.C + bz * g.sC + (long long)row * g.ldc + col;
+  *c = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*c);
 }
 
 // Column dots: partial sums over kDiagParts row slabs, then a fixed-order sum -> deterministic.
@@ -141,6 +218,8 @@ __global__ void diag_dot_final(int n, double alpha, double beta, const double* _
 }  // namespace
 
 thread_local Profiler* g_prof = nullptr;
+thread_local double* g_gemm_ws = nullptr;
+thread_local size_t g_gemm_ws_cap = 0;
 
 hipEvent_t Profiler::get() {
   if (next == pool.size()) {
@@ -167,19 +246,42 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
     // handled by a k=1 launch with alpha = 0 would read A; do it explicitly instead
     return hipErrorInvalidValue;
   }
-  dim3 grid((g.n + BN - 1) / BN, (g.m + BM - 1) / BM, g.batch);
+  const int tiles = ((g.n + BN - 1) / BN) * ((g.m + BM - 1) / BM) * g.batch;
+  // K split: aim for ~512 workgroups (2 per CU) with at least 128 of K per split
+  int splits = 1;
+  if (tiles < 512 && g.k >= 256) {
+    splits = (512 + tiles - 1) / tiles;
+    splits = std::min(splits, std::min(8, g.k / 128));
+    const size_t need = (size_t)splits * g.batch * (size_t)g.m * g.n;
+    if (splits < 2 || !g_gemm_ws || need > g_gemm_ws_cap) splits = 1;
+  }
+  int kchunk = g.k;
+  if (splits > 1) {
+    kchunk = ((g.k + splits - 1) / splits + BK - 1) / BK * BK;
+    splits = (g.k + kchunk - 1) / kchunk;
+  }
+  dim3 grid((g.n + BN - 1) / BN, (g.m + BM - 1) / BM, g.batch * splits);
   dim3 block(256);
   const bool sc = g.s != nullptr;
   Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
   // algorithmic work of the product: 2mnk flops; bytes = each operand and C read/written once
   if (pf) pf->begin(st, PROF_GEMM_F64, 2.0 * g.m * g.n * (double)g.k * g.batch,
                     8.0 * g.batch * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
+  double* part = splits > 1 ? g_gemm_ws : nullptr;
+  bool launched = false;
 #define KOT_GEMM_CASE(TA, TB, SC_) \
-  if (g.transa == TA && g.transb == TB && sc == SC_) { hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, SC_>), grid, block, 0, st, g); if (pf) pf->end(st); return hipGetLastError(); }
+  if (!launched && g.transa == TA && g.transb == TB && sc == SC_) { hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, SC_>), grid, block, 0, st, g, splits, kchunk, part); launched = true; }
   KOT_GEMM_CASE(0, 0, false) KOT_GEMM_CASE(0, 1, false) KOT_GEMM_CASE(1, 0, false) KOT_GEMM_CASE(1, 1, false)
   KOT_GEMM_CASE(0, 0, true) KOT_GEMM_CASE(0, 1, true) KOT_GEMM_CASE(1, 0, true) KOT_GEMM_CASE(1, 1, true)
 #undef KOT_GEMM_CASE
-  return hipErrorInvalidValue;
+  if (!launched) return hipErrorInvalidValue;
+  if (splits > 1) {
+    const long long mn = (long long)g.m * g.n;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((mn + 255) / 256), g.batch), dim3(256), 0, st, g, splits,
+                       (const double*)part);
+  }
+  if (pf) pf->end(st);
+  return hipGetLastError();
 }
 
 hipError_t diag_dot(int r0, int r1, int n, double alpha, const double* A, int lda, const double* B, int ldb,

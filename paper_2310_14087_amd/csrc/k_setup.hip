@@ -154,23 +154,34 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int l, int k0, int nb, 
   }
 }
 
-// Panel: rows r >= k0+nb solve L21 L11^T = A21, one thread per row, forward substitution.
-__global__ __launch_bounds__(64) void trsm_panel_kernel(int l, int k0, int nb, double* __restrict__ W) {
+// Panel: rows r >= k0+nb solve L21 L11^T = A21.  A workgroup stages 64 rows x nb of the panel through LDS
+// (coalesced along the row), then each of 64 threads forward-substitutes its row in LDS.
+__global__ __launch_bounds__(256) void trsm_panel_kernel(int l, int k0, int nb, double* __restrict__ W) {
   __shared__ double L11[CB][CB + 1];
-  for (int u = threadIdx.x; u < nb * nb; u += 64) {
+  __shared__ double P[64][CB + 1];
+  const int rbase = k0 + nb + blockIdx.x * 64;
+  for (int u = threadIdx.x; u < nb * nb; u += 256) {
     const int i = u / nb, j = u % nb;
     L11[i][j] = W[(long long)(k0 + i) * l + k0 + j];
   }
-  __syncthreads();
-  const int r = k0 + nb + blockIdx.x * 64 + threadIdx.x;
-  if (r >= l) return;
-  double x[CB];
-  for (int j = 0; j < nb; ++j) {
-    double v = W[(long long)r * l + k0 + j];
-    for (int c = 0; c < j; ++c) v -= x[c] * L11[j][c];
-    x[j] = v / L11[j][j];
+  for (int u = threadIdx.x; u < 64 * nb; u += 256) {
+    const int r = u / nb, j = u % nb;
+    P[r][j] = (rbase + r < l) ? W[(long long)(rbase + r) * l + k0 + j] : 0.0;
   }
-  for (int j = 0; j < nb; ++j) W[(long long)r * l + k0 + j] = x[j];
+  __syncthreads();
+  if (threadIdx.x < 64 && rbase + threadIdx.x < l) {
+    const int r = threadIdx.x;
+    for (int j = 0; j < nb; ++j) {
+      double v = P[r][j];
+      for (int c = 0; c < j; ++c) v -= P[r][c] * L11[j][c];
+      P[r][j] = v / L11[j][j];
+    }
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u < 64 * nb; u += 256) {
+    const int r = u / nb, j = u % nb;
+    if (rbase + r < l) W[(long long)(rbase + r) * l + k0 + j] = P[r][j];
+  }
 }
 
 __global__ void copy_jitter_kernel(int l, const double* __restrict__ A, double eps, double* __restrict__ W) {
@@ -188,7 +199,69 @@ __global__ void lower_to_upper_kernel(int l, const double* __restrict__ L, doubl
   R[u] = (j >= i) ? L[(long long)j * l + i] : 0.0;
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// Y = R^{-1} for upper-triangular R, by row blocks of TRB from the bottom: the block's rows start as identity
+// rows, receive -R[blk, below] Y[below, :] from the MFMA GEMM, then are solved against the diagonal block.
+constexpr int TRB = 32;
+
+__global__ void eye_rows_kernel(int l, int r0, int nb, double* __restrict__ Y) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)nb * l) return;
+  const int r = (int)(u / l), c = (int)(u % l);
+  Y[(long long)(r0 + r) * l + c] = (r0 + r == c) ? 1.0 : 0.0;
+}
+
+// Y[r0:r0+nb, c] <- R_dd^{-1} Y[r0:r0+nb, c] for every column c (R_dd = R[r0:r0+nb, r0:r0+nb] upper).
+__global__ __launch_bounds__(256) void trsv_block_kernel(int l, int r0, int nb, const double* __restrict__ R,
+                                                         double* __restrict__ Y) {
+  __shared__ double D[TRB][TRB + 1];
+  for (int u = threadIdx.x; u < nb * nb; u += 256) {
+    const int i = u / nb, j = u % nb;
+    D[i][j] = R[(long long)(r0 + i) * l + r0 + j];
+  }
+  __syncthreads();
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= l) return;
+  double y[TRB];
+#pragma unroll
+  for (int r = 0; r < TRB; ++r) y[r] = (r < nb) ? Y[(long long)(r0 + r) * l + c] : 0.0;
+#pragma unroll
+  for (int r = TRB - 1; r >= 0; --r) {
+    if (r < nb) {
+      double v = y[r];
+#pragma unroll
+      for (int k = r + 1; k < TRB; ++k)
+        if (k < nb) v -= D[r][k] * y[k];
+      y[r] = v / D[r][r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < TRB; ++r)
+    if (r < nb) Y[(long long)(r0 + r) * l + c] = y[r];
+}
+
 }  // namespace
+
+hipError_t trtri_upper(int l, const double* R, double* Y, hipStream_t st) {
+  const int last = ((l - 1) / TRB) * TRB;
+  for (int r0 = last; r0 >= 0; r0 -= TRB) {
+    const int nb = (l - r0 < TRB) ? (l - r0) : TRB;
+    hipLaunchKernelGGL(eye_rows_kernel, dim3((unsigned)(((long long)nb * l + 255) / 256)), dim3(256), 0, st, l, r0, nb, Y);
+    KOT_HIP_TRY(hipGetLastError());
+    const int below = l - r0 - nb;
+    if (below > 0) {
+      GemmArgs g{};
+      g.transa = 0; g.transb = 0; g.m = nb; g.n = l; g.k = below; g.alpha = -1.0; g.beta = 1.0;
+      g.A = R + (long long)r0 * l + r0 + nb; g.lda = l;
+      g.B = Y + (long long)(r0 + nb) * l; g.ldb = l;
+      g.C = Y + (long long)r0 * l; g.ldc = l; g.batch = 1;
+      KOT_HIP_TRY(gemm_f64(g, st));
+    }
+    hipLaunchKernelGGL(trsv_block_kernel, dim3((l + 255) / 256), dim3(256), 0, st, l, r0, nb, R, Y);
+    KOT_HIP_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
 
 hipError_t gram_build(int l, int d, const double* xf, const double* yf, double sigma, double* Q, double* K,
                       hipStream_t st) {
@@ -231,7 +304,7 @@ hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double*
     KOT_HIP_TRY(hipGetLastError());
     const int rest = l - k0 - nb;
     if (rest <= 0) break;
-    hipLaunchKernelGGL(trsm_panel_kernel, dim3((rest + 63) / 64), dim3(64), 0, st, l, k0, nb, W);
+    hipLaunchKernelGGL(trsm_panel_kernel, dim3((rest + 63) / 64), dim3(256), 0, st, l, k0, nb, W);
     KOT_HIP_TRY(hipGetLastError());
     // W22 -= L21 L21^T  (full trailing block; keeps it symmetric)
     GemmArgs g{};

@@ -56,6 +56,8 @@ struct kot_ctx {
   int* hint = nullptr;
   double* part = nullptr;      // reduction partials (>= max(kRedBlocks, kDiagParts*l, n))
   size_t part_cap = 0;
+  double* gemm_ws = nullptr;   // split-K partial tiles (4 l^2 doubles)
+  size_t gemm_ws_cap = 0;
   // matrices (cap x cap)
   double *Qb, *Rb, *Kb, *KKb, *Z, *T1, *T2, *T3, *T4, *Bm, *dX, *Mr, *eigtmp, *Pe1, *Pe2, *Xh;
   // vectors (cap)
@@ -63,6 +65,12 @@ struct kot_ctx {
   State S[4];  // 0: w, 1: trial, 2: v, 3: scratch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   Profiler prof;
+  // warm-start network workspace
+  std::vector<void*> mbufs;
+  size_t mlp_rows = 0, mlp_h = 0;
+  float *fA1 = nullptr, *fA2 = nullptr, *fdZ1 = nullptr, *fdZ2 = nullptr, *fout = nullptr, *fdout = nullptr,
+        *fpart = nullptr, *fX = nullptr;
+  double* rs3 = nullptr;
 };
 
 namespace {
@@ -94,6 +102,10 @@ kot_status fail(kot_ctx* c, kot_status st, const char* fmt, ...) {
 void free_ws(kot_ctx* c) {
   for (void* p : c->bufs) hipFree(p);
   c->bufs.clear();
+  c->gemm_ws = nullptr;
+  c->gemm_ws_cap = 0;
+  g_gemm_ws = nullptr;
+  g_gemm_ws_cap = 0;
   if (c->eig) { eig_work_destroy(c->eig); c->eig = nullptr; }
   c->cap = 0;
 }
@@ -131,6 +143,10 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   }
   if (!(ctx->part = alloc(need_part * sizeof(double)))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   ctx->part_cap = need_part;
+  if (!(ctx->gemm_ws = alloc(4 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  ctx->gemm_ws_cap = 4 * (size_t)cap * cap;
+  g_gemm_ws = ctx->gemm_ws;
+  g_gemm_ws_cap = ctx->gemm_ws_cap;
   ctx->eig = eig_work_create(cap);
   if (!ctx->eig) return fail(ctx, KOT_ERR_OOM, "eigensolver workspace allocation failed");
   ctx->cap = cap;
@@ -197,9 +213,15 @@ kot_status eig_run(kot_ctx* ctx, int l, const double* Z, const double* P0, doubl
   return KOT_OK;
 }
 
-// Pi(Z) = P_alpha diag(w_alpha) P_alpha^T given ascending spectral data with a positives.
-kot_status proj_from_eig(kot_ctx* ctx, int l, const double* P, const double* w, int a, double* out) {
-  HIPCHK(mm(ctx->stream, 0, 1, l, l, a, 1.0, P + (l - a), l, w + (l - a), P + (l - a), l, 0.0, out, l));
+// Pi(Z) = P_alpha diag(w_alpha) P_alpha^T given ascending spectral data with a positives; when more than half
+// the eigenvalues are positive, the same matrix as Z - P_abar diag(w_abar) P_abar^T (inner size l - a).
+kot_status proj_from_eig(kot_ctx* ctx, int l, const double* Z, const double* P, const double* w, int a, double* out) {
+  if (a <= l - a) {
+    HIPCHK(mm(ctx->stream, 0, 1, l, l, a, 1.0, P + (l - a), l, w + (l - a), P + (l - a), l, 0.0, out, l));
+  } else {
+    HIPCHK(vec_copy(l * l, Z, out, ctx->stream));
+    if (l - a > 0) HIPCHK(mm(ctx->stream, 0, 1, l, l, l - a, -1.0, P, l, w, P, l, 1.0, out, l));
+  }
   return KOT_OK;
 }
 
@@ -216,7 +238,7 @@ kot_status residual_state(kot_ctx* ctx, const CoreView& cv, State& s, const doub
   HIPCHK(count_positive(l, s.s, ctx->dint, st));
   KCHK(sync_read(ctx, 0, 1));
   s.a = ctx->hint[0];
-  KCHK(proj_from_eig(ctx, l, s.P, s.s, s.a, ctx->T1));
+  KCHK(proj_from_eig(ctx, l, ctx->Z, s.P, s.s, s.a, ctx->T1));
   HIPCHK(mat_sub(l * l, s.X, ctx->T1, s.r2, st));
   KCHK(r1_op(ctx, cv, s.g, s.X, s.r1, ctx->T2));
   HIPCHK(dot(l, s.r1, s.r1, ctx->dsc + 0, ctx->part, st));
@@ -368,7 +390,7 @@ kot_status proj_psd(kot_ctx* ctx, int l, double* Y, double* Pbasis, double* wbuf
   HIPCHK(vec_copy(l * l, ctx->T2, Pbasis, ctx->stream));
   HIPCHK(count_positive(l, wbuf, ctx->dint, ctx->stream));
   KCHK(sync_read(ctx, 0, 1));
-  KCHK(proj_from_eig(ctx, l, Pbasis, wbuf, ctx->hint[0], out));
+  KCHK(proj_from_eig(ctx, l, Y, Pbasis, wbuf, ctx->hint[0], out));
   return KOT_OK;
 }
 
@@ -435,6 +457,95 @@ kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
   return KOT_OK;
 }
 
+kot_status ensure_mlp(kot_ctx* ctx, size_t rows, size_t H, size_t l) {
+  const size_t need_rows = std::max(rows, l);
+  if (need_rows <= ctx->mlp_rows && H <= ctx->mlp_h && ctx->rs3) return KOT_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (void* p : ctx->mbufs) hipFree(p);
+  ctx->mbufs.clear();
+  const size_t R = std::max(need_rows, ctx->mlp_rows), Hh = std::max(H, ctx->mlp_h);
+  auto falloc = [&](size_t n) -> float* {
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(float)) != hipSuccess) return nullptr;
+    ctx->mbufs.push_back(p);
+    return (float*)p;
+  };
+  if (!(ctx->fA1 = falloc(R * Hh)) || !(ctx->fA2 = falloc(R * Hh)) || !(ctx->fdZ1 = falloc(R * Hh)) ||
+      !(ctx->fdZ2 = falloc(R * Hh)) || !(ctx->fout = falloc(R)) || !(ctx->fdout = falloc(R)) ||
+      !(ctx->fpart = falloc(16 * Hh + 16)) || !(ctx->fX = falloc(R * kFeatures)))
+    return fail(ctx, KOT_ERR_OOM, "network workspace allocation failed");
+  void* p = nullptr;
+  if (hipMalloc(&p, 3 * R * sizeof(double)) != hipSuccess) return fail(ctx, KOT_ERR_OOM, "allocation failed");
+  ctx->mbufs.push_back(p);
+  ctx->rs3 = (double*)p;
+  ctx->mlp_rows = R;
+  ctx->mlp_h = Hh;
+  return KOT_OK;
+}
+
+struct MlpView {
+  int F, H;
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+};
+MlpView mlp_view(int F, int H, const float* th) {
+  MlpView v;
+  v.F = F; v.H = H;
+  v.W1 = th; v.b1 = v.W1 + (size_t)F * H; v.W2 = v.b1 + H; v.b2 = v.W2 + (size_t)H * H; v.W3 = v.b2 + H; v.b3 = v.W3 + H;
+  return v;
+}
+GemmF32Args g32(int ta, int tb, int m, int n, int k, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+                const float* bias = nullptr, int act = 0, const float* mask = nullptr, int ldm = 0) {
+  GemmF32Args g{};
+  g.ta = ta; g.tb = tb; g.m = m; g.n = n; g.k = k; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.beta = 0.f; g.bias = bias; g.act = act; g.mask = mask; g.ldm = ldm;
+  return g;
+}
+
+kot_status mlp_forward_impl(kot_ctx* ctx, int n, const MlpView& w, const float* X, float* out) {
+  hipStream_t st = ctx->stream;
+  const int F = w.F, H = w.H;
+  HIPCHK(gemm_f32(g32(0, 0, n, H, F, X, F, w.W1, H, ctx->fA1, H, w.b1, 1), st));
+  HIPCHK(gemm_f32(g32(0, 0, n, H, H, ctx->fA1, H, w.W2, H, ctx->fA2, H, w.b2, 1), st));
+  HIPCHK(gemm_f32(g32(0, 0, n, 1, H, ctx->fA2, H, w.W3, 1, out, 1, w.b3, 0), st));
+  return KOT_OK;
+}
+
+kot_status mlp_loss_grad_impl(kot_ctx* ctx, int n, const MlpView& w, const float* X, const float* y, float* grad,
+                              double* loss) {
+  hipStream_t st = ctx->stream;
+  const int F = w.F, H = w.H;
+  KCHK(mlp_forward_impl(ctx, n, w, X, ctx->fout));
+  HIPCHK(mse_grad(n, ctx->fout, y, ctx->fdout, ctx->dsc + 0, ctx->part, st));
+  float* gW1 = grad;
+  float* gb1 = gW1 + (size_t)F * H;
+  float* gW2 = gb1 + H;
+  float* gb2 = gW2 + (size_t)H * H;
+  float* gW3 = gb2 + H;
+  float* gb3 = gW3 + H;
+  HIPCHK(gemm_f32(g32(1, 0, H, 1, n, ctx->fA2, H, ctx->fdout, 1, gW3, 1), st));
+  HIPCHK(colsum_f32(n, 1, ctx->fdout, gb3, ctx->fpart, st));
+  HIPCHK(gemm_f32(g32(0, 1, n, H, 1, ctx->fdout, 1, w.W3, 1, ctx->fdZ2, H, nullptr, 0, ctx->fA2, H), st));
+  HIPCHK(gemm_f32(g32(1, 0, H, H, n, ctx->fA1, H, ctx->fdZ2, H, gW2, H), st));
+  HIPCHK(colsum_f32(n, H, ctx->fdZ2, gb2, ctx->fpart, st));
+  HIPCHK(gemm_f32(g32(0, 1, n, H, H, ctx->fdZ2, H, w.W2, H, ctx->fdZ1, H, nullptr, 0, ctx->fA1, H), st));
+  HIPCHK(gemm_f32(g32(1, 0, F, H, n, X, F, ctx->fdZ1, H, gW1, H), st));
+  HIPCHK(colsum_f32(n, H, ctx->fdZ1, gb1, ctx->fpart, st));
+  KCHK(sync_read(ctx, 1, 0));
+  *loss = ctx->hsc[0];
+  return KOT_OK;
+}
+
+// gamma0 = lambda1 * f(features) for the prepared core (KK must be set).
+kot_status predict_gamma0(kot_ctx* ctx, const CoreView& cv, int F, int H, const float* theta, double* gamma0) {
+  const int l = cv.l;
+  if (F != kFeatures) return fail(ctx, KOT_ERR_ARG, "the feature map has %d features (got F=%d)", kFeatures, F);
+  KCHK(ensure_mlp(ctx, l, H, l));
+  HIPCHK(features(l, cv.Q, cv.z, cv.wsum, ctx->Kb, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + 8, ctx->fX, ctx->stream));
+  KCHK(mlp_forward_impl(ctx, l, mlp_view(F, H, theta), ctx->fX, ctx->fout));
+  HIPCHK(f32_to_f64_scaled(l, ctx->fout, cv.lam1, gamma0, ctx->stream));
+  return KOT_OK;
+}
+
 // Algorithm 2 on a prepared core.
 kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const double* gamma0, kot_result* res) {
   const int l = cv.l;
@@ -446,11 +557,38 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   State* W = &ctx->S[0];
   State* T = &ctx->S[1];
   State* V = &ctx->S[2];
+  if (p->ws_theta && !gamma0) {  // learned start
+    KCHK(predict_gamma0(ctx, cv, p->ws_F, p->ws_H, p->ws_theta, ctx->S[1].g));
+    gamma0 = ctx->S[1].g;
+  }
   if (gamma0) HIPCHK(vec_copy(l, gamma0, W->g, st));
   else HIPCHK(vec_fill(l, 0.0, W->g, st));
-  HIPCHK(vec_fill(l * l, 0.0, W->X, st));
+  if (gamma0 && p->lift_x0) {
+    // X0 = R^-T diag(y) R^-1 with y = (Q gamma0 - z)/(2 lam2) (stationarity's value of Phi(X)) on the
+    // constraints predicted active, small entries dropped, so that Phi(X0) = y
+    HIPCHK(trtri_upper(l, cv.R, ctx->T1, st));
+    HIPCHK(mm(st, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, W->g, 1, 0.0, ctx->vtmp, 1));
+    HIPCHK(lift_diag(l, ctx->vtmp, cv.z, W->g, cv.lam1, cv.lam2, 0.02, ctx->dg, ctx->part, st));
+    HIPCHK(mm(st, 1, 0, l, l, l, 1.0, ctx->T1, l, ctx->dg, ctx->T1, l, 0.0, W->X, l));
+  } else {
+    HIPCHK(vec_fill(l * l, 0.0, W->X, st));
+  }
   int sweeps = 0;
   KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+  res->warm_used = 0;
+  if (gamma0) {
+    // fallback: the cold start w = (0, 0) has |R| = |z|/(2 lam2) (Pi(-lambda1 I) = 0); keep the better one
+    HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + 0, ctx->part, st));
+    KCHK(sync_read(ctx, 1, 0));
+    const double cold = std::sqrt(ctx->hsc[0]) / (2.0 * cv.lam2);
+    if (!(W->rn <= cold)) {
+      HIPCHK(vec_fill(l, 0.0, W->g, st));
+      HIPCHK(vec_fill(l * l, 0.0, W->X, st));
+      KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+    } else {
+      res->warm_used = 1;
+    }
+  }
   const bool use_eg = p->safeguard == KOT_SAFEGUARD_EG;
   if (use_eg) KCHK(copy_state(ctx, l, *W, *V));
   double theta = p->theta0;
@@ -558,6 +696,8 @@ kot_status check_ctx(kot_ctx* ctx) {
   if (!ctx) return KOT_ERR_ARG;
   ctx->err.clear();
   g_prof = &ctx->prof;
+  g_gemm_ws = ctx->gemm_ws;
+  g_gemm_ws_cap = ctx->gemm_ws_cap;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, KOT_ERR_HIP, "hipSetDevice failed");
   return KOT_OK;
 }
@@ -593,6 +733,10 @@ void kot_params_default(kot_params* p) {
   p->null_step = 1;
   p->eig_max_sweeps = 30;
   p->warm_eig = 1;
+  p->lift_x0 = 1;
+  p->ws_F = 0;
+  p->ws_H = 0;
+  p->ws_theta = nullptr;
 }
 
 kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {
@@ -624,6 +768,8 @@ kot_status kot_destroy(kot_ctx* ctx) {
   hipSetDevice(ctx->device);
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   free_ws(ctx);
+  for (void* p : ctx->mbufs) hipFree(p);
+  ctx->mbufs.clear();
   hipFree(ctx->dsc);
   hipHostFree(ctx->hsc);
   hipFree(ctx->dint);
@@ -758,6 +904,69 @@ kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double
   return KOT_OK;
 }
 
+int kot_mlp_params(int F, int H) { return F * H + H + H * H + H + H + 1; }
+
+kot_status kot_features(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, const double* wsum,
+                        double q2, const kot_params* p, float* X) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_params(ctx, p, false));
+  if (l < 1 || l > 4096 || !Q || !z || !R || !wsum || !X) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  KCHK(ensure_mlp(ctx, l, 1, l));
+  CoreView cv;
+  cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.wsum = wsum; cv.q2 = q2; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  KCHK(prepare_core(ctx, cv));
+  HIPCHK(features(l, Q, z, wsum, ctx->Kb, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + 8, X, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
+kot_status kot_mlp_forward(kot_ctx* ctx, int n, int F, int H, const float* X, const float* theta, float* out) {
+  KCHK(check_ctx(ctx));
+  if (n < 1 || F < 1 || H < 1 || !X || !theta || !out) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_mlp(ctx, n, H, 1));
+  KCHK(mlp_forward_impl(ctx, n, mlp_view(F, H, theta), X, out));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
+kot_status kot_mlp_loss_grad(kot_ctx* ctx, int n, int F, int H, const float* X, const float* y, const float* theta,
+                             float* grad, double* loss) {
+  KCHK(check_ctx(ctx));
+  if (n < 1 || F < 1 || H < 1 || !X || !y || !theta || !grad || !loss) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  if (!ctx->dsc) return fail(ctx, KOT_ERR_ARG, "context not initialised");
+  KCHK(ensure_ws(ctx, 1, 0));  // reduction partials
+  KCHK(ensure_mlp(ctx, n, H, 1));
+  return mlp_loss_grad_impl(ctx, n, mlp_view(F, H, theta), X, y, grad, loss);
+}
+
+kot_status kot_mlp_adam(kot_ctx* ctx, int P, float* theta, const float* grad, float* m, float* v, int t, float lr,
+                        float beta1, float beta2, float eps) {
+  KCHK(check_ctx(ctx));
+  if (P < 1 || t < 1 || !theta || !grad || !m || !v) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  HIPCHK(adam_f32(P, theta, grad, m, v, lr, beta1, beta2, eps, t, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
+kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, int F, int H, const float* theta,
+                         double* gamma0) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_problem(ctx, pb));
+  KCHK(check_params(ctx, p, true));
+  if (!theta || !gamma0 || H < 1) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, pb->l, std::max(pb->n_src, pb->n_tgt)));
+  double q2 = 0.0;
+  KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2));
+  CoreView cv;
+  cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb; cv.q2 = q2;
+  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  KCHK(prepare_core(ctx, cv));
+  KCHK(predict_gamma0(ctx, cv, F, H, theta, gamma0));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
 kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass) {
   KCHK(check_ctx(ctx));
   if (enable) {
@@ -787,6 +996,7 @@ kot_status kot_gemm(kot_ctx* ctx, int transa, int transb, int m, int n, int k, d
                     const double* s, const double* B, int ldb, double beta, double* C, int ldc) {
   KCHK(check_ctx(ctx));
   if (m < 0 || n < 0 || k < 1 || !A || !B || !C) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  if (std::max(m, n) <= 4096) KCHK(ensure_ws(ctx, std::max(std::max(m, n), 1), 0));  // split-K workspace
   HIPCHK(mm(ctx->stream, transa ? 1 : 0, transb ? 1 : 0, m, n, k, alpha, A, lda, s, B, ldb, beta, C, ldc));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;

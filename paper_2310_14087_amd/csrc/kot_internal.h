@@ -36,6 +36,10 @@ struct GemmArgs {
   int batch;
 };
 hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
+// Split-K workspace used by gemm_f64 on the calling thread (set per library call by the context; null or
+// too small => no K split).
+extern thread_local double* g_gemm_ws;
+extern thread_local size_t g_gemm_ws_cap;  // doubles
 
 // y[j] = alpha * sum_{r in [r0, r1)} A[r*lda + j] * B[r*ldb + j] + beta * y[j], j < n (column dots).
 // part: workspace of at least kDiagParts * n doubles.
@@ -100,6 +104,34 @@ hipError_t sym_plus(int l, const double* G, double a, const double* S, double b,
 // scale columns: out[i][j] = A[i][j] * s[j]
 hipError_t scale_cols(int rows, int cols, const double* A, int lda, const double* s, double* out, int ldo,
                       hipStream_t st);
+
+// ---- warm-start network (k_mlp.hip) ----------------------------------------------------------------------
+constexpr int kFeatures = 12;
+struct GemmF32Args {
+  int ta, tb, m, n, k;
+  const float* A; int lda;
+  const float* B; int ldb;
+  float* C; int ldc;
+  float beta;
+  const float* bias;   // per output column, may be null
+  int act;             // 1 = relu
+  const float* mask;   // multiply by (mask > 0), may be null
+  int ldm;
+};
+hipError_t gemm_f32(const GemmF32Args& g, hipStream_t st);
+hipError_t colsum_f32(int rows, int cols, const float* X, float* out, float* part, hipStream_t st);
+hipError_t mse_grad(int n, const float* out, const float* y, float* dout, double* loss, double* part, hipStream_t st);
+hipError_t adam_f32(int n, float* th, const float* g, float* m, float* v, float lr, float b1, float b2, float eps, int t,
+                    hipStream_t st);
+// X (l x kFeatures, FP32); rs: workspace 3l doubles; pooled: 2 device doubles
+hipError_t features(int l, const double* Q, const double* z, const double* wsum, const double* K, const double* KK,
+                    double lam1, double* rs, double* pooled, float* X, hipStream_t st);
+hipError_t f32_to_f64_scaled(int n, const float* x, double s, double* y, hipStream_t st);
+hipError_t trtri_upper(int l, const double* R, double* Y, hipStream_t st);
+// d = ((Q g - z)/(2 lam2)) on predicted-active points (g_i <= -0.9 lambda1), zeroed below frac * mean of the
+// positive entries; part: >= 128 doubles.
+hipError_t lift_diag(int l, const double* Qg, const double* z, const double* g, double lam1, double lam2, double frac,
+                     double* d, double* part, hipStream_t st);
 
 }  // namespace kot
 

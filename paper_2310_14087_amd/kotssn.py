@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "KOT_OK", 1: "KOT_NOT_CONVERGED", -1: "KOT_ERR_ARG", -2: "KOT
 
 EXPORTED = ["kot_params_default", "kot_create", "kot_destroy", "kot_last_error", "kot_setup", "kot_solve",
             "kot_solve_core", "kot_eigh", "kot_residual", "kot_ssn_direction", "kot_eg_step", "kot_cholesky",
-            "kot_gemm", "kot_profile"]
+            "kot_gemm", "kot_profile", "kot_mlp_params", "kot_features", "kot_mlp_forward", "kot_mlp_loss_grad",
+            "kot_mlp_adam", "kot_warmstart"]
 
 
 class KotParams(C.Structure):
@@ -36,7 +37,8 @@ class KotParams(C.Structure):
                 ("beta0", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("theta0", C.c_double),
                 ("theta_min", C.c_double), ("theta_max", C.c_double), ("eg_step", C.c_double),
                 ("precision", C.c_int), ("safeguard", C.c_int), ("null_step", C.c_int),
-                ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int)]
+                ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int), ("lift_x0", C.c_int), ("ws_F", C.c_int),
+                ("ws_H", C.c_int), ("ws_theta", C.c_void_p)]
 
 
 class KotProblem(C.Structure):
@@ -48,7 +50,8 @@ class KotResult(C.Structure):
     _fields_ = [("gamma", C.c_void_p), ("X", C.c_void_p), ("res_hist", C.c_void_p), ("res_v_hist", C.c_void_p),
                 ("hist_cap", C.c_int), ("ot", C.c_double), ("residual", C.c_double), ("iters", C.c_int),
                 ("cg_iters_total", C.c_int), ("eg_accepts", C.c_int), ("null_steps", C.c_int),
-                ("eig_sweeps_total", C.c_int), ("alpha_last", C.c_int), ("time_ms", C.c_double)]
+                ("eig_sweeps_total", C.c_int), ("alpha_last", C.c_int), ("warm_used", C.c_int),
+                ("time_ms", C.c_double)]
 
 
 _lib = None
@@ -80,6 +83,12 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
         "kot_cholesky": (i, [vp, i, vp, d, vp]),
         "kot_gemm": (i, [vp, i, i, i, i, i, d, vp, i, vp, vp, i, d, vp, i]),
         "kot_profile": (i, [vp, i, vp, i]),
+        "kot_mlp_params": (i, [i, i]),
+        "kot_features": (i, [vp, i, vp, vp, vp, vp, d, P(KotParams), vp]),
+        "kot_mlp_forward": (i, [vp, i, i, i, vp, vp, vp]),
+        "kot_mlp_loss_grad": (i, [vp, i, i, i, vp, vp, vp, vp, P(d)]),
+        "kot_mlp_adam": (i, [vp, i, vp, vp, vp, vp, i, C.c_float, C.c_float, C.c_float, C.c_float]),
+        "kot_warmstart": (i, [vp, P(KotProblem), P(KotParams), i, i, vp, vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(lib, name)
@@ -106,15 +115,28 @@ def default_params(**kw) -> KotParams:
     return p
 
 
-def _ptr(t) -> int | None:
+def _ptr(t, dtype=None) -> int | None:
     if t is None:
         return None
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
-    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-        raise ValueError("expected a contiguous float64 CUDA tensor")
+    dtype = dtype or torch.float64
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
     return t.data_ptr()
+
+
+def _fptr(t) -> int | None:
+    import torch
+    return _ptr(t, torch.float32)
+
+
+def mlp_params(F: int, H: int) -> int:
+    return load().kot_mlp_params(F, H)
+
+
+N_FEATURES = 12
 
 
 @dataclass
@@ -128,6 +150,7 @@ class SolveResult:
     null_steps: int
     eig_sweeps_total: int
     alpha_last: int
+    warm_used: int
     time_ms: float
     res_hist: np.ndarray
     res_v_hist: np.ndarray
@@ -198,7 +221,8 @@ class Context:
     def _pack(st, res, rh, rvh) -> SolveResult:
         n = min(res.iters + 1, len(rh))
         return SolveResult(st, res.ot, res.residual, res.iters, res.cg_iters_total, res.eg_accepts, res.null_steps,
-                           res.eig_sweeps_total, res.alpha_last, res.time_ms, rh[:n].copy(), rvh[:n].copy())
+                           res.eig_sweeps_total, res.alpha_last, res.warm_used, res.time_ms, rh[:n].copy(),
+                           rvh[:n].copy())
 
     def solve(self, xs, ys, xf, yf, prm: KotParams, gamma0=None, want_X=False, hist_cap=1024):
         l, dd = xf.shape
@@ -258,6 +282,44 @@ class Context:
         R = torch.empty_like(A)
         self._check(self.lib.kot_cholesky(self.h, A.shape[0], _ptr(A), float(eps), _ptr(R)))
         return R
+
+    # ---- warm-start network ----
+    def features(self, Q, z, R, wsum, q2, prm: KotParams):
+        import torch
+        l = Q.shape[0]
+        X = torch.empty((l, N_FEATURES), device=Q.device, dtype=torch.float32)
+        self._check(self.lib.kot_features(self.h, l, _ptr(Q), _ptr(z), _ptr(R), _ptr(wsum), float(q2), C.byref(prm),
+                                          _fptr(X)))
+        return X
+
+    def mlp_forward(self, X, theta, H):
+        import torch
+        n, F = X.shape
+        out = torch.empty(n, device=X.device, dtype=torch.float32)
+        self._check(self.lib.kot_mlp_forward(self.h, n, F, H, _fptr(X), _fptr(theta), _fptr(out)))
+        return out
+
+    def mlp_loss_grad(self, X, y, theta, H, grad=None):
+        import torch
+        n, F = X.shape
+        if grad is None:
+            grad = torch.empty_like(theta)
+        loss = C.c_double()
+        self._check(self.lib.kot_mlp_loss_grad(self.h, n, F, H, _fptr(X), _fptr(y), _fptr(theta), _fptr(grad),
+                                               C.byref(loss)))
+        return loss.value, grad
+
+    def mlp_adam(self, theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.kot_mlp_adam(self.h, theta.numel(), _fptr(theta), _fptr(grad), _fptr(m), _fptr(v), int(t),
+                                          float(lr), float(beta1), float(beta2), float(eps)))
+
+    def warmstart(self, xs, ys, xf, yf, prm: KotParams, theta, H):
+        import torch
+        l, dd = xf.shape
+        pb = KotProblem(xs.shape[0], ys.shape[0], dd, l, _ptr(xs), _ptr(ys), _ptr(xf), _ptr(yf))
+        g0 = torch.empty(l, device=xs.device, dtype=torch.float64)
+        self._check(self.lib.kot_warmstart(self.h, C.byref(pb), C.byref(prm), N_FEATURES, H, _fptr(theta), _ptr(g0)))
+        return g0
 
     PROFILE_CLASSES = ("gemm_f64", "eig_round", "reserved")
 

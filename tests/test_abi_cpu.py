@@ -49,9 +49,9 @@ def test_params_default_host_only(lib):
 def test_struct_layouts_match_header():
     """ctypes mirrors of the C structs have the sizes the header implies (field order / padding)."""
     from paper_2310_14087_amd import kotssn
-    assert C.sizeof(kotssn.KotParams) == 8 * 3 + 8 + 8 + 4 + 4 + 8 * 11 + 4 * 5 + 4
+    assert C.sizeof(kotssn.KotParams) == 8 * 5 + 4 * 2 + 8 * 11 + 4 * 8 + 8
     assert C.sizeof(kotssn.KotProblem) == 16 + 4 * 8
-    assert C.sizeof(kotssn.KotResult) == 8 * 4 + 8 + 8 + 8 + 4 * 6 + 8
+    assert C.sizeof(kotssn.KotResult) == 8 * 4 + 8 + 8 + 8 + 4 * 7 + 4 + 8
 
 
 def test_null_arguments_are_rejected_without_a_device(lib):

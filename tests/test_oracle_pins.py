@@ -363,3 +363,43 @@ def test_paper_constants_golden():
     for k in ("alpha1", "alpha2", "beta0", "beta2", "cg_max_iter"):
         assert getattr(prm, k) == gold["constants"][k], k
     assert prm.beta1 == pytest.approx(1.0 / gold["constants"]["beta1_printed"])
+
+
+# ------------------------------------------------------------------------------------------------------------
+# Warm-start network oracle (not in the paper)
+# ------------------------------------------------------------------------------------------------------------
+def test_mlp_gradient_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    F, H, N = 5, 7, 11
+    theta = rng.standard_normal(mlp.n_params(F, H)) * 0.5
+    X = rng.standard_normal((N, F))
+    y = rng.standard_normal(N)
+    loss, g = mlp.loss_and_grad(theta, X, y, F, H)
+    h = 1e-6
+    for idx in rng.choice(len(theta), 40, replace=False):
+        e = np.zeros_like(theta)
+        e[idx] = h
+        fd = (mlp.loss_and_grad(theta + e, X, y, F, H)[0] - mlp.loss_and_grad(theta - e, X, y, F, H)[0]) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_mlp_forward_by_hand():
+    from oracle import mlp
+    F, H = 2, 2
+    W1 = np.array([[1.0, -1.0], [0.5, 2.0]]); b1 = np.array([0.1, -0.2])
+    W2 = np.array([[1.0, 0.0], [-1.0, 1.0]]); b2 = np.array([0.0, 0.3])
+    W3 = np.array([[2.0], [-1.0]]); b3 = np.array([0.5])
+    th = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3])
+    x = np.array([[1.0, 1.0]])
+    a1 = np.maximum(np.array([1.0 + 0.5 + 0.1, -1.0 + 2.0 - 0.2]), 0)
+    a2 = np.maximum(np.array([a1[0] - a1[1], a1[1] + 0.3]), 0)
+    assert mlp.forward(th, x, F, H)[0][0] == pytest.approx(2 * a2[0] - a2[1] + 0.5)
+
+
+def test_adam_first_step():
+    """After one step from zero moments the bias-corrected update is -lr * g/(|g| + eps)."""
+    from oracle import mlp
+    g = np.array([0.3, -2.0, 1e-3])
+    th, m, v = mlp.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=1e-8)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8))
