@@ -57,7 +57,8 @@ typedef struct kot_params {
   double alpha1, alpha2, beta0, beta1, beta2;
   double theta0, theta_min, theta_max;
   double eg_step;
-  int precision;       /* kot_precision: arithmetic of the CG matvec GEMMs */
+  int precision;       /* kot_precision of the CG matvec chain (Algorithm 1): FP64, or FP32 / BF16 products with
+                          FP32 accumulation inside FP64 iterative refinement (Eq. 4.5 checked in FP64) */
   int safeguard;       /* kot_safeguard */
   int null_step;
   int eig_max_sweeps;  /* Jacobi sweep cap (default 30) */
@@ -192,7 +193,8 @@ kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* prob, const kot_params
  * of the instrumented kernel classes on the context's stream; enable = 0 stops, waits for the stream, and
  * writes 4 values per class into out (host, 4 * nclass doubles; may be NULL): launches, total milliseconds
  * between the events, algorithmic flops and algorithmic bytes.  Classes: 0 = FP64 GEMM (2mnk flops),
- * 1 = one Jacobi round (pair solves + tile updates; flops of the 16x16 tile products), 2 = reserved. */
+ * 1 = one Jacobi round (pair solves + tile updates; flops of the 16x16 tile products), 2 = reserved,
+ * 3 = FP32 chain GEMM, 4 = BF16 chain GEMM (2mnk flops each). */
 kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass);
 
 #ifdef __cplusplus

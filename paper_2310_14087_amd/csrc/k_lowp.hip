@@ -1,0 +1,202 @@
+// Reduced-precision GEMMs for the CG matvec chain (Algorithm 1): inputs FP32 in global memory, products on the
+// matrix cores in BF16 (v_mfma_f32_16x16x16bf16_1k, operands rounded to bfloat16) or FP32
+// (v_mfma_f32_16x16x4f32), accumulation in FP32.  The first product of the chain carries the Hadamard weight
+// Psi of Section 4.3 in its epilogue.
+#include "kot_internal.h"
+
+namespace kot {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short shrt4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int LBM = 64, LBN = 64, LBK = 32;
+constexpr int LMK = LBK + 1;  // [row][k] tiles (lanes along k)
+constexpr int LKM = LBN + 4;  // [k][col] tiles (lanes along col)
+
+__device__ __forceinline__ short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (short)(u >> 16);
+}
+
+// Psi weight of entry (r, j) (eigen-index r, ascending eigenvalues w, alpha = [l-a, l)); see psi_kernel.
+__device__ __forceinline__ double psi_weight(int r, int j, int l, int a, double mu, const double* __restrict__ w,
+                                             int complement, double diag_scale, double off_scale) {
+  const int split = l - a;
+  const bool r_in = r >= split, j_in = j >= split;
+  if (r_in == j_in) return diag_scale / mu;
+  const int ia = r_in ? r : j, ib = r_in ? j : r;
+  const double sa = w[ia], sb = -w[ib];
+  const double one_m_eta = sb / (sa + sb), eta = sa / (sa + sb);
+  return complement ? off_scale * (one_m_eta * (1.0 + mu) / (mu * (mu + one_m_eta)))
+                    : off_scale * (eta / (mu + one_m_eta));
+}
+
+// C (m x n) = A (m x k, row-major, rows along k) diag(s) op(B); op(B) = B^T (TB: B is n x k) or B (k x n).
+template <bool BF16, bool TB, bool PSI>
+__global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g) {
+  __shared__ float As[LBM * LMK];
+  __shared__ float Bs[LBK * LKM > LBN * LMK ? LBK * LKM : LBN * LMK];
+  const int M = g.m, N = g.n, K = g.k;
+  const int m0 = blockIdx.y * LBM, n0 = blockIdx.x * LBN;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  flt4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += LBK) {
+    {  // A rows, lanes along k
+      const int kk = t & 31, mm = t >> 5;
+      const int gk = k0 + kk;
+      const float sc = (g.s && gk < K) ? (float)g.s[gk] : 1.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gm = m0 + mm + 8 * u;
+        As[(mm + 8 * u) * LMK + kk] = (gm < M && gk < K) ? g.A[(long long)gm * g.lda + gk] * sc : 0.f;
+      }
+    }
+    if (TB) {  // B[n][k], lanes along k -> [n][k]
+      const int kk = t & 31, nn = t >> 5;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gn = n0 + nn + 8 * u, gk = k0 + kk;
+        Bs[(nn + 8 * u) * LMK + kk] = (gn < N && gk < K) ? g.B[(long long)gn * g.ldb + gk] : 0.f;
+      }
+    } else {   // B[k][n], lanes along n -> [k][n]
+      const int nn = t & 63, kk = t >> 6;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int gn = n0 + nn, gk = k0 + kk + 4 * u;
+        Bs[(kk + 4 * u) * LKM + nn] = (gn < N && gk < K) ? g.B[(long long)gk * g.ldb + gn] : 0.f;
+      }
+    }
+    __syncthreads();
+    if (BF16) {
+#pragma unroll
+      for (int ks = 0; ks < LBK; ks += 16) {
+        shrt4 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float* ap = As + (wm * 32 + i * 16 + r16) * LMK + ks + 4 * k4;
+          a[i] = shrt4{to_bf16(ap[0]), to_bf16(ap[1]), to_bf16(ap[2]), to_bf16(ap[3])};
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = wn * 32 + j * 16 + r16, kb = ks + 4 * k4;
+          if (TB) {
+            const float* bp = Bs + col * LMK + kb;
+            b[j] = shrt4{to_bf16(bp[0]), to_bf16(bp[1]), to_bf16(bp[2]), to_bf16(bp[3])};
+          } else {
+            b[j] = shrt4{to_bf16(Bs[kb * LKM + col]), to_bf16(Bs[(kb + 1) * LKM + col]),
+                         to_bf16(Bs[(kb + 2) * LKM + col]), to_bf16(Bs[(kb + 3) * LKM + col])};
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < LBK; ks += 4) {
+        float a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[(wm * 32 + i * 16 + r16) * LMK + ks + k4];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = wn * 32 + j * 16 + r16, kk = ks + k4;
+          b[j] = TB ? Bs[col * LMK + kk] : Bs[kk * LKM + col];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // accumulator layout of both 16x16 f32-output instructions: lane L holds D[4*(L/16) + v][L%16]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 32 + i * 16 + 4 * k4 + v;
+        const int col = n0 + wn * 32 + j * 16 + r16;
+        if (row < M && col < N) {
+          float r = acc[i][j][v];
+          if (PSI) r *= (float)psi_weight(g.r0 + row, col, g.l, g.a, g.mu, g.w, g.complement, g.diag_scale, g.off_scale);
+          g.C[(long long)row * g.ldc + col] = r;
+        }
+      }
+}
+
+__global__ void f64_to_f32_kernel(long long n, const double* __restrict__ x, float* __restrict__ y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+// y[j] += alpha * sum_{r < m} A[r][j] * B[r][j]  (FP32 products, FP64 sums; 16 slabs then fixed order)
+__global__ __launch_bounds__(256) void diag_dot_lowp_part(int m, int n, const float* __restrict__ A, int lda,
+                                                          const float* __restrict__ B, int ldb, double* __restrict__ part) {
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int sub = threadIdx.x >> 6;
+  const int slab = blockIdx.y;
+  const int per = (m + 15) / 16;
+  const int s0 = slab * per, s1 = min(m, s0 + per);
+  double acc = 0.0;
+  if (col < n)
+    for (int r = s0 + sub; r < s1; r += 4) acc += (double)(A[(long long)r * lda + col] * B[(long long)r * ldb + col]);
+  __shared__ double red[4][64];
+  red[sub][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (sub == 0 && col < n)
+    part[(long long)slab * n + col] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+__global__ void diag_dot_lowp_final(int n, double alpha, const double* __restrict__ part, double* __restrict__ y) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n) return;
+  double s = 0.0;
+  for (int p = 0; p < 16; ++p) s += part[(long long)p * n + col];
+  y[col] += alpha * s;
+}
+
+}  // namespace
+
+hipError_t gemm_lowp(const LowpArgs& g, bool bf16, bool psi, hipStream_t st) {
+  if (g.m <= 0 || g.n <= 0 || g.k <= 0) return hipErrorInvalidValue;
+  dim3 grid((g.n + LBN - 1) / LBN, (g.m + LBM - 1) / LBM);
+  Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
+  if (pf) pf->begin(st, bf16 ? PROF_GEMM_BF16 : PROF_GEMM_F32, 2.0 * g.m * g.n * (double)g.k,
+                    4.0 * ((double)g.m * g.k + (double)g.k * g.n + (double)g.m * g.n));
+#define KOT_LOWP(BF, TB_, PS) \
+  if (bf16 == BF && (g.transb != 0) == TB_ && psi == PS) hipLaunchKernelGGL((gemm_lowp_kernel<BF, TB_, PS>), grid, dim3(256), 0, st, g);
+  KOT_LOWP(true, true, true) KOT_LOWP(true, true, false) KOT_LOWP(true, false, true) KOT_LOWP(true, false, false)
+  KOT_LOWP(false, true, true) KOT_LOWP(false, true, false) KOT_LOWP(false, false, true) KOT_LOWP(false, false, false)
+#undef KOT_LOWP
+  if (pf) pf->end(st);
+  return hipGetLastError();
+}
+
+hipError_t f64_to_f32(long long n, const double* x, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t diag_dot_lowp(int m, int n, double alpha, const float* A, int lda, const float* B, int ldb, double* y,
+                         double* part, hipStream_t st) {
+  if (n <= 0 || m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(diag_dot_lowp_part, dim3((n + 63) / 64, 16), dim3(256), 0, st, m, n, A, lda, B, ldb, part);
+  KOT_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(diag_dot_lowp_final, dim3((n + 255) / 256), dim3(256), 0, st, n, alpha, part, y);
+  return hipGetLastError();
+}
+
+}  // namespace kot

@@ -61,7 +61,8 @@ struct kot_ctx {
   // matrices (cap x cap)
   double *Qb, *Rb, *Kb, *KKb, *Z, *T1, *T2, *T3, *T4, *Bm, *dX, *Mr, *eigtmp, *Pe1, *Pe2, *Xh;
   // vectors (cap)
-  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *vtmp, *gh, *s_e1, *s_e2, *r1h;
+  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
+  float *Bf = nullptr, *Cf = nullptr, *Ef = nullptr;  // reduced-precision chain operands
   State S[4];  // 0: w, 1: trial, 2: v, 3: scratch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   Profiler prof;
@@ -132,7 +133,8 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
     if (!(*m = alloc(mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed (l=%d)", cap);
   if (!(ctx->eigtmp = alloc(2 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   double** vecs[] = {&ctx->zb, &ctx->wsumb, &ctx->wmu, &ctx->wnu, &ctx->dg, &ctx->a1, &ctx->cx, &ctx->cr, &ctx->cp,
-                     &ctx->cAp, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h};
+                     &ctx->cAp, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
+                     &ctx->lAp};
   for (double** v : vecs)
     if (!(*v = alloc(vv))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   for (auto& s : ctx->S) {
@@ -144,6 +146,8 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   if (!(ctx->part = alloc(need_part * sizeof(double)))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   ctx->part_cap = need_part;
   if (!(ctx->gemm_ws = alloc(4 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  if (!(ctx->Bf = (float*)alloc(mm / 2)) || !(ctx->Cf = (float*)alloc(mm / 2)) || !(ctx->Ef = (float*)alloc(mm / 2)))
+    return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   ctx->gemm_ws_cap = 4 * (size_t)cap * cap;
   g_gemm_ws = ctx->gemm_ws;
   g_gemm_ws_cap = ctx->gemm_ws_cap;
@@ -321,9 +325,33 @@ kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const
   return KOT_OK;
 }
 
+// Same operator with the chain in reduced precision (Bf holds B in FP32): FP32/BF16 products, FP32
+// accumulation, FP64 for the Q and (K o K) terms.
+kot_status schur_matvec_lowp(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const double* v, double* y, bool bf16) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / (2.0 * cv.lam2), cv.Q, l, nullptr, v, 1, 0.0, y, 1));
+  HIPCHK(vec_axpby(l, tp.mu, v, 1.0, y, st));
+  if (tp.comp) HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / tp.mu, cv.KK, l, nullptr, v, 1, 1.0, y, 1));
+  if (tp.m == 0) return KOT_OK;
+  const float* Bs = ctx->Bf + (long long)tp.r0 * l;
+  LowpArgs g{};
+  g.m = tp.m; g.n = l; g.k = l; g.A = Bs; g.lda = l; g.s = v; g.B = ctx->Bf; g.ldb = l; g.transb = 1;
+  g.C = ctx->Cf; g.ldc = l; g.l = l; g.a = tp.a; g.r0 = tp.r0; g.mu = tp.mu; g.w = tp.w; g.complement = tp.comp ? 1 : 0;
+  g.diag_scale = 1.0; g.off_scale = 2.0;
+  HIPCHK(gemm_lowp(g, bf16, true, st));                 // H = Psi o (B_set diag(v) B^T)
+  LowpArgs g2{};
+  g2.m = tp.m; g2.n = l; g2.k = l; g2.A = ctx->Cf; g2.lda = l; g2.s = nullptr; g2.B = ctx->Bf; g2.ldb = l; g2.transb = 0;
+  g2.C = ctx->Ef; g2.ldc = l;
+  HIPCHK(gemm_lowp(g2, bf16, false, st));               // E = H B
+  HIPCHK(diag_dot_lowp(tp.m, l, tp.comp ? -1.0 : 1.0, Bs, l, ctx->Ef, l, y, ctx->part, st));
+  return KOT_OK;
+}
+
 struct DirInfo {
   int cg_iters = 0;
   double cg_res = 0.0;
+  int sweeps = 0;
 };
 
 // Algorithm 1 at state s with regularization mu: writes ctx->dg, ctx->dX.
@@ -343,34 +371,88 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   double* r = ctx->cr;
   double* pp = ctx->cp;
   double* Ap = ctx->cAp;
-  HIPCHK(vec_fill(l, 0.0, x, st));
-  HIPCHK(vec_copy(l, ctx->a1, r, st));
-  HIPCHK(vec_copy(l, ctx->a1, pp, st));
-  HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
-  KCHK(sync_read(ctx, 1, 0));
-  double rr = ctx->hsc[0];
-  double xx = 0.0;
-  int it = 0;
   const double rnorm = s.rn;
-  while (it < p->cg_max_iter) {
-    const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
-    if (std::sqrt(rr) <= thr) break;
-    KCHK(schur_matvec(ctx, cv, tp, pp, Ap));
-    HIPCHK(dot(l, pp, Ap, ctx->dsc + 0, ctx->part, st));
-    KCHK(sync_read(ctx, 1, 0));
-    const double pAp = ctx->hsc[0];
-    if (!(pAp > 0.0)) break;
-    const double alpha = rr / pAp;
-    HIPCHK(vec_axpby(l, alpha, pp, 1.0, x, st));
-    HIPCHK(vec_axpby(l, -alpha, Ap, 1.0, r, st));
+  int it = 0;
+  double rr = 0.0;
+  if (p->precision == KOT_FP64) {
+    HIPCHK(vec_fill(l, 0.0, x, st));
+    HIPCHK(vec_copy(l, ctx->a1, r, st));
+    HIPCHK(vec_copy(l, ctx->a1, pp, st));
     HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
-    HIPCHK(dot(l, x, x, ctx->dsc + 1, ctx->part, st));
-    KCHK(sync_read(ctx, 2, 0));
-    const double rr_new = ctx->hsc[0];
-    xx = ctx->hsc[1];
-    HIPCHK(vec_axpby(l, 1.0, r, rr_new / rr, pp, st));
-    rr = rr_new;
-    ++it;
+    KCHK(sync_read(ctx, 1, 0));
+    rr = ctx->hsc[0];
+    double xx = 0.0;
+    while (it < p->cg_max_iter) {
+      const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
+      if (std::sqrt(rr) <= thr) break;
+      KCHK(schur_matvec(ctx, cv, tp, pp, Ap));
+      HIPCHK(dot(l, pp, Ap, ctx->dsc + 0, ctx->part, st));
+      KCHK(sync_read(ctx, 1, 0));
+      const double pAp = ctx->hsc[0];
+      if (!(pAp > 0.0)) break;
+      const double alpha = rr / pAp;
+      HIPCHK(vec_axpby(l, alpha, pp, 1.0, x, st));
+      HIPCHK(vec_axpby(l, -alpha, Ap, 1.0, r, st));
+      HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
+      HIPCHK(dot(l, x, x, ctx->dsc + 1, ctx->part, st));
+      KCHK(sync_read(ctx, 2, 0));
+      const double rr_new = ctx->hsc[0];
+      xx = ctx->hsc[1];
+      HIPCHK(vec_axpby(l, 1.0, r, rr_new / rr, pp, st));
+      rr = rr_new;
+      ++it;
+    }
+  } else {
+    // Iterative refinement: each sweep solves M~ d = r with CG whose chain runs in reduced precision, then
+    // x += d and the true residual r = a1 - M x is recomputed in FP64; Eq. 4.5 is checked on that residual.
+    const bool bf16 = p->precision == KOT_MIXED_BF16;
+    const double inner_rel = bf16 ? 1e-2 : 1e-4;
+    HIPCHK(f64_to_f32((long long)l * l, ctx->Bm, ctx->Bf, st));
+    HIPCHK(vec_fill(l, 0.0, x, st));
+    HIPCHK(vec_copy(l, ctx->a1, r, st));
+    double xx = 0.0;
+    int sweeps = 0;
+    while (true) {
+      HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
+      HIPCHK(dot(l, x, x, ctx->dsc + 1, ctx->part, st));
+      KCHK(sync_read(ctx, 2, 0));
+      rr = ctx->hsc[0];
+      xx = ctx->hsc[1];
+      const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
+      if (std::sqrt(rr) <= thr || sweeps >= 8 || it >= 4 * std::max(1, p->cg_max_iter)) break;
+      // inner CG from d = 0 on the reduced-precision operator
+      double* d = ctx->lx;
+      double* ri = ctx->lr;
+      double* pi = ctx->lp;
+      double* Api = ctx->lAp;
+      HIPCHK(vec_fill(l, 0.0, d, st));
+      HIPCHK(vec_copy(l, r, ri, st));
+      HIPCHK(vec_copy(l, r, pi, st));
+      double rri = rr;
+      const double stop_in = std::max(inner_rel * std::sqrt(rr), 0.5 * thr);
+      for (int j = 0; j < std::max(1, p->cg_max_iter); ++j) {
+        if (std::sqrt(rri) <= stop_in) break;
+        KCHK(schur_matvec_lowp(ctx, cv, tp, pi, Api, bf16));
+        HIPCHK(dot(l, pi, Api, ctx->dsc + 0, ctx->part, st));
+        KCHK(sync_read(ctx, 1, 0));
+        const double pAp = ctx->hsc[0];
+        if (!(pAp > 0.0)) break;
+        const double alpha = rri / pAp;
+        HIPCHK(vec_axpby(l, alpha, pi, 1.0, d, st));
+        HIPCHK(vec_axpby(l, -alpha, Api, 1.0, ri, st));
+        HIPCHK(dot(l, ri, ri, ctx->dsc + 0, ctx->part, st));
+        KCHK(sync_read(ctx, 1, 0));
+        const double rr_new = ctx->hsc[0];
+        HIPCHK(vec_axpby(l, 1.0, ri, rr_new / rri, pi, st));
+        rri = rr_new;
+        ++it;
+      }
+      HIPCHK(vec_axpby(l, 1.0, d, 1.0, x, st));
+      KCHK(schur_matvec(ctx, cv, tp, x, Ap));                 // FP64 residual
+      HIPCHK(vec_lincomb(l, 1.0, ctx->a1, -1.0, Ap, r, st));
+      ++sweeps;
+    }
+    info->sweeps = sweeps;
   }
   info->cg_iters = it;
   info->cg_res = std::sqrt(rr);
@@ -451,7 +533,8 @@ kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
   if (need_sigma && !(p->sigma > 0.0)) return fail(ctx, KOT_ERR_ARG, "sigma must be > 0");
   if (!(p->lambda1 > 0.0) || !(p->lambda2 > 0.0)) return fail(ctx, KOT_ERR_ARG, "lambda1, lambda2 must be > 0");
   if (p->max_iter < 0 || p->cg_max_iter < 0) return fail(ctx, KOT_ERR_ARG, "negative iteration cap");
-  if (p->precision != KOT_FP64) return fail(ctx, KOT_ERR_ARG, "precision %d is not available in this build", p->precision);
+  if (p->precision != KOT_FP64 && p->precision != KOT_FP32 && p->precision != KOT_MIXED_BF16)
+    return fail(ctx, KOT_ERR_ARG, "unknown precision %d", p->precision);
   if (p->safeguard != KOT_SAFEGUARD_EG && p->safeguard != KOT_SAFEGUARD_NONE)
     return fail(ctx, KOT_ERR_ARG, "unknown safeguard %d", p->safeguard);
   return KOT_OK;

@@ -8,7 +8,8 @@
 namespace kot {
 
 // ---- optional launch profiler (events around kernel launches on the issuing stream) -----------------------
-enum ProfClass { PROF_GEMM_F64 = 0, PROF_EIG_ROUND = 1, PROF_EIG_OTHER = 2, PROF_NCLASS = 3 };
+enum ProfClass { PROF_GEMM_F64 = 0, PROF_EIG_ROUND = 1, PROF_EIG_OTHER = 2, PROF_GEMM_F32 = 3, PROF_GEMM_BF16 = 4,
+                 PROF_NCLASS = 5 };
 struct Profiler {
   bool on = false;
   struct Rec { int cls; double flops; double bytes; hipEvent_t a, b; };
@@ -132,6 +133,27 @@ hipError_t trtri_upper(int l, const double* R, double* Y, hipStream_t st);
 // positive entries; part: >= 128 doubles.
 hipError_t lift_diag(int l, const double* Qg, const double* z, const double* g, double lam1, double lam2, double frac,
                      double* d, double* part, hipStream_t st);
+
+// ---- reduced-precision CG chain (k_lowp.hip) --------------------------------------------------------------
+struct LowpArgs {
+  int m, n, k;
+  const float* A; int lda;   // m x k, row-major
+  const double* s;           // diag scale on k (may be null)
+  const float* B; int ldb;   // n x k (transb) or k x n
+  int transb;
+  float* C; int ldc;
+  // Psi epilogue (see psi_hadamard): row r of C is eigen-index r0 + r
+  int l, a, r0;
+  double mu;
+  const double* w;
+  int complement;
+  double diag_scale, off_scale;
+};
+hipError_t gemm_lowp(const LowpArgs& g, bool bf16, bool psi, hipStream_t st);
+hipError_t f64_to_f32(long long n, const double* x, float* y, hipStream_t st);
+// y[j] += alpha * sum_{r < m} A[r][j] B[r][j]; part >= 16 n doubles
+hipError_t diag_dot_lowp(int m, int n, double alpha, const float* A, int lda, const float* B, int ldb, double* y,
+                         double* part, hipStream_t st);
 
 }  // namespace kot
 

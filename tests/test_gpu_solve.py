@@ -56,3 +56,21 @@ def test_tiny_fixed_iterations(gpu_ctx, iters):
     hist = np.array([h["res"] for h in ref["history"]])
     np.testing.assert_allclose(r.res_hist, hist, rtol=1e-6)
     np.testing.assert_allclose(_n(gamma), ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("name,l,n,seed", [("mix1000", 150, 600, 0), ("batch", 120, 500, 8)])
+def test_solve_reduced_precision_cg(gpu_ctx, precision, name, l, n, seed):
+    """Full solves with the FP32 / BF16 CG chain reach the oracle's estimate; eigendecompositions,
+    projections and residuals stay FP64."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem(name, seed, l=l, n=n)
+    print(f"[case] kot_solve precision={precision} {name} seed={seed} l={p.l}", flush=True)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=p.tol))
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=precision)
+    gamma, X, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, want_X=True)
+    assert r.status == kotssn.KOT_OK and r.residual <= p.tol
+    assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
+    _, _, rn, _ = ko.residual(core, _n(gamma), _n(X))
+    assert rn <= 1.01 * p.tol

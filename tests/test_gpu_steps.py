@@ -174,3 +174,23 @@ def test_eg_step(gpu_ctx, name, l, n):
     ogn, oXn = ko.eg_step(core, g, X, eta)
     np.testing.assert_allclose(_n(gn), ogn, rtol=1e-11, atol=1e-12 * np.abs(ogn).max())
     np.testing.assert_allclose(_n(Xn), oXn, atol=1e-11 * max(1.0, np.abs(oXn).max()))
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("name,l,n,mu", [("tiny", None, None, 0.3), ("mix1000", 120, 400, 0.05),
+                                         ("gauss500", 80, 300, 1.0)])
+def test_ssn_direction_reduced_precision(gpu_ctx, precision, name, l, n, mu):
+    """FP32 / BF16 chain inside FP64 iterative refinement: with a tight Eq. 4.5 the direction reaches the
+    FP64 one (the refinement residual is evaluated in FP64)."""
+    from paper_2310_14087_amd import kotssn
+    p, core = _core_case(name, l, n)
+    print(f"[case] kot_ssn_direction precision={precision} {name} l={core.l} mu={mu}", flush=True)
+    g, X = _random_iterate(core.l, 23)
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2, cg_max_iter=200, tau=1e-12, kappa=1e-12,
+                                precision=precision)
+    dg, dX, info = gpu_ctx.ssn_direction(_t(core.Q), _t(core.z), _t(core.R), _t(g), _t(X), mu, prm)
+    o1, o2, on, eig = ko.residual(core, g, X)
+    assert 0 < info["alpha"] < core.l      # the chain is exercised
+    odg, odX, _ = ko.ssn_direction(core, o1, o2, eig, mu, ko.Params(cg_max_iter=400, tau=1e-13, kappa=1e-13))
+    np.testing.assert_allclose(_n(dg), odg, atol=1e-6 * np.abs(odg).max())
+    np.testing.assert_allclose(_n(dX), odX, atol=1e-6 * np.abs(odX).max())
