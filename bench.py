@@ -6,7 +6,11 @@ embeddings, q^2, Cholesky factor) and Algorithm 2 to |R(w)| <= 1e-6.  The worklo
 samples per side, d = 10, two 4-component Gaussian mixtures, l = 1000 filling points), one instance per
 seed.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--arm fp64] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--arm fp64|warm|mixed|all] [--no-cpu-baseline]
+
+Arms: ``fp64`` cold start, FP64 everywhere; ``warm`` learned warm start, FP64; ``mixed`` learned warm start
+with the CG matvec chain in BF16 (FP32 accumulation) inside FP64 iterative refinement.  ``value`` is the
+rate of the last arm run (``mixed`` by default); every arm's rate is in ``config.arms``.
 """
 from __future__ import annotations
 
@@ -62,15 +66,56 @@ def _cpu_model():
     return "unknown"
 
 
+def batch_bench(a):
+    """Uneven batch (n ~ U{200..2000}, l ~ U{100..400}, d ~ U{2..10}): solves/s through kot_solve_batched with
+    `lanes` concurrent streams vs one lane; FP32 CG chain, FP64 projections."""
+    import numpy as np
+    import torch
+    from paper_2310_14087_amd import kotssn
+    from paper_2310_14087_amd.inputs import make_problem
+    dev = torch.device("cuda:0")
+    probs = [make_problem("batch", s) for s in range(a.batch)]
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    inputs = [(t(p.xs), t(p.ys), t(p.xf), t(p.yf)) for p in probs]
+    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=1, max_iter=60)
+            for p in probs]
+    ctx = kotssn.Context(0)
+    if a.tune:
+        if os.path.exists(a.tune):
+            ctx.autotune_load(a.tune)
+        else:
+            ctx.autotune(sorted({p.l for p in probs}), a.tune)
+    res = {}
+    for lanes in sorted({1, a.lanes}):
+        ctx.solve_batched(inputs[:min(4, len(inputs))], prms[:min(4, len(inputs))], lanes=lanes)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.solve_batched(inputs, prms, lanes=lanes)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        conv = sum(1 for _, r in out if r.status == kotssn.KOT_OK)
+        res[f"lanes{lanes}"] = dict(solves_per_s=len(probs) / dt, seconds=dt, converged=conv,
+                                    iters=[r.iters for _, r in out])
+        _log(f"lanes={lanes}: {len(probs) / dt:.2f} solves/s, {conv}/{len(probs)} converged")
+    ctx.close()
+    print(json.dumps({"metric": "batched SSN solves/s (uneven problems)", "problems": len(probs),
+                      "sizes": {"l": [p.l for p in probs], "n": [p.n_src for p in probs], "d": [p.d for p in probs]},
+                      "results": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mix1000")
-    ap.add_argument("--arm", default="both", choices=["fp64", "warm", "both"])
+    ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed", "all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the metric line: time kot_solve_batched on this many 'batch' problems")
+    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--tune", default=None, help="autotune table to load (or create when missing)")
     a = ap.parse_args()
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -85,6 +130,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if a.batch:
+        return batch_bench(a)
     n_inst = max(1, a.steps)
     _log(f"generating {n_inst} {a.workload} instances")
     probs = [make_problem(a.workload, s) for s in range(n_inst)]
@@ -94,17 +141,19 @@ def main():
 
     ctx = kotssn.Context(0)
     base = [dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol) for p in probs]
-    arms = ["fp64", "warm"] if a.arm == "both" else [a.arm]
+    arms = ["fp64", "warm", "mixed"] if a.arm == "all" else [a.arm]
     theta_dev, H = None, 0
-    if "warm" in arms:
+    if "warm" in arms or "mixed" in arms:
         from paper_2310_14087_amd import warmstart
         theta, F, H, meta = warmstart.load()
         theta_dev = torch.from_numpy(theta).to(dev)
 
     def params(i, arm):
         kw = dict(base[i])
-        if arm == "warm":
+        if arm in ("warm", "mixed"):
             kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
+        if arm == "mixed":
+            kw.update(precision=kotssn.KOT_MIXED_BF16)
         return kotssn.default_params(**kw)
 
     def run_arm(arm, profile):
@@ -138,11 +187,14 @@ def main():
                              cg_iters=[r.cg_iters_total for r in results], ot=[r.ot for r in results])
         if arm == arms[-1]:
             elapsed, prof, final = el, pr, arm
+        _log(f"{arm}: {a.steps / el:.2f} solves/s, {conv}/{a.steps} converged")
     ctx.close()
-    if "fp64" in out_arms and "warm" in out_arms:
-        ot_dev = max(abs(x - y) / abs(y) for x, y in zip(out_arms["warm"]["ot"], out_arms["fp64"]["ot"]))
-        out_arms["warm"]["ot_rel_dev_vs_fp64"] = ot_dev
-        out_arms["speedup_warm_vs_fp64"] = out_arms["warm"]["solves_per_s"] / out_arms["fp64"]["solves_per_s"]
+    if "fp64" in out_arms:
+        for arm in ("warm", "mixed"):
+            if arm in out_arms:
+                out_arms[arm]["ot_rel_dev_vs_fp64"] = max(
+                    abs(x - y) / abs(y) for x, y in zip(out_arms[arm]["ot"], out_arms["fp64"]["ot"]))
+                out_arms[f"speedup_{arm}_vs_fp64"] = out_arms[arm]["solves_per_s"] / out_arms["fp64"]["solves_per_s"]
     value = a.steps / elapsed
     out = {
         "metric": "SSN solves/s to residual<=1e-6 at l=1000: plain FP64 vs warm-start+mixed",

@@ -123,6 +123,23 @@ kot_status kot_setup(kot_ctx* ctx, const kot_problem* prob, const kot_params* pr
 kot_status kot_solve(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm, const double* gamma0,
                      kot_result* res);
 
+/* Many independent problems (any mix of n_src, n_tgt, d, l): each is solved as by kot_solve.  prms holds
+ * 1 entry (shared) or nprob entries; gamma0 (host array of nprob device pointers) may be NULL; results[i]
+ * (gamma required) and status[i] (host) receive problem i's outputs.  The problems are spread over `lanes`
+ * child contexts (0 = 4), each with its own HIP stream and workspace and driven by its own host thread, so
+ * kernels of different problems overlap on the device.  Returns the most severe error status if a problem
+ * failed (KOT_NOT_CONVERGED is reported per problem only). */
+kot_status kot_solve_batched(kot_ctx* ctx, int nprob, const kot_problem* probs, const kot_params* prms, int nparams,
+                             const double* const* gamma0, kot_result* results, int* status, int lanes);
+
+/* GEMM tiling autotuner (not in the paper).  For each size L in sizes (host, nsizes entries, 1..4096) times the
+ * two product shapes of a solve (L x L x L and L/2 x L x L with a diagonal scale) for each split-K target
+ * (0 = no K split, 256, 512, 1024 workgroups) and keeps the fastest per size bucket (128-wide).  The table
+ * (33 entries, copied to table_out when non-NULL) is used by every later call on this context and its batch
+ * lanes; path (may be NULL) receives it as text.  kot_autotune_load installs a saved table. */
+kot_status kot_autotune(kot_ctx* ctx, const int* sizes, int nsizes, const char* path, int* table_out);
+kot_status kot_autotune_load(kot_ctx* ctx, const char* path);
+
 /* Algorithm 2 on given dual data (Eq. 3.4): Q, z, R (any factor with R^T R = K), wsum (device) and q2
  * (host).  prm->sigma is ignored. */
 kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, double q2,
@@ -193,7 +210,8 @@ kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* prob, const kot_params
  * of the instrumented kernel classes on the context's stream; enable = 0 stops, waits for the stream, and
  * writes 4 values per class into out (host, 4 * nclass doubles; may be NULL): launches, total milliseconds
  * between the events, algorithmic flops and algorithmic bytes.  Classes: 0 = FP64 GEMM (2mnk flops),
- * 1 = one Jacobi round (pair solves + tile updates; flops of the 16x16 tile products), 2 = reserved,
+ * 1 = one Jacobi sweep (all rounds of pair solves + tile updates, replayed as one captured HIP graph; flops of
+ * the 16x16 tile products), 2 = reserved,
  * 3 = FP32 chain GEMM, 4 = BF16 chain GEMM (2mnk flops each). */
 kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass);
 

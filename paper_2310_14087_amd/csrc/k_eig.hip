@@ -34,7 +34,8 @@ __device__ __forceinline__ void circle16(int r, int k, int& a, int& b) {
 
 __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __restrict__ A, const int2* __restrict__ pairs,
                                                         double* __restrict__ Uout, int* __restrict__ flag,
-                                                        double thresh, int max_inner) {
+                                                        const double* __restrict__ thresh_ptr, int max_inner) {
+  const double thresh = *thresh_ptr;
   __shared__ double S[SLOT][SLOT + 1];
   __shared__ double U[SLOT][SLOT + 1];
   __shared__ double cs[8][2];
@@ -278,13 +279,18 @@ __global__ void permute_cols_kernel(int l, const double* __restrict__ V, const i
 
 struct EigWork {
   int lmax = 0;
+  // one captured sweep (all rounds) per (l, A/V buffers); replayed with hipGraphLaunch
+  int graph_l = -1;
+  const double* graph_tmp = nullptr;
+  hipGraphExec_t graph = nullptr;
+  bool graph_failed = false;
   int nb = -1;                // block count of the current pair table
   int2* pairs = nullptr;      // device [(nb-1) * nb/2]
   double* U = nullptr;        // device [npairs_max * 256]
   int* flag = nullptr;        // device [npairs_max]
   double* part = nullptr;     // device [2 * 512]
-  double* norms = nullptr;    // device [2]
-  double* hnorms = nullptr;   // pinned host [2]
+  double* norms = nullptr;    // device [4]: off, |A|_F, rotation threshold
+  double* hnorms = nullptr;   // pinned host [4]
   int* perm = nullptr;        // device [lmax]
 };
 
@@ -297,8 +303,8 @@ EigWork* eig_work_create(int lmax) {
             hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256) == hipSuccess &&
             hipMalloc(&w->flag, sizeof(int) * (size_t)npm) == hipSuccess &&
             hipMalloc(&w->part, sizeof(double) * 1024) == hipSuccess &&
-            hipMalloc(&w->norms, sizeof(double) * 2) == hipSuccess &&
-            hipHostMalloc(&w->hnorms, sizeof(double) * 2) == hipSuccess &&
+            hipMalloc(&w->norms, sizeof(double) * 4) == hipSuccess &&
+            hipHostMalloc(&w->hnorms, sizeof(double) * 4) == hipSuccess &&
             hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess;
   if (!ok) { eig_work_destroy(w); return nullptr; }
   return w;
@@ -306,6 +312,7 @@ EigWork* eig_work_create(int lmax) {
 
 void eig_work_destroy(EigWork* w) {
   if (!w) return;
+  if (w->graph) hipGraphExecDestroy(w->graph);
   hipFree(w->pairs); hipFree(w->U); hipFree(w->flag); hipFree(w->part); hipFree(w->norms);
   hipHostFree(w->hnorms); hipFree(w->perm);
   delete w;
@@ -375,22 +382,47 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   KOT_HIP_TRY(off_norm(w, l, A, st, &off, &all));
   int s = 0;
   const double thresh_rel = 1e-18;
-  while (off > tol * all && s < max_sweeps) {
-    const double thresh = thresh_rel * all;
-    Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
+  auto launch_sweep = [&](hipStream_t s_) -> hipError_t {
     for (int r = 0; r < nb - 1; ++r) {
       const int2* pr = w->pairs + (size_t)r * np;
-      // one round: A <- G^T A G and V <- V G through 16x16 tiles: 2 x (2*16^3) flops per A tile, 2*16^3 per V tile
-      if (pf) pf->begin(st, PROF_EIG_ROUND, 4.0 * 4096.0 * np * np + 2.0 * 4096.0 * ((l + SLOT - 1) / SLOT) * np,
-                        16.0 * l * (double)l * 2.0);
-      hipLaunchKernelGGL(pair_solve_kernel, dim3(np), dim3(64), 0, st, l, A, pr, w->U, w->flag, thresh, 8);
+      hipLaunchKernelGGL(pair_solve_kernel, dim3(np), dim3(64), 0, s_, l, A, pr, w->U, w->flag, w->norms + 2, 8);
       KOT_HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(apply_A_kernel, dim3(np, np), dim3(64), 0, st, l, A, pr, w->U, w->flag);
+      hipLaunchKernelGGL(apply_A_kernel, dim3(np, np), dim3(64), 0, s_, l, A, pr, w->U, w->flag);
       KOT_HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(apply_V_kernel, dim3((l + SLOT - 1) / SLOT, np), dim3(64), 0, st, l, V, pr, w->U, w->flag);
+      hipLaunchKernelGGL(apply_V_kernel, dim3((l + SLOT - 1) / SLOT, np), dim3(64), 0, s_, l, V, pr, w->U, w->flag);
       KOT_HIP_TRY(hipGetLastError());
-      if (pf) pf->end(st);
     }
+    return hipSuccess;
+  };
+  // flops of one sweep: per round 2 x 2 x 16^3 per A tile and 2 x 16^3 per V tile
+  const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * ((l + SLOT - 1) / SLOT) * np);
+  while (off > tol * all && s < max_sweeps) {
+    w->hnorms[2] = thresh_rel * all;
+    KOT_HIP_TRY(hipMemcpyAsync(w->norms + 2, w->hnorms + 2, sizeof(double), hipMemcpyHostToDevice, st));
+    if (!w->graph_failed && (w->graph == nullptr || w->graph_l != l || w->graph_tmp != tmp)) {
+      if (w->graph) { hipGraphExecDestroy(w->graph); w->graph = nullptr; }
+      hipGraph_t gr = nullptr;
+      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        const hipError_t le = launch_sweep(st);
+        ok = hipStreamEndCapture(st, &gr) == hipSuccess && le == hipSuccess && gr != nullptr;
+      }
+      if (ok) ok = hipGraphInstantiate(&w->graph, gr, nullptr, nullptr, 0) == hipSuccess;
+      if (gr) hipGraphDestroy(gr);
+      if (!ok) {
+        (void)hipGetLastError();
+        w->graph = nullptr;
+        w->graph_failed = true;
+      } else {
+        w->graph_l = l;
+        w->graph_tmp = tmp;
+      }
+    }
+    Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
+    if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, 32.0 * l * (double)l * (nb - 1));
+    if (w->graph) KOT_HIP_TRY(hipGraphLaunch(w->graph, st));
+    else KOT_HIP_TRY(launch_sweep(st));
+    if (pf) pf->end(st);
     ++s;
     KOT_HIP_TRY(off_norm(w, l, A, st, &off, &all));
   }

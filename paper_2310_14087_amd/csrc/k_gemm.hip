@@ -220,6 +220,7 @@ __global__ void diag_dot_final(int n, double alpha, double beta, const double* _
 thread_local Profiler* g_prof = nullptr;
 thread_local double* g_gemm_ws = nullptr;
 thread_local size_t g_gemm_ws_cap = 0;
+thread_local const int* g_gemm_tune = nullptr;
 
 hipEvent_t Profiler::get() {
   if (next == pool.size()) {
@@ -247,10 +248,12 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
     return hipErrorInvalidValue;
   }
   const int tiles = ((g.n + BN - 1) / BN) * ((g.m + BM - 1) / BM) * g.batch;
-  // K split: aim for ~512 workgroups (2 per CU) with at least 128 of K per split
+  // K split: aim for `target` workgroups (default 512 = 2 per CU; per size bucket from the autotuner's table)
+  // with at least 128 of K per split
   int splits = 1;
-  if (tiles < 512 && g.k >= 256) {
-    splits = (512 + tiles - 1) / tiles;
+  const int target = g_gemm_tune ? g_gemm_tune[gemm_tune_bucket(std::max(g.m, g.n))] : 512;
+  if (target > 0 && tiles < target && g.k >= 256) {
+    splits = (target + tiles - 1) / tiles;
     splits = std::min(splits, std::min(8, g.k / 128));
     const size_t need = (size_t)splits * g.batch * (size_t)g.m * g.n;
     if (splits < 2 || !g_gemm_ws || need > g_gemm_ws_cap) splits = 1;

@@ -5,7 +5,9 @@
 #include "kot_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -72,6 +74,11 @@ struct kot_ctx {
   float *fA1 = nullptr, *fA2 = nullptr, *fdZ1 = nullptr, *fdZ2 = nullptr, *fout = nullptr, *fdout = nullptr,
         *fpart = nullptr, *fX = nullptr;
   double* rs3 = nullptr;
+  // batched solves: child contexts (own stream and workspace), one host worker thread each
+  std::vector<kot_ctx*> lanes;
+  // split-K targets per size bucket (autotuner)
+  int tune[kTuneBuckets];
+  bool tuned = false;
 };
 
 namespace {
@@ -781,6 +788,9 @@ kot_status check_ctx(kot_ctx* ctx) {
   g_prof = &ctx->prof;
   g_gemm_ws = ctx->gemm_ws;
   g_gemm_ws_cap = ctx->gemm_ws_cap;
+  g_gemm_tune = ctx->tuned ? ctx->tune : nullptr;
+  // the context's own stream does not order after the null stream: wait for work the caller queued there
+  if (ctx->own_stream && hipStreamSynchronize(nullptr) != hipSuccess) return fail(ctx, KOT_ERR_HIP, "null stream sync");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, KOT_ERR_HIP, "hipSetDevice failed");
   return KOT_OK;
 }
@@ -850,6 +860,8 @@ kot_status kot_destroy(kot_ctx* ctx) {
   if (!ctx) return KOT_ERR_ARG;
   hipSetDevice(ctx->device);
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  for (kot_ctx* ln : ctx->lanes) kot_destroy(ln);
+  ctx->lanes.clear();
   free_ws(ctx);
   for (void* p : ctx->mbufs) hipFree(p);
   ctx->mbufs.clear();
@@ -984,6 +996,138 @@ kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double
   HIPCHK(cholesky_upper(l, A, eps, R, ctx->T1, ctx->dint, ctx->stream));
   KCHK(sync_read(ctx, 0, 1));
   if (ctx->hint[0] != 0) return fail(ctx, KOT_ERR_FACTOR, "matrix is not positive definite (pivot %d)", ctx->hint[0]);
+  return KOT_OK;
+}
+
+kot_status kot_solve_batched(kot_ctx* ctx, int nprob, const kot_problem* probs, const kot_params* prms, int nparams,
+                             const double* const* gamma0, kot_result* results, int* status, int lanes) {
+  KCHK(check_ctx(ctx));
+  if (nprob < 0 || (nprob > 0 && (!probs || !prms || !results || !status)) || (nparams != 1 && nparams != nprob))
+    return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  for (int i = 0; i < nprob; ++i) {
+    KCHK(check_problem(ctx, &probs[i]));
+    KCHK(check_params(ctx, &prms[nparams == 1 ? 0 : i], true));
+    if (!results[i].gamma) return fail(ctx, KOT_ERR_ARG, "results[%d].gamma is NULL", i);
+  }
+  if (nprob == 0) return KOT_OK;
+  if (lanes <= 0) lanes = 4;  // hardware queues per process on this device class
+  lanes = std::min(lanes, std::min(nprob, 16));
+  while ((int)ctx->lanes.size() < lanes) {
+    kot_ctx* c = nullptr;
+    kot_status s = kot_create(&c, ctx->device, nullptr);
+    if (s != KOT_OK) return fail(ctx, s, "could not create a batch lane");
+    ctx->lanes.push_back(c);
+  }
+  // inputs may come from any stream of the caller: make them visible to the lanes' streams
+  HIPCHK(hipDeviceSynchronize());
+  std::atomic<int> next(0);
+  auto worker = [&](kot_ctx* lane) {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= nprob) break;
+      const kot_params* p = &prms[nparams == 1 ? 0 : i];
+      status[i] = kot_solve(lane, &probs[i], p, gamma0 ? gamma0[i] : nullptr, &results[i]);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 0; t < lanes; ++t) {
+    if (ctx->tuned) {
+      std::copy(ctx->tune, ctx->tune + kTuneBuckets, ctx->lanes[t]->tune);
+      ctx->lanes[t]->tuned = true;
+    }
+    th.emplace_back(worker, ctx->lanes[t]);
+  }
+  for (auto& t : th) t.join();
+  g_prof = &ctx->prof;
+  g_gemm_ws = ctx->gemm_ws;
+  g_gemm_ws_cap = ctx->gemm_ws_cap;
+  int worst = KOT_OK;
+  for (int i = 0; i < nprob; ++i)
+    if (status[i] < worst) worst = status[i];
+  if (worst < 0) {
+    for (int i = 0; i < nprob; ++i)
+      if (status[i] == worst) return fail(ctx, (kot_status)worst, "problem %d failed with status %d", i, worst);
+  }
+  return KOT_OK;
+}
+
+kot_status kot_autotune(kot_ctx* ctx, const int* sizes, int nsizes, const char* path, int* table_out) {
+  KCHK(check_ctx(ctx));
+  if (nsizes < 1 || !sizes) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  int Lmax = 1;
+  for (int i = 0; i < nsizes; ++i) {
+    if (sizes[i] < 1 || sizes[i] > 4096) return fail(ctx, KOT_ERR_ARG, "sizes must be in [1, 4096]");
+    Lmax = std::max(Lmax, sizes[i]);
+  }
+  KCHK(ensure_ws(ctx, Lmax, 0));
+  if (!ctx->tuned) {
+    for (int b = 0; b < kTuneBuckets; ++b) ctx->tune[b] = 512;
+  }
+  hipStream_t st = ctx->stream;
+  double* A = ctx->T1;
+  double* B = ctx->T2;
+  double* Cm = ctx->T3;
+  HIPCHK(vec_fill(Lmax * Lmax, 0.5, A, st));
+  HIPCHK(vec_fill(Lmax * Lmax, 0.25, B, st));
+  HIPCHK(vec_fill(Lmax, 1.0, ctx->vtmp, st));
+  const int cand[4] = {0, 256, 512, 1024};
+  int local[kTuneBuckets];
+  std::copy(ctx->tune, ctx->tune + kTuneBuckets, local);
+  for (int i = 0; i < nsizes; ++i) {
+    const int L = sizes[i];
+    double best_t = 1e300;
+    int best = 512;
+    for (int c : cand) {
+      local[gemm_tune_bucket(L)] = c;
+      g_gemm_tune = local;
+      for (int rep = 0; rep < 2; ++rep) {  // warm, then timed
+        HIPCHK(hipEventRecord(ctx->ev0, st));
+        for (int r = 0; r < 5; ++r) {
+          HIPCHK(mm(st, 0, 0, L, L, L, 1.0, A, L, nullptr, B, L, 0.0, Cm, L));
+          HIPCHK(mm(st, 0, 1, std::max(1, L / 2), L, L, 1.0, A, L, ctx->vtmp, B, L, 0.0, Cm, L));
+        }
+        HIPCHK(hipEventRecord(ctx->ev1, st));
+        HIPCHK(hipEventSynchronize(ctx->ev1));
+      }
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      if (ms < best_t) { best_t = ms; best = c; }
+    }
+    local[gemm_tune_bucket(L)] = best;
+  }
+  std::copy(local, local + kTuneBuckets, ctx->tune);
+  ctx->tuned = true;
+  g_gemm_tune = ctx->tune;
+  if (table_out) std::copy(ctx->tune, ctx->tune + kTuneBuckets, table_out);
+  if (path) {
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(ctx, KOT_ERR_ARG, "cannot write %s", path);
+    std::fprintf(f, "kot-gemm-tune 1\n");
+    for (int b = 0; b < kTuneBuckets; ++b) std::fprintf(f, "%d %d\n", b, ctx->tune[b]);
+    std::fclose(f);
+  }
+  return KOT_OK;
+}
+
+kot_status kot_autotune_load(kot_ctx* ctx, const char* path) {
+  KCHK(check_ctx(ctx));
+  if (!path) return fail(ctx, KOT_ERR_ARG, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(ctx, KOT_ERR_ARG, "cannot read %s", path);
+  int ver = 0;
+  int tab[kTuneBuckets];
+  for (int b = 0; b < kTuneBuckets; ++b) tab[b] = 512;
+  if (std::fscanf(f, "kot-gemm-tune %d", &ver) != 1 || ver != 1) {
+    std::fclose(f);
+    return fail(ctx, KOT_ERR_ARG, "%s is not a tuning table", path);
+  }
+  int b = 0, v = 0;
+  while (std::fscanf(f, "%d %d", &b, &v) == 2)
+    if (b >= 0 && b < kTuneBuckets && v >= 0 && v <= 4096) tab[b] = v;
+  std::fclose(f);
+  std::copy(tab, tab + kTuneBuckets, ctx->tune);
+  ctx->tuned = true;
+  g_gemm_tune = ctx->tune;
   return KOT_OK;
 }
 

@@ -41,6 +41,10 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
 // too small => no K split).
 extern thread_local double* g_gemm_ws;
 extern thread_local size_t g_gemm_ws_cap;  // doubles
+// Split-K target workgroup count per size bucket (0 = never split); null => 512 everywhere.
+constexpr int kTuneBuckets = 33;
+inline int gemm_tune_bucket(int size) { const int b = (size + 127) / 128; return b < kTuneBuckets ? b : kTuneBuckets - 1; }
+extern thread_local const int* g_gemm_tune;
 
 // y[j] = alpha * sum_{r in [r0, r1)} A[r*lda + j] * B[r*ldb + j] + beta * y[j], j < n (column dots).
 // part: workspace of at least kDiagParts * n doubles.

@@ -152,8 +152,10 @@ def make_problem(name: str, s: int = 0, *, l: int | None = None, n: int | None =
         xs = _mixture(rng, mx, n_)
         ys = _mixture(rng, my, n_)
     else:  # batch
-        n_ = n or int(rng.integers(200, 2001))
-        l_ = l or int(rng.integers(100, 401))
+        n_draw = int(rng.integers(200, 2001))
+        l_draw = int(rng.integers(100, 401))
+        n_ = n or n_draw
+        l_ = l or l_draw
         d = int(rng.integers(2, 11))
         shift = rng.uniform(-1.0, 1.0, size=d)
         xs = rng.standard_normal((n_, d))

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "KOT_OK", 1: "KOT_NOT_CONVERGED", -1: "KOT_ERR_ARG", -2: "KOT
 EXPORTED = ["kot_params_default", "kot_create", "kot_destroy", "kot_last_error", "kot_setup", "kot_solve",
             "kot_solve_core", "kot_eigh", "kot_residual", "kot_ssn_direction", "kot_eg_step", "kot_cholesky",
             "kot_gemm", "kot_profile", "kot_mlp_params", "kot_features", "kot_mlp_forward", "kot_mlp_loss_grad",
-            "kot_mlp_adam", "kot_warmstart"]
+            "kot_mlp_adam", "kot_warmstart", "kot_solve_batched", "kot_autotune", "kot_autotune_load"]
 
 
 class KotParams(C.Structure):
@@ -89,6 +89,9 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
         "kot_mlp_loss_grad": (i, [vp, i, i, i, vp, vp, vp, vp, P(d)]),
         "kot_mlp_adam": (i, [vp, i, vp, vp, vp, vp, i, C.c_float, C.c_float, C.c_float, C.c_float]),
         "kot_warmstart": (i, [vp, P(KotProblem), P(KotParams), i, i, vp, vp]),
+        "kot_solve_batched": (i, [vp, i, P(KotProblem), P(KotParams), i, vp, P(KotResult), P(i), i]),
+        "kot_autotune": (i, [vp, P(i), i, C.c_char_p, P(i)]),
+        "kot_autotune_load": (i, [vp, C.c_char_p]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(lib, name)
@@ -232,6 +235,31 @@ class Context:
                          (KOT_OK, KOT_NOT_CONVERGED))
         return gamma, X, self._pack(st, res, rh, rvh)
 
+    def solve_batched(self, problems, prms, lanes=0, hist_cap=256):
+        """problems: list of (xs, ys, xf, yf) device tensors; prms: one KotParams or a list of them."""
+        nprob = len(problems)
+        probs = (KotProblem * nprob)()
+        for i, (xs, ys, xf, yf) in enumerate(problems):
+            l, dd = xf.shape
+            probs[i] = KotProblem(xs.shape[0], ys.shape[0], dd, l, _ptr(xs), _ptr(ys), _ptr(xf), _ptr(yf))
+        plist = prms if isinstance(prms, (list, tuple)) else [prms]
+        parr = (KotParams * len(plist))(*plist)
+        outs = [self._result(xf.shape[0], xf.device, False, hist_cap) for (_, _, xf, _) in problems]
+        res = (KotResult * nprob)(*[o[4] for o in outs])
+        st = (C.c_int * nprob)()
+        self._check(self.lib.kot_solve_batched(self.h, nprob, probs, parr, len(plist), None, res, st, int(lanes)),
+                    (KOT_OK, KOT_NOT_CONVERGED))
+        return [(outs[i][0], self._pack(st[i], res[i], outs[i][2], outs[i][3])) for i in range(nprob)]
+
+    def autotune(self, sizes, path=None):
+        arr = (C.c_int * len(sizes))(*sizes)
+        out = (C.c_int * 33)()
+        self._check(self.lib.kot_autotune(self.h, arr, len(sizes), path.encode() if path else None, out))
+        return list(out)
+
+    def autotune_load(self, path):
+        self._check(self.lib.kot_autotune_load(self.h, str(path).encode()))
+
     def solve_core(self, Q, z, R, q2, wsum, prm: KotParams, gamma0=None, want_X=False, hist_cap=1024):
         l = Q.shape[0]
         gamma, X, rh, rvh, res = self._result(l, Q.device, want_X, hist_cap)
@@ -321,7 +349,7 @@ class Context:
         self._check(self.lib.kot_warmstart(self.h, C.byref(pb), C.byref(prm), N_FEATURES, H, _fptr(theta), _ptr(g0)))
         return g0
 
-    PROFILE_CLASSES = ("gemm_f64", "eig_round", "reserved", "gemm_f32", "gemm_bf16")
+    PROFILE_CLASSES = ("gemm_f64", "eig_sweep", "reserved", "gemm_f32", "gemm_bf16")
 
     def profile_start(self):
         self._check(self.lib.kot_profile(self.h, 1, None, 0))
