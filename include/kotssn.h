@@ -140,8 +140,10 @@ kot_status kot_solve_batched(kot_ctx* ctx, int nprob, const kot_problem* probs, 
 kot_status kot_autotune(kot_ctx* ctx, const int* sizes, int nsizes, const char* path, int* table_out);
 kot_status kot_autotune_load(kot_ctx* ctx, const char* path);
 
-/* Algorithm 2 on given dual data (Eq. 3.4): Q, z, R (any factor with R^T R = K), wsum (device) and q2
- * (host).  prm->sigma is ignored. */
+/* Algorithm 2 on given dual data (Eq. 3.4): Q, z, R (the upper-triangular factor with R^T R = K, as
+ * kot_setup / kot_cholesky return it), wsum (device) and q2 (host).  prm->sigma is ignored.  Here and in
+ * kot_residual, kot_ssn_direction, kot_eg_step and kot_features, an R with a nonzero entry below its
+ * diagonal is rejected with KOT_ERR_ARG (the products with R skip its zero triangle). */
 kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, double q2,
                           const double* wsum, const kot_params* prm, const double* gamma0, kot_result* res);
 
@@ -211,7 +213,7 @@ kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* prob, const kot_params
  * writes 4 values per class into out (host, 4 * nclass doubles; may be NULL): launches, total milliseconds
  * between the events, algorithmic flops and algorithmic bytes.  Classes: 0 = FP64 GEMM (2mnk flops),
  * 1 = one Jacobi sweep (all rounds of pair solves + tile updates, replayed as one captured HIP graph; flops of
- * the 16x16 tile products), 2 = reserved,
+ * the 16x16 tile products), 2 = FP64 matrix-vector product (2mk flops, bytes of the matrix and vectors),
  * 3 = FP32 chain GEMM, 4 = BF16 chain GEMM (2mnk flops each). */
 kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass);
 

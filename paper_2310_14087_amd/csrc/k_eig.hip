@@ -4,14 +4,19 @@
 // every pair of blocks meets once per sweep.  In one round the pairs are disjoint:
 //   1. pair_solve: one wavefront per pair loads its 16x16 subproblem into LDS and diagonalizes it with
 //      cyclic scalar Jacobi (8 disjoint rotations at a time), giving an orthogonal 16x16 U;
-//   2. apply_A / apply_V: A <- G^T A G and V <- V G with G the block-diagonal of the U's, each 16x16 tile
+//   2. apply (one launch): A <- G^T A G and V <- V G with G the block-diagonal of the U's, each 16x16 tile
 //      updated by two 16x16x16 products on the matrix cores (v_mfma_f64_16x16x4f64; accumulator lane L
 //      holds rows L/16 + 4v, v = 0..3, of column L%16).
-// Sweeps repeat until off(A) <= tol * |A|_F; the eigenvalues are diag(A), sorted ascending with V's
-// columns permuted alongside.  A warm start replaces (Z, I) by (P0^T Z P0, P0).
+// Sweeps repeat until off(A) <= tol * |A|_F, measured from the norms of the 8x8 blocks.  When few block
+// pairs carry off-diagonal mass above a threshold (tau, chosen so that all pairs below it already satisfy the
+// stopping test), a sweep rotates only those: they are packed into rounds of disjoint pairs, completed to a
+// partition of the blocks by pairs that rotate nothing; otherwise the sweep is the full tournament, captured
+// once per size as a HIP graph.  The eigenvalues are diag(A), sorted ascending (by ranks) with V's columns
+// permuted alongside.  A warm start replaces (Z, I) by (P0^T Z P0, P0).
 #include "kot_internal.h"
-#include <vector>
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace kot {
 
@@ -26,15 +31,37 @@ __device__ __forceinline__ int pair_slot_index(int p, int q, int s, int l) {
   return (g < l) ? g : -1;
 }
 
+// Round-robin tournament over nb (even) blocks, circle method: in round r < nb - 1, pair 0 = (nb-1, r) and
+// pair k = ((r + k) mod (nb-1), (r - k) mod (nb-1)); every pair of blocks meets once in nb - 1 rounds.
+__device__ __forceinline__ int2 round_pair(int r, int k, int nb) {
+  const int m = nb - 1;
+  if (k == 0) return make_int2(m, r);
+  int a = r + k, b = r - k;
+  if (a >= m) a -= m;
+  if (b < 0) b += m;
+  return make_int2(a, b);
+}
+
+// Pair k of a round: from the tournament formula, or from an explicit list (threshold sweeps).
+__device__ __forceinline__ int2 get_pair(int round, int nb, const int2* __restrict__ list, int k) {
+  return list ? list[k] : round_pair(round, k, nb);
+}
+
 // 16-player circle ordering: in sub-round r, pair 0 = (15, r), pair k = ((r+k)%15, (r-k+15)%15).
 __device__ __forceinline__ void circle16(int r, int k, int& a, int& b) {
   if (k == 0) { a = 15; b = r; }
   else { a = (r + k) % 15; b = (r - k + 15) % 15; }
 }
 
-__global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __restrict__ A, const int2* __restrict__ pairs,
+// With an explicit list, pairs k >= kact only complete the partition of the blocks: they rotate nothing.
+__global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __restrict__ A, int round, int nb,
+                                                        const int2* __restrict__ list, int kact,
                                                         double* __restrict__ Uout, int* __restrict__ flag,
                                                         const double* __restrict__ thresh_ptr, int max_inner) {
+  if (list && (int)blockIdx.x >= kact) {
+    if (threadIdx.x == 0) flag[blockIdx.x] = 0;
+    return;
+  }
   const double thresh = *thresh_ptr;
   __shared__ double S[SLOT][SLOT + 1];
   __shared__ double U[SLOT][SLOT + 1];
@@ -42,15 +69,23 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
   __shared__ int idx[SLOT];
   __shared__ int any_rot;
   const int k = blockIdx.x;
-  const int2 pq = pairs[k];
+  const int2 pq = get_pair(round, nb, list, k);
   const int lane = threadIdx.x;
   if (lane < SLOT) idx[lane] = pair_slot_index(pq.x, pq.y, lane, l);
   if (lane == 0) any_rot = 0;
   __syncthreads();
-  for (int u = lane; u < SLOT * SLOT; u += 64) {
-    const int i = u >> 4, j = u & 15;
+  // the four loads of a lane are issued together (register buffer), then staged
+  double sv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q, i = u >> 4, j = u & 15;
     const int gi = idx[i], gj = idx[j];
-    S[i][j] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
+    sv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q, i = u >> 4, j = u & 15;
+    S[i][j] = sv[q];
     U[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -98,7 +133,7 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
         }
       }
       __syncthreads();
-      // rows: S <- J^T S
+      // rows: S <- J^T S; the annihilated pair (a, b), (b, a) is set to zero exactly
       for (int u = lane; u < 128; u += 64) {
         const int col = u >> 3, pk = u & 7;
         int a, b;
@@ -107,15 +142,9 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
         const double c = cs[pk][0], s = cs[pk][1];
         if (s != 0.0) {
           const double x = S[a][col], y = S[b][col];
-          S[a][col] = c * x - s * y;
-          S[b][col] = s * x + c * y;
+          S[a][col] = (col == b) ? 0.0 : c * x - s * y;
+          S[b][col] = (col == a) ? 0.0 : s * x + c * y;
         }
-      }
-      __syncthreads();
-      if (lane < 8) {
-        int a, b;
-        circle16(r, lane, a, b);
-        if (cs[lane][1] != 0.0) { S[a][b] = 0.0; S[b][a] = 0.0; }
       }
       __syncthreads();
     }
@@ -125,41 +154,60 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
   if (lane == 0) flag[k] = any_rot;
 }
 
-// A_PQ <- U_P^T A_PQ U_Q for every pair-block tile (P, Q).
-__global__ __launch_bounds__(64) void apply_A_kernel(int l, double* __restrict__ A, const int2* __restrict__ pairs,
-                                                     const double* __restrict__ Ub, const int* __restrict__ flag) {
-  const int P = blockIdx.y, Qb = blockIdx.x;
-  if (!flag[P] && !flag[Qb]) return;
+// A_PQ <- U_P^T A_PQ U_Q for the pair-block tile (P, Q); a pair without rotations (flag 0) acts as the
+// identity, so its U is not read.
+__device__ __forceinline__ void apply_A_tile(int l, double* __restrict__ A, int round, int nb, const int2* __restrict__ list,
+                                             const double* __restrict__ Ub, const int* __restrict__ flag, int P, int Qb) {
+  const bool fP = flag[P] != 0, fQ = flag[Qb] != 0;
+  if (!fP && !fQ) return;
   __shared__ double M[SLOT][SLOT + 1];
   __shared__ double T[SLOT][SLOT + 1];
   __shared__ int ip[SLOT], iq[SLOT];
   const int lane = threadIdx.x;
-  const int2 pp = pairs[P], qq = pairs[Qb];
+  const int2 pp = get_pair(round, nb, list, P), qq = get_pair(round, nb, list, Qb);
   if (lane < SLOT) {
     ip[lane] = pair_slot_index(pp.x, pp.y, lane, l);
     iq[lane] = pair_slot_index(qq.x, qq.y, lane, l);
   }
   __syncthreads();
-  for (int u = lane; u < SLOT * SLOT; u += 64) {
-    const int i = u >> 4, j = u & 15;
+  double mv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q, i = u >> 4, j = u & 15;
     const int gi = ip[i], gj = iq[j];
-    M[i][j] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
+    mv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q;
+    M[u >> 4][u & 15] = mv[q];
   }
   __syncthreads();
   const double* UP = Ub + (long long)P * SLOT * SLOT;
   const double* UQ = Ub + (long long)Qb * SLOT * SLOT;
   const int r16 = lane & 15, k4 = lane >> 4;
-  dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (fQ) {
+    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int ks = 0; ks < SLOT; ks += 4)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UQ[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
+    for (int ks = 0; ks < SLOT; ks += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UQ[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = acc[v];
+    for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = acc[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = M[k4 + 4 * v][r16];
+  }
   __syncthreads();
-  dbl4 acc2 = dbl4{0.0, 0.0, 0.0, 0.0};
+  dbl4 acc2;
+  if (fP) {
+    acc2 = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int ks = 0; ks < SLOT; ks += 4)
-    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(UP[(ks + k4) * SLOT + r16], T[ks + k4][r16], acc2, 0, 0, 0);
+    for (int ks = 0; ks < SLOT; ks += 4)
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(UP[(ks + k4) * SLOT + r16], T[ks + k4][r16], acc2, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc2[v] = T[k4 + 4 * v][r16];
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int gi = ip[k4 + 4 * v], gj = iq[r16];
@@ -167,22 +215,27 @@ __global__ __launch_bounds__(64) void apply_A_kernel(int l, double* __restrict__
   }
 }
 
-// V[R, idx_P] <- V[R, idx_P] U_P for 16-row slabs R.
-__global__ __launch_bounds__(64) void apply_V_kernel(int l, double* __restrict__ V, const int2* __restrict__ pairs,
-                                                     const double* __restrict__ Ub, const int* __restrict__ flag) {
-  const int P = blockIdx.y;
+// V[R, idx_P] <- V[R, idx_P] U_P for the 16-row slab R starting at r0.
+__device__ __forceinline__ void apply_V_slab(int l, double* __restrict__ V, int round, int nb, const int2* __restrict__ list,
+                                             const double* __restrict__ Ub, const int* __restrict__ flag, int P, int r0) {
   if (!flag[P]) return;
-  const int r0 = blockIdx.x * SLOT;
   __shared__ double M[SLOT][SLOT + 1];
   __shared__ int ip[SLOT];
   const int lane = threadIdx.x;
-  const int2 pp = pairs[P];
+  const int2 pp = get_pair(round, nb, list, P);
   if (lane < SLOT) ip[lane] = pair_slot_index(pp.x, pp.y, lane, l);
   __syncthreads();
-  for (int u = lane; u < SLOT * SLOT; u += 64) {
-    const int i = u >> 4, j = u & 15;
+  double mv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q, i = u >> 4, j = u & 15;
     const int gj = ip[j];
-    M[i][j] = (r0 + i < l && gj >= 0) ? V[(long long)(r0 + i) * l + gj] : 0.0;
+    mv[q] = (r0 + i < l && gj >= 0) ? V[(long long)(r0 + i) * l + gj] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q;
+    M[u >> 4][u & 15] = mv[q];
   }
   __syncthreads();
   const double* UP = Ub + (long long)P * SLOT * SLOT;
@@ -198,39 +251,36 @@ __global__ __launch_bounds__(64) void apply_V_kernel(int l, double* __restrict__
   }
 }
 
-// part[b] = (sum of off-diagonal squares, sum of all squares) over a grid-stride slice; fixed order.
-__global__ __launch_bounds__(256) void offnorm_part_kernel(int l, const double* __restrict__ A, double* __restrict__ part) {
-  __shared__ double r0[256], r1[256];
-  const long long nn = (long long)l * l;
-  double off = 0.0, all = 0.0;
-  for (long long u = (long long)blockIdx.x * 256 + threadIdx.x; u < nn; u += (long long)gridDim.x * 256) {
-    const double v = A[u];
-    const int i = (int)(u / l), j = (int)(u % l);
-    all += v * v;
-    if (i != j) off += v * v;
-  }
-  r0[threadIdx.x] = off;
-  r1[threadIdx.x] = all;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) { r0[threadIdx.x] += r0[threadIdx.x + h]; r1[threadIdx.x] += r1[threadIdx.x + h]; }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) { part[2 * blockIdx.x] = r0[0]; part[2 * blockIdx.x + 1] = r1[0]; }
+// One launch per round for both updates (A and V are separate arrays): workgroups x < np take the A tiles
+// (P = y, Q = x), the rest take the 16-row slabs of V for pair y.
+__global__ __launch_bounds__(64) void apply_kernel(int l, int np, double* __restrict__ A, double* __restrict__ V,
+                                                   int round, int nb, const int2* __restrict__ list,
+                                                   const double* __restrict__ Ub, const int* __restrict__ flag) {
+  const int P = blockIdx.y;
+  if ((int)blockIdx.x < np) apply_A_tile(l, A, round, nb, list, Ub, flag, P, blockIdx.x);
+  else apply_V_slab(l, V, round, nb, list, Ub, flag, P, ((int)blockIdx.x - np) * SLOT);
 }
 
-__global__ __launch_bounds__(256) void offnorm_final_kernel(int nb, const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double r0[256], r1[256];
-  double off = 0.0, all = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) { off += part[2 * b]; all += part[2 * b + 1]; }
-  r0[threadIdx.x] = off;
-  r1[threadIdx.x] = all;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) { r0[threadIdx.x] += r0[threadIdx.x + h]; r1[threadIdx.x] += r1[threadIdx.x + h]; }
-    __syncthreads();
+// Squared Frobenius norms of the 8 x 8 blocks (b1, b2), b1 <= b2 (A symmetric): boff = off-diagonal part,
+// ball = all entries, counted twice for b1 < b2 so that the sums over b1 <= b2 are the norms of A.
+__global__ __launch_bounds__(64) void block_norm_kernel(int l, int nb, const double* __restrict__ A,
+                                                        double* __restrict__ boff, double* __restrict__ ball) {
+  const int b1 = blockIdx.y, b2 = blockIdx.x;
+  if (b2 < b1) return;
+  const int t = threadIdx.x;
+  const int i = b1 * BSZ + (t >> 3), j = b2 * BSZ + (t & 7);
+  const double v = (i < l && j < l) ? A[(long long)i * l + j] : 0.0;
+  double off = (i != j) ? v * v : 0.0;
+  double all = (b1 < b2 ? 2.0 : 1.0) * v * v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_xor(off, o);
+    all += __shfl_xor(all, o);
   }
-  if (threadIdx.x == 0) { out[0] = sqrt(r0[0]); out[1] = sqrt(r1[0]); }
+  if (t == 0) {
+    boff[(long long)b1 * nb + b2] = off;
+    ball[(long long)b1 * nb + b2] = all;
+  }
 }
 
 __global__ void eye_kernel(int l, double* __restrict__ V) {
@@ -239,33 +289,53 @@ __global__ void eye_kernel(int l, double* __restrict__ V) {
   V[u] = ((u / l) == (u % l)) ? 1.0 : 0.0;
 }
 
-// Single-workgroup bitonic sort of (diag(A), index) ascending; writes w and perm.
-__global__ __launch_bounds__(1024) void sort_diag_kernel(int l, int npow2, const double* __restrict__ A, double* __restrict__ w,
-                                                         int* __restrict__ perm) {
-  extern __shared__ unsigned char smem[];
-  double* key = reinterpret_cast<double*>(smem);
-  int* val = reinterpret_cast<int*>(key + npow2);
-  for (int i = threadIdx.x; i < npow2; i += blockDim.x) {
-    key[i] = (i < l) ? A[(long long)i * l + i] : INFINITY;
-    val[i] = i;
-  }
-  __syncthreads();
-  for (int size = 2; size <= npow2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < npow2; i += blockDim.x) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool up = ((i & size) == 0);
-          const double ki = key[i], kj = key[j];
-          const int vi = val[i], vj = val[j];
-          const bool gt = (ki > kj) || (ki == kj && vi > vj);
-          if (gt == up) { key[i] = kj; key[j] = ki; val[i] = vj; val[j] = vi; }
-        }
-      }
-      __syncthreads();
+// Ascending order of diag(A) by ranks: element i goes to position #{j : k_j < k_i, or k_j == k_i and j < i}
+// (keys ordered totally, NaN as +inf, so the positions are a permutation).  Workgroup b ranks elements
+// 64 b .. 64 b + 63; its four waves count over four quarters of the keys, staged in LDS (l <= 4096).
+__global__ __launch_bounds__(256) void rank_sort_kernel(int l, const double* __restrict__ A, double* __restrict__ w,
+                                                        int* __restrict__ perm) {
+  __shared__ double key[4096];
+  __shared__ int cnt[4][64];
+  const int t = threadIdx.x;
+  for (int j0 = 0; j0 < l; j0 += 4 * 256) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + t + 256 * q;
+      v[q] = (j < l) ? A[(long long)j * l + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + t + 256 * q;
+      if (j < l) key[j] = isnan(v[q]) ? INFINITY : v[q];
     }
   }
-  for (int i = threadIdx.x; i < l; i += blockDim.x) { w[i] = key[i]; perm[i] = val[i]; }
+  __syncthreads();
+  const int il = t & 63, part = t >> 6;
+  const int i = blockIdx.x * 64 + il;
+  const double ki = (i < l) ? key[i] : 0.0;
+  const int per = (l + 3) / 4;
+  const int jb = part * per, je = min(l, jb + per);
+  int c = 0;
+  int j = jb;
+  for (; j + 16 <= je; j += 16) {  // sixteen LDS reads in flight per pass
+    double kj[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) kj[q] = key[j + q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) c += (kj[q] < ki || (kj[q] == ki && j + q < i)) ? 1 : 0;
+  }
+  for (; j < je; ++j) {
+    const double kj = key[j];
+    c += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+  }
+  cnt[part][il] = c;
+  __syncthreads();
+  if (part == 0 && i < l) {
+    const int r = cnt[0][il] + cnt[1][il] + cnt[2][il] + cnt[3][il];
+    w[r] = A[(long long)i * l + i];
+    perm[r] = i;
+  }
 }
 
 __global__ void permute_cols_kernel(int l, const double* __restrict__ V, const int* __restrict__ perm, double* __restrict__ P) {
@@ -279,33 +349,45 @@ __global__ void permute_cols_kernel(int l, const double* __restrict__ V, const i
 
 struct EigWork {
   int lmax = 0;
-  // one captured sweep (all rounds) per (l, A/V buffers); replayed with hipGraphLaunch
+  // one captured full-tournament sweep (all rounds) per (l, A/V buffers); replayed with hipGraphLaunch
   int graph_l = -1;
   const double* graph_tmp = nullptr;
   hipGraphExec_t graph = nullptr;
   bool graph_failed = false;
-  int nb = -1;                // block count of the current pair table
-  int2* pairs = nullptr;      // device [(nb-1) * nb/2]
   double* U = nullptr;        // device [npairs_max * 256]
   int* flag = nullptr;        // device [npairs_max]
-  double* part = nullptr;     // device [2 * 512]
-  double* norms = nullptr;    // device [4]: off, |A|_F, rotation threshold
+  double* norms = nullptr;    // device [4]: slot 2 = rotation threshold
   double* hnorms = nullptr;   // pinned host [4]
   int* perm = nullptr;        // device [lmax]
+  double* boff = nullptr;     // device [nbmax^2] block norms (off-diagonal part), then all entries
+  double* hb = nullptr;       // pinned host copy [2 * nbmax^2]
+  int2* list = nullptr;       // device pair lists of a threshold sweep [(nbmax - 1) * nbmax / 2]
+  int2* hlist = nullptr;      // pinned host staging of the lists
+  std::vector<int> round_k;   // active pairs per round of the current threshold sweep
 };
+static int block_count(int l) {
+  int nb = (l + BSZ - 1) / BSZ;
+  if (nb < 2) nb = 2;
+  if (nb & 1) ++nb;
+  return nb;
+}
 
 EigWork* eig_work_create(int lmax) {
   EigWork* w = new EigWork();
   w->lmax = lmax;
-  const int nbmax = ((lmax + BSZ - 1) / BSZ + 1) & ~1;
+  const int nbmax = block_count(lmax);
   const int npm = nbmax / 2;
-  bool ok = hipMalloc(&w->pairs, sizeof(int2) * (size_t)(nbmax) * npm + 16) == hipSuccess &&
-            hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256) == hipSuccess &&
+  const size_t nb2 = (size_t)nbmax * nbmax;
+  const size_t nlist = (size_t)(nbmax - 1) * npm;
+  bool ok = hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256) == hipSuccess &&
             hipMalloc(&w->flag, sizeof(int) * (size_t)npm) == hipSuccess &&
-            hipMalloc(&w->part, sizeof(double) * 1024) == hipSuccess &&
             hipMalloc(&w->norms, sizeof(double) * 4) == hipSuccess &&
             hipHostMalloc(&w->hnorms, sizeof(double) * 4) == hipSuccess &&
-            hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess;
+            hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess &&
+            hipMalloc(&w->boff, sizeof(double) * 2 * nb2) == hipSuccess &&
+            hipHostMalloc(&w->hb, sizeof(double) * 2 * nb2) == hipSuccess &&
+            hipMalloc(&w->list, sizeof(int2) * nlist) == hipSuccess &&
+            hipHostMalloc(&w->hlist, sizeof(int2) * nlist) == hipSuccess;
   if (!ok) { eig_work_destroy(w); return nullptr; }
   return w;
 }
@@ -313,42 +395,101 @@ EigWork* eig_work_create(int lmax) {
 void eig_work_destroy(EigWork* w) {
   if (!w) return;
   if (w->graph) hipGraphExecDestroy(w->graph);
-  hipFree(w->pairs); hipFree(w->U); hipFree(w->flag); hipFree(w->part); hipFree(w->norms);
-  hipHostFree(w->hnorms); hipFree(w->perm);
+  hipFree(w->U); hipFree(w->flag); hipFree(w->norms); hipHostFree(w->hnorms); hipFree(w->perm);
+  hipFree(w->boff); hipHostFree(w->hb); hipFree(w->list); hipHostFree(w->hlist);
   delete w;
 }
 
-static hipError_t ensure_pairs(EigWork* w, int nb, hipStream_t st) {
-  if (w->nb == nb) return hipSuccess;
-  const int np = nb / 2;
-  std::vector<int2> h((size_t)(nb - 1) * np);
-  for (int r = 0; r < nb - 1; ++r) {
-    for (int k = 0; k < np; ++k) {
-      int a, b;
-      if (k == 0) { a = nb - 1; b = r; }
-      else { a = (r + k) % (nb - 1); b = (r - k + (nb - 1)) % (nb - 1); }
-      h[(size_t)r * np + k] = make_int2(a, b);
-    }
-  }
-  KOT_HIP_TRY(hipMemcpyAsync(w->pairs, h.data(), sizeof(int2) * h.size(), hipMemcpyHostToDevice, st));
+// Block norms of A to the host; returns off(A) and |A|_F (sums in a fixed order on the host).
+static hipError_t block_norms(EigWork* w, int l, int nb, const double* A, hipStream_t st, double* off, double* all) {
+  const size_t nb2 = (size_t)nb * nb;
+  hipLaunchKernelGGL(block_norm_kernel, dim3(nb, nb), dim3(64), 0, st, l, nb, A, w->boff, w->boff + nb2);
+  KOT_HIP_TRY(hipGetLastError());
+  KOT_HIP_TRY(hipMemcpyAsync(w->hb, w->boff, sizeof(double) * 2 * nb2, hipMemcpyDeviceToHost, st));
   KOT_HIP_TRY(hipStreamSynchronize(st));
-  w->nb = nb;
+  double so = 0.0, sa = 0.0;
+  for (int b1 = 0; b1 < nb; ++b1)
+    for (int b2 = b1; b2 < nb; ++b2) {
+      const size_t u = (size_t)b1 * nb + b2;
+      so += (b2 > b1 ? 2.0 : 1.0) * w->hb[u];
+      sa += w->hb[nb2 + u];
+    }
+  *off = std::sqrt(so);
+  *all = std::sqrt(sa);
   return hipSuccess;
 }
 
-static hipError_t off_norm(EigWork* w, int l, const double* A, hipStream_t st, double* off, double* all) {
-  const long long nn = (long long)l * l;
-  int nbk = (int)((nn + 255) / 256);
-  if (nbk > 512) nbk = 512;
-  hipLaunchKernelGGL(offnorm_part_kernel, dim3(nbk), dim3(256), 0, st, l, A, w->part);
-  KOT_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(offnorm_final_kernel, dim3(1), dim3(256), 0, st, nbk, w->part, w->norms);
-  KOT_HIP_TRY(hipGetLastError());
-  KOT_HIP_TRY(hipMemcpyAsync(w->hnorms, w->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  KOT_HIP_TRY(hipStreamSynchronize(st));
-  *off = w->hnorms[0];
-  *all = w->hnorms[1];
-  return hipSuccess;
+// Threshold sweep schedule: block pairs whose off-diagonal norm exceeds tau (and blocks with internal
+// off-diagonal mass) are packed greedily, largest first, into rounds of disjoint pairs; each round is then
+// completed to a partition of all blocks by pairs that rotate nothing.  Returns false (no schedule) when the
+// active set is too large for this to beat the full tournament.
+static bool threshold_schedule(EigWork* w, int nb, double tau2) {
+  const size_t nb2 = (size_t)nb * nb;
+  struct E { double v; int a, b; };
+  std::vector<E> edges;
+  std::vector<char> self(nb, 0);
+  for (int b1 = 0; b1 < nb; ++b1) {
+    if (w->hb[(size_t)b1 * nb + b1] > tau2) self[b1] = 1;
+    for (int b2 = b1 + 1; b2 < nb; ++b2) {
+      const double v = w->hb[(size_t)b1 * nb + b2];
+      if (v > tau2) edges.push_back({v, b1, b2});
+    }
+  }
+  const int np = nb / 2, maxr = nb - 1;
+  if ((long long)edges.size() > (long long)np * maxr / 4) return false;
+  std::stable_sort(edges.begin(), edges.end(), [](const E& x, const E& y) { return x.v > y.v; });
+  std::vector<std::vector<char>> used;
+  std::vector<std::vector<int2>> rounds;
+  std::vector<char> covered(nb, 0);
+  auto place = [&](int a, int b) -> bool {
+    size_t r = 0;
+    while (r < rounds.size() && (used[r][a] || used[r][b])) ++r;
+    if (r == rounds.size()) {
+      if ((int)r >= maxr / 2) return false;
+      rounds.emplace_back();
+      used.emplace_back(nb, 0);
+    }
+    rounds[r].push_back(make_int2(a, b));
+    used[r][a] = used[r][b] = 1;
+    covered[a] = covered[b] = 1;
+    return true;
+  };
+  for (const E& e : edges)
+    if (!place(e.a, e.b)) return false;
+  for (int b = 0; b < nb; ++b) {
+    if (!self[b] || covered[b]) continue;
+    // pair b with the first block free in the first round where b is free (another uncovered block if any)
+    size_t r = 0;
+    while (r < rounds.size() && used[r][b]) ++r;
+    int partner = -1;
+    if (r < rounds.size()) {
+      for (int c = 0; c < nb && partner < 0; ++c)
+        if (c != b && !used[r][c] && self[c] && !covered[c]) partner = c;
+      for (int c = 0; c < nb && partner < 0; ++c)
+        if (c != b && !used[r][c]) partner = c;
+    } else {
+      for (int c = 0; c < nb && partner < 0; ++c)
+        if (c != b && self[c] && !covered[c]) partner = c;
+      if (partner < 0) partner = (b == 0) ? 1 : 0;
+    }
+    if (!place(std::min(b, partner), std::max(b, partner))) return false;
+  }
+  if (rounds.empty()) return false;
+  w->round_k.assign(rounds.size(), 0);
+  for (size_t r = 0; r < rounds.size(); ++r) {
+    int2* dst = w->hlist + r * np;
+    int k = 0;
+    for (const int2& pr : rounds[r]) dst[k++] = pr;
+    w->round_k[r] = k;
+    int pending = -1;
+    for (int b = 0; b < nb; ++b) {
+      if (used[r][b]) continue;
+      if (pending < 0) pending = b;
+      else { dst[k++] = make_int2(pending, b); pending = -1; }
+    }
+  }
+  (void)nb2;
+  return true;
 }
 
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
@@ -365,74 +506,85 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     g.A = Z; g.lda = l; g.B = P0; g.ldb = l; g.C = V; g.ldc = l; g.batch = 1;
     KOT_HIP_TRY(gemm_f64(g, st));
     g.transa = 1; g.A = P0; g.B = V; g.C = A;
+    g.lower = 1; g.mirror = 1;  // symmetric result: lower tiles, mirrored
     KOT_HIP_TRY(gemm_f64(g, st));
-    KOT_HIP_TRY(symmetrize(l, A, st));
     KOT_HIP_TRY(hipMemcpyAsync(V, P0, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
   } else {
     KOT_HIP_TRY(hipMemcpyAsync(A, Z, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(eye_kernel, dim3(eb), dim3(256), 0, st, l, V);
     KOT_HIP_TRY(hipGetLastError());
   }
-  int nb = (l + BSZ - 1) / BSZ;
-  if (nb < 2) nb = 2;
-  if (nb & 1) ++nb;
-  KOT_HIP_TRY(ensure_pairs(w, nb, st));
+  const int nb = block_count(l);
   const int np = nb / 2;
+  const int nslab = (l + SLOT - 1) / SLOT;
   double off = 0.0, all = 0.0;
-  KOT_HIP_TRY(off_norm(w, l, A, st, &off, &all));
+  KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all));
   int s = 0;
   const double thresh_rel = 1e-18;
+  auto launch_round = [&](hipStream_t s_, int r, const int2* list, int kact) -> hipError_t {
+    hipLaunchKernelGGL(pair_solve_kernel, dim3(np), dim3(64), 0, s_, l, A, r, nb, list, kact, w->U, w->flag,
+                       w->norms + 2, 8);
+    KOT_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(apply_kernel, dim3(np + nslab, np), dim3(64), 0, s_, l, np, A, V, r, nb, list, w->U, w->flag);
+    return hipGetLastError();
+  };
   auto launch_sweep = [&](hipStream_t s_) -> hipError_t {
-    for (int r = 0; r < nb - 1; ++r) {
-      const int2* pr = w->pairs + (size_t)r * np;
-      hipLaunchKernelGGL(pair_solve_kernel, dim3(np), dim3(64), 0, s_, l, A, pr, w->U, w->flag, w->norms + 2, 8);
-      KOT_HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(apply_A_kernel, dim3(np, np), dim3(64), 0, s_, l, A, pr, w->U, w->flag);
-      KOT_HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(apply_V_kernel, dim3((l + SLOT - 1) / SLOT, np), dim3(64), 0, s_, l, V, pr, w->U, w->flag);
-      KOT_HIP_TRY(hipGetLastError());
-    }
+    for (int r = 0; r < nb - 1; ++r) KOT_HIP_TRY(launch_round(s_, r, nullptr, np));
     return hipSuccess;
   };
-  // flops of one sweep: per round 2 x 2 x 16^3 per A tile and 2 x 16^3 per V tile
-  const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * ((l + SLOT - 1) / SLOT) * np);
+  // flops of one full sweep: per round 2 x 2 x 16^3 per A tile and 2 x 16^3 per V tile
+  const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * nslab * np);
+  const double npairs = 0.5 * nb * (nb + 1.0);
   while (off > tol * all && s < max_sweeps) {
     w->hnorms[2] = thresh_rel * all;
     KOT_HIP_TRY(hipMemcpyAsync(w->norms + 2, w->hnorms + 2, sizeof(double), hipMemcpyHostToDevice, st));
-    if (!w->graph_failed && (w->graph == nullptr || w->graph_l != l || w->graph_tmp != tmp)) {
-      if (w->graph) { hipGraphExecDestroy(w->graph); w->graph = nullptr; }
-      hipGraph_t gr = nullptr;
-      bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
-      if (ok) {
-        const hipError_t le = launch_sweep(st);
-        ok = hipStreamEndCapture(st, &gr) == hipSuccess && le == hipSuccess && gr != nullptr;
-      }
-      if (ok) ok = hipGraphInstantiate(&w->graph, gr, nullptr, nullptr, 0) == hipSuccess;
-      if (gr) hipGraphDestroy(gr);
-      if (!ok) {
-        (void)hipGetLastError();
-        w->graph = nullptr;
-        w->graph_failed = true;
-      } else {
-        w->graph_l = l;
-        w->graph_tmp = tmp;
-      }
-    }
     Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
-    if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, 32.0 * l * (double)l * (nb - 1));
-    if (w->graph) KOT_HIP_TRY(hipGraphLaunch(w->graph, st));
-    else KOT_HIP_TRY(launch_sweep(st));
-    if (pf) pf->end(st);
+    // threshold sweep over the block pairs above tau; if every pair is at or below tau, then
+    // off(A)^2 <= npairs tau^2 = (tol |A|_F / 2)^2, so the stopping test is met
+    const double tau2 = 0.25 * tol * tol * all * all / npairs;
+    if (threshold_schedule(w, nb, tau2)) {
+      const int R = (int)w->round_k.size();
+      KOT_HIP_TRY(hipMemcpyAsync(w->list, w->hlist, sizeof(int2) * (size_t)R * np, hipMemcpyHostToDevice, st));
+      double fl = 0.0;
+      for (int r = 0; r < R; ++r) {
+        const double k = w->round_k[r];
+        fl += 8192.0 * (2.0 * k * k + 2.0 * k * (np - k) + k * nslab);
+      }
+      if (pf) pf->begin(st, PROF_EIG_ROUND, fl, 0.0);
+      for (int r = 0; r < R; ++r) KOT_HIP_TRY(launch_round(st, 0, w->list + (size_t)r * np, w->round_k[r]));
+      if (pf) pf->end(st);
+    } else {
+      if (!w->graph_failed && (w->graph == nullptr || w->graph_l != l || w->graph_tmp != tmp)) {
+        if (w->graph) { hipGraphExecDestroy(w->graph); w->graph = nullptr; }
+        hipGraph_t gr = nullptr;
+        bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+          const hipError_t le = launch_sweep(st);
+          ok = hipStreamEndCapture(st, &gr) == hipSuccess && le == hipSuccess && gr != nullptr;
+        }
+        if (ok) ok = hipGraphInstantiate(&w->graph, gr, nullptr, nullptr, 0) == hipSuccess;
+        if (gr) hipGraphDestroy(gr);
+        if (!ok) {
+          (void)hipGetLastError();
+          w->graph = nullptr;
+          w->graph_failed = true;
+        } else {
+          w->graph_l = l;
+          w->graph_tmp = tmp;
+        }
+      }
+      if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, 32.0 * l * (double)l * (nb - 1));
+      if (w->graph) KOT_HIP_TRY(hipGraphLaunch(w->graph, st));
+      else KOT_HIP_TRY(launch_sweep(st));
+      if (pf) pf->end(st);
+    }
     ++s;
-    KOT_HIP_TRY(off_norm(w, l, A, st, &off, &all));
+    KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all));
   }
   *sweeps = s;
   *rel_off = (all > 0.0) ? off / all : 0.0;
-  int npow2 = 1;
-  while (npow2 < l) npow2 <<= 1;
-  const size_t sm = (size_t)npow2 * (sizeof(double) + sizeof(int));
-  if (sm > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sort_diag_kernel, dim3(1), dim3(1024), sm, st, l, npow2, A, wv, w->perm);
+  if (l > 4096) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 63) / 64), dim3(256), 0, st, l, A, wv, w->perm);
   KOT_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, V, w->perm, P);
   return hipGetLastError();

@@ -107,12 +107,20 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, i
   const double* __restrict__ S = SC ? g.s + bz * g.sS : nullptr;
   double* __restrict__ C = g.C + bz * g.sC;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (g.lower && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal (uniform per workgroup)
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int kbeg = sp * kchunk;
-  const int kend = min(g.k, kbeg + kchunk);
-  const int nk = (kend - kbeg + BK - 1) / BK;
+  // K range of this split, narrowed to where the triangular operands can be nonzero for this tile
+  int klo = 0, khi = g.k;
+  if (g.tri & 1) klo = max(klo, m0);            // op(A) upper: op(A)[m][k] = 0 for k < m
+  if (g.tri & 8) klo = max(klo, n0);            // op(B) lower: op(B)[k][n] = 0 for k < n
+  if (g.tri & 2) khi = min(khi, m0 + BM);       // op(A) lower: zero for k > m
+  if (g.tri & 4) khi = min(khi, n0 + BN);       // op(B) upper: zero for k > n
+  klo &= ~(BK - 1);
+  const int kbeg = max(sp * kchunk, klo);
+  const int kend = min(min(g.k, sp * kchunk + kchunk), khi);
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   using T = Tile<TA, TB, SC>;
 
   dbl4 acc[2][2];
@@ -167,6 +175,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, i
             double* p = C + (long long)row * g.ldc + col;
             const double r = g.alpha * acc[i][j][v];
             *p = (g.beta == 0.0) ? r : r + g.beta * (*p);
+            if (g.mirror && n0 < m0) {  // strictly lower tile of a symmetric result: write the transpose too
+              double* q = C + (long long)col * g.ldc + row;
+              *q = (g.beta == 0.0) ? r : r + g.beta * (*q);
+            }
           }
         }
       }
@@ -182,8 +194,36 @@ __global__ void splitk_reduce_kernel(GemmArgs g, int splits, const double* __res
   double s = 0.0;
   for (int q = 0; q < splits; ++q) s += p[q * mn];
   const int row = (int)(u / g.n), col = (int)(u % g.n);
+  if (g.lower && (col / BN) * BN > (row / BM) * BM + BM - 1) return;  // partial tile was not written
   double* c = g.C + bz * g.sC + (long long)row * g.ldc + col;
   *c = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*c);
+  if (g.mirror && (col / BN) < (row / BM)) {
+    double* q = g.C + bz * g.sC + (long long)col * g.ldc + row;
+    *q = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*q);
+  }
+}
+
+// y[r] = alpha * sum_k A[r][k] s[k] x[k] + beta * y[r]: one wavefront per row (loads along k), fixed-order
+// lane partials and a butterfly reduction, so the result does not depend on the launch.
+__global__ __launch_bounds__(256) void gemv_f64_kernel(int m, int k, double alpha, const double* __restrict__ A, int lda,
+                                                        const double* __restrict__ s, const double* __restrict__ x, int incx,
+                                                        double beta, double* __restrict__ y, int incy) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= m) return;  // uniform per wavefront
+  const double* __restrict__ a = A + (long long)row * lda;
+  double acc = 0.0;
+  if (s) {
+    for (int c = lane; c < k; c += 64) acc += a[c] * (s[c] * x[(long long)c * incx]);
+  } else {
+    for (int c = lane; c < k; c += 64) acc += a[c] * x[(long long)c * incx];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    double* p = y + (long long)row * incy;
+    *p = (beta == 0.0) ? alpha * acc : alpha * acc + beta * (*p);
+  }
 }
 
 // Column dots: partial sums over kDiagParts row slabs, then a fixed-order sum -> deterministic.
@@ -241,11 +281,40 @@ void Profiler::end(hipStream_t st) {
 void Profiler::clear() { recs.clear(); next = 0; }
 Profiler::~Profiler() { for (auto e : pool) hipEventDestroy(e); }
 
+// Multiply-add work of one call as the kernel schedules it: 2 x rows x cols x (K range) summed over the
+// output tiles it computes (tiles skipped by `lower` and K ranges cut by `tri` excluded).
+static double gemm_work_flops(const GemmArgs& g) {
+  if (!g.lower && !g.tri) return 2.0 * g.m * g.n * (double)g.k * g.batch;
+  double fl = 0.0;
+  for (int m0 = 0; m0 < g.m; m0 += BM)
+    for (int n0 = 0; n0 < g.n; n0 += BN) {
+      if (g.lower && n0 > m0 + BM - 1) continue;
+      int klo = 0, khi = g.k;
+      if (g.tri & 1) klo = std::max(klo, m0);
+      if (g.tri & 8) klo = std::max(klo, n0);
+      if (g.tri & 2) khi = std::min(khi, m0 + BM);
+      if (g.tri & 4) khi = std::min(khi, n0 + BN);
+      if (khi > klo) fl += 2.0 * std::min(BM, g.m - m0) * std::min(BN, g.n - n0) * (double)(khi - klo);
+    }
+  return fl * g.batch;
+}
+
 hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return hipSuccess;
   if (g.k <= 0) {  // C = beta C
     // handled by a k=1 launch with alpha = 0 would read A; do it explicitly instead
     return hipErrorInvalidValue;
+  }
+  if (g.n == 1 && g.batch == 1 && !g.transa) {
+    // x[c] = op(B)[c][0]: B[c*ldb] (k x 1) or B[c] (1 x k, transposed)
+    const int incx = g.transb ? 1 : g.ldb;
+    Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
+    if (pf) pf->begin(st, PROF_GEMV_F64, 2.0 * g.m * (double)g.k,
+                      8.0 * ((double)g.m * g.k + g.k + (g.beta != 0.0 ? 2.0 : 1.0) * g.m));
+    hipLaunchKernelGGL(gemv_f64_kernel, dim3((unsigned)((g.m + 3) / 4)), dim3(256), 0, st, g.m, g.k, g.alpha, g.A,
+                       g.lda, g.s, g.B, incx, g.beta, g.C, g.ldc);
+    if (pf) pf->end(st);
+    return hipGetLastError();
   }
   const int tiles = ((g.n + BN - 1) / BN) * ((g.m + BM - 1) / BM) * g.batch;
   // K split: aim for `target` workgroups (default 512 = 2 per CU; per size bucket from the autotuner's table)
@@ -267,8 +336,8 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
   dim3 block(256);
   const bool sc = g.s != nullptr;
   Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
-  // algorithmic work of the product: 2mnk flops; bytes = each operand and C read/written once
-  if (pf) pf->begin(st, PROF_GEMM_F64, 2.0 * g.m * g.n * (double)g.k * g.batch,
+  // work of the product (2mnk flops, less the skipped tiles and K ranges); bytes = each operand and C once
+  if (pf) pf->begin(st, PROF_GEMM_F64, gemm_work_flops(g),
                     8.0 * g.batch * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
   double* part = splits > 1 ? g_gemm_ws : nullptr;
   bool launched = false;

@@ -62,43 +62,79 @@ __global__ __launch_bounds__(256) void embed_kernel(int n, int l, int d, const d
   if (threadIdx.x < EPT && i0 + threadIdx.x < l) w[i0 + threadIdx.x] = red[threadIdx.x][0] / (double)n;
 }
 
-// part[i] = sum_j k(x_i, x_j) for row i (one workgroup per row).
-__global__ __launch_bounds__(256) void gram_rowsum_kernel(int n, int d, const double* __restrict__ x, double inv2s2,
+// Sum of k(x_i, x_j) over the pairs i < j of one 64 x 64 tile pair (I, J), I <= J (symmetry halves the
+// work; the diagonal contributes n exactly since k(x, x) = 1).  Both tiles are staged in LDS; lane t of
+// wave g takes column j = 64 J + t against rows 64 I + 16 g .. + 15, so the row operands are LDS
+// broadcasts.  Workgroups with J < I write a zero partial.  part[I * nt + J]; fixed order throughout.
+constexpr int QT = 64;
+__global__ __launch_bounds__(256) void gram_pairsum_kernel(int n, int d, const double* __restrict__ x, double inv2s2,
                                                            double* __restrict__ part) {
+  __shared__ double xi[QT][QT + 1];   // [row][k]
+  __shared__ double xj[QT][QT + 1];   // [k][col]
   __shared__ double red[256];
-  __shared__ double xi[64];
-  const int i = blockIdx.x;
-  if (threadIdx.x < d && threadIdx.x < 64) xi[threadIdx.x] = x[(long long)i * d + threadIdx.x];
-  __syncthreads();
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += 256) {
-    double d2 = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double a = x[(long long)j * d + k] - xi[k];
-      d2 += a * a;
-    }
-    acc += exp(-d2 * inv2s2);
+  const int J = blockIdx.x, I = blockIdx.y, nt = gridDim.x;
+  const int t = threadIdx.x;
+  if (J < I) {
+    if (t == 0) part[(long long)I * nt + J] = 0.0;
+    return;
   }
-  red[threadIdx.x] = acc;
+  const int i0 = I * QT, j0 = J * QT;
+  for (int u0 = 0; u0 < QT * d; u0 += 4 * 256) {  // four loads per operand in flight per pass
+    double vi[4], vj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int u = u0 + t + 256 * q, r = u / d, k = u - r * d;
+      const bool in = u < QT * d;
+      vi[q] = (in && i0 + r < n) ? x[(long long)(i0 + r) * d + k] : 0.0;
+      vj[q] = (in && j0 + r < n) ? x[(long long)(j0 + r) * d + k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int u = u0 + t + 256 * q, r = u / d, k = u - r * d;
+      if (u < QT * d) { xi[r][k] = vi[q]; xj[k][r] = vj[q]; }
+    }
+  }
+  __syncthreads();
+  const int c = t & 63, g = t >> 6;
+  double d2[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) d2[r] = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double v = xj[k][c];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const double a = xi[g * 16 + r][k] - v;
+      d2[r] += a * a;
+    }
+  }
+  const int gj = j0 + c;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int gi = i0 + g * 16 + r;
+    if (gi < gj && gj < n) acc += exp(-d2[r] * inv2s2);
+  }
+  red[t] = acc;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if (t < h) red[t] += red[t + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[i] = red[0];
+  if (t == 0) part[(long long)I * nt + J] = red[0];
 }
 
-__global__ __launch_bounds__(256) void sum_scale_kernel(int n, const double* __restrict__ part, double scale, double* out) {
+// out[0] = (n + 2 sum(part[0..np))) / n^2
+__global__ __launch_bounds__(256) void pairsum_final_kernel(int n, int np, const double* __restrict__ part, double* out) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += 256) acc += part[j];
+  for (int j = threadIdx.x; j < np; j += 256) acc += part[j];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0] * scale;
+  if (threadIdx.x == 0) out[0] = ((double)n + 2.0 * red[0]) / ((double)n * (double)n);
 }
 
 __global__ void z_kernel(int l, int d, const double* __restrict__ xf, const double* __restrict__ yf, const double* __restrict__ wmu,
@@ -116,70 +152,106 @@ __global__ void z_kernel(int l, int d, const double* __restrict__ xf, const doub
 }
 
 // ---------------------------------------------------------------------------------------------------------
-// Blocked right-looking Cholesky on a working copy W (lower triangle), block size CB.
+// Blocked right-looking Cholesky on a working copy W (lower triangle), panel width CB.  One launch per panel
+// factors the diagonal block and solves the rows below it; the trailing update is an MFMA GEMM restricted
+// to the lower triangle.
 constexpr int CB = 32;
 
-// Factor the diagonal block W[k0:k0+nb, k0:k0+nb] in LDS (one workgroup).
-__global__ __launch_bounds__(256) void potrf_diag_kernel(int l, int k0, int nb, double* __restrict__ W, int* info) {
-  __shared__ double T[CB][CB + 1];
-  for (int u = threadIdx.x; u < nb * nb; u += 256) {
-    const int i = u / nb, j = u % nb;
-    T[i][j] = W[(long long)(k0 + i) * l + k0 + j];
-  }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (threadIdx.x == 0) {
-      const double piv = T[j][j];
-      if (!(piv > 0.0)) {
-        info[0] = k0 + j + 1;
-        T[j][j] = 1.0;
-      } else {
-        T[j][j] = sqrt(piv);
-      }
-    }
-    __syncthreads();
-    const double djj = T[j][j];
-    for (int i = j + 1 + threadIdx.x; i < nb; i += 256) T[i][j] /= djj;
-    __syncthreads();
-    // trailing update of the block's lower triangle
-    for (int u = threadIdx.x; u < nb * nb; u += 256) {
-      const int i = u / nb, c = u % nb;
-      if (i > j && c > j && c <= i) T[i][c] -= T[i][j] * T[c][j];
-    }
-    __syncthreads();
-  }
-  for (int u = threadIdx.x; u < nb * nb; u += 256) {
-    const int i = u / nb, j = u % nb;
-    W[(long long)(k0 + i) * l + k0 + j] = (j <= i) ? T[i][j] : 0.0;
-  }
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Panel: rows r >= k0+nb solve L21 L11^T = A21.  A workgroup stages 64 rows x nb of the panel through LDS
-// (coalesced along the row), then each of 64 threads forward-substitutes its row in LDS.
-__global__ __launch_bounds__(256) void trsm_panel_kernel(int l, int k0, int nb, double* __restrict__ W) {
+// One wavefront per workgroup.  Every workgroup factors the CB x CB diagonal block W[k0.., k0..] in
+// registers (lane i holds row i; the column entries L_cj reach the other rows through v_readlane, so the
+// factorization has no barrier and no LDS traffic); workgroup 0 writes L11 back (zeros above the diagonal)
+// and reports a non-positive pivot through info.  Workgroup b >= 1 takes the 64 panel rows starting at
+// k0 + nb + 64 (b - 1) and solves L21 L11^T = A21 by forward substitution, one row per lane held in
+// registers, L11 broadcast from LDS.  Loads and stores are staged through LDS to run along the rows.
+__global__ __launch_bounds__(64) void chol_panel_kernel(int l, int k0, int nb, double* __restrict__ W, int* info) {
   __shared__ double L11[CB][CB + 1];
   __shared__ double P[64][CB + 1];
-  const int rbase = k0 + nb + blockIdx.x * 64;
-  for (int u = threadIdx.x; u < nb * nb; u += 256) {
-    const int i = u / nb, j = u % nb;
-    L11[i][j] = W[(long long)(k0 + i) * l + k0 + j];
-  }
-  for (int u = threadIdx.x; u < 64 * nb; u += 256) {
-    const int r = u / nb, j = u % nb;
-    P[r][j] = (rbase + r < l) ? W[(long long)(rbase + r) * l + k0 + j] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64 && rbase + threadIdx.x < l) {
-    const int r = threadIdx.x;
-    for (int j = 0; j < nb; ++j) {
-      double v = P[r][j];
-      for (int c = 0; c < j; ++c) v -= P[r][c] * L11[j][c];
-      P[r][j] = v / L11[j][j];
+  __shared__ double inv_d[CB];
+  const int t = threadIdx.x;
+  {
+    // all sixteen loads of a lane in flight together (register buffer), then staged in LDS
+    double v[CB * CB / 64];
+#pragma unroll
+    for (int q = 0; q < CB * CB / 64; ++q) {
+      const int u = t + 64 * q, i = u >> 5, j = u & 31;
+      if (i < nb && j < nb) v[q] = (j <= i) ? W[(long long)(k0 + i) * l + k0 + j] : 0.0;
+      else v[q] = (i == j) ? 1.0 : 0.0;  // pad a short last block with the identity
+    }
+#pragma unroll
+    for (int q = 0; q < CB * CB / 64; ++q) {
+      const int u = t + 64 * q;
+      L11[u >> 5][u & 31] = v[q];
     }
   }
   __syncthreads();
-  for (int u = threadIdx.x; u < 64 * nb; u += 256) {
-    const int r = u / nb, j = u % nb;
+  const int i = t & 31;  // lanes 32..63 mirror rows 0..31
+  double a[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) a[c] = L11[i][c];
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    double piv = readlane_f64(a[j], j);
+    if (!(piv > 0.0)) {
+      if (j < nb && !bad) bad = k0 + j + 1;
+      piv = 1.0;
+    }
+    const double dj = sqrt(piv), rdj = 1.0 / dj;
+    const double lij = a[j] * rdj;  // L_ij on lanes i > j
+#pragma unroll
+    for (int c = j + 1; c < CB; ++c) a[c] -= lij * readlane_f64(lij, c);  // entries c > i are never used
+    a[j] = (i == j) ? dj : lij;
+    if (t == 0) inv_d[j] = rdj;
+  }
+  __syncthreads();  // all rows read from L11 before it is overwritten
+  if (t < CB)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) L11[i][c] = (c <= i) ? a[c] : 0.0;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (t == 0 && bad) atomicCAS(info, 0, bad);
+    for (int u = t; u < nb * CB; u += 64) {
+      const int r = u >> 5, j = u & 31;
+      if (j < nb) W[(long long)(k0 + r) * l + k0 + j] = L11[r][j];
+    }
+    return;
+  }
+  // panel rows (nb == CB here: only the last panel is short, and it has no rows below it)
+  const int rbase = k0 + nb + ((int)blockIdx.x - 1) * 64;
+  double x[CB];
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    const int u = t + 64 * q, r = u >> 5, j = u & 31;
+    x[q] = (rbase + r < l) ? W[(long long)(rbase + r) * l + k0 + j] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    const int u = t + 64 * q;
+    P[u >> 5][u & 31] = x[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CB; ++c) x[c] = P[t][c];
+  // column-oriented substitution: once x_j is final it is eliminated from every later entry, so the
+  // dependent chain is one multiply-add per column and the updates of one step are independent
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    x[j] *= inv_d[j];
+#pragma unroll
+    for (int c = j + 1; c < CB; ++c) x[c] -= x[j] * L11[c][j];
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) P[t][c] = x[c];
+  __syncthreads();
+  for (int u = t; u < 64 * CB; u += 64) {
+    const int r = u >> 5, j = u & 31;
     if (rbase + r < l) W[(long long)(rbase + r) * l + k0 + j] = P[r][j];
   }
 }
@@ -200,65 +272,82 @@ __global__ void lower_to_upper_kernel(int l, const double* __restrict__ L, doubl
 }
 
 // ---------------------------------------------------------------------------------------------------------
-// Y = R^{-1} for upper-triangular R, by row blocks of TRB from the bottom: the block's rows start as identity
-// rows, receive -R[blk, below] Y[below, :] from the MFMA GEMM, then are solved against the diagonal block.
+// Y = R^{-1} for upper-triangular R by recursive doubling: all TRB x TRB diagonal blocks are inverted at
+// once, then adjacent inverted blocks of width b merge into width 2b through
+//   Y12 = -Y11 (R12 Y22),
+// every merge of one level in a single batched MFMA GEMM pair.
 constexpr int TRB = 32;
 
-__global__ void eye_rows_kernel(int l, int r0, int nb, double* __restrict__ Y) {
-  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= (long long)nb * l) return;
-  const int r = (int)(u / l), c = (int)(u % l);
-  Y[(long long)(r0 + r) * l + c] = (r0 + r == c) ? 1.0 : 0.0;
-}
-
-// Y[r0:r0+nb, c] <- R_dd^{-1} Y[r0:r0+nb, c] for every column c (R_dd = R[r0:r0+nb, r0:r0+nb] upper).
-__global__ __launch_bounds__(256) void trsv_block_kernel(int l, int r0, int nb, const double* __restrict__ R,
-                                                         double* __restrict__ Y) {
+// Inverse of the diagonal block starting at r0 = TRB * blockIdx.x (upper triangular); thread c computes
+// column c by back substitution.  Entries of the block below its diagonal are written as zero.
+__global__ __launch_bounds__(64) void trtri_diag_kernel(int l, const double* __restrict__ R, double* __restrict__ Y) {
   __shared__ double D[TRB][TRB + 1];
-  for (int u = threadIdx.x; u < nb * nb; u += 256) {
-    const int i = u / nb, j = u % nb;
-    D[i][j] = R[(long long)(r0 + i) * l + r0 + j];
-  }
-  __syncthreads();
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= l) return;
-  double y[TRB];
+  const int r0 = blockIdx.x * TRB;
+  const int nb = min(TRB, l - r0);
+  {
+    double v[TRB * TRB / 64];
 #pragma unroll
-  for (int r = 0; r < TRB; ++r) y[r] = (r < nb) ? Y[(long long)(r0 + r) * l + c] : 0.0;
+    for (int q = 0; q < TRB * TRB / 64; ++q) {
+      const int u = threadIdx.x + 64 * q, i = u >> 5, j = u & 31;
+      v[q] = (i < nb && j < nb) ? R[(long long)(r0 + i) * l + r0 + j] : (i == j ? 1.0 : 0.0);
+    }
 #pragma unroll
-  for (int r = TRB - 1; r >= 0; --r) {
-    if (r < nb) {
-      double v = y[r];
-#pragma unroll
-      for (int k = r + 1; k < TRB; ++k)
-        if (k < nb) v -= D[r][k] * y[k];
-      y[r] = v / D[r][r];
+    for (int q = 0; q < TRB * TRB / 64; ++q) {
+      const int u = threadIdx.x + 64 * q;
+      D[u >> 5][u & 31] = v[q];
     }
   }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c >= TRB) return;
+  double y[TRB];
 #pragma unroll
-  for (int r = 0; r < TRB; ++r)
-    if (r < nb) Y[(long long)(r0 + r) * l + c] = y[r];
+  for (int i = TRB - 1; i >= 0; --i) {
+    double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = i + 1; k < TRB; ++k) v -= D[i][k] * y[k];
+    y[i] = (i <= c) ? v / D[i][i] : 0.0;
+  }
+  if (c < nb)
+#pragma unroll
+    for (int i = 0; i < TRB; ++i)
+      if (i < nb) Y[(long long)(r0 + i) * l + r0 + c] = y[i];
 }
 
 }  // namespace
 
-hipError_t trtri_upper(int l, const double* R, double* Y, hipStream_t st) {
-  const int last = ((l - 1) / TRB) * TRB;
-  for (int r0 = last; r0 >= 0; r0 -= TRB) {
-    const int nb = (l - r0 < TRB) ? (l - r0) : TRB;
-    hipLaunchKernelGGL(eye_rows_kernel, dim3((unsigned)(((long long)nb * l + 255) / 256)), dim3(256), 0, st, l, r0, nb, Y);
-    KOT_HIP_TRY(hipGetLastError());
-    const int below = l - r0 - nb;
-    if (below > 0) {
+hipError_t trtri_upper(int l, const double* R, double* Y, double* T, hipStream_t st) {
+  KOT_HIP_TRY(mat_fill(l, l, 0.0, Y, l, st));
+  hipLaunchKernelGGL(trtri_diag_kernel, dim3((l + TRB - 1) / TRB), dim3(64), 0, st, l, R, Y);
+  KOT_HIP_TRY(hipGetLastError());
+  for (int b = TRB; b < l; b *= 2) {
+    // merges at s = 2b p: left block [s, s+b), right block [s+b, s+b+b2), b2 = min(b, l - s - b)
+    const int full = l / (2 * b);                 // merges with b2 == b
+    const int s_last = full * 2 * b;              // a ragged merge starts here if s_last + b < l
+    for (int pass = 0; pass < 2; ++pass) {
+      const int cnt = pass == 0 ? full : ((s_last + b < l) ? 1 : 0);
+      if (cnt == 0) continue;
+      const int s0 = pass == 0 ? 0 : s_last;
+      const int b2 = pass == 0 ? b : l - s_last - b;
+      const long long stride = 2LL * b * (l + 1);
       GemmArgs g{};
-      g.transa = 0; g.transb = 0; g.m = nb; g.n = l; g.k = below; g.alpha = -1.0; g.beta = 1.0;
-      g.A = R + (long long)r0 * l + r0 + nb; g.lda = l;
-      g.B = Y + (long long)(r0 + nb) * l; g.ldb = l;
-      g.C = Y + (long long)r0 * l; g.ldc = l; g.batch = 1;
+      g.batch = cnt;
+      g.alpha = 1.0; g.beta = 0.0;
+      // T12 = R12 Y22  (b x b2)
+      g.transa = 0; g.transb = 0; g.m = b; g.n = b2; g.k = b2;
+      g.tri = 4;  // Y22 upper triangular
+      g.A = R + (long long)s0 * l + s0 + b; g.lda = l; g.sA = stride;
+      g.B = Y + (long long)(s0 + b) * l + s0 + b; g.ldb = l; g.sB = stride;
+      g.C = T + (long long)s0 * l + s0 + b; g.ldc = l; g.sC = stride;
+      KOT_HIP_TRY(gemm_f64(g, st));
+      // Y12 = -Y11 T12  (b x b2)
+      g.alpha = -1.0; g.m = b; g.n = b2; g.k = b;
+      g.tri = 1;  // Y11 upper triangular
+      g.A = Y + (long long)s0 * l + s0; g.lda = l; g.sA = stride;
+      g.B = T + (long long)s0 * l + s0 + b; g.ldb = l; g.sB = stride;
+      g.C = Y + (long long)s0 * l + s0 + b; g.ldc = l; g.sC = stride;
       KOT_HIP_TRY(gemm_f64(g, st));
     }
-    hipLaunchKernelGGL(trsv_block_kernel, dim3((l + 255) / 256), dim3(256), 0, st, l, r0, nb, R, Y);
-    KOT_HIP_TRY(hipGetLastError());
   }
   return hipSuccess;
 }
@@ -278,11 +367,17 @@ hipError_t mean_embedding(int n, int l, int d, const double* samples, const doub
   return hipGetLastError();
 }
 
+size_t mean_gram_part_size(int n) {
+  const size_t nt = (size_t)((n + QT - 1) / QT);
+  return nt * nt;
+}
+
 hipError_t mean_gram(int n, int d, const double* x, double sigma, double* out, double* part, hipStream_t st) {
-  if (d > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gram_rowsum_kernel, dim3(n), dim3(256), 0, st, n, d, x, 1.0 / (2.0 * sigma * sigma), part);
+  if (d > QT || n <= 0) return hipErrorInvalidValue;
+  const int nt = (n + QT - 1) / QT;
+  hipLaunchKernelGGL(gram_pairsum_kernel, dim3(nt, nt), dim3(256), 0, st, n, d, x, 1.0 / (2.0 * sigma * sigma), part);
   KOT_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(sum_scale_kernel, dim3(1), dim3(256), 0, st, n, part, 1.0 / ((double)n * (double)n), out);
+  hipLaunchKernelGGL(pairsum_final_kernel, dim3(1), dim3(256), 0, st, n, nt * nt, part, out);
   return hipGetLastError();
 }
 
@@ -300,13 +395,11 @@ hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double*
   KOT_HIP_TRY(hipGetLastError());
   for (int k0 = 0; k0 < l; k0 += CB) {
     const int nb = (l - k0 < CB) ? (l - k0) : CB;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, l, k0, nb, W, info);
-    KOT_HIP_TRY(hipGetLastError());
     const int rest = l - k0 - nb;
-    if (rest <= 0) break;
-    hipLaunchKernelGGL(trsm_panel_kernel, dim3((rest + 63) / 64), dim3(256), 0, st, l, k0, nb, W);
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(1 + (rest + 63) / 64), dim3(64), 0, st, l, k0, nb, W, info);
     KOT_HIP_TRY(hipGetLastError());
-    // W22 -= L21 L21^T  (full trailing block; keeps it symmetric)
+    if (rest <= 0) break;
+    // W22 -= L21 L21^T on the lower triangle
     GemmArgs g{};
     g.transa = 0; g.transb = 1; g.m = rest; g.n = rest; g.k = nb;
     g.alpha = -1.0; g.beta = 1.0;
@@ -314,6 +407,7 @@ hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double*
     g.B = W + (long long)(k0 + nb) * l + k0; g.ldb = l;
     g.C = W + (long long)(k0 + nb) * l + (k0 + nb); g.ldc = l;
     g.batch = 1;
+    g.lower = 1;
     KOT_HIP_TRY(gemm_f64(g, st));
   }
   hipLaunchKernelGGL(lower_to_upper_kernel, dim3(eb), dim3(256), 0, st, l, W, R);

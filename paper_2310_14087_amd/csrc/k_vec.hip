@@ -86,6 +86,8 @@ __global__ __launch_bounds__(256) void max_kernel(int n, const double* __restric
   }
   if (threadIdx.x == 0) out[0] = red[0];
 }
+__global__ void fill_int_kernel(int* __restrict__ out) { out[0] = 0; }
+
 __global__ __launch_bounds__(256) void count_pos_kernel(int l, const double* __restrict__ w, int* __restrict__ out) {
   __shared__ int red[256];
   int c = 0;
@@ -97,6 +99,23 @@ __global__ __launch_bounds__(256) void count_pos_kernel(int l, const double* __r
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// out[0] += number of nonzero entries strictly below the diagonal (one 256-row slab per workgroup column)
+__global__ __launch_bounds__(256) void count_lower_kernel(int l, const double* __restrict__ R, int* __restrict__ out) {
+  __shared__ int red[256];
+  int c = 0;
+  for (long long u = (long long)blockIdx.x * 256 + threadIdx.x; u < (long long)l * l; u += (long long)gridDim.x * 256) {
+    const int i = (int)(u / l), j = (int)(u - (long long)i * l);
+    if (j < i && R[u] != 0.0) ++c;
+  }
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0]) atomicAdd(out, red[0]);
 }
 
 // Psi weights (Section 4.3), eigenvalues w ascending so alpha = [l-a, l).
@@ -226,6 +245,14 @@ hipError_t rowsum_abs_max(int l, const double* A, bool square_entries, double* o
   hipLaunchKernelGGL(rowsum_abs_kernel, dim3(l), dim3(256), 0, st, l, A, square_entries ? 1 : 0, part);
   KOT_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, l, part, out);
+  return hipGetLastError();
+}
+hipError_t count_lower_nonzero(int l, const double* R, int* out_int, hipStream_t st) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, st, out_int);
+  KOT_HIP_TRY(hipGetLastError());
+  long long nb = ((long long)l * l + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(count_lower_kernel, dim3((unsigned)nb), dim3(256), 0, st, l, R, out_int);
   return hipGetLastError();
 }
 hipError_t count_positive(int l, const double* w, int* out_int, hipStream_t st) {

@@ -56,7 +56,7 @@ struct kot_ctx {
   double* hsc = nullptr;
   int* dint = nullptr;
   int* hint = nullptr;
-  double* part = nullptr;      // reduction partials (>= max(kRedBlocks, kDiagParts*l, n))
+  double* part = nullptr;      // reduction partials (>= max(kRedBlocks, kDiagParts*l, n, q^2 tile pairs))
   size_t part_cap = 0;
   double* gemm_ws = nullptr;   // split-K partial tiles (4 l^2 doubles)
   size_t gemm_ws_cap = 0;
@@ -121,7 +121,7 @@ void free_ws(kot_ctx* c) {
 kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   HIPCHK(hipSetDevice(ctx->device));
   const size_t need_part = std::max<size_t>({(size_t)kRedBlocks, (size_t)kDiagParts * l + 64, (size_t)nmax + 64,
-                                             (size_t)l + 64});
+                                             (size_t)l + 64, nmax > 0 ? mean_gram_part_size(nmax) : (size_t)0});
   if (l <= ctx->cap && need_part <= ctx->part_cap) return KOT_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   free_ws(ctx);
@@ -172,8 +172,11 @@ kot_status sync_read(kot_ctx* ctx, int nd, int ni) {
 }
 
 // ---- GEMM helpers ------------------------------------------------------------------------------------------
+// tri: known zero triangles of op(A) / op(B) (GemmArgs::tri); sym: the result is symmetric (m == n, and C
+// symmetric when beta != 0), so only the lower tiles are computed and mirrored.
 hipError_t mm(hipStream_t st, int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda,
-              const double* s, const double* B, int ldb, double beta, double* C, int ldc) {
+              const double* s, const double* B, int ldb, double beta, double* C, int ldc, int tri = 0,
+              bool sym = false) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (k <= 0) {
     if (beta != 0.0) return hipErrorInvalidValue;  // not needed by callers
@@ -182,20 +185,24 @@ hipError_t mm(hipStream_t st, int ta, int tb, int m, int n, int k, double alpha,
   GemmArgs g{};
   g.transa = ta; g.transb = tb; g.m = m; g.n = n; g.k = k; g.alpha = alpha; g.beta = beta;
   g.A = A; g.lda = lda; g.s = s; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.batch = 1;
+  g.tri = tri;
+  if (sym && m == n) { g.lower = 1; g.mirror = 1; }
   return gemm_f64(g, st);
 }
 
-// out = Phi*(g) = R diag(g) R^T
+constexpr int TRI_A_UPPER = 1, TRI_A_LOWER = 2, TRI_B_UPPER = 4, TRI_B_LOWER = 8;
+
+// out = Phi*(g) = R diag(g) R^T  (R upper: the k-th term touches only rows and columns <= k)
 kot_status phi_star(kot_ctx* ctx, const CoreView& cv, const double* g, double* out) {
   const int l = cv.l;
-  HIPCHK(mm(ctx->stream, 0, 1, l, l, l, 1.0, cv.R, l, g, cv.R, l, 0.0, out, l));
+  HIPCHK(mm(ctx->stream, 0, 1, l, l, l, 1.0, cv.R, l, g, cv.R, l, 0.0, out, l, TRI_A_UPPER | TRI_B_LOWER, true));
   return KOT_OK;
 }
 
 // y = alpha*Phi(X) + beta*y, Phi(X)_i = R[:,i]^T X R[:,i]; uses tmp (l x l)
 kot_status phi_op(kot_ctx* ctx, const CoreView& cv, const double* X, double alpha, double beta, double* y, double* tmp) {
   const int l = cv.l;
-  HIPCHK(mm(ctx->stream, 0, 0, l, l, l, 1.0, X, l, nullptr, cv.R, l, 0.0, tmp, l));
+  HIPCHK(mm(ctx->stream, 0, 0, l, l, l, 1.0, X, l, nullptr, cv.R, l, 0.0, tmp, l, TRI_B_UPPER));
   HIPCHK(diag_dot(0, l, l, alpha, cv.R, l, tmp, l, beta, y, ctx->part, ctx->stream));
   return KOT_OK;
 }
@@ -228,10 +235,10 @@ kot_status eig_run(kot_ctx* ctx, int l, const double* Z, const double* P0, doubl
 // the eigenvalues are positive, the same matrix as Z - P_abar diag(w_abar) P_abar^T (inner size l - a).
 kot_status proj_from_eig(kot_ctx* ctx, int l, const double* Z, const double* P, const double* w, int a, double* out) {
   if (a <= l - a) {
-    HIPCHK(mm(ctx->stream, 0, 1, l, l, a, 1.0, P + (l - a), l, w + (l - a), P + (l - a), l, 0.0, out, l));
+    HIPCHK(mm(ctx->stream, 0, 1, l, l, a, 1.0, P + (l - a), l, w + (l - a), P + (l - a), l, 0.0, out, l, 0, true));
   } else {
     HIPCHK(vec_copy(l * l, Z, out, ctx->stream));
-    if (l - a > 0) HIPCHK(mm(ctx->stream, 0, 1, l, l, l - a, -1.0, P, l, w, P, l, 1.0, out, l));
+    if (l - a > 0) HIPCHK(mm(ctx->stream, 0, 1, l, l, l - a, -1.0, P, l, w, P, l, 1.0, out, l, 0, true));
   }
   return KOT_OK;
 }
@@ -367,7 +374,7 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   hipStream_t st = ctx->stream;
   TPlan tp = make_tplan(l, s.a, mu, s.P, s.s);
   // B = P^T R
-  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, s.P, l, nullptr, cv.R, l, 0.0, ctx->Bm, l));
+  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, s.P, l, nullptr, cv.R, l, 0.0, ctx->Bm, l, TRI_B_UPPER));
   // M = r2 + T[r2]  (kept in Mr), a1 = -r1 - Phi(M)/(mu+1)
   KCHK(t_apply(ctx, tp, s.r2, ctx->T1));
   HIPCHK(vec_lincomb(l * l, 1.0, s.r2, 1.0, ctx->T1, ctx->Mr, st));
@@ -520,7 +527,7 @@ kot_status prepare_core(kot_ctx* ctx, CoreView& cv) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
   // KK = (R^T R) o (R^T R)
-  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, cv.R, l, nullptr, cv.R, l, 0.0, ctx->Kb, l));
+  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, cv.R, l, nullptr, cv.R, l, 0.0, ctx->Kb, l, TRI_A_LOWER | TRI_B_UPPER, true));
   HIPCHK(hadamard_square(l * l, ctx->Kb, ctx->KKb, st));
   cv.KK = ctx->KKb;
   return KOT_OK;
@@ -656,10 +663,10 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   if (gamma0 && p->lift_x0) {
     // X0 = R^-T diag(y) R^-1 with y = (Q gamma0 - z)/(2 lam2) (stationarity's value of Phi(X)) on the
     // constraints predicted active, small entries dropped, so that Phi(X0) = y
-    HIPCHK(trtri_upper(l, cv.R, ctx->T1, st));
+    HIPCHK(trtri_upper(l, cv.R, ctx->T1, ctx->T2, st));
     HIPCHK(mm(st, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, W->g, 1, 0.0, ctx->vtmp, 1));
     HIPCHK(lift_diag(l, ctx->vtmp, cv.z, W->g, cv.lam1, cv.lam2, 0.02, ctx->dg, ctx->part, st));
-    HIPCHK(mm(st, 1, 0, l, l, l, 1.0, ctx->T1, l, ctx->dg, ctx->T1, l, 0.0, W->X, l));
+    HIPCHK(mm(st, 1, 0, l, l, l, 1.0, ctx->T1, l, ctx->dg, ctx->T1, l, 0.0, W->X, l, TRI_A_LOWER | TRI_B_UPPER, true));
   } else {
     HIPCHK(vec_fill(l * l, 0.0, W->X, st));
   }
@@ -769,6 +776,15 @@ kot_status setup_impl(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, 
   *q2 = ctx->hsc[0] + ctx->hsc[1];
   if (ctx->hint[0] != 0)
     return fail(ctx, KOT_ERR_FACTOR, "K + eps I is not positive definite (pivot %d)", ctx->hint[0]);
+  return KOT_OK;
+}
+
+// Caller-supplied factors must be upper triangular (the products with R skip its zero triangle).
+kot_status check_upper(kot_ctx* ctx, int l, const double* R) {
+  HIPCHK(count_lower_nonzero(l, R, ctx->dint, ctx->stream));
+  KCHK(sync_read(ctx, 0, 1));
+  if (ctx->hint[0] != 0)
+    return fail(ctx, KOT_ERR_ARG, "R must be upper triangular (%d nonzero entries below the diagonal)", ctx->hint[0]);
   return KOT_OK;
 }
 
@@ -909,6 +925,7 @@ kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z,
   if (l < 1 || l > 4096) return fail(ctx, KOT_ERR_ARG, "l must be in [1, 4096]");
   if (!Q || !z || !R || !wsum || !res || !res->gamma) return fail(ctx, KOT_ERR_ARG, "null pointer argument");
   KCHK(ensure_ws(ctx, l, 0));
+  KCHK(check_upper(ctx, l, R));
   CoreView cv;
   cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.wsum = wsum; cv.q2 = q2; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
   return run_alg2(ctx, cv, p, gamma0, res);
@@ -933,6 +950,7 @@ kot_status kot_residual(kot_ctx* ctx, int l, const double* Q, const double* z, c
   if (l < 1 || l > 4096 || !Q || !z || !R || !gamma || !X || !r1 || !r2 || !norms)
     return fail(ctx, KOT_ERR_ARG, "invalid argument");
   KCHK(ensure_ws(ctx, l, 0));
+  KCHK(check_upper(ctx, l, R));
   CoreView cv;
   cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
   State& s = ctx->S[3];
@@ -955,6 +973,7 @@ kot_status kot_ssn_direction(kot_ctx* ctx, int l, const double* Q, const double*
   if (l < 1 || l > 4096 || !Q || !z || !R || !gamma || !X || !dgamma || !dX || !info || !(mu > 0.0))
     return fail(ctx, KOT_ERR_ARG, "invalid argument");
   KCHK(ensure_ws(ctx, l, 0));
+  KCHK(check_upper(ctx, l, R));
   CoreView cv;
   cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
   KCHK(prepare_core(ctx, cv));
@@ -981,6 +1000,7 @@ kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, co
   if (l < 1 || l > 4096 || !Q || !z || !R || !gamma || !X || !gamma_out || !X_out || !(eta > 0.0))
     return fail(ctx, KOT_ERR_ARG, "invalid argument");
   KCHK(ensure_ws(ctx, l, 0));
+  KCHK(check_upper(ctx, l, R));
   CoreView cv;
   cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
   KCHK(r1_op(ctx, cv, gamma, X, ctx->vtmp, ctx->T2));
@@ -1139,6 +1159,7 @@ kot_status kot_features(kot_ctx* ctx, int l, const double* Q, const double* z, c
   KCHK(check_params(ctx, p, false));
   if (l < 1 || l > 4096 || !Q || !z || !R || !wsum || !X) return fail(ctx, KOT_ERR_ARG, "invalid argument");
   KCHK(ensure_ws(ctx, l, 0));
+  KCHK(check_upper(ctx, l, R));
   KCHK(ensure_mlp(ctx, l, 1, l));
   CoreView cv;
   cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.wsum = wsum; cv.q2 = q2; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;

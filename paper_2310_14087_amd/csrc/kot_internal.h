@@ -8,7 +8,7 @@
 namespace kot {
 
 // ---- optional launch profiler (events around kernel launches on the issuing stream) -----------------------
-enum ProfClass { PROF_GEMM_F64 = 0, PROF_EIG_ROUND = 1, PROF_EIG_OTHER = 2, PROF_GEMM_F32 = 3, PROF_GEMM_BF16 = 4,
+enum ProfClass { PROF_GEMM_F64 = 0, PROF_EIG_ROUND = 1, PROF_GEMV_F64 = 2, PROF_GEMM_F32 = 3, PROF_GEMM_BF16 = 4,
                  PROF_NCLASS = 5 };
 struct Profiler {
   bool on = false;
@@ -26,7 +26,12 @@ struct Profiler {
 extern thread_local Profiler* g_prof;
 
 // ---- GEMM (FP64 MFMA): C = alpha * op(A) * diag(s) * op(B) + beta * C, row-major --------------------------
-// Batched over grid.z with element strides sA, sB, sS, sC (0 for a shared operand).
+// Batched over grid.z with element strides sA, sB, sS, sC (0 for a shared operand).  lower != 0: only the
+// 64x64 output tiles that meet the lower triangle (col <= row) are computed; entries above it are left
+// unspecified, unless mirror != 0 (square symmetric results, m == n): then every strictly-lower tile also
+// writes its transpose.  tri: known zero triangles of the operands, bit 1 op(A) upper, 2 op(A) lower,
+// 4 op(B) upper, 8 op(B) lower; each tile then runs only over the K range where both can be nonzero.
+// A single product with n == 1 and op(A) = A runs as a GEMV (HBM-bound, no matrix cores).
 struct GemmArgs {
   int transa, transb, m, n, k;
   double alpha, beta;
@@ -35,6 +40,7 @@ struct GemmArgs {
   const double* B; int ldb; long long sB;
   double* C; int ldc; long long sC;
   int batch;
+  int lower, mirror, tri;
 };
 hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
 // Split-K workspace used by gemm_f64 on the calling thread (set per library call by the context; null or
@@ -57,7 +63,8 @@ hipError_t gram_build(int l, int d, const double* xf, const double* yf, double s
                       hipStream_t st);
 hipError_t mean_embedding(int n, int l, int d, const double* samples, const double* pts, double sigma,
                           double* w, hipStream_t st);
-// sum_{i,j} k(x_i, x_j) / n^2 written to out[0]; part: workspace of at least n doubles.
+// sum_{i,j} k(x_i, x_j) / n^2 written to out[0] (d <= 64); part: workspace of mean_gram_part_size(n) doubles.
+size_t mean_gram_part_size(int n);
 hipError_t mean_gram(int n, int d, const double* x, double sigma, double* out, double* part, hipStream_t st);
 hipError_t build_z(int l, int d, const double* xf, const double* yf, const double* wmu, const double* wnu,
                    double lam2, double* z, double* wsum, hipStream_t st);
@@ -92,6 +99,8 @@ constexpr int kRedBlocks = 256;
 hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st);
 // out[0] = max_i sum_j |A_ij| (row-sum norm)
 hipError_t rowsum_abs_max(int l, const double* A, bool square_entries, double* out, double* part, hipStream_t st);
+// out_int[0] = number of nonzero entries strictly below the diagonal of R (l x l)
+hipError_t count_lower_nonzero(int l, const double* R, int* out_int, hipStream_t st);
 // count of w[i] > 0 (ascending w): out_int[0]
 hipError_t count_positive(int l, const double* w, int* out_int, hipStream_t st);
 // Psi rows for the eigen-index range [r0, r0 + m): H[r][j] = weight(r, j) * C[r][j] (in place), with
@@ -132,7 +141,8 @@ hipError_t adam_f32(int n, float* th, const float* g, float* m, float* v, float 
 hipError_t features(int l, const double* Q, const double* z, const double* wsum, const double* K, const double* KK,
                     double lam1, double* rs, double* pooled, float* X, hipStream_t st);
 hipError_t f32_to_f64_scaled(int n, const float* x, double s, double* y, hipStream_t st);
-hipError_t trtri_upper(int l, const double* R, double* Y, hipStream_t st);
+// Y = R^{-1} (R upper triangular, l x l); T: l x l workspace.
+hipError_t trtri_upper(int l, const double* R, double* Y, double* T, hipStream_t st);
 // d = ((Q g - z)/(2 lam2)) on predicted-active points (g_i <= -0.9 lambda1), zeroed below frac * mean of the
 // positive entries; part: >= 128 doubles.
 hipError_t lift_diag(int l, const double* Qg, const double* z, const double* g, double lam1, double lam2, double frac,

@@ -349,7 +349,7 @@ class Context:
         self._check(self.lib.kot_warmstart(self.h, C.byref(pb), C.byref(prm), N_FEATURES, H, _fptr(theta), _ptr(g0)))
         return g0
 
-    PROFILE_CLASSES = ("gemm_f64", "eig_sweep", "reserved", "gemm_f32", "gemm_bf16")
+    PROFILE_CLASSES = ("gemm_f64", "eig_sweep", "gemv_f64", "gemm_f32", "gemm_bf16")
 
     def profile_start(self):
         self._check(self.lib.kot_profile(self.h, 1, None, 0))

@@ -24,7 +24,8 @@ def _case(msg):
     print(f"[case] {msg}", flush=True)
 
 
-@pytest.mark.parametrize("m,n,k", [(64, 64, 16), (1, 1, 1), (37, 129, 70), (200, 3, 65), (130, 257, 300)])
+@pytest.mark.parametrize("m,n,k", [(64, 64, 16), (1, 1, 1), (37, 129, 70), (200, 3, 65), (130, 257, 300),
+                                   (300, 1, 257), (5, 1, 1000)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 @pytest.mark.parametrize("scaled", [False, True])
 def test_gemm_f64(gpu_ctx, m, n, k, ta, tb, scaled):
@@ -79,6 +80,26 @@ def test_eigh(gpu_ctx, l):
     assert np.abs(P.T @ P - np.eye(l)).max() <= 1e-13 * max(1, l ** 0.5)
 
 
+@pytest.mark.parametrize("l,nc", [(77, 3), (300, 6), (1000, 40), (1000, 0)])
+def test_eigh_sparse(gpu_ctx, l, nc):
+    """Diagonal plus a few coupled clusters (the structure of the SSN matrices when the filling points are
+    far apart relative to the bandwidth): the sweeps rotate only the block pairs above the threshold."""
+    from paper_2310_14087_amd import kotssn
+    _case(f"kot_eigh sparse l={l} clusters={nc}")
+    rng = np.random.default_rng(l + nc)
+    Z = np.diag(rng.standard_normal(l))
+    for _ in range(nc):
+        idx = rng.choice(l, size=int(rng.integers(2, 6)), replace=False)
+        B = rng.standard_normal((len(idx), len(idx))) * 0.1
+        Z[np.ix_(idx, idx)] += B + B.T
+    w, P = gpu_ctx.eigh(_t(Z), kotssn.default_params())
+    w, P = _n(w), _n(P)
+    scale = np.abs(w).max()
+    np.testing.assert_allclose(w, np.linalg.eigvalsh(Z), atol=1e-13 * scale * l ** 0.5)
+    assert np.abs(Z @ P - P * w).max() <= 1e-13 * scale * l ** 0.5
+    assert np.abs(P.T @ P - np.eye(l)).max() <= 1e-13 * l ** 0.5
+
+
 def test_eigh_degenerate(gpu_ctx):
     """Repeated and zero eigenvalues: invariants still hold."""
     from paper_2310_14087_amd import kotssn
@@ -94,7 +115,7 @@ def test_eigh_degenerate(gpu_ctx):
     assert np.abs(P.T @ P - np.eye(48)).max() <= 1e-12
 
 
-@pytest.mark.parametrize("l", [1, 31, 100])
+@pytest.mark.parametrize("l", [1, 31, 32, 33, 100, 257, 1000])
 def test_cholesky(gpu_ctx, l):
     _case(f"kot_cholesky l={l}")
     rng = np.random.default_rng(l + 7)
@@ -141,6 +162,19 @@ def test_residual(gpu_ctx, name, l, n):
     np.testing.assert_allclose(_n(r2), o2, atol=1e-11 * max(1.0, np.abs(X).max()))
     assert a == int(np.sum(s > 0))
     assert abs(n1 + n2 - on) <= 1e-10 * on
+
+
+def test_residual_rejects_non_triangular_factor(gpu_ctx):
+    """The dual data's factor must be the upper-triangular one; another factor of K is refused."""
+    from paper_2310_14087_amd import kotssn
+    p, core = _core_case("tiny", None, None)
+    _case("kot_residual with a rotated factor (expects KOT_ERR_ARG)")
+    Qo, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((core.l, core.l)))
+    g, X = _random_iterate(core.l, 11)
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2)
+    with pytest.raises(kotssn.KotError) as e:
+        gpu_ctx.residual(_t(core.Q), _t(core.z), _t(Qo @ core.R), _t(g), _t(X), prm)
+    assert e.value.status == kotssn.KOT_ERR_ARG
 
 
 @pytest.mark.parametrize("name,l,n,mu", [("tiny", None, None, 0.3), ("mix1000", 120, 400, 0.05),

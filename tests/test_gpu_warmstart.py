@@ -117,7 +117,7 @@ def test_learned_warm_start_gain(gpu_ctx):
     assert np.mean(warm_it) < 0.7 * np.mean(cold_it)
 
 
-@pytest.mark.parametrize("name,l,n,seed", [("mix256", 70, 200, 11), ("tiny", None, None, 0)])
+@pytest.mark.parametrize("name,l,n,seed", [("mix256", 70, 200, 11), ("tiny", None, None, 0), ("mix256", 200, 300, 5)])
 def test_lifted_start_matrix(gpu_ctx, name, l, n, seed):
     """max_iter = 0 returns the start point: X0 = R^-T diag(y) R^-1 with the lift's rule, checked with numpy
     (dense factor at 'tiny': exercises the blocked triangular inverse)."""
