@@ -134,7 +134,8 @@ kot_status kot_solve_batched(kot_ctx* ctx, int nprob, const kot_problem* probs, 
 
 /* GEMM tiling autotuner (not in the paper).  For each size L in sizes (host, nsizes entries, 1..4096) times the
  * two product shapes of a solve (L x L x L and L/2 x L x L with a diagonal scale) for each split-K target
- * (0 = no K split, 256, 512, 1024 workgroups) and keeps the fastest per size bucket (128-wide).  The table
+ * (0 = no K split, 128, 256, 512, 1024 workgroups; default 256, doubled for triangular operands) and keeps
+ * the fastest per size bucket (128-wide).  The table
  * (33 entries, copied to table_out when non-NULL) is used by every later call on this context and its batch
  * lanes; path (may be NULL) receives it as text.  kot_autotune_load installs a saved table. */
 kot_status kot_autotune(kot_ctx* ctx, const int* sizes, int nsizes, const char* path, int* table_out);

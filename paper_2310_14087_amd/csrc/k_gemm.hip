@@ -15,75 +15,80 @@ constexpr int MK_S = BK + 1;   // m-major tile [BM][MK_S] (operand loaded along 
 constexpr int TILE_D = BK * KM_S;  // == BM * MK_S == 2112 doubles either way
 static_assert(BK * KM_S == BM * MK_S, "tile sizes");
 
-// One 64x64 output tile per workgroup of 256 threads = 4 waves in a 2x2 grid; each wave owns 32x32 =
-// 2x2 MFMA blocks of 16x16.  MFMA operand layout (16x16x4 f64): lane L supplies A[L%16][L/16] and
+// One 64x64 output tile per workgroup.  The workgroup has NW = (4/FM)(4/FN) waves; each wave owns a
+// (16 FM) x (16 FN) block of FM x FN MFMA tiles of 16x16 (FM = FN = 2: 4 waves of 32x32; FM = 1, FN = 2:
+// 8 waves; FM = FN = 1: 16 waves).  More waves per SIMD keep the FP64 matrix pipeline fed when the grid
+// has about one tile per CU.  MFMA operand layout (16x16x4 f64): lane L supplies A[L%16][L/16] and
 // B[L/16][L%16]; the accumulator lane L holds D[L/16 + 4*v][L%16], v = 0..3.
 // Each operand is staged in LDS along the dimension it is contiguous in (global loads and LDS stores both
 // run along that dimension; the odd row stride of the m-major layout keeps the 16-row MFMA reads
 // conflict-free).  The next 32-deep K slice is prefetched into registers while the current one feeds the
 // matrix cores.
-template <bool TA, bool TB, bool SC>
+template <bool TA, bool TB, bool SC, int NT>
 struct Tile {
-  double a[8], b[8];
+  static constexpr int PER = BM * BK / NT;     // elements of each operand per thread and K slice
+  static constexpr int RK = NT / BK;           // rows per pass when lanes run along k
+  static constexpr int RM = NT / BM;           // k-rows per pass when lanes run along m / n
+  double a[PER], b[PER];
   __device__ __forceinline__ void load(const GemmArgs& g, const double* __restrict__ A, const double* __restrict__ B,
                                        const double* __restrict__ S, int m0, int n0, int k0, int t) {
     const int M = g.m, N = g.n, K = g.k;
-    if (!TA) {  // A[m*lda + k]: lanes along k (32), 8 rows per pass
-      const int kk = t & 31, mm = t >> 5;
+    if (!TA) {  // A[m*lda + k]: lanes along k (32)
+      const int kk = t & (BK - 1), mm = t / BK;
       const int gk = k0 + kk;
       const double sc = (SC && gk < K) ? S[gk] : 1.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int gm = m0 + mm + 8 * u;
+      for (int u = 0; u < PER; ++u) {
+        const int gm = m0 + mm + RK * u;
         const double v = (gm < M && gk < K) ? A[(long long)gm * g.lda + gk] : 0.0;
         a[u] = SC ? v * sc : v;
       }
-    } else {    // A[k*lda + m]: lanes along m (64), 4 k-rows per pass
-      const int mm = t & 63, kk = t >> 6;
+    } else {    // A[k*lda + m]: lanes along m (64)
+      const int mm = t & (BM - 1), kk = t / BM;
       const int gm = m0 + mm;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int gk = k0 + kk + 4 * u;
+      for (int u = 0; u < PER; ++u) {
+        const int gk = k0 + kk + RM * u;
         const double v = (gm < M && gk < K) ? A[(long long)gk * g.lda + gm] : 0.0;
         a[u] = SC ? ((gk < K) ? v * S[gk] : 0.0) : v;
       }
     }
     if (!TB) {  // B[k*ldb + n]: lanes along n
-      const int nn = t & 63, kk = t >> 6;
+      const int nn = t & (BN - 1), kk = t / BN;
       const int gn = n0 + nn;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int gk = k0 + kk + 4 * u;
+      for (int u = 0; u < PER; ++u) {
+        const int gk = k0 + kk + RM * u;
         b[u] = (gn < N && gk < K) ? B[(long long)gk * g.ldb + gn] : 0.0;
       }
     } else {    // B[n*ldb + k]: lanes along k
-      const int kk = t & 31, nn = t >> 5;
+      const int kk = t & (BK - 1), nn = t / BK;
       const int gk = k0 + kk;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int gn = n0 + nn + 8 * u;
+      for (int u = 0; u < PER; ++u) {
+        const int gn = n0 + nn + RK * u;
         b[u] = (gn < N && gk < K) ? B[(long long)gn * g.ldb + gk] : 0.0;
       }
     }
   }
   __device__ __forceinline__ void store(double* __restrict__ As, double* __restrict__ Bs, int t) const {
     if (!TA) {  // m-major
-      const int kk = t & 31, mm = t >> 5;
+      const int kk = t & (BK - 1), mm = t / BK;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) As[(mm + 8 * u) * MK_S + kk] = a[u];
+      for (int u = 0; u < PER; ++u) As[(mm + RK * u) * MK_S + kk] = a[u];
     } else {    // k-major
-      const int mm = t & 63, kk = t >> 6;
+      const int mm = t & (BM - 1), kk = t / BM;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) As[(kk + 4 * u) * KM_S + mm] = a[u];
+      for (int u = 0; u < PER; ++u) As[(kk + RM * u) * KM_S + mm] = a[u];
     }
     if (!TB) {  // k-major
-      const int nn = t & 63, kk = t >> 6;
+      const int nn = t & (BN - 1), kk = t / BN;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) Bs[(kk + 4 * u) * KM_S + nn] = b[u];
+      for (int u = 0; u < PER; ++u) Bs[(kk + RM * u) * KM_S + nn] = b[u];
     } else {    // n-major
-      const int kk = t & 31, nn = t >> 5;
+      const int kk = t & (BK - 1), nn = t / BK;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) Bs[(nn + 8 * u) * MK_S + kk] = b[u];
+      for (int u = 0; u < PER; ++u) Bs[(nn + RK * u) * MK_S + kk] = b[u];
     }
   }
   // op(A)[m][k] and op(B)[k][n] from the staged tiles
@@ -97,8 +102,11 @@ struct Tile {
 
 // blockIdx.z = batch * splits + split.  With splits > 1 the workgroup covers K slices
 // [split*kchunk, (split+1)*kchunk) and writes its raw partial tile to part (layout [batch][split][m][n]).
-template <bool TA, bool TB, bool SC>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, int kchunk, double* __restrict__ part) {
+template <bool TA, bool TB, bool SC, int FM, int FN>
+__global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(GemmArgs g, int splits, int kchunk,
+                                                                             double* __restrict__ part) {
+  constexpr int WN = 4 / FN;                   // waves along n
+  constexpr int NT = 64 * (4 / FM) * WN;
   __shared__ double As[TILE_D];
   __shared__ double Bs[TILE_D];
   const int bz = blockIdx.z / splits, sp = blockIdx.z % splits;
@@ -110,7 +118,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, i
   if (g.lower && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal (uniform per workgroup)
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   // K range of this split, narrowed to where the triangular operands can be nonzero for this tile
   int klo = 0, khi = g.k;
   if (g.tri & 1) klo = max(klo, m0);            // op(A) upper: op(A)[m][k] = 0 for k < m
@@ -121,13 +129,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, i
   const int kbeg = max(sp * kchunk, klo);
   const int kend = min(min(g.k, sp * kchunk + kchunk), khi);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-  using T = Tile<TA, TB, SC>;
+  using T = Tile<TA, TB, SC, NT>;
 
-  dbl4 acc[2][2];
+  dbl4 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   T tile;
   GemmArgs gk = g;
@@ -141,15 +149,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, i
     if (more) tile.load(gk, A, B, S, m0, n0, kbeg + (kt + 1) * BK, t);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double a[2], b[2];
+      double a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = T::ga(As, wm * 32 + i * 16 + r16, ks + k4);
+      for (int i = 0; i < FM; ++i) a[i] = T::ga(As, wm * 16 * FM + i * 16 + r16, ks + k4);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = T::gb(Bs, ks + k4, wn * 32 + j * 16 + r16);
+      for (int j = 0; j < FN; ++j) b[j] = T::gb(Bs, ks + k4, wn * 16 * FN + j * 16 + r16);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
@@ -161,13 +169,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int splits, i
   // ---- epilogue ----
   const int M = g.m, N = g.n;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 32 + i * 16 + k4 + 4 * v;
-        const int col = n0 + wn * 32 + j * 16 + r16;
+        const int row = m0 + wm * 16 * FM + i * 16 + k4 + 4 * v;
+        const int col = n0 + wn * 16 * FN + j * 16 + r16;
         if (row < M && col < N) {
           if (splits > 1) {
             part[(((long long)bz * splits + sp) * M + row) * N + col] = acc[i][j][v];
@@ -299,7 +307,9 @@ static double gemm_work_flops(const GemmArgs& g) {
   return fl * g.batch;
 }
 
-hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
+hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) { return gemm_f64_cfg(g, st, 0, 0); }
+
+hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits_req) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return hipSuccess;
   if (g.k <= 0) {  // C = beta C
     // handled by a k=1 launch with alpha = 0 would read A; do it explicitly instead
@@ -317,15 +327,25 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
     return hipGetLastError();
   }
   const int tiles = ((g.n + BN - 1) / BN) * ((g.m + BM - 1) / BM) * g.batch;
-  // K split: aim for `target` workgroups (default 512 = 2 per CU; per size bucket from the autotuner's table)
-  // with at least 128 of K per split
+  // 16 waves per workgroup: measured fastest on every solver shape (four waves per SIMD at one tile per CU)
+  if (waves == 0) waves = 16;
   int splits = 1;
-  const int target = g_gemm_tune ? g_gemm_tune[gemm_tune_bucket(std::max(g.m, g.n))] : 512;
-  if (target > 0 && tiles < target && g.k >= 256) {
-    splits = (target + tiles - 1) / tiles;
-    splits = std::min(splits, std::min(8, g.k / 128));
+  if (splits_req > 0) {
+    splits = std::min(splits_req, std::max(1, g.k / BK));
+  } else {
+    // K split: aim for `target` workgroups (one per CU by default, twice that when triangular operands make
+    // the K ranges of the tiles uneven; per size bucket from the autotuner's table), at least 64 of K each
+    int target = g_gemm_tune ? g_gemm_tune[gemm_tune_bucket(std::max(g.m, g.n))] : 256;
+    if (g.tri) target *= 2;
+    const int computed = g.lower ? (tiles + ((g.n + BN - 1) / BN) * g.batch) / 2 : tiles;
+    if (target > 0 && computed < target && g.k >= 128) {
+      splits = (target + computed - 1) / computed;
+      splits = std::min(splits, std::min(8, g.k / 64));
+    }
+  }
+  if (splits > 1) {
     const size_t need = (size_t)splits * g.batch * (size_t)g.m * g.n;
-    if (splits < 2 || !g_gemm_ws || need > g_gemm_ws_cap) splits = 1;
+    if (!g_gemm_ws || need > g_gemm_ws_cap) splits = 1;
   }
   int kchunk = g.k;
   if (splits > 1) {
@@ -333,7 +353,6 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
     splits = (g.k + kchunk - 1) / kchunk;
   }
   dim3 grid((g.n + BN - 1) / BN, (g.m + BM - 1) / BM, g.batch * splits);
-  dim3 block(256);
   const bool sc = g.s != nullptr;
   Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
   // work of the product (2mnk flops, less the skipped tiles and K ranges); bytes = each operand and C once
@@ -341,10 +360,18 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
                     8.0 * g.batch * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
   double* part = splits > 1 ? g_gemm_ws : nullptr;
   bool launched = false;
-#define KOT_GEMM_CASE(TA, TB, SC_) \
-  if (!launched && g.transa == TA && g.transb == TB && sc == SC_) { hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, SC_>), grid, block, 0, st, g, splits, kchunk, part); launched = true; }
-  KOT_GEMM_CASE(0, 0, false) KOT_GEMM_CASE(0, 1, false) KOT_GEMM_CASE(1, 0, false) KOT_GEMM_CASE(1, 1, false)
-  KOT_GEMM_CASE(0, 0, true) KOT_GEMM_CASE(0, 1, true) KOT_GEMM_CASE(1, 0, true) KOT_GEMM_CASE(1, 1, true)
+#define KOT_GEMM_CASE(TA, TB, SC_, FM, FN)                                                                       \
+  if (!launched && g.transa == TA && g.transb == TB && sc == SC_ && waves == (4 / FM) * (4 / FN)) {               \
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, SC_, FM, FN>), grid, dim3(64 * (4 / FM) * (4 / FN)), 0, st, g,    \
+                       splits, kchunk, part);                                                                      \
+    launched = true;                                                                                               \
+  }
+#define KOT_GEMM_WAVES(FM, FN)                                                                                     \
+  KOT_GEMM_CASE(0, 0, false, FM, FN) KOT_GEMM_CASE(0, 1, false, FM, FN) KOT_GEMM_CASE(1, 0, false, FM, FN)         \
+  KOT_GEMM_CASE(1, 1, false, FM, FN) KOT_GEMM_CASE(0, 0, true, FM, FN) KOT_GEMM_CASE(0, 1, true, FM, FN)           \
+  KOT_GEMM_CASE(1, 0, true, FM, FN) KOT_GEMM_CASE(1, 1, true, FM, FN)
+  KOT_GEMM_WAVES(2, 2) KOT_GEMM_WAVES(1, 2) KOT_GEMM_WAVES(1, 1)
+#undef KOT_GEMM_WAVES
 #undef KOT_GEMM_CASE
   if (!launched) return hipErrorInvalidValue;
   if (splits > 1) {

@@ -1081,7 +1081,7 @@ kot_status kot_autotune(kot_ctx* ctx, const int* sizes, int nsizes, const char* 
   }
   KCHK(ensure_ws(ctx, Lmax, 0));
   if (!ctx->tuned) {
-    for (int b = 0; b < kTuneBuckets; ++b) ctx->tune[b] = 512;
+    for (int b = 0; b < kTuneBuckets; ++b) ctx->tune[b] = 256;
   }
   hipStream_t st = ctx->stream;
   double* A = ctx->T1;
@@ -1090,13 +1090,13 @@ kot_status kot_autotune(kot_ctx* ctx, const int* sizes, int nsizes, const char* 
   HIPCHK(vec_fill(Lmax * Lmax, 0.5, A, st));
   HIPCHK(vec_fill(Lmax * Lmax, 0.25, B, st));
   HIPCHK(vec_fill(Lmax, 1.0, ctx->vtmp, st));
-  const int cand[4] = {0, 256, 512, 1024};
+  const int cand[5] = {0, 128, 256, 512, 1024};
   int local[kTuneBuckets];
   std::copy(ctx->tune, ctx->tune + kTuneBuckets, local);
   for (int i = 0; i < nsizes; ++i) {
     const int L = sizes[i];
     double best_t = 1e300;
-    int best = 512;
+    int best = 256;
     for (int c : cand) {
       local[gemm_tune_bucket(L)] = c;
       g_gemm_tune = local;
@@ -1136,7 +1136,7 @@ kot_status kot_autotune_load(kot_ctx* ctx, const char* path) {
   if (!f) return fail(ctx, KOT_ERR_ARG, "cannot read %s", path);
   int ver = 0;
   int tab[kTuneBuckets];
-  for (int b = 0; b < kTuneBuckets; ++b) tab[b] = 512;
+  for (int b = 0; b < kTuneBuckets; ++b) tab[b] = 256;
   if (std::fscanf(f, "kot-gemm-tune %d", &ver) != 1 || ver != 1) {
     std::fclose(f);
     return fail(ctx, KOT_ERR_ARG, "%s is not a tuning table", path);

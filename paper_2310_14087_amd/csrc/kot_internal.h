@@ -43,6 +43,9 @@ struct GemmArgs {
   int lower, mirror, tri;
 };
 hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
+// Same with an explicit launch shape: waves per workgroup (4, 8 or 16; 0 = default) and K splits (0 = from
+// the split-K target of the size bucket).
+hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits);
 // Split-K workspace used by gemm_f64 on the calling thread (set per library call by the context; null or
 // too small => no K split).
 extern thread_local double* g_gemm_ws;
