@@ -263,8 +263,10 @@ __global__ __launch_bounds__(64) void apply_kernel(int l, int np, double* __rest
 
 // Squared Frobenius norms of the 8 x 8 blocks (b1, b2), b1 <= b2 (A symmetric): boff = off-diagonal part,
 // ball = all entries, counted twice for b1 < b2 so that the sums over b1 <= b2 are the norms of A.
+// bpos[b] counts the positive diagonal entries of block b (the eigenvalues once A is diagonal).
 __global__ __launch_bounds__(64) void block_norm_kernel(int l, int nb, const double* __restrict__ A,
-                                                        double* __restrict__ boff, double* __restrict__ ball) {
+                                                        double* __restrict__ boff, double* __restrict__ ball,
+                                                        double* __restrict__ bpos) {
   const int b1 = blockIdx.y, b2 = blockIdx.x;
   if (b2 < b1) return;
   const int t = threadIdx.x;
@@ -272,14 +274,17 @@ __global__ __launch_bounds__(64) void block_norm_kernel(int l, int nb, const dou
   const double v = (i < l && j < l) ? A[(long long)i * l + j] : 0.0;
   double off = (i != j) ? v * v : 0.0;
   double all = (b1 < b2 ? 2.0 : 1.0) * v * v;
+  double pos = (i == j && v > 0.0) ? 1.0 : 0.0;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     off += __shfl_xor(off, o);
     all += __shfl_xor(all, o);
+    pos += __shfl_xor(pos, o);
   }
   if (t == 0) {
     boff[(long long)b1 * nb + b2] = off;
     ball[(long long)b1 * nb + b2] = all;
+    if (b1 == b2) bpos[b1] = pos;
   }
 }
 
@@ -359,8 +364,9 @@ struct EigWork {
   double* norms = nullptr;    // device [4]: slot 2 = rotation threshold
   double* hnorms = nullptr;   // pinned host [4]
   int* perm = nullptr;        // device [lmax]
-  double* boff = nullptr;     // device [nbmax^2] block norms (off-diagonal part), then all entries
-  double* hb = nullptr;       // pinned host copy [2 * nbmax^2]
+  double* boff = nullptr;     // device block norms: off-diagonal part [nbmax^2], all entries [nbmax^2], positive
+                              // diagonal counts [nbmax]
+  double* hb = nullptr;       // pinned host copy
   int2* list = nullptr;       // device pair lists of a threshold sweep [(nbmax - 1) * nbmax / 2]
   int2* hlist = nullptr;      // pinned host staging of the lists
   std::vector<int> round_k;   // active pairs per round of the current threshold sweep
@@ -384,8 +390,8 @@ EigWork* eig_work_create(int lmax) {
             hipMalloc(&w->norms, sizeof(double) * 4) == hipSuccess &&
             hipHostMalloc(&w->hnorms, sizeof(double) * 4) == hipSuccess &&
             hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess &&
-            hipMalloc(&w->boff, sizeof(double) * 2 * nb2) == hipSuccess &&
-            hipHostMalloc(&w->hb, sizeof(double) * 2 * nb2) == hipSuccess &&
+            hipMalloc(&w->boff, sizeof(double) * (2 * nb2 + nbmax)) == hipSuccess &&
+            hipHostMalloc(&w->hb, sizeof(double) * (2 * nb2 + nbmax)) == hipSuccess &&
             hipMalloc(&w->list, sizeof(int2) * nlist) == hipSuccess &&
             hipHostMalloc(&w->hlist, sizeof(int2) * nlist) == hipSuccess;
   if (!ok) { eig_work_destroy(w); return nullptr; }
@@ -400,22 +406,28 @@ void eig_work_destroy(EigWork* w) {
   delete w;
 }
 
-// Block norms of A to the host; returns off(A) and |A|_F (sums in a fixed order on the host).
-static hipError_t block_norms(EigWork* w, int l, int nb, const double* A, hipStream_t st, double* off, double* all) {
+// Block norms of A to the host; returns off(A), |A|_F (sums in a fixed order on the host) and the number of
+// positive diagonal entries.
+static hipError_t block_norms(EigWork* w, int l, int nb, const double* A, hipStream_t st, double* off, double* all,
+                              int* npos) {
   const size_t nb2 = (size_t)nb * nb;
-  hipLaunchKernelGGL(block_norm_kernel, dim3(nb, nb), dim3(64), 0, st, l, nb, A, w->boff, w->boff + nb2);
+  hipLaunchKernelGGL(block_norm_kernel, dim3(nb, nb), dim3(64), 0, st, l, nb, A, w->boff, w->boff + nb2,
+                     w->boff + 2 * nb2);
   KOT_HIP_TRY(hipGetLastError());
-  KOT_HIP_TRY(hipMemcpyAsync(w->hb, w->boff, sizeof(double) * 2 * nb2, hipMemcpyDeviceToHost, st));
+  KOT_HIP_TRY(hipMemcpyAsync(w->hb, w->boff, sizeof(double) * (2 * nb2 + nb), hipMemcpyDeviceToHost, st));
   KOT_HIP_TRY(hipStreamSynchronize(st));
-  double so = 0.0, sa = 0.0;
-  for (int b1 = 0; b1 < nb; ++b1)
+  double so = 0.0, sa = 0.0, sp = 0.0;
+  for (int b1 = 0; b1 < nb; ++b1) {
     for (int b2 = b1; b2 < nb; ++b2) {
       const size_t u = (size_t)b1 * nb + b2;
       so += (b2 > b1 ? 2.0 : 1.0) * w->hb[u];
       sa += w->hb[nb2 + u];
     }
+    sp += w->hb[2 * nb2 + b1];
+  }
   *off = std::sqrt(so);
   *all = std::sqrt(sa);
+  *npos = (int)sp;
   return hipSuccess;
 }
 
@@ -493,7 +505,7 @@ static bool threshold_schedule(EigWork* w, int nb, double tau2) {
 }
 
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
-                       int max_sweeps, double tol, int* sweeps, double* rel_off, hipStream_t st) {
+                       int max_sweeps, double tol, int* sweeps, double* rel_off, int* npos, hipStream_t st) {
   if (l > w->lmax) return hipErrorInvalidValue;
   double* A = tmp;
   double* V = tmp + (long long)l * l;
@@ -518,7 +530,8 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   const int np = nb / 2;
   const int nslab = (l + SLOT - 1) / SLOT;
   double off = 0.0, all = 0.0;
-  KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all));
+  int pos = 0;
+  KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all, &pos));
   int s = 0;
   const double thresh_rel = 1e-18;
   auto launch_round = [&](hipStream_t s_, int r, const int2* list, int kact) -> hipError_t {
@@ -579,10 +592,11 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       if (pf) pf->end(st);
     }
     ++s;
-    KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all));
+    KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all, &pos));
   }
   *sweeps = s;
   *rel_off = (all > 0.0) ? off / all : 0.0;
+  if (npos) *npos = pos;
   if (l > 4096) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 63) / 64), dim3(256), 0, st, l, A, wv, w->perm);
   KOT_HIP_TRY(hipGetLastError());

@@ -35,28 +35,121 @@ __global__ void symmetrize_kernel(int l, double* __restrict__ Z) {
   Z[u] = v;
   Z[(long long)j * l + i] = v;
 }
-__global__ __launch_bounds__(256) void dot_part_kernel(long long n, const double* __restrict__ x, const double* __restrict__ y,
-                                                       double* __restrict__ part) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) acc += x[i] * y[i];
-  red[threadIdx.x] = acc;
+// Partial dot products of one or two vector pairs over a grid-stride slice, four loads in flight per pass;
+// part[2 b] (and part[2 b + 1]) per block, fixed order.
+__global__ __launch_bounds__(256) void dot2_part_kernel(long long n, const double* __restrict__ x1, const double* __restrict__ y1,
+                                                        const double* __restrict__ x2, const double* __restrict__ y2,
+                                                        double* __restrict__ part) {
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i0 = (long long)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    double u[4], v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long i = i0 + q * stride;
+      u[q] = (i < n) ? x1[i] * y1[i] : 0.0;
+      v[q] = (x2 && i < n) ? x2[i] * y2[i] : 0.0;
+    }
+    a += (u[0] + u[1]) + (u[2] + u[3]);
+    b += (v[0] + v[1]) + (v[2] + v[3]);
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if (threadIdx.x < h) { red[0][threadIdx.x] += red[0][threadIdx.x + h]; red[1][threadIdx.x] += red[1][threadIdx.x + h]; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = red[0][0]; part[2 * blockIdx.x + 1] = red[1][0]; }
 }
-__global__ __launch_bounds__(256) void sum_final_kernel(int nb, const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double red[256];
-  red[threadIdx.x] = (threadIdx.x < nb) ? part[threadIdx.x] : 0.0;
+__global__ __launch_bounds__(256) void dot2_final_kernel(int nb, const double* __restrict__ part, double* __restrict__ o1,
+                                                         double* __restrict__ o2) {
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = (threadIdx.x < nb) ? part[2 * threadIdx.x] : 0.0;
+  red[1][threadIdx.x] = (threadIdx.x < nb) ? part[2 * threadIdx.x + 1] : 0.0;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    if (threadIdx.x < h) { red[0][threadIdx.x] += red[0][threadIdx.x + h]; red[1][threadIdx.x] += red[1][threadIdx.x + h]; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) {
+    o1[0] = red[0][0];
+    if (o2) o2[0] = red[1][0];
+  }
+}
+// Short vectors (n <= kSmallDot): one workgroup, eight loads in flight per thread, fixed order.
+constexpr int kSmallDot = 8192;
+__global__ __launch_bounds__(1024) void dot2_small_kernel(int n, const double* __restrict__ x1, const double* __restrict__ y1,
+                                                          const double* __restrict__ x2, const double* __restrict__ y2,
+                                                          double* __restrict__ o1, double* __restrict__ o2) {
+  __shared__ double red[2][1024];
+  double u[8], v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = threadIdx.x + 1024 * q;
+    u[q] = (i < n) ? x1[i] * y1[i] : 0.0;
+    v[q] = (x2 && i < n) ? x2[i] * y2[i] : 0.0;
+  }
+  red[0][threadIdx.x] = ((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7]));
+  red[1][threadIdx.x] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (threadIdx.x < h) { red[0][threadIdx.x] += red[0][threadIdx.x + h]; red[1][threadIdx.x] += red[1][threadIdx.x + h]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    o1[0] = red[0][0];
+    if (o2) o2[0] = red[1][0];
+  }
+}
+// Z = sym(X - a T) + c I with sym(M) = (M + M^T)/2: one workgroup per 32x32 tile pair (I, J), I <= J, both
+// tiles staged in LDS so the transposed reads stay coalesced; Z is exactly symmetric.
+__global__ __launch_bounds__(256) void form_z_kernel(int l, const double* __restrict__ X, double a,
+                                                     const double* __restrict__ T, double c, double* __restrict__ Z) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (J < I) return;
+  __shared__ double mij[32][33], mji[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  double u[4], v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
+    const int i = I * 32 + r, j = J * 32 + tx;
+    u[q] = (i < l && j < l) ? X[(long long)i * l + j] - a * T[(long long)i * l + j] : 0.0;
+    const int i2 = J * 32 + r, j2 = I * 32 + tx;
+    v[q] = (i2 < l && j2 < l) ? X[(long long)i2 * l + j2] - a * T[(long long)i2 * l + j2] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    mij[ty + 8 * q][tx] = u[q];
+    mji[ty + 8 * q][tx] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = ty + 8 * q;
+    const int i = I * 32 + r, j = J * 32 + tx;
+    if (i < l && j < l) {
+      double z = 0.5 * (mij[r][tx] + mji[tx][r]);
+      if (i == j) z += c;
+      Z[(long long)i * l + j] = z;
+    }
+    const int i2 = J * 32 + r, j2 = I * 32 + tx;
+    if (I != J && i2 < l && j2 < l) Z[(long long)i2 * l + j2] = 0.5 * (mji[r][tx] + mij[tx][r]);
+  }
+}
+
+// CG update with the step length on the device: alpha = rr / pAp (0 if pAp <= 0, which the host then sees);
+// x += alpha p, r -= alpha Ap.
+__global__ void cg_step_kernel(int n, double rr, const double* __restrict__ pAp, const double* __restrict__ p,
+                               const double* __restrict__ Ap, double* __restrict__ x, double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = *pAp;
+  const double alpha = (d > 0.0) ? rr / d : 0.0;
+  x[i] = alpha * p[i] + x[i];
+  r[i] = -alpha * Ap[i] + r[i];
 }
 __global__ __launch_bounds__(256) void rowsum_abs_kernel(int l, const double* __restrict__ A, int sq, double* __restrict__ rows) {
   __shared__ double red[256];
@@ -232,13 +325,30 @@ hipError_t symmetrize(int l, double* Z, hipStream_t st) {
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk((long long)l * l)), dim3(256), 0, st, l, Z);
   return hipGetLastError();
 }
-hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st) {
-  int nb = nblk(n);
+hipError_t dot2(long long n, const double* x1, const double* y1, double* o1, const double* x2, const double* y2,
+               double* o2, double* part, hipStream_t st) {
+  if (n <= kSmallDot) {
+    hipLaunchKernelGGL(dot2_small_kernel, dim3(1), dim3(1024), 0, st, (int)n, x1, y1, x2, y2, o1, o2);
+    return hipGetLastError();
+  }
+  long long nb = (n + 4 * 256 - 1) / (4 * 256);
   if (nb > kRedBlocks) nb = kRedBlocks;
-  if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(dot_part_kernel, dim3(nb), dim3(256), 0, st, (long long)n, x, y, part);
+  hipLaunchKernelGGL(dot2_part_kernel, dim3((unsigned)nb), dim3(256), 0, st, n, x1, y1, x2, y2, part);
   KOT_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(256), 0, st, nb, part, out);
+  hipLaunchKernelGGL(dot2_final_kernel, dim3(1), dim3(256), 0, st, (int)nb, part, o1, o2);
+  return hipGetLastError();
+}
+hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st) {
+  return dot2(n, x, y, out, nullptr, nullptr, nullptr, part, st);
+}
+hipError_t form_z(int l, const double* X, double a, const double* T, double c, double* Z, hipStream_t st) {
+  const int nt = (l + 31) / 32;
+  hipLaunchKernelGGL(form_z_kernel, dim3(nt, nt), dim3(256), 0, st, l, X, a, T, c, Z);
+  return hipGetLastError();
+}
+hipError_t cg_step(int n, double rr, const double* pAp, const double* p, const double* Ap, double* x, double* r,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(cg_step_kernel, dim3(nblk(n)), dim3(256), 0, st, n, rr, pAp, p, Ap, x, r);
   return hipGetLastError();
 }
 hipError_t rowsum_abs_max(int l, const double* A, bool square_entries, double* out, double* part, hipStream_t st) {

@@ -18,6 +18,14 @@ using namespace kot;
 
 namespace {
 
+constexpr int kScalarDoubles = 64, kScalarInts = 16;
+constexpr size_t kScalarBytes = kScalarDoubles * sizeof(double) + kScalarInts * sizeof(int);
+// scalar slots: 0-3 per-call temporaries; residual norms (|r1|^2, |r2|^2) of the EG point 4-5 and of the trial
+// 6-7; the theta-rule dots 8-11; inputs of the default EG step 12-13; |z|^2 14; CG scalars 16-19; pooled
+// feature statistics 24-25
+enum : int { SL_TMP = 0, SL_VN = 4, SL_TN = 6, SL_THETA = 8, SL_ETA = 12, SL_ZZ = 14, SL_RR = 16, SL_PAP = 17,
+             SL_XX = 18, SL_POOL = 24 };
+
 struct State {  // an iterate w = (gamma, X) with its residual and the spectral data of Z
   double* g = nullptr;
   double* X = nullptr;
@@ -51,7 +59,8 @@ struct kot_ctx {
   EigWork* eig = nullptr;
   int cap = 0;  // workspace l capacity
   std::vector<void*> bufs;
-  // scalar exchange
+  // scalar exchange: kScalarDoubles doubles then kScalarInts ints, device and pinned host, copied whole by
+  // every sync_read (slots below)
   double* dsc = nullptr;
   double* hsc = nullptr;
   int* dint = nullptr;
@@ -120,7 +129,7 @@ void free_ws(kot_ctx* c) {
 
 kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   HIPCHK(hipSetDevice(ctx->device));
-  const size_t need_part = std::max<size_t>({(size_t)kRedBlocks, (size_t)kDiagParts * l + 64, (size_t)nmax + 64,
+  const size_t need_part = std::max<size_t>({(size_t)2 * kRedBlocks, (size_t)kDiagParts * l + 64, (size_t)nmax + 64,
                                              (size_t)l + 64, nmax > 0 ? mean_gram_part_size(nmax) : (size_t)0});
   if (l <= ctx->cap && need_part <= ctx->part_cap) return KOT_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -164,9 +173,10 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   return KOT_OK;
 }
 
-kot_status sync_read(kot_ctx* ctx, int nd, int ni) {
-  if (nd > 0) HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->dsc, sizeof(double) * nd, hipMemcpyDeviceToHost, ctx->stream));
-  if (ni > 0) HIPCHK(hipMemcpyAsync(ctx->hint, ctx->dint, sizeof(int) * ni, hipMemcpyDeviceToHost, ctx->stream));
+// Copies every scalar slot to the host and waits for the stream: each host value read afterwards is that of
+// the last kernel enqueued before this call that wrote its slot.
+kot_status sync_read(kot_ctx* ctx, int = 0, int = 0) {
+  HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->dsc, kScalarBytes, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;
 }
@@ -217,12 +227,14 @@ kot_status r1_op(kot_ctx* ctx, const CoreView& cv, const double* g, const double
   return KOT_OK;
 }
 
+// Eigendecomposition of Z (warm basis P0 or null); *npos receives the number of positive eigenvalues.  The
+// host is synchronized with the stream on return.
 kot_status eig_run(kot_ctx* ctx, int l, const double* Z, const double* P0, double* P, double* w, const kot_params* p,
-                   int* sweeps_acc) {
+                   int* sweeps_acc, int* npos) {
   int sw = 0;
   double rel = 0.0;
   const int max_sw = p->eig_max_sweeps > 0 ? p->eig_max_sweeps : 30;
-  HIPCHK(eigh_jacobi(ctx->eig, l, Z, P0, P, w, ctx->eigtmp, max_sw, 1e-14, &sw, &rel, ctx->stream));
+  HIPCHK(eigh_jacobi(ctx->eig, l, Z, P0, P, w, ctx->eigtmp, max_sw, 1e-14, &sw, &rel, npos, ctx->stream));
   if (sweeps_acc) *sweeps_acc += sw;
   if (!(rel <= 1e-14)) {
     if (!std::isfinite(rel)) return fail(ctx, KOT_ERR_NUMERIC, "non-finite matrix in eigensolver");
@@ -243,29 +255,32 @@ kot_status proj_from_eig(kot_ctx* ctx, int l, const double* Z, const double* P, 
   return KOT_OK;
 }
 
-// Residual map Eq. (4.2) at state s (g, X set); fills r1, r2, P, s, a, norms.  P0: warm basis or null.
+// Residual map Eq. (4.2) at state s (g, X set); fills r1, r2, P, s, a.  P0: warm basis or null.  The squared
+// norms go to slots (slot, slot + 1); with defer the host reads them later (finish_norms after a sync_read),
+// otherwise at once.
+void finish_norms(kot_ctx* ctx, State& s, int slot) {
+  s.r1n = std::sqrt(ctx->hsc[slot]);
+  s.r2n = std::sqrt(ctx->hsc[slot + 1]);
+  s.rn = s.r1n + s.r2n;
+}
+
 kot_status residual_state(kot_ctx* ctx, const CoreView& cv, State& s, const double* P0, const kot_params* p,
-                          int* sweeps_acc) {
+                          int* sweeps_acc, int slot = SL_TMP, bool defer = false) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
   KCHK(phi_star(ctx, cv, s.g, ctx->T1));
-  HIPCHK(mat_sub(l * l, s.X, ctx->T1, ctx->Z, st));
-  HIPCHK(add_diag(l, -cv.lam1, ctx->Z, st));
-  HIPCHK(symmetrize(l, ctx->Z, st));
-  KCHK(eig_run(ctx, l, ctx->Z, P0, s.P, s.s, p, sweeps_acc));
-  HIPCHK(count_positive(l, s.s, ctx->dint, st));
-  KCHK(sync_read(ctx, 0, 1));
-  s.a = ctx->hint[0];
+  HIPCHK(form_z(l, s.X, 1.0, ctx->T1, -cv.lam1, ctx->Z, st));
+  KCHK(eig_run(ctx, l, ctx->Z, P0, s.P, s.s, p, sweeps_acc, &s.a));
   KCHK(proj_from_eig(ctx, l, ctx->Z, s.P, s.s, s.a, ctx->T1));
   HIPCHK(mat_sub(l * l, s.X, ctx->T1, s.r2, st));
   KCHK(r1_op(ctx, cv, s.g, s.X, s.r1, ctx->T2));
-  HIPCHK(dot(l, s.r1, s.r1, ctx->dsc + 0, ctx->part, st));
-  HIPCHK(dot(l * l, s.r2, s.r2, ctx->dsc + 1, ctx->part, st));
-  KCHK(sync_read(ctx, 2, 0));
-  s.r1n = std::sqrt(ctx->hsc[0]);
-  s.r2n = std::sqrt(ctx->hsc[1]);
-  s.rn = s.r1n + s.r2n;
+  HIPCHK(dot(l, s.r1, s.r1, ctx->dsc + slot, ctx->part, st));
+  HIPCHK(dot2((long long)l * l, s.r2, s.r2, ctx->dsc + slot + 1, nullptr, nullptr, nullptr, ctx->part, st));
   s.has_eig = true;
+  if (!defer) {
+    KCHK(sync_read(ctx));
+    finish_norms(ctx, s, slot);
+  }
   return KOT_OK;
 }
 
@@ -392,26 +407,23 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
     HIPCHK(vec_fill(l, 0.0, x, st));
     HIPCHK(vec_copy(l, ctx->a1, r, st));
     HIPCHK(vec_copy(l, ctx->a1, pp, st));
-    HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
-    KCHK(sync_read(ctx, 1, 0));
-    rr = ctx->hsc[0];
+    HIPCHK(dot(l, r, r, ctx->dsc + SL_RR, ctx->part, st));
+    KCHK(sync_read(ctx));
+    rr = ctx->hsc[SL_RR];
     double xx = 0.0;
+    // one host synchronization per iteration: the step length stays on the device, the host reads
+    // (p.Ap, r.r, x.x) after the update and decides on Eq. (4.5)
     while (it < p->cg_max_iter) {
       const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
       if (std::sqrt(rr) <= thr) break;
       KCHK(schur_matvec(ctx, cv, tp, pp, Ap));
-      HIPCHK(dot(l, pp, Ap, ctx->dsc + 0, ctx->part, st));
-      KCHK(sync_read(ctx, 1, 0));
-      const double pAp = ctx->hsc[0];
-      if (!(pAp > 0.0)) break;
-      const double alpha = rr / pAp;
-      HIPCHK(vec_axpby(l, alpha, pp, 1.0, x, st));
-      HIPCHK(vec_axpby(l, -alpha, Ap, 1.0, r, st));
-      HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
-      HIPCHK(dot(l, x, x, ctx->dsc + 1, ctx->part, st));
-      KCHK(sync_read(ctx, 2, 0));
-      const double rr_new = ctx->hsc[0];
-      xx = ctx->hsc[1];
+      HIPCHK(dot(l, pp, Ap, ctx->dsc + SL_PAP, ctx->part, st));
+      HIPCHK(cg_step(l, rr, ctx->dsc + SL_PAP, pp, Ap, x, r, st));
+      HIPCHK(dot2(l, r, r, ctx->dsc + SL_RR, x, x, ctx->dsc + SL_XX, ctx->part, st));
+      KCHK(sync_read(ctx));
+      if (!(ctx->hsc[SL_PAP] > 0.0)) break;  // the device skipped the update
+      const double rr_new = ctx->hsc[SL_RR];
+      xx = ctx->hsc[SL_XX];
       HIPCHK(vec_axpby(l, 1.0, r, rr_new / rr, pp, st));
       rr = rr_new;
       ++it;
@@ -427,11 +439,10 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
     double xx = 0.0;
     int sweeps = 0;
     while (true) {
-      HIPCHK(dot(l, r, r, ctx->dsc + 0, ctx->part, st));
-      HIPCHK(dot(l, x, x, ctx->dsc + 1, ctx->part, st));
-      KCHK(sync_read(ctx, 2, 0));
-      rr = ctx->hsc[0];
-      xx = ctx->hsc[1];
+      HIPCHK(dot2(l, r, r, ctx->dsc + SL_RR, x, x, ctx->dsc + SL_XX, ctx->part, st));
+      KCHK(sync_read(ctx));
+      rr = ctx->hsc[SL_RR];
+      xx = ctx->hsc[SL_XX];
       const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
       if (std::sqrt(rr) <= thr || sweeps >= 8 || it >= 4 * std::max(1, p->cg_max_iter)) break;
       // inner CG from d = 0 on the reduced-precision operator
@@ -447,16 +458,12 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
       for (int j = 0; j < std::max(1, p->cg_max_iter); ++j) {
         if (std::sqrt(rri) <= stop_in) break;
         KCHK(schur_matvec_lowp(ctx, cv, tp, pi, Api, bf16));
-        HIPCHK(dot(l, pi, Api, ctx->dsc + 0, ctx->part, st));
-        KCHK(sync_read(ctx, 1, 0));
-        const double pAp = ctx->hsc[0];
-        if (!(pAp > 0.0)) break;
-        const double alpha = rri / pAp;
-        HIPCHK(vec_axpby(l, alpha, pi, 1.0, d, st));
-        HIPCHK(vec_axpby(l, -alpha, Api, 1.0, ri, st));
-        HIPCHK(dot(l, ri, ri, ctx->dsc + 0, ctx->part, st));
-        KCHK(sync_read(ctx, 1, 0));
-        const double rr_new = ctx->hsc[0];
+        HIPCHK(dot(l, pi, Api, ctx->dsc + SL_PAP, ctx->part, st));
+        HIPCHK(cg_step(l, rri, ctx->dsc + SL_PAP, pi, Api, d, ri, st));
+        HIPCHK(dot(l, ri, ri, ctx->dsc + SL_TMP, ctx->part, st));
+        KCHK(sync_read(ctx));
+        if (!(ctx->hsc[SL_PAP] > 0.0)) break;
+        const double rr_new = ctx->hsc[SL_TMP];
         HIPCHK(vec_axpby(l, 1.0, ri, rr_new / rri, pi, st));
         rri = rr_new;
         ++it;
@@ -478,15 +485,13 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   return KOT_OK;
 }
 
-// Pi(Y) into out via an eigendecomposition warm-started from Pbasis (updated in place); ws: w buffer.
+// Pi(Y) into out via an eigendecomposition warm-started from Pbasis (updated in place); Y symmetric; wbuf: w.
 kot_status proj_psd(kot_ctx* ctx, int l, double* Y, double* Pbasis, double* wbuf, bool warm, double* out,
                     const kot_params* p, int* sweeps_acc) {
-  HIPCHK(symmetrize(l, Y, ctx->stream));
-  KCHK(eig_run(ctx, l, Y, warm ? Pbasis : nullptr, ctx->T2, wbuf, p, sweeps_acc));
+  int a = 0;
+  KCHK(eig_run(ctx, l, Y, warm ? Pbasis : nullptr, ctx->T2, wbuf, p, sweeps_acc, &a));
   HIPCHK(vec_copy(l * l, ctx->T2, Pbasis, ctx->stream));
-  HIPCHK(count_positive(l, wbuf, ctx->dint, ctx->stream));
-  KCHK(sync_read(ctx, 0, 1));
-  KCHK(proj_from_eig(ctx, l, Y, Pbasis, wbuf, ctx->hint[0], out));
+  KCHK(proj_from_eig(ctx, l, Y, Pbasis, wbuf, a, out));
   return KOT_OK;
 }
 
@@ -498,15 +503,13 @@ kot_status eg_step_impl(kot_ctx* ctx, const CoreView& cv, const double* g, const
   // half step: gh = g - eta r1(g,X);  Xh = Pi(X - eta (Phi*(g) + lam1 I))
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, r1, ctx->gh, st));
   KCHK(phi_star(ctx, cv, g, ctx->T1));
-  HIPCHK(vec_lincomb(l * l, 1.0, X, -eta, ctx->T1, ctx->Z, st));
-  HIPCHK(add_diag(l, -eta * cv.lam1, ctx->Z, st));
+  HIPCHK(form_z(l, X, eta, ctx->T1, -eta * cv.lam1, ctx->Z, st));
   KCHK(proj_psd(ctx, l, ctx->Z, ctx->Pe1, ctx->s_e1, warm, ctx->Xh, p, sweeps_acc));
   // full step with F at the half point
   KCHK(r1_op(ctx, cv, ctx->gh, ctx->Xh, ctx->r1h, ctx->T1));
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, ctx->r1h, gn, st));
   KCHK(phi_star(ctx, cv, ctx->gh, ctx->T1));
-  HIPCHK(vec_lincomb(l * l, 1.0, X, -eta, ctx->T1, ctx->Z, st));
-  HIPCHK(add_diag(l, -eta * cv.lam1, ctx->Z, st));
+  HIPCHK(form_z(l, X, eta, ctx->T1, -eta * cv.lam1, ctx->Z, st));
   KCHK(proj_psd(ctx, l, ctx->Z, ctx->Pe2, ctx->s_e2, warm, Xn, p, sweeps_acc));
   return KOT_OK;
 }
@@ -533,13 +536,16 @@ kot_status prepare_core(kot_ctx* ctx, CoreView& cv) {
   return KOT_OK;
 }
 
-kot_status default_eta(kot_ctx* ctx, const CoreView& cv, double* eta) {
+// Default EG step (Section 4.2): eta = 1 / (2 L) with L bounded by |Q|_inf/(2 lam2) + sqrt(|K o K|_inf).  The
+// row-sum maxima go to the SL_ETA slots; default_eta_read takes them after a later sync_read.
+kot_status default_eta_launch(kot_ctx* ctx, const CoreView& cv) {
   const int l = cv.l;
-  HIPCHK(rowsum_abs_max(l, cv.Q, false, ctx->dsc + 0, ctx->part, ctx->stream));
-  HIPCHK(rowsum_abs_max(l, cv.KK, false, ctx->dsc + 1, ctx->part, ctx->stream));
-  KCHK(sync_read(ctx, 2, 0));
-  *eta = 0.5 / (ctx->hsc[0] / (2.0 * cv.lam2) + std::sqrt(ctx->hsc[1]));
+  HIPCHK(rowsum_abs_max(l, cv.Q, false, ctx->dsc + SL_ETA, ctx->part, ctx->stream));
+  HIPCHK(rowsum_abs_max(l, cv.KK, false, ctx->dsc + SL_ETA + 1, ctx->part, ctx->stream));
   return KOT_OK;
+}
+double default_eta_read(kot_ctx* ctx, const CoreView& cv) {
+  return 0.5 / (ctx->hsc[SL_ETA] / (2.0 * cv.lam2) + std::sqrt(ctx->hsc[SL_ETA + 1]));
 }
 
 kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
@@ -637,7 +643,7 @@ kot_status predict_gamma0(kot_ctx* ctx, const CoreView& cv, int F, int H, const 
   const int l = cv.l;
   if (F != kFeatures) return fail(ctx, KOT_ERR_ARG, "the feature map has %d features (got F=%d)", kFeatures, F);
   KCHK(ensure_mlp(ctx, l, H, l));
-  HIPCHK(features(l, cv.Q, cv.z, cv.wsum, ctx->Kb, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + 8, ctx->fX, ctx->stream));
+  HIPCHK(features(l, cv.Q, cv.z, cv.wsum, ctx->Kb, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + SL_POOL, ctx->fX, ctx->stream));
   KCHK(mlp_forward_impl(ctx, l, mlp_view(F, H, theta), ctx->fX, ctx->fout));
   HIPCHK(f32_to_f64_scaled(l, ctx->fout, cv.lam1, gamma0, ctx->stream));
   return KOT_OK;
@@ -650,7 +656,9 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   HIPCHK(hipEventRecord(ctx->ev0, st));
   KCHK(prepare_core(ctx, cv));
   double eta = p->eg_step;
-  if (!(eta > 0.0)) KCHK(default_eta(ctx, cv, &eta));
+  const bool eta_default = !(eta > 0.0);
+  if (eta_default) KCHK(default_eta_launch(ctx, cv));       // read with the first residual's norms
+  if (gamma0 || p->ws_theta) HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + SL_ZZ, ctx->part, st));
   State* W = &ctx->S[0];
   State* T = &ctx->S[1];
   State* V = &ctx->S[2];
@@ -672,12 +680,11 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   }
   int sweeps = 0;
   KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+  if (eta_default) eta = default_eta_read(ctx, cv);
   res->warm_used = 0;
   if (gamma0) {
     // fallback: the cold start w = (0, 0) has |R| = |z|/(2 lam2) (Pi(-lambda1 I) = 0); keep the better one
-    HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + 0, ctx->part, st));
-    KCHK(sync_read(ctx, 1, 0));
-    const double cold = std::sqrt(ctx->hsc[0]) / (2.0 * cv.lam2);
+    const double cold = std::sqrt(ctx->hsc[SL_ZZ]) / (2.0 * cv.lam2);
     if (!(W->rn <= cold)) {
       HIPCHK(vec_fill(l, 0.0, W->g, st));
       HIPCHK(vec_fill(l * l, 0.0, W->X, st));
@@ -705,7 +712,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
       warm_e = true;
       std::swap(H->g, V->g);
       std::swap(H->X, V->X);
-      KCHK(residual_state(ctx, cv, *V, p->warm_eig ? V->P : nullptr, p, &sweeps));
+      KCHK(residual_state(ctx, cv, *V, p->warm_eig ? V->P : nullptr, p, &sweeps, SL_VN, true));
     }
     // (2) regularized SSN trial
     const double mu = theta * W->rn;
@@ -714,15 +721,17 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     cg_total += di.cg_iters;
     HIPCHK(vec_lincomb(l, 1.0, W->g, 1.0, ctx->dg, T->g, st));
     HIPCHK(vec_lincomb(l * l, 1.0, W->X, 1.0, ctx->dX, T->X, st));
-    KCHK(residual_state(ctx, cv, *T, p->warm_eig ? W->P : nullptr, p, &sweeps));
-    // theta rule (Section 4.3): rho = -<R(w + dw), dw>
-    HIPCHK(dot(l, T->r1, ctx->dg, ctx->dsc + 0, ctx->part, st));
-    HIPCHK(dot(l * l, T->r2, ctx->dX, ctx->dsc + 1, ctx->part, st));
-    HIPCHK(dot(l, ctx->dg, ctx->dg, ctx->dsc + 2, ctx->part, st));
-    HIPCHK(dot(l * l, ctx->dX, ctx->dX, ctx->dsc + 3, ctx->part, st));
-    KCHK(sync_read(ctx, 4, 0));
-    const double rho = -(ctx->hsc[0] + ctx->hsc[1]);
-    const double dwn = std::sqrt(ctx->hsc[2]) + std::sqrt(ctx->hsc[3]);
+    KCHK(residual_state(ctx, cv, *T, p->warm_eig ? W->P : nullptr, p, &sweeps, SL_TN, true));
+    // theta rule (Section 4.3): rho = -<R(w + dw), dw>; one host synchronization brings these dots and the
+    // deferred residual norms of the trial and of the EG point
+    HIPCHK(dot2(l, T->r1, ctx->dg, ctx->dsc + SL_THETA, ctx->dg, ctx->dg, ctx->dsc + SL_THETA + 2, ctx->part, st));
+    HIPCHK(dot2((long long)l * l, T->r2, ctx->dX, ctx->dsc + SL_THETA + 1, ctx->dX, ctx->dX, ctx->dsc + SL_THETA + 3,
+                ctx->part, st));
+    KCHK(sync_read(ctx));
+    finish_norms(ctx, *T, SL_TN);
+    if (use_eg) finish_norms(ctx, *V, SL_VN);
+    const double rho = -(ctx->hsc[SL_THETA] + ctx->hsc[SL_THETA + 1]);
+    const double dwn = std::sqrt(ctx->hsc[SL_THETA + 2]) + std::sqrt(ctx->hsc[SL_THETA + 3]);
     const double dw2 = dwn * dwn;
     if (rho >= p->alpha2 * dw2) theta = std::max(p->theta_min, p->beta0 * theta);
     else if (rho >= p->alpha1 * dw2) theta = p->beta1 * theta;
@@ -750,10 +759,10 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   // outputs
   if (res->gamma) HIPCHK(vec_copy(l, W->g, res->gamma, st));
   if (res->X) HIPCHK(vec_copy(l * l, W->X, res->X, st));
-  HIPCHK(dot(l, W->g, cv.wsum, ctx->dsc + 0, ctx->part, st));
+  HIPCHK(dot(l, W->g, cv.wsum, ctx->dsc + SL_TMP, ctx->part, st));
   HIPCHK(hipEventRecord(ctx->ev1, st));
-  KCHK(sync_read(ctx, 1, 0));
-  res->ot = (cv.q2 - ctx->hsc[0]) / (2.0 * cv.lam2);
+  KCHK(sync_read(ctx));
+  res->ot = (cv.q2 - ctx->hsc[SL_TMP]) / (2.0 * cv.lam2);
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   res->time_ms = ms;
@@ -862,11 +871,12 @@ kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return KOT_ERR_HIP; }
     ctx->own_stream = true;
   }
-  bool ok = hipMalloc(&ctx->dsc, 64 * sizeof(double)) == hipSuccess &&
-            hipHostMalloc(&ctx->hsc, 64 * sizeof(double)) == hipSuccess &&
-            hipMalloc(&ctx->dint, 16 * sizeof(int)) == hipSuccess &&
-            hipHostMalloc(&ctx->hint, 16 * sizeof(int)) == hipSuccess &&
+  bool ok = hipMalloc(&ctx->dsc, kScalarBytes) == hipSuccess && hipHostMalloc(&ctx->hsc, kScalarBytes) == hipSuccess &&
             hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
+  if (ok) {
+    ctx->dint = reinterpret_cast<int*>(ctx->dsc + kScalarDoubles);
+    ctx->hint = reinterpret_cast<int*>(ctx->hsc + kScalarDoubles);
+  }
   if (!ok) { kot_destroy(ctx); return KOT_ERR_HIP; }
   *out = ctx;
   return KOT_OK;
@@ -883,8 +893,6 @@ kot_status kot_destroy(kot_ctx* ctx) {
   ctx->mbufs.clear();
   hipFree(ctx->dsc);
   hipHostFree(ctx->hsc);
-  hipFree(ctx->dint);
-  hipHostFree(ctx->hint);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
   if (ctx->ev1) hipEventDestroy(ctx->ev1);
   if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
@@ -935,10 +943,9 @@ kot_status kot_eigh(kot_ctx* ctx, int l, const double* Z, double* P, double* w, 
   KCHK(check_ctx(ctx));
   if (l < 1 || l > 4096 || !Z || !P || !w || !p) return fail(ctx, KOT_ERR_ARG, "invalid argument");
   KCHK(ensure_ws(ctx, l, 0));
-  HIPCHK(vec_copy(l * l, Z, ctx->Z, ctx->stream));
-  HIPCHK(symmetrize(l, ctx->Z, ctx->stream));
-  int sw = 0;
-  kot_status s = eig_run(ctx, l, ctx->Z, nullptr, P, w, p, &sw);
+  HIPCHK(form_z(l, Z, 0.0, Z, 0.0, ctx->Z, ctx->stream));  // (Z + Z^T)/2
+  int sw = 0, npos = 0;
+  kot_status s = eig_run(ctx, l, ctx->Z, nullptr, P, w, p, &sw, &npos);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return s;
 }
@@ -1164,7 +1171,7 @@ kot_status kot_features(kot_ctx* ctx, int l, const double* Q, const double* z, c
   CoreView cv;
   cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.wsum = wsum; cv.q2 = q2; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
   KCHK(prepare_core(ctx, cv));
-  HIPCHK(features(l, Q, z, wsum, ctx->Kb, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + 8, X, ctx->stream));
+  HIPCHK(features(l, Q, z, wsum, ctx->Kb, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + SL_POOL, X, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;
 }

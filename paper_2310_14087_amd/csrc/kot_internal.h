@@ -80,10 +80,11 @@ struct EigWork;
 EigWork* eig_work_create(int lmax);
 void eig_work_destroy(EigWork* w);
 // Z (l x l) -> P (columns eigenvectors), wv ascending.  If P0 is non-null, starts from the basis P0
-// (columns orthonormal).  Returns the sweep count through *sweeps and off/norm through *rel_off.
+// (columns orthonormal).  Returns the sweep count through *sweeps, off/norm through *rel_off and the number
+// of positive eigenvalues through *npos (may be null); the host has synchronized with the stream on return.
 // tmp: workspace of at least 2*l*l doubles.
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
-                       int max_sweeps, double tol, int* sweeps, double* rel_off, hipStream_t st);
+                       int max_sweeps, double tol, int* sweeps, double* rel_off, int* npos, hipStream_t st);
 
 // ---- vector kernels -----------------------------------------------------------------------------------------
 hipError_t vec_fill(int n, double v, double* x, hipStream_t st);
@@ -97,9 +98,17 @@ hipError_t vec_lincomb(int n, double a, const double* x, double b, const double*
 hipError_t add_diag(int l, double a, double* X, hipStream_t st);
 // Z = 0.5 * (Z + Z^T)
 hipError_t symmetrize(int l, double* Z, hipStream_t st);
-// Deterministic reductions: out[slot] = sum x*y (or sum x^2); partials in part (>= kRedBlocks doubles).
+// Deterministic reductions: out[0] = sum x*y; partials in part (>= 2 kRedBlocks doubles).  dot2 forms one or
+// two dot products (x2 null: one) in the same launches.
 constexpr int kRedBlocks = 256;
 hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st);
+hipError_t dot2(long long n, const double* x1, const double* y1, double* o1, const double* x2, const double* y2,
+                double* o2, double* part, hipStream_t st);
+// Z = (M + M^T)/2 + c I with M = X - a T (l x l; Z must not alias X or T)
+hipError_t form_z(int l, const double* X, double a, const double* T, double c, double* Z, hipStream_t st);
+// CG update with a device step length: alpha = rr / pAp[0] (0 when pAp[0] <= 0); x += alpha p; r -= alpha Ap.
+hipError_t cg_step(int n, double rr, const double* pAp, const double* p, const double* Ap, double* x, double* r,
+                   hipStream_t st);
 // out[0] = max_i sum_j |A_ij| (row-sum norm)
 hipError_t rowsum_abs_max(int l, const double* A, bool square_entries, double* out, double* part, hipStream_t st);
 // out_int[0] = number of nonzero entries strictly below the diagonal of R (l x l)
