@@ -24,11 +24,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_mix1000_traffic.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2310_14087_amd", "csrc", "k_gemm.hip")
+
 PEAK = {  # MI355X published dense peaks
     "fp64_tflops": 78.6,
     "fp32_tflops": 157.3,
     "bf16_tflops": 2500.0,
     "hbm_gbs": 8000.0,
+}
+
+
+# profiler class -> (bound, published peak, unit)
+CLASS_ROOF = {
+    "gemm_f64": ("mfma", PEAK["fp64_tflops"], "TFLOP/s"),
+    "eig_sweep": ("mfma", PEAK["fp64_tflops"], "TFLOP/s"),
+    "gemv_f64": ("hbm", PEAK["hbm_gbs"], "GB/s"),
+    "gemm_f32": ("mfma", PEAK["fp32_tflops"], "TFLOP/s"),
+    "gemm_bf16": ("mfma", PEAK["bf16_tflops"], "TFLOP/s"),
 }
 
 
@@ -64,6 +77,35 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def gemm_traffic():
+    """HBM bytes per FP64 GEMM call from the committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy of known size), or None when there is none or the GEMM source changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.strip().lstrip("- ").split(": ", 1) for line in f if ": " in line)
+        with open(GEMM_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("gemm_source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_call"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_calibrate(mb):
+    """Device-to-device copies of a known size, for scaling the HBM byte counters."""
+    import torch
+    n = int(mb * (1 << 20) // 8)
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n,
+                                           "copies": 3}}), flush=True)
 
 
 def batch_bench(a):
@@ -109,13 +151,15 @@ def main():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mix1000")
-    ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed", "all"])
+    ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed", "mixed32", "all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the metric line: time kot_solve_batched on this many 'batch' problems")
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--tune", default=None, help="autotune table to load (or create when missing)")
+    ap.add_argument("--copy-calibrate", type=float, default=0.0,
+                    help="instead of the metric line: copy this many MiB device-to-device three times")
     a = ap.parse_args()
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -132,6 +176,8 @@ def main():
     dev = torch.device("cuda:0")
     if a.batch:
         return batch_bench(a)
+    if a.copy_calibrate > 0:
+        return copy_calibrate(a.copy_calibrate)
     n_inst = max(1, a.steps)
     _log(f"generating {n_inst} {a.workload} instances")
     probs = [make_problem(a.workload, s) for s in range(n_inst)]
@@ -141,19 +187,21 @@ def main():
 
     ctx = kotssn.Context(0)
     base = [dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol) for p in probs]
-    arms = ["fp64", "warm", "mixed"] if a.arm == "all" else [a.arm]
+    arms = ["fp64", "warm", "mixed32", "mixed"] if a.arm == "all" else [a.arm]
     theta_dev, H = None, 0
-    if "warm" in arms or "mixed" in arms:
+    if any(x != "fp64" for x in arms):
         from paper_2310_14087_amd import warmstart
         theta, F, H, meta = warmstart.load()
         theta_dev = torch.from_numpy(theta).to(dev)
 
     def params(i, arm):
         kw = dict(base[i])
-        if arm in ("warm", "mixed"):
+        if arm != "fp64":
             kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
         if arm == "mixed":
             kw.update(precision=kotssn.KOT_MIXED_BF16)
+        elif arm == "mixed32":
+            kw.update(precision=kotssn.KOT_FP32)
         return kotssn.default_params(**kw)
 
     def run_arm(arm, profile):
@@ -190,7 +238,7 @@ def main():
         _log(f"{arm}: {a.steps / el:.2f} solves/s, {conv}/{a.steps} converged")
     ctx.close()
     if "fp64" in out_arms:
-        for arm in ("warm", "mixed"):
+        for arm in ("warm", "mixed32", "mixed"):
             if arm in out_arms:
                 out_arms[arm]["ot_rel_dev_vs_fp64"] = max(
                     abs(x - y) / abs(y) for x, y in zip(out_arms[arm]["ot"], out_arms["fp64"]["ot"]))
@@ -216,11 +264,18 @@ def main():
     if prof:
         dom = max(prof, key=lambda c: prof[c]["ms"])
         pc = prof[dom]
-        ach = pc["flops"] / (pc["ms"] * 1e-3) / 1e12 if pc["ms"] > 0 else 0.0
-        out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
-                           "frac": ach / PEAK["fp64_tflops"], "traffic": None, "kernel": dom,
-                           "launches": pc["launches"], "avg_launch_us": 1e3 * pc["ms"] / max(1, pc["launches"]),
-                           "share_of_step": pc["ms"] * 1e-3 / elapsed}
+        bound, peak, unit = CLASS_ROOF[dom]
+        sec = pc["ms"] * 1e-3
+        if bound == "hbm":
+            ach = pc["bytes"] / sec / 1e9 if sec > 0 else 0.0
+        else:
+            ach = pc["flops"] / sec / 1e12 if sec > 0 else 0.0
+        nl = max(1, pc["launches"])
+        out["roofline"] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                           "traffic": gemm_traffic() if dom == "gemm_f64" else None,
+                           "traffic_unit": "HBM bytes per call", "kernel": dom, "launches": pc["launches"],
+                           "avg_launch_us": 1e6 * sec / nl, "flops_per_launch": pc["flops"] / nl,
+                           "algorithmic_bytes_per_launch": pc["bytes"] / nl, "share_of_step": sec / elapsed}
         out["profile"] = {c: {"launches": v["launches"], "ms": round(v["ms"], 3),
                               "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0}
                           for c, v in prof.items()}

@@ -3,6 +3,7 @@
 // (v_mfma_f32_16x16x4f32), accumulation in FP32.  The first product of the chain carries the Hadamard weight
 // Psi of Section 4.3 in its epilogue.
 #include "kot_internal.h"
+#include <algorithm>
 
 namespace kot {
 
@@ -35,11 +36,14 @@ __device__ __forceinline__ double psi_weight(int r, int j, int l, int a, double 
 }
 
 // C (m x n) = A (m x k, row-major, rows along k) diag(s) op(B); op(B) = B^T (TB: B is n x k) or B (k x n).
+// blockIdx.z = K split: with splits > 1 the raw partial tile goes to part[split][m][n] and the reduction
+// applies the epilogue.
 template <bool BF16, bool TB, bool PSI>
-__global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g) {
+__global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g, int splits, int kchunk, float* __restrict__ part) {
   __shared__ float As[LBM * LMK];
   __shared__ float Bs[LBK * LKM > LBN * LMK ? LBK * LKM : LBN * LMK];
-  const int M = g.m, N = g.n, K = g.k;
+  const int M = g.m, N = g.n;
+  const int kbeg = blockIdx.z * kchunk, K = min(g.k, kbeg + kchunk);
   const int m0 = blockIdx.y * LBM, n0 = blockIdx.x * LBN;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += LBK) {
+  for (int k0 = kbeg; k0 < K; k0 += LBK) {
     {  // A rows, lanes along k
       const int kk = t & 31, mm = t >> 5;
       const int gk = k0 + kk;
@@ -132,10 +136,26 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g) {
         const int col = n0 + wn * 32 + j * 16 + r16;
         if (row < M && col < N) {
           float r = acc[i][j][v];
-          if (PSI) r *= (float)psi_weight(g.r0 + row, col, g.l, g.a, g.mu, g.w, g.complement, g.diag_scale, g.off_scale);
-          g.C[(long long)row * g.ldc + col] = r;
+          if (splits > 1) {
+            part[((long long)blockIdx.z * M + row) * N + col] = r;
+          } else {
+            if (PSI) r *= (float)psi_weight(g.r0 + row, col, g.l, g.a, g.mu, g.w, g.complement, g.diag_scale, g.off_scale);
+            g.C[(long long)row * g.ldc + col] = r;
+          }
         }
       }
+}
+
+// C = sum over splits of the partial tiles (fixed order), then the Psi weight when requested.
+__global__ void lowp_reduce_kernel(LowpArgs g, int splits, int psi, const float* __restrict__ part) {
+  const long long mn = (long long)g.m * g.n;
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= mn) return;
+  float r = 0.f;
+  for (int q = 0; q < splits; ++q) r += part[q * mn + u];
+  const int row = (int)(u / g.n), col = (int)(u % g.n);
+  if (psi) r *= (float)psi_weight(g.r0 + row, col, g.l, g.a, g.mu, g.w, g.complement, g.diag_scale, g.off_scale);
+  g.C[(long long)row * g.ldc + col] = r;
 }
 
 __global__ void f64_to_f32_kernel(long long n, const double* __restrict__ x, float* __restrict__ y) {
@@ -172,15 +192,33 @@ __global__ void diag_dot_lowp_final(int n, double alpha, const double* __restric
 
 hipError_t gemm_lowp(const LowpArgs& g, bool bf16, bool psi, hipStream_t st) {
   if (g.m <= 0 || g.n <= 0 || g.k <= 0) return hipErrorInvalidValue;
-  dim3 grid((g.n + LBN - 1) / LBN, (g.m + LBM - 1) / LBM);
+  const int tiles = ((g.n + LBN - 1) / LBN) * ((g.m + LBM - 1) / LBM);
+  // K split for thin products (the chain runs with m = min(|alpha|, l - |alpha|) rows): about one workgroup
+  // per CU, at least 64 of K per split, partials in the split-K workspace (as floats)
+  int splits = 1;
+  if (tiles < 256 && g.k >= 128) splits = std::min(16, std::min((256 + tiles - 1) / tiles, g.k / 64));
+  float* part = reinterpret_cast<float*>(g_gemm_ws);
+  while (splits > 1 && (!part || (size_t)splits * g.m * g.n > 2 * g_gemm_ws_cap)) --splits;
+  int kchunk = g.k;
+  if (splits > 1) {
+    kchunk = ((g.k + splits - 1) / splits + LBK - 1) / LBK * LBK;
+    splits = (g.k + kchunk - 1) / kchunk;
+  }
+  dim3 grid((g.n + LBN - 1) / LBN, (g.m + LBM - 1) / LBM, splits);
   Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
   if (pf) pf->begin(st, bf16 ? PROF_GEMM_BF16 : PROF_GEMM_F32, 2.0 * g.m * g.n * (double)g.k,
                     4.0 * ((double)g.m * g.k + (double)g.k * g.n + (double)g.m * g.n));
 #define KOT_LOWP(BF, TB_, PS) \
-  if (bf16 == BF && (g.transb != 0) == TB_ && psi == PS) hipLaunchKernelGGL((gemm_lowp_kernel<BF, TB_, PS>), grid, dim3(256), 0, st, g);
+  if (bf16 == BF && (g.transb != 0) == TB_ && psi == PS) \
+    hipLaunchKernelGGL((gemm_lowp_kernel<BF, TB_, PS>), grid, dim3(256), 0, st, g, splits, kchunk, part);
   KOT_LOWP(true, true, true) KOT_LOWP(true, true, false) KOT_LOWP(true, false, true) KOT_LOWP(true, false, false)
   KOT_LOWP(false, true, true) KOT_LOWP(false, true, false) KOT_LOWP(false, false, true) KOT_LOWP(false, false, false)
 #undef KOT_LOWP
+  if (splits > 1) {
+    const long long mn = (long long)g.m * g.n;
+    hipLaunchKernelGGL(lowp_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, g, splits, psi ? 1 : 0,
+                       (const float*)part);
+  }
   if (pf) pf->end(st);
   return hipGetLastError();
 }
