@@ -6,11 +6,13 @@ embeddings, q^2, Cholesky factor) and Algorithm 2 to |R(w)| <= 1e-6.  The worklo
 samples per side, d = 10, two 4-component Gaussian mixtures, l = 1000 filling points), one instance per
 seed.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--arm fp64|warm|mixed|all] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--arm fp64|warm|mixed32|mixed16|mixed|all]
+                    [--no-cpu-baseline]
 
-Arms: ``fp64`` cold start, FP64 everywhere; ``warm`` learned warm start, FP64; ``mixed`` learned warm start
-with the CG matvec chain in BF16 (FP32 accumulation) inside FP64 iterative refinement.  ``value`` is the
-rate of the last arm run (``mixed`` by default); every arm's rate is in ``config.arms``.
+Arms: ``fp64`` cold start, FP64 everywhere; ``warm`` learned warm start, FP64; ``mixed32``, ``mixed16`` and
+``mixed``: learned warm start with the CG matvec chain in FP32, BF16 and split BF16 (three BF16 products per
+FP32 product) on the matrix cores, FP32 accumulation, inside FP64 iterative refinement.  ``value`` is the rate
+of the last arm run (``mixed`` by default); every arm's rate is in ``config.arms``.
 """
 from __future__ import annotations
 
@@ -42,6 +44,7 @@ CLASS_ROOF = {
     "gemv_f64": ("hbm", PEAK["hbm_gbs"], "GB/s"),
     "gemm_f32": ("mfma", PEAK["fp32_tflops"], "TFLOP/s"),
     "gemm_bf16": ("mfma", PEAK["bf16_tflops"], "TFLOP/s"),
+    "potential": ("alu", PEAK["fp64_tflops"], "TFLOP/s"),
 }
 
 
@@ -151,7 +154,7 @@ def main():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mix1000")
-    ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed", "mixed32", "all"])
+    ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed32", "mixed16", "mixed", "all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
@@ -187,7 +190,7 @@ def main():
 
     ctx = kotssn.Context(0)
     base = [dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol) for p in probs]
-    arms = ["fp64", "warm", "mixed32", "mixed"] if a.arm == "all" else [a.arm]
+    arms = ["fp64", "warm", "mixed32", "mixed16", "mixed"] if a.arm == "all" else [a.arm]
     theta_dev, H = None, 0
     if any(x != "fp64" for x in arms):
         from paper_2310_14087_amd import warmstart
@@ -199,6 +202,8 @@ def main():
         if arm != "fp64":
             kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
         if arm == "mixed":
+            kw.update(precision=kotssn.KOT_MIXED_BF16X3)
+        elif arm == "mixed16":
             kw.update(precision=kotssn.KOT_MIXED_BF16)
         elif arm == "mixed32":
             kw.update(precision=kotssn.KOT_FP32)
@@ -238,7 +243,7 @@ def main():
         _log(f"{arm}: {a.steps / el:.2f} solves/s, {conv}/{a.steps} converged")
     ctx.close()
     if "fp64" in out_arms:
-        for arm in ("warm", "mixed32", "mixed"):
+        for arm in ("warm", "mixed32", "mixed16", "mixed"):
             if arm in out_arms:
                 out_arms[arm]["ot_rel_dev_vs_fp64"] = max(
                     abs(x - y) / abs(y) for x, y in zip(out_arms[arm]["ot"], out_arms["fp64"]["ot"]))

@@ -36,8 +36,13 @@ typedef enum {
   KOT_ERR_EIG = -6         /* eigensolver did not reach its off-diagonal tolerance */
 } kot_status;
 
-typedef enum { KOT_FP64 = 0, KOT_FP32 = 1, KOT_MIXED_BF16 = 2 } kot_precision;
-typedef enum { KOT_SAFEGUARD_EG = 0, KOT_SAFEGUARD_NONE = 1 } kot_safeguard;
+/* Arithmetic of the CG matvec chain: FP64; FP32 products; BF16 products; or split BF16 products (each FP32
+ * operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi), product hi*hi + hi*lo + lo*hi), all three with
+ * FP32 accumulation inside FP64 iterative refinement. */
+typedef enum { KOT_FP64 = 0, KOT_FP32 = 1, KOT_MIXED_BF16 = 2, KOT_MIXED_BF16X3 = 3 } kot_precision;
+/* Algorithm 2 with its extragradient safeguard (EG), the regularized SSN steps alone (NONE), or the safeguard
+ * alone: pure extragradient iterations on Eq. (4.1), the comparison method of Appendix F (EG_ONLY). */
+typedef enum { KOT_SAFEGUARD_EG = 0, KOT_SAFEGUARD_NONE = 1, KOT_SAFEGUARD_EG_ONLY = 2 } kot_safeguard;
 
 /* Parameters of Algorithm 2 and the inexactness rule Eq. (4.5).  kot_params_default fills the values
  * used throughout: tol 1e-6, max_iter 200, cg_max_iter 20 (Remark 4.5), tau = kappa = 0.5,
@@ -209,13 +214,24 @@ kot_status kot_mlp_adam(kot_ctx* ctx, int P, float* theta, const float* grad, fl
 kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm, int F, int H,
                          const float* theta, double* gamma0);
 
+/* Kantorovich potentials and transport map of a solved problem (Section 3): with the dual gamma (device, l)
+ * returned by kot_solve for the same problem and parameters, the maximizers of Eq. (3.2) are
+ *   u(x) = (w_mu(x) - sum_i gamma_i k(xf_i, x)) / (2 lambda2),  v(y) = (w_nu(y) - sum_i gamma_i k(yf_i, y)) / (2 lambda2),
+ * w_mu(x) = (1/n_src) sum_j k(xs_j, x), and for the cost |x - y|^2/2 the map T(x) = x - grad u(x).
+ * xq, yq: m query points (device, m x d, row-major; either may be NULL); u, v (device, m) receive u(xq), v(yq);
+ * Tx (device, m x d, may be NULL; needs xq) receives T(xq).  d <= 64.  Deterministic (fixed-order sums).
+ * The context keeps a workspace of about 1024 x 17 doubles per 256 queries (grown on demand). */
+kot_status kot_potentials(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm, const double* gamma, int m,
+                          const double* xq, const double* yq, double* u, double* v, double* Tx);
+
 /* Launch profiler for measurement.  enable = 1 clears and starts recording HIP events around every launch
  * of the instrumented kernel classes on the context's stream; enable = 0 stops, waits for the stream, and
  * writes 4 values per class into out (host, 4 * nclass doubles; may be NULL): launches, total milliseconds
  * between the events, algorithmic flops and algorithmic bytes.  Classes: 0 = FP64 GEMM (2mnk flops),
  * 1 = one Jacobi sweep (all rounds of pair solves + tile updates, replayed as one captured HIP graph; flops of
  * the 16x16 tile products), 2 = FP64 matrix-vector product (2mk flops, bytes of the matrix and vectors),
- * 3 = FP32 chain GEMM, 4 = BF16 chain GEMM (2mnk flops each). */
+ * 3 = FP32 chain GEMM, 4 = BF16 chain GEMM (2mnk flops each), 5 = potential evaluation (kot_potentials;
+ * (6d + 3) flops per query-source pair, counting the exponential as one). */
 kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass);
 
 #ifdef __cplusplus

@@ -66,7 +66,8 @@ class Params:
     theta_min: float = 1e-6
     theta_max: float = 1e6
     eg_step: float = 0.0           # 0 => default bound-based step
-    safeguard: str = "eg"          # "eg" (Algorithm 2 as written) or "none" (pure regularized SSN)
+    safeguard: str = "eg"          # "eg" (Algorithm 2 as written), "none" (pure regularized SSN) or "eg_only"
+                                   # (pure extragradient, the comparison method of Appendix F)
     null_step: bool = True         # reading: keep w_k when it beats both the trial and v_{k+1}
     eps_jitter: float = 1e-10
 
@@ -352,6 +353,11 @@ def solve(core: Core, prm: Params | None = None, gamma0=None, X0=None, record: b
             break
         if k == prm.max_iter:
             break
+        if prm.safeguard == "eg_only":
+            g, X = eg_step(core, g, X, eta)
+            r1, r2, rn, eig = residual(core, g, X)
+            rv = rn
+            continue
         # (1) safeguard sequence: one EG step on v
         if prm.safeguard == "eg":
             vg, vX = eg_step(core, vg, vX, eta)

@@ -19,7 +19,7 @@ INCLUDE = ROOT / "include"
 BUILD = PKG / "_build"
 LIB = PKG / "libkotssn.so"
 
-SOURCES = ["k_gemm.hip", "k_setup.hip", "k_eig.hip", "k_vec.hip", "k_mlp.hip", "k_lowp.hip", "kot_api.cpp"]
+SOURCES = ["k_gemm.hip", "k_setup.hip", "k_eig.hip", "k_vec.hip", "k_mlp.hip", "k_lowp.hip", "k_pot.hip", "kot_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KOT_OFFLOAD_ARCH", "gfx950")

@@ -1,7 +1,8 @@
 // Reduced-precision GEMMs for the CG matvec chain (Algorithm 1): inputs FP32 in global memory, products on the
-// matrix cores in BF16 (v_mfma_f32_16x16x16bf16_1k, operands rounded to bfloat16) or FP32
-// (v_mfma_f32_16x16x4f32), accumulation in FP32.  The first product of the chain carries the Hadamard weight
-// Psi of Section 4.3 in its epilogue.
+// matrix cores in FP32 (v_mfma_f32_16x16x4f32), BF16 (v_mfma_f32_16x16x16bf16_1k, operands rounded to
+// bfloat16) or split BF16 (each operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the product is
+// hi*hi + hi*lo + lo*hi, about 16 significant bits from three BF16 products), accumulation in FP32.  The
+// first product of the chain carries the Hadamard weight Psi of Section 4.3 in its epilogue.
 #include "kot_internal.h"
 #include <algorithm>
 
@@ -21,6 +22,16 @@ __device__ __forceinline__ short to_bf16(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
   return (short)(u >> 16);
 }
+__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float((unsigned)(unsigned short)h << 16); }
+// hi and lo parts of four values
+__device__ __forceinline__ void split4(const float f[4], shrt4& hi, shrt4& lo) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const short h = to_bf16(f[q]);
+    hi[q] = h;
+    lo[q] = to_bf16(f[q] - from_bf16(h));
+  }
+}
 
 // Psi weight of entry (r, j) (eigen-index r, ascending eigenvalues w, alpha = [l-a, l)); see psi_kernel.
 __device__ __forceinline__ double psi_weight(int r, int j, int l, int a, double mu, const double* __restrict__ w,
@@ -38,7 +49,8 @@ __device__ __forceinline__ double psi_weight(int r, int j, int l, int a, double 
 // C (m x n) = A (m x k, row-major, rows along k) diag(s) op(B); op(B) = B^T (TB: B is n x k) or B (k x n).
 // blockIdx.z = K split: with splits > 1 the raw partial tile goes to part[split][m][n] and the reduction
 // applies the epilogue.
-template <bool BF16, bool TB, bool PSI>
+// MODE: 0 FP32, 1 BF16, 2 split BF16
+template <int MODE, bool TB, bool PSI>
 __global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g, int splits, int kchunk, float* __restrict__ part) {
   __shared__ float As[LBM * LMK];
   __shared__ float Bs[LBK * LKM > LBN * LMK ? LBK * LKM : LBN * LMK];
@@ -80,7 +92,7 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g, int splits, 
       }
     }
     __syncthreads();
-    if (BF16) {
+    if (MODE == 1) {
 #pragma unroll
       for (int ks = 0; ks < LBK; ks += 16) {
         shrt4 a[2], b[2];
@@ -105,6 +117,38 @@ __global__ __launch_bounds__(256) void gemm_lowp_kernel(LowpArgs g, int splits, 
 #pragma unroll
           for (int j = 0; j < 2; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    } else if (MODE == 2) {
+#pragma unroll
+      for (int ks = 0; ks < LBK; ks += 16) {
+        shrt4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float* ap = As + (wm * 32 + i * 16 + r16) * LMK + ks + 4 * k4;
+          const float f[4] = {ap[0], ap[1], ap[2], ap[3]};
+          split4(f, ah[i], al[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = wn * 32 + j * 16 + r16, kb = ks + 4 * k4;
+          float f[4];
+          if (TB) {
+            const float* bp = Bs + col * LMK + kb;
+            f[0] = bp[0]; f[1] = bp[1]; f[2] = bp[2]; f[3] = bp[3];
+          } else {
+            f[0] = Bs[kb * LKM + col]; f[1] = Bs[(kb + 1) * LKM + col];
+            f[2] = Bs[(kb + 2) * LKM + col]; f[3] = Bs[(kb + 3) * LKM + col];
+          }
+          split4(f, bh[j], bl[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          }
       }
     } else {
 #pragma unroll
@@ -190,7 +234,7 @@ __global__ void diag_dot_lowp_final(int n, double alpha, const double* __restric
 
 }  // namespace
 
-hipError_t gemm_lowp(const LowpArgs& g, bool bf16, bool psi, hipStream_t st) {
+hipError_t gemm_lowp(const LowpArgs& g, int mode, bool psi, hipStream_t st) {
   if (g.m <= 0 || g.n <= 0 || g.k <= 0) return hipErrorInvalidValue;
   const int tiles = ((g.n + LBN - 1) / LBN) * ((g.m + LBM - 1) / LBM);
   // K split for thin products (the chain runs with m = min(|alpha|, l - |alpha|) rows): about one workgroup
@@ -206,13 +250,15 @@ hipError_t gemm_lowp(const LowpArgs& g, bool bf16, bool psi, hipStream_t st) {
   }
   dim3 grid((g.n + LBN - 1) / LBN, (g.m + LBM - 1) / LBM, splits);
   Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
-  if (pf) pf->begin(st, bf16 ? PROF_GEMM_BF16 : PROF_GEMM_F32, 2.0 * g.m * g.n * (double)g.k,
+  if (pf) pf->begin(st, mode ? PROF_GEMM_BF16 : PROF_GEMM_F32, 2.0 * g.m * g.n * (double)g.k,
                     4.0 * ((double)g.m * g.k + (double)g.k * g.n + (double)g.m * g.n));
-#define KOT_LOWP(BF, TB_, PS) \
-  if (bf16 == BF && (g.transb != 0) == TB_ && psi == PS) \
-    hipLaunchKernelGGL((gemm_lowp_kernel<BF, TB_, PS>), grid, dim3(256), 0, st, g, splits, kchunk, part);
-  KOT_LOWP(true, true, true) KOT_LOWP(true, true, false) KOT_LOWP(true, false, true) KOT_LOWP(true, false, false)
-  KOT_LOWP(false, true, true) KOT_LOWP(false, true, false) KOT_LOWP(false, false, true) KOT_LOWP(false, false, false)
+#define KOT_LOWP(MD, TB_, PS) \
+  if (mode == MD && (g.transb != 0) == TB_ && psi == PS) \
+    hipLaunchKernelGGL((gemm_lowp_kernel<MD, TB_, PS>), grid, dim3(256), 0, st, g, splits, kchunk, part);
+#define KOT_LOWP_MODE(MD) \
+  KOT_LOWP(MD, true, true) KOT_LOWP(MD, true, false) KOT_LOWP(MD, false, true) KOT_LOWP(MD, false, false)
+  KOT_LOWP_MODE(0) KOT_LOWP_MODE(1) KOT_LOWP_MODE(2)
+#undef KOT_LOWP_MODE
 #undef KOT_LOWP
   if (splits > 1) {
     const long long mn = (long long)g.m * g.n;

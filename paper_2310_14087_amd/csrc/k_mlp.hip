@@ -32,38 +32,66 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmF32Args g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += FBK) {
-    if (!TA) {  // A[m][k], lanes along k -> m-major tile
+  // the next K slice is loaded into registers while the current one feeds the matrix cores
+  float ra[8], rb[8];
+  auto load = [&](int k0) {
+    if (!TA) {  // A[m][k], lanes along k
       const int kk = t & 31, mm = t >> 5;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int gm = m0 + mm + 8 * u, gk = k0 + kk;
-        As[(mm + 8 * u) * FMK + kk] = (gm < M && gk < K) ? g.A[(long long)gm * g.lda + gk] : 0.f;
+        ra[u] = (gm < M && gk < K) ? g.A[(long long)gm * g.lda + gk] : 0.f;
       }
-    } else {    // A[k][m], lanes along m -> k-major tile
+    } else {    // A[k][m], lanes along m
       const int mm = t & 63, kk = t >> 6;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int gm = m0 + mm, gk = k0 + kk + 4 * u;
-        As[(kk + 4 * u) * FKM + mm] = (gm < M && gk < K) ? g.A[(long long)gk * g.lda + gm] : 0.f;
+        ra[u] = (gm < M && gk < K) ? g.A[(long long)gk * g.lda + gm] : 0.f;
       }
     }
-    if (!TB) {  // B[k][n], lanes along n -> k-major
+    if (!TB) {  // B[k][n], lanes along n
       const int nn = t & 63, kk = t >> 6;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int gn = n0 + nn, gk = k0 + kk + 4 * u;
-        Bs[(kk + 4 * u) * FKM + nn] = (gn < N && gk < K) ? g.B[(long long)gk * g.ldb + gn] : 0.f;
+        rb[u] = (gn < N && gk < K) ? g.B[(long long)gk * g.ldb + gn] : 0.f;
       }
-    } else {    // B[n][k], lanes along k -> n-major
+    } else {    // B[n][k], lanes along k
       const int kk = t & 31, nn = t >> 5;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int gn = n0 + nn + 8 * u, gk = k0 + kk;
-        Bs[(nn + 8 * u) * FMK + kk] = (gn < N && gk < K) ? g.B[(long long)gn * g.ldb + gk] : 0.f;
+        rb[u] = (gn < N && gk < K) ? g.B[(long long)gn * g.ldb + gk] : 0.f;
       }
     }
-    __syncthreads();
+  };
+  auto store = [&]() {
+    if (!TA) {
+      const int kk = t & 31, mm = t >> 5;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) As[(mm + 8 * u) * FMK + kk] = ra[u];
+    } else {
+      const int mm = t & 63, kk = t >> 6;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) As[(kk + 4 * u) * FKM + mm] = ra[u];
+    }
+    if (!TB) {
+      const int nn = t & 63, kk = t >> 6;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Bs[(kk + 4 * u) * FKM + nn] = rb[u];
+    } else {
+      const int kk = t & 31, nn = t >> 5;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Bs[(nn + 8 * u) * FMK + kk] = rb[u];
+    }
+  };
+  load(0);
+  store();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += FBK) {
+    const bool more = k0 + FBK < K;
+    if (more) load(k0 + FBK);
 #pragma unroll
     for (int ks = 0; ks < FBK; ks += 4) {
       float a[2], b[2];
@@ -82,7 +110,11 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmF32Args g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
+    if (more) {
+      __syncthreads();
+      store();
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -102,6 +134,26 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmF32Args g) {
           *p = r;
         }
       }
+}
+
+// n == 1 with op(A) = A and op(B) = B (k x 1): one wavefront per row, the same epilogue as the GEMM.
+__global__ __launch_bounds__(256) void gemv_f32_kernel(GemmF32Args g) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= g.m) return;
+  const float* a = g.A + (long long)row * g.lda;
+  float acc = 0.f;
+  for (int c = lane; c < g.k; c += 64) acc += a[c] * g.B[(long long)c * g.ldb];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    float* p = g.C + (long long)row * g.ldc;
+    float r = acc;
+    if (g.beta != 0.f) r += g.beta * (*p);
+    if (g.bias) r += g.bias[0];
+    if (g.act == 1) r = fmaxf(r, 0.f);
+    if (g.mask) r = (g.mask[(long long)row * g.ldm] > 0.f) ? r : 0.f;
+    *p = r;
+  }
 }
 
 // out[j] = sum_i X[i][j] over rows, in 16 fixed slabs then a fixed-order sum.
@@ -275,6 +327,10 @@ __global__ __launch_bounds__(256) void lift_threshold_kernel(int l, int nb, cons
 
 hipError_t gemm_f32(const GemmF32Args& g, hipStream_t st) {
   if (g.m <= 0 || g.n <= 0 || g.k <= 0) return hipErrorInvalidValue;
+  if (g.n == 1 && g.ta == 0 && g.tb == 0) {
+    hipLaunchKernelGGL(gemv_f32_kernel, dim3((g.m + 3) / 4), dim3(256), 0, st, g);
+    return hipGetLastError();
+  }
   dim3 grid((g.n + FBN - 1) / FBN, (g.m + FBM - 1) / FBM);
   if (g.ta == 0 && g.tb == 0) hipLaunchKernelGGL((gemm_f32_kernel<false, false>), grid, dim3(256), 0, st, g);
   else if (g.ta == 0 && g.tb == 1) hipLaunchKernelGGL((gemm_f32_kernel<false, true>), grid, dim3(256), 0, st, g);

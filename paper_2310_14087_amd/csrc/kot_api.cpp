@@ -47,6 +47,7 @@ struct CoreView {  // dual data of Eq. (3.4) on the device
   double q2 = 0.0;
   double lam1 = 0.0, lam2 = 0.0;
   double* KK = nullptr;  // (R^T R) o (R^T R)
+  double kb_eps = -1.0;  // >= 0: the context's K buffer holds K from the setup; R^T R = K + kb_eps I
 };
 
 }  // namespace
@@ -85,6 +86,9 @@ struct kot_ctx {
   double* rs3 = nullptr;
   // batched solves: child contexts (own stream and workspace), one host worker thread each
   std::vector<kot_ctx*> lanes;
+  // potentials: split partial sums (grown on demand)
+  double* pot_part = nullptr;
+  size_t pot_part_cap = 0;
   // split-K targets per size bucket (autotuner)
   int tune[kTuneBuckets];
   bool tuned = false;
@@ -356,7 +360,7 @@ kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const
 
 // Same operator with the chain in reduced precision (Bf holds B in FP32): FP32/BF16 products, FP32
 // accumulation, FP64 for the Q and (K o K) terms.
-kot_status schur_matvec_lowp(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const double* v, double* y, bool bf16) {
+kot_status schur_matvec_lowp(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const double* v, double* y, int mode) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
   HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / (2.0 * cv.lam2), cv.Q, l, nullptr, v, 1, 0.0, y, 1));
@@ -368,11 +372,11 @@ kot_status schur_matvec_lowp(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, 
   g.m = tp.m; g.n = l; g.k = l; g.A = Bs; g.lda = l; g.s = v; g.B = ctx->Bf; g.ldb = l; g.transb = 1;
   g.C = ctx->Cf; g.ldc = l; g.l = l; g.a = tp.a; g.r0 = tp.r0; g.mu = tp.mu; g.w = tp.w; g.complement = tp.comp ? 1 : 0;
   g.diag_scale = 1.0; g.off_scale = 2.0;
-  HIPCHK(gemm_lowp(g, bf16, true, st));                 // H = Psi o (B_set diag(v) B^T)
+  HIPCHK(gemm_lowp(g, mode, true, st));                 // H = Psi o (B_set diag(v) B^T)
   LowpArgs g2{};
   g2.m = tp.m; g2.n = l; g2.k = l; g2.A = ctx->Cf; g2.lda = l; g2.s = nullptr; g2.B = ctx->Bf; g2.ldb = l; g2.transb = 0;
   g2.C = ctx->Ef; g2.ldc = l;
-  HIPCHK(gemm_lowp(g2, bf16, false, st));               // E = H B
+  HIPCHK(gemm_lowp(g2, mode, false, st));               // E = H B
   HIPCHK(diag_dot_lowp(tp.m, l, tp.comp ? -1.0 : 1.0, Bs, l, ctx->Ef, l, y, ctx->part, st));
   return KOT_OK;
 }
@@ -431,8 +435,8 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   } else {
     // Iterative refinement: each sweep solves M~ d = r with CG whose chain runs in reduced precision, then
     // x += d and the true residual r = a1 - M x is recomputed in FP64; Eq. 4.5 is checked on that residual.
-    const bool bf16 = p->precision == KOT_MIXED_BF16;
-    const double inner_rel = bf16 ? 1e-2 : 1e-4;
+    const int mode = p->precision == KOT_MIXED_BF16 ? 1 : (p->precision == KOT_MIXED_BF16X3 ? 2 : 0);
+    const double inner_rel = mode == 1 ? 1e-2 : 1e-4;
     HIPCHK(f64_to_f32((long long)l * l, ctx->Bm, ctx->Bf, st));
     HIPCHK(vec_fill(l, 0.0, x, st));
     HIPCHK(vec_copy(l, ctx->a1, r, st));
@@ -457,7 +461,7 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
       const double stop_in = std::max(inner_rel * std::sqrt(rr), 0.5 * thr);
       for (int j = 0; j < std::max(1, p->cg_max_iter); ++j) {
         if (std::sqrt(rri) <= stop_in) break;
-        KCHK(schur_matvec_lowp(ctx, cv, tp, pi, Api, bf16));
+        KCHK(schur_matvec_lowp(ctx, cv, tp, pi, Api, mode));
         HIPCHK(dot(l, pi, Api, ctx->dsc + SL_PAP, ctx->part, st));
         HIPCHK(cg_step(l, rri, ctx->dsc + SL_PAP, pi, Api, d, ri, st));
         HIPCHK(dot(l, ri, ri, ctx->dsc + SL_TMP, ctx->part, st));
@@ -489,8 +493,7 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
 kot_status proj_psd(kot_ctx* ctx, int l, double* Y, double* Pbasis, double* wbuf, bool warm, double* out,
                     const kot_params* p, int* sweeps_acc) {
   int a = 0;
-  KCHK(eig_run(ctx, l, Y, warm ? Pbasis : nullptr, ctx->T2, wbuf, p, sweeps_acc, &a));
-  HIPCHK(vec_copy(l * l, ctx->T2, Pbasis, ctx->stream));
+  KCHK(eig_run(ctx, l, Y, warm ? Pbasis : nullptr, Pbasis, wbuf, p, sweeps_acc, &a));  // P0 may alias P
   KCHK(proj_from_eig(ctx, l, Y, Pbasis, wbuf, a, out));
   return KOT_OK;
 }
@@ -529,8 +532,10 @@ kot_status copy_state(kot_ctx* ctx, int l, const State& from, State& to) {
 kot_status prepare_core(kot_ctx* ctx, CoreView& cv) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
-  // KK = (R^T R) o (R^T R)
-  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, cv.R, l, nullptr, cv.R, l, 0.0, ctx->Kb, l, TRI_A_LOWER | TRI_B_UPPER, true));
+  // KK = (R^T R) o (R^T R); after the setup R^T R = K + eps I is at hand without the product
+  if (cv.kb_eps >= 0.0) HIPCHK(add_diag(l, cv.kb_eps, ctx->Kb, st));
+  else HIPCHK(mm(st, 1, 0, l, l, l, 1.0, cv.R, l, nullptr, cv.R, l, 0.0, ctx->Kb, l, TRI_A_LOWER | TRI_B_UPPER, true));
+  cv.kb_eps = -1.0;  // Kb now holds R^T R
   HIPCHK(hadamard_square(l * l, ctx->Kb, ctx->KKb, st));
   cv.KK = ctx->KKb;
   return KOT_OK;
@@ -553,9 +558,10 @@ kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
   if (need_sigma && !(p->sigma > 0.0)) return fail(ctx, KOT_ERR_ARG, "sigma must be > 0");
   if (!(p->lambda1 > 0.0) || !(p->lambda2 > 0.0)) return fail(ctx, KOT_ERR_ARG, "lambda1, lambda2 must be > 0");
   if (p->max_iter < 0 || p->cg_max_iter < 0) return fail(ctx, KOT_ERR_ARG, "negative iteration cap");
-  if (p->precision != KOT_FP64 && p->precision != KOT_FP32 && p->precision != KOT_MIXED_BF16)
+  if (p->precision != KOT_FP64 && p->precision != KOT_FP32 && p->precision != KOT_MIXED_BF16 &&
+      p->precision != KOT_MIXED_BF16X3)
     return fail(ctx, KOT_ERR_ARG, "unknown precision %d", p->precision);
-  if (p->safeguard != KOT_SAFEGUARD_EG && p->safeguard != KOT_SAFEGUARD_NONE)
+  if (p->safeguard != KOT_SAFEGUARD_EG && p->safeguard != KOT_SAFEGUARD_NONE && p->safeguard != KOT_SAFEGUARD_EG_ONLY)
     return fail(ctx, KOT_ERR_ARG, "unknown safeguard %d", p->safeguard);
   return KOT_OK;
 }
@@ -705,6 +711,15 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     if (!std::isfinite(W->rn)) { status = KOT_ERR_NUMERIC; break; }
     if (W->rn <= p->tol) { status = KOT_OK; break; }
     if (k >= p->max_iter) break;
+    if (p->safeguard == KOT_SAFEGUARD_EG_ONLY) {  // pure extragradient: w_{k+1} = EG step from w_k
+      State* H = &ctx->S[3];
+      KCHK(eg_step_impl(ctx, cv, W->g, W->X, W->r1, eta, H->g, H->X, warm_e && p->warm_eig, p, &sweeps));
+      warm_e = true;
+      std::swap(H->g, W->g);
+      std::swap(H->X, W->X);
+      KCHK(residual_state(ctx, cv, *W, p->warm_eig ? W->P : nullptr, p, &sweeps));
+      continue;
+    }
     // (1) safeguard: one EG step on v, then R(v_{k+1})
     if (use_eg) {
       State* H = &ctx->S[3];
@@ -891,6 +906,7 @@ kot_status kot_destroy(kot_ctx* ctx) {
   free_ws(ctx);
   for (void* p : ctx->mbufs) hipFree(p);
   ctx->mbufs.clear();
+  if (ctx->pot_part) hipFree(ctx->pot_part);
   hipFree(ctx->dsc);
   hipHostFree(ctx->hsc);
   if (ctx->ev0) hipEventDestroy(ctx->ev0);
@@ -922,7 +938,7 @@ kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, c
   KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2));
   CoreView cv;
   cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb; cv.q2 = q2;
-  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2; cv.kb_eps = p->eps_jitter;
   return run_alg2(ctx, cv, p, gamma0, res);
 }
 
@@ -1215,9 +1231,41 @@ kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* pb, const kot_params* 
   KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2));
   CoreView cv;
   cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb; cv.q2 = q2;
-  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2; cv.kb_eps = p->eps_jitter;
   KCHK(prepare_core(ctx, cv));
   KCHK(predict_gamma0(ctx, cv, F, H, theta, gamma0));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KOT_OK;
+}
+
+kot_status kot_potentials(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, const double* gamma, int m,
+                          const double* xq, const double* yq, double* u, double* v, double* Tx) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_problem(ctx, pb));
+  KCHK(check_params(ctx, p, true));
+  if (m < 0 || !gamma || (m > 0 && !((xq && u) || (yq && v))) || (Tx && !xq))
+    return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  if (m == 0) return KOT_OK;
+  const int d = pb->d;
+  const int splits_x = potential_splits(m, pb->n_src, pb->l), splits_y = potential_splits(m, pb->n_tgt, pb->l);
+  const size_t need = std::max(potential_part_size(m, d, splits_x), potential_part_size(m, d, splits_y));
+  if (need > ctx->pot_part_cap) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->pot_part) hipFree(ctx->pot_part);
+    ctx->pot_part = nullptr;
+    ctx->pot_part_cap = 0;
+    if (hipMalloc(&ctx->pot_part, need * sizeof(double)) != hipSuccess) {
+      ctx->pot_part = nullptr;
+      return fail(ctx, KOT_ERR_OOM, "potential workspace allocation failed");
+    }
+    ctx->pot_part_cap = need;
+  }
+  if (xq && u)
+    HIPCHK(potential_eval(m, d, xq, pb->xs, pb->n_src, pb->xf, pb->l, gamma, p->sigma, p->lambda2, splits_x,
+                          ctx->pot_part, u, Tx, ctx->stream));
+  if (yq && v)
+    HIPCHK(potential_eval(m, d, yq, pb->ys, pb->n_tgt, pb->yf, pb->l, gamma, p->sigma, p->lambda2, splits_y,
+                          ctx->pot_part, v, nullptr, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;
 }

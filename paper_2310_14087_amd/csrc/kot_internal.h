@@ -9,7 +9,7 @@ namespace kot {
 
 // ---- optional launch profiler (events around kernel launches on the issuing stream) -----------------------
 enum ProfClass { PROF_GEMM_F64 = 0, PROF_EIG_ROUND = 1, PROF_GEMV_F64 = 2, PROF_GEMM_F32 = 3, PROF_GEMM_BF16 = 4,
-                 PROF_NCLASS = 5 };
+                 PROF_POTENTIAL = 5, PROF_NCLASS = 6 };
 struct Profiler {
   bool on = false;
   struct Rec { int cls; double flops; double bytes; hipEvent_t a, b; };
@@ -160,6 +160,17 @@ hipError_t trtri_upper(int l, const double* R, double* Y, double* T, hipStream_t
 hipError_t lift_diag(int l, const double* Qg, const double* z, const double* g, double lam1, double lam2, double frac,
                      double* d, double* part, hipStream_t st);
 
+// ---- potentials and transport map (k_pot.hip) ----------------------------------------------------------------
+// u(q_i) = (w(q_i) - sum_j gamma_j k(fill_j, q_i)) / (2 lam2) and, when T is non-null, T(q_i) = q_i - grad u(q_i),
+// for m query rows q (m x d, d <= 64), samples (ns x d), fill (l x d).  part: potential_part_size(m, d, splits)
+// doubles; splits from potential_splits.
+int potential_dim(int d);
+size_t potential_part_size(int m, int d, int splits);
+int potential_splits(int m, int ns, int l);
+hipError_t potential_eval(int m, int d, const double* q, const double* samples, int ns, const double* fill, int l,
+                          const double* gamma, double sigma, double lam2, int splits, double* part, double* u,
+                          double* T, hipStream_t st);
+
 // ---- reduced-precision CG chain (k_lowp.hip) --------------------------------------------------------------
 struct LowpArgs {
   int m, n, k;
@@ -175,7 +186,8 @@ struct LowpArgs {
   int complement;
   double diag_scale, off_scale;
 };
-hipError_t gemm_lowp(const LowpArgs& g, bool bf16, bool psi, hipStream_t st);
+// mode: 0 FP32 products, 1 BF16, 2 split BF16 (three products); FP32 accumulation
+hipError_t gemm_lowp(const LowpArgs& g, int mode, bool psi, hipStream_t st);
 hipError_t f64_to_f32(long long n, const double* x, float* y, hipStream_t st);
 // y[j] += alpha * sum_{r < m} A[r][j] B[r][j]; part >= 16 n doubles
 hipError_t diag_dot_lowp(int m, int n, double alpha, const float* A, int lda, const float* B, int ldb, double* y,

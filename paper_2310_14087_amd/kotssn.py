@@ -18,8 +18,8 @@ _LIBPATH = Path(__file__).resolve().parent / "libkotssn.so"
 
 KOT_OK, KOT_NOT_CONVERGED = 0, 1
 KOT_ERR_ARG, KOT_ERR_HIP, KOT_ERR_OOM, KOT_ERR_FACTOR, KOT_ERR_NUMERIC, KOT_ERR_EIG = -1, -2, -3, -4, -5, -6
-KOT_FP64, KOT_FP32, KOT_MIXED_BF16 = 0, 1, 2
-KOT_SAFEGUARD_EG, KOT_SAFEGUARD_NONE = 0, 1
+KOT_FP64, KOT_FP32, KOT_MIXED_BF16, KOT_MIXED_BF16X3 = 0, 1, 2, 3
+KOT_SAFEGUARD_EG, KOT_SAFEGUARD_NONE, KOT_SAFEGUARD_EG_ONLY = 0, 1, 2
 
 STATUS_NAMES = {0: "KOT_OK", 1: "KOT_NOT_CONVERGED", -1: "KOT_ERR_ARG", -2: "KOT_ERR_HIP", -3: "KOT_ERR_OOM",
                 -4: "KOT_ERR_FACTOR", -5: "KOT_ERR_NUMERIC", -6: "KOT_ERR_EIG"}
@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "KOT_OK", 1: "KOT_NOT_CONVERGED", -1: "KOT_ERR_ARG", -2: "KOT
 EXPORTED = ["kot_params_default", "kot_create", "kot_destroy", "kot_last_error", "kot_setup", "kot_solve",
             "kot_solve_core", "kot_eigh", "kot_residual", "kot_ssn_direction", "kot_eg_step", "kot_cholesky",
             "kot_gemm", "kot_profile", "kot_mlp_params", "kot_features", "kot_mlp_forward", "kot_mlp_loss_grad",
-            "kot_mlp_adam", "kot_warmstart", "kot_solve_batched", "kot_autotune", "kot_autotune_load"]
+            "kot_mlp_adam", "kot_warmstart", "kot_solve_batched", "kot_autotune", "kot_autotune_load",
+            "kot_potentials"]
 
 
 class KotParams(C.Structure):
@@ -92,6 +93,7 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
         "kot_solve_batched": (i, [vp, i, P(KotProblem), P(KotParams), i, vp, P(KotResult), P(i), i]),
         "kot_autotune": (i, [vp, P(i), i, C.c_char_p, P(i)]),
         "kot_autotune_load": (i, [vp, C.c_char_p]),
+        "kot_potentials": (i, [vp, P(KotProblem), P(KotParams), vp, i, vp, vp, vp, vp, vp]),
     }
     for name, (rt, args) in sig.items():
         f = getattr(lib, name)
@@ -349,7 +351,24 @@ class Context:
         self._check(self.lib.kot_warmstart(self.h, C.byref(pb), C.byref(prm), N_FEATURES, H, _fptr(theta), _ptr(g0)))
         return g0
 
-    PROFILE_CLASSES = ("gemm_f64", "eig_sweep", "gemv_f64", "gemm_f32", "gemm_bf16")
+    def potentials(self, xs, ys, xf, yf, prm: KotParams, gamma, xq=None, yq=None, want_map=True):
+        """(u(xq), v(yq), T(xq)) of a solved problem; entries for a missing query set are None."""
+        import torch
+        l, dd = xf.shape
+        pb = KotProblem(xs.shape[0], ys.shape[0], dd, l, _ptr(xs), _ptr(ys), _ptr(xf), _ptr(yf))
+        q = xq if xq is not None else yq
+        m = 0 if q is None else q.shape[0]
+        mk = lambda *shape: torch.empty(shape, device=xf.device, dtype=torch.float64)
+        u = mk(m) if xq is not None else None
+        v = mk(m) if yq is not None else None
+        T = mk(m, dd) if (xq is not None and want_map) else None
+        if xq is not None and yq is not None and xq.shape[0] != yq.shape[0]:
+            raise ValueError("xq and yq must have the same number of rows")
+        self._check(self.lib.kot_potentials(self.h, C.byref(pb), C.byref(prm), _ptr(gamma), m, _ptr(xq), _ptr(yq),
+                                            _ptr(u), _ptr(v), _ptr(T)))
+        return u, v, T
+
+    PROFILE_CLASSES = ("gemm_f64", "eig_sweep", "gemv_f64", "gemm_f32", "gemm_bf16", "potential")
 
     def profile_start(self):
         self._check(self.lib.kot_profile(self.h, 1, None, 0))

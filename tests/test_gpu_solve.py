@@ -58,7 +58,7 @@ def test_tiny_fixed_iterations(gpu_ctx, iters):
     np.testing.assert_allclose(_n(gamma), ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
 
 
-@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("precision", [1, 2, 3])
 @pytest.mark.parametrize("name,l,n,seed", [("mix1000", 150, 600, 0), ("batch", 120, 500, 8)])
 def test_solve_reduced_precision_cg(gpu_ctx, precision, name, l, n, seed):
     """Full solves with the FP32 / BF16 CG chain reach the oracle's estimate; eigendecompositions,
@@ -74,3 +74,20 @@ def test_solve_reduced_precision_cg(gpu_ctx, precision, name, l, n, seed):
     assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
     _, _, rn, _ = ko.residual(core, _n(gamma), _n(X))
     assert rn <= 1.01 * p.tol
+
+
+def test_pure_extragradient_trajectory(gpu_ctx):
+    """The safeguard alone (Appendix F's comparison method): the GPU residual history follows the oracle's
+    iteration by iteration, and both end at the SSN solution."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem("mix256", 1, l=12, n=60)
+    print("[case] kot_solve safeguard=EG_ONLY mix256 l=12", flush=True)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=1e-8, max_iter=5000, safeguard="eg_only"))
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=1e-8, max_iter=5000,
+                                safeguard=kotssn.KOT_SAFEGUARD_EG_ONLY)
+    g, _, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, hist_cap=64)
+    assert r.status == kotssn.KOT_OK and abs(r.iters - ref["iters"]) <= 2
+    oh = np.array([h["res"] for h in ref["history"][:64]])
+    np.testing.assert_allclose(r.res_hist[:len(oh)], oh, rtol=1e-8)
+    np.testing.assert_allclose(_n(g), ref["gamma"], atol=1e-9 * np.abs(ref["gamma"]).max())

@@ -210,7 +210,7 @@ def test_eg_step(gpu_ctx, name, l, n):
     np.testing.assert_allclose(_n(Xn), oXn, atol=1e-11 * max(1.0, np.abs(oXn).max()))
 
 
-@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("precision", [1, 2, 3])
 @pytest.mark.parametrize("name,l,n,mu", [("tiny", None, None, 0.3), ("mix1000", 120, 400, 0.05),
                                          ("gauss500", 80, 300, 1.0)])
 def test_ssn_direction_reduced_precision(gpu_ctx, precision, name, l, n, mu):

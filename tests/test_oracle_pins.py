@@ -403,3 +403,17 @@ def test_adam_first_step():
     g = np.array([0.3, -2.0, 1e-3])
     th, m, v = mlp.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=1e-8)
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8))
+
+
+def test_pure_extragradient_reaches_the_ssn_solution():
+    """Pure extragradient (Appendix F's comparison method) and Algorithm 2 solve the same monotone inclusion:
+    run long enough, EG's dual agrees with the SSN dual (unique, Q > 0)."""
+    p = make_problem("mix256", 1, l=12, n=60)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=1e-11))
+    eg = ko.solve(core, ko.Params(tol=1e-8, max_iter=20000, safeguard="eg_only"), record=False)
+    assert ref["status"] == "converged" and eg["status"] == "converged"
+    np.testing.assert_allclose(eg["gamma"], ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
+    hist = ko.solve(core, ko.Params(tol=0.0, max_iter=50, safeguard="eg_only"))["history"]
+    # Korpelevich's method with step below 1/L: the distance to the solution does not grow; the residual falls
+    assert hist[-1]["res"] < hist[0]["res"]
