@@ -364,9 +364,9 @@ struct EigWork {
   double* norms = nullptr;    // device [4]: slot 2 = rotation threshold
   double* hnorms = nullptr;   // pinned host [4]
   int* perm = nullptr;        // device [lmax]
-  double* boff = nullptr;     // device block norms: off-diagonal part [nbmax^2], all entries [nbmax^2], positive
-                              // diagonal counts [nbmax]
-  double* hb = nullptr;       // pinned host copy
+  double* hb = nullptr;       // block norms: off-diagonal part [nbmax^2], all entries [nbmax^2], positive diagonal
+                              // counts [nbmax]; pinned, mapped and coherent host memory written by the kernel
+  double* boff = nullptr;     // device address of hb
   int2* list = nullptr;       // device pair lists of a threshold sweep [(nbmax - 1) * nbmax / 2]
   int2* hlist = nullptr;      // pinned host staging of the lists
   std::vector<int> round_k;   // active pairs per round of the current threshold sweep
@@ -390,8 +390,9 @@ EigWork* eig_work_create(int lmax) {
             hipMalloc(&w->norms, sizeof(double) * 4) == hipSuccess &&
             hipHostMalloc(&w->hnorms, sizeof(double) * 4) == hipSuccess &&
             hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess &&
-            hipMalloc(&w->boff, sizeof(double) * (2 * nb2 + nbmax)) == hipSuccess &&
-            hipHostMalloc(&w->hb, sizeof(double) * (2 * nb2 + nbmax)) == hipSuccess &&
+            hipHostMalloc(&w->hb, sizeof(double) * (2 * nb2 + nbmax), hipHostMallocMapped | hipHostMallocCoherent) ==
+                hipSuccess &&
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&w->boff), w->hb, 0) == hipSuccess &&
             hipMalloc(&w->list, sizeof(int2) * nlist) == hipSuccess &&
             hipHostMalloc(&w->hlist, sizeof(int2) * nlist) == hipSuccess;
   if (!ok) { eig_work_destroy(w); return nullptr; }
@@ -402,7 +403,7 @@ void eig_work_destroy(EigWork* w) {
   if (!w) return;
   if (w->graph) hipGraphExecDestroy(w->graph);
   hipFree(w->U); hipFree(w->flag); hipFree(w->norms); hipHostFree(w->hnorms); hipFree(w->perm);
-  hipFree(w->boff); hipHostFree(w->hb); hipFree(w->list); hipHostFree(w->hlist);
+  hipHostFree(w->hb); hipFree(w->list); hipHostFree(w->hlist);
   delete w;
 }
 
@@ -414,7 +415,6 @@ static hipError_t block_norms(EigWork* w, int l, int nb, const double* A, hipStr
   hipLaunchKernelGGL(block_norm_kernel, dim3(nb, nb), dim3(64), 0, st, l, nb, A, w->boff, w->boff + nb2,
                      w->boff + 2 * nb2);
   KOT_HIP_TRY(hipGetLastError());
-  KOT_HIP_TRY(hipMemcpyAsync(w->hb, w->boff, sizeof(double) * (2 * nb2 + nb), hipMemcpyDeviceToHost, st));
   KOT_HIP_TRY(hipStreamSynchronize(st));
   double so = 0.0, sa = 0.0, sp = 0.0;
   for (int b1 = 0; b1 < nb; ++b1) {
@@ -520,9 +520,9 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     g.transa = 1; g.A = P0; g.B = V; g.C = A;
     g.lower = 1; g.mirror = 1;  // symmetric result: lower tiles, mirrored
     KOT_HIP_TRY(gemm_f64(g, st));
-    KOT_HIP_TRY(hipMemcpyAsync(V, P0, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    KOT_HIP_TRY(vec_copy((int)nn, P0, V, st));
   } else {
-    KOT_HIP_TRY(hipMemcpyAsync(A, Z, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    KOT_HIP_TRY(vec_copy((int)nn, Z, A, st));
     hipLaunchKernelGGL(eye_kernel, dim3(eb), dim3(256), 0, st, l, V);
     KOT_HIP_TRY(hipGetLastError());
   }

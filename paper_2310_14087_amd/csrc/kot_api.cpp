@@ -63,7 +63,8 @@ struct kot_ctx {
   // scalar exchange: kScalarDoubles doubles then kScalarInts ints, device and pinned host, copied whole by
   // every sync_read (slots below)
   double* dsc = nullptr;
-  double* hsc = nullptr;
+  double* hsc = nullptr;      // pinned, mapped and coherent: written by a device copy, read by the host
+  double* hsc_dev = nullptr;  // device address of hsc
   int* dint = nullptr;
   int* hint = nullptr;
   double* part = nullptr;      // reduction partials (>= max(kRedBlocks, kDiagParts*l, n, q^2 tile pairs))
@@ -180,7 +181,8 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
 // Copies every scalar slot to the host and waits for the stream: each host value read afterwards is that of
 // the last kernel enqueued before this call that wrote its slot.
 kot_status sync_read(kot_ctx* ctx, int = 0, int = 0) {
-  HIPCHK(hipMemcpyAsync(ctx->hsc, ctx->dsc, kScalarBytes, hipMemcpyDeviceToHost, ctx->stream));
+  static_assert(kScalarBytes % 16 == 0, "scalar block copied as double pairs");
+  HIPCHK(vec_copy((int)(kScalarBytes / sizeof(double)), ctx->dsc, ctx->hsc_dev, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;
 }
@@ -886,7 +888,9 @@ kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return KOT_ERR_HIP; }
     ctx->own_stream = true;
   }
-  bool ok = hipMalloc(&ctx->dsc, kScalarBytes) == hipSuccess && hipHostMalloc(&ctx->hsc, kScalarBytes) == hipSuccess &&
+  bool ok = hipMalloc(&ctx->dsc, kScalarBytes) == hipSuccess &&
+            hipHostMalloc(&ctx->hsc, kScalarBytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->hsc_dev), ctx->hsc, 0) == hipSuccess &&
             hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;
   if (ok) {
     ctx->dint = reinterpret_cast<int*>(ctx->dsc + kScalarDoubles);
