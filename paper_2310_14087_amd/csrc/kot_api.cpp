@@ -6,7 +6,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
+#include <functional>
+#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstdio>
@@ -49,6 +53,8 @@ struct CoreView {  // dual data of Eq. (3.4) on the device
   double* KK = nullptr;  // (R^T R) o (R^T R)
   double kb_eps = -1.0;  // >= 0: the context's K buffer holds K from the setup; R^T R = K + kb_eps I
 };
+
+struct SideRunner;
 
 }  // namespace
 
@@ -93,6 +99,9 @@ struct kot_ctx {
   // split-K targets per size bucket (autotuner)
   int tune[kTuneBuckets];
   bool tuned = false;
+  // second stream and host thread for the extragradient branch of Algorithm 2 (created on first use)
+  SideRunner* side = nullptr;
+  bool is_lane = false;  // a child context of kot_solve_batched
 };
 
 namespace {
@@ -657,6 +666,129 @@ kot_status predict_gamma0(kot_ctx* ctx, const CoreView& cv, int F, int H, const 
   return KOT_OK;
 }
 
+// ---- the extragradient branch on a second stream ---------------------------------------------------------
+// In each iteration of Algorithm 2 the extragradient iterate v_{k+1} and its residual depend only on v_k, and
+// the Newton trial only on w_k: the branches meet in the accept test alone, so they can run concurrently.  A
+// child context (own stream, workspace and eigensolver state) runs the extragradient branch from a host
+// thread of its own while the calling thread runs the Newton branch; the kernels and their inputs are the
+// same as on one stream, so are the iterates.  Between jobs the thread spins for a few milliseconds (the next
+// job of a solve comes within that), then sleeps on a condition variable.
+struct SideRunner {
+  kot_ctx* c = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cvar;
+  std::atomic<int> state{0};  // 0 idle, 1 job posted, 2 job done
+  std::atomic<bool> quit{false};
+  std::function<kot_status()> job;
+  kot_status rc = KOT_OK;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at a post; the side stream waits for it
+};
+
+void bind_thread(kot_ctx* c) {
+  g_prof = &c->prof;
+  g_gemm_ws = c->gemm_ws;
+  g_gemm_ws_cap = c->gemm_ws_cap;
+  g_gemm_tune = c->tuned ? c->tune : nullptr;
+}
+
+void side_loop(SideRunner* s) {
+  using clk = std::chrono::steady_clock;
+  for (;;) {
+    const auto t0 = clk::now();
+    int spins = 0;
+    while (s->state.load(std::memory_order_acquire) != 1) {
+      if (s->quit.load(std::memory_order_acquire)) return;
+      if (++spins >= 256) {
+        spins = 0;
+        if (clk::now() - t0 > std::chrono::milliseconds(5)) {
+          std::unique_lock<std::mutex> lk(s->mu);
+          s->cvar.wait(lk, [s] { return s->quit.load() || s->state.load() == 1; });
+          continue;
+        }
+      }
+      __builtin_ia32_pause();
+    }
+    kot_ctx* c = s->c;
+    bind_thread(c);
+    kot_status rc;
+    if (hipSetDevice(c->device) != hipSuccess || hipStreamWaitEvent(c->stream, s->ready, 0) != hipSuccess)
+      rc = fail(c, KOT_ERR_HIP, "could not order the side stream after the caller's stream");
+    else
+      rc = s->job();
+    s->rc = rc;
+    s->state.store(2, std::memory_order_release);
+  }
+}
+
+kot_status side_ensure(kot_ctx* ctx, int l) {
+  if (!ctx->side) {
+    SideRunner* s = new SideRunner();
+    kot_ctx* c = nullptr;
+    const kot_status st = kot_create(&c, ctx->device, nullptr);
+    if (st != KOT_OK) {
+      delete s;
+      return fail(ctx, st, "could not create the side context");
+    }
+    s->c = c;
+    if (hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess) {
+      kot_destroy(c);
+      delete s;
+      return fail(ctx, KOT_ERR_HIP, "could not create the side event");
+    }
+    s->th = std::thread(side_loop, s);
+    ctx->side = s;
+  }
+  kot_ctx* c = ctx->side->c;
+  c->tuned = ctx->tuned;
+  if (ctx->tuned) std::copy(ctx->tune, ctx->tune + kTuneBuckets, c->tune);
+  const kot_status st = ensure_ws(c, l, 0);
+  bind_thread(ctx);  // ensure_ws binds the calling thread to the context it sizes
+  if (st < 0) return fail(ctx, st, "side workspace: %s", c->err.c_str());
+  return KOT_OK;
+}
+
+kot_status side_post(kot_ctx* ctx, std::function<kot_status()> f) {
+  SideRunner* s = ctx->side;
+  HIPCHK(hipEventRecord(s->ready, ctx->stream));
+  s->c->prof.on = ctx->prof.on;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->job = std::move(f);
+    s->state.store(1, std::memory_order_release);
+  }
+  s->cvar.notify_one();
+  return KOT_OK;
+}
+
+// Waits for the posted job; on return the side stream has finished all of the job's work (the job ends with a
+// host synchronization of that stream).
+kot_status side_join(kot_ctx* ctx) {
+  SideRunner* s = ctx->side;
+  while (s->state.load(std::memory_order_acquire) != 2) __builtin_ia32_pause();
+  s->state.store(0, std::memory_order_relaxed);
+  s->job = nullptr;
+  if (s->rc < 0) return fail(ctx, s->rc, "extragradient branch: %s", s->c->err.c_str());
+  return KOT_OK;
+}
+
+void side_destroy(kot_ctx* ctx) {
+  SideRunner* s = ctx->side;
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->quit.store(true, std::memory_order_release);
+  }
+  s->cvar.notify_one();
+  if (s->th.joinable()) s->th.join();
+  if (s->ready) hipEventDestroy(s->ready);
+  kot_destroy(s->c);
+  delete s;
+  ctx->side = nullptr;
+}
+
+constexpr int kOverlapMinL = 128;
+
 // Algorithm 2 on a prepared core.
 kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const double* gamma0, kot_result* res) {
   const int l = cv.l;
@@ -702,6 +834,9 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     }
   }
   const bool use_eg = p->safeguard == KOT_SAFEGUARD_EG;
+  const bool overlap = use_eg && p->overlap && l >= kOverlapMinL && !ctx->is_lane;
+  int side_sweeps = 0;
+  if (overlap) KCHK(side_ensure(ctx, l));
   if (use_eg) KCHK(copy_state(ctx, l, *W, *V));
   double theta = p->theta0;
   int k = 0, cg_total = 0, eg_acc = 0, nulls = 0;
@@ -722,8 +857,19 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
       KCHK(residual_state(ctx, cv, *W, p->warm_eig ? W->P : nullptr, p, &sweeps));
       continue;
     }
-    // (1) safeguard: one EG step on v, then R(v_{k+1})
-    if (use_eg) {
+    // (1) safeguard: one EG step on v, then R(v_{k+1}); on the side stream when overlapped
+    if (use_eg && overlap) {
+      const bool warm_v = warm_e && p->warm_eig;
+      KCHK(side_post(ctx, [ctx, &cv, V, eta, warm_v, p, &side_sweeps]() -> kot_status {
+        kot_ctx* c = ctx->side->c;
+        State* H = &ctx->S[3];
+        KCHK(eg_step_impl(c, cv, V->g, V->X, V->r1, eta, H->g, H->X, warm_v, p, &side_sweeps));
+        std::swap(H->g, V->g);
+        std::swap(H->X, V->X);
+        return residual_state(c, cv, *V, p->warm_eig ? V->P : nullptr, p, &side_sweeps, SL_VN, false);
+      }));
+      warm_e = true;
+    } else if (use_eg) {
       State* H = &ctx->S[3];
       KCHK(eg_step_impl(ctx, cv, V->g, V->X, V->r1, eta, H->g, H->X, warm_e && p->warm_eig, p, &sweeps));
       warm_e = true;
@@ -734,19 +880,31 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     // (2) regularized SSN trial
     const double mu = theta * W->rn;
     DirInfo di;
-    KCHK(ssn_direction(ctx, cv, *W, mu, p, &di));
-    cg_total += di.cg_iters;
-    HIPCHK(vec_lincomb(l, 1.0, W->g, 1.0, ctx->dg, T->g, st));
-    HIPCHK(vec_lincomb(l * l, 1.0, W->X, 1.0, ctx->dX, T->X, st));
-    KCHK(residual_state(ctx, cv, *T, p->warm_eig ? W->P : nullptr, p, &sweeps, SL_TN, true));
-    // theta rule (Section 4.3): rho = -<R(w + dw), dw>; one host synchronization brings these dots and the
-    // deferred residual norms of the trial and of the EG point
-    HIPCHK(dot2(l, T->r1, ctx->dg, ctx->dsc + SL_THETA, ctx->dg, ctx->dg, ctx->dsc + SL_THETA + 2, ctx->part, st));
-    HIPCHK(dot2((long long)l * l, T->r2, ctx->dX, ctx->dsc + SL_THETA + 1, ctx->dX, ctx->dX, ctx->dsc + SL_THETA + 3,
-                ctx->part, st));
-    KCHK(sync_read(ctx));
+    auto newton = [&]() -> kot_status {
+      KCHK(ssn_direction(ctx, cv, *W, mu, p, &di));
+      cg_total += di.cg_iters;
+      HIPCHK(vec_lincomb(l, 1.0, W->g, 1.0, ctx->dg, T->g, st));
+      HIPCHK(vec_lincomb(l * l, 1.0, W->X, 1.0, ctx->dX, T->X, st));
+      KCHK(residual_state(ctx, cv, *T, p->warm_eig ? W->P : nullptr, p, &sweeps, SL_TN, true));
+      // theta rule (Section 4.3): rho = -<R(w + dw), dw>; one host synchronization brings these dots and the
+      // deferred residual norms of the trial and of the EG point
+      HIPCHK(dot2(l, T->r1, ctx->dg, ctx->dsc + SL_THETA, ctx->dg, ctx->dg, ctx->dsc + SL_THETA + 2, ctx->part, st));
+      HIPCHK(dot2((long long)l * l, T->r2, ctx->dX, ctx->dsc + SL_THETA + 1, ctx->dX, ctx->dX,
+                  ctx->dsc + SL_THETA + 3, ctx->part, st));
+      KCHK(sync_read(ctx));
+      return KOT_OK;
+    };
+    const kot_status rc_newton = newton();
+    if (use_eg && overlap) {
+      const kot_status rc_side = side_join(ctx);  // joined even when the Newton branch failed
+      sweeps += side_sweeps;
+      side_sweeps = 0;
+      KCHK(rc_newton);
+      KCHK(rc_side);
+    }
+    KCHK(rc_newton);
     finish_norms(ctx, *T, SL_TN);
-    if (use_eg) finish_norms(ctx, *V, SL_VN);
+    if (use_eg && !overlap) finish_norms(ctx, *V, SL_VN);
     const double rho = -(ctx->hsc[SL_THETA] + ctx->hsc[SL_THETA + 1]);
     const double dwn = std::sqrt(ctx->hsc[SL_THETA + 2]) + std::sqrt(ctx->hsc[SL_THETA + 3]);
     const double dw2 = dwn * dwn;
@@ -872,6 +1030,7 @@ void kot_params_default(kot_params* p) {
   p->ws_F = 0;
   p->ws_H = 0;
   p->ws_theta = nullptr;
+  p->overlap = 1;
 }
 
 kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {
@@ -905,6 +1064,7 @@ kot_status kot_destroy(kot_ctx* ctx) {
   if (!ctx) return KOT_ERR_ARG;
   hipSetDevice(ctx->device);
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  side_destroy(ctx);
   for (kot_ctx* ln : ctx->lanes) kot_destroy(ln);
   ctx->lanes.clear();
   free_ws(ctx);
@@ -1063,6 +1223,7 @@ kot_status kot_solve_batched(kot_ctx* ctx, int nprob, const kot_problem* probs, 
     kot_ctx* c = nullptr;
     kot_status s = kot_create(&c, ctx->device, nullptr);
     if (s != KOT_OK) return fail(ctx, s, "could not create a batch lane");
+    c->is_lane = true;
     ctx->lanes.push_back(c);
   }
   // inputs may come from any stream of the caller: make them visible to the lanes' streams
@@ -1276,26 +1437,36 @@ kot_status kot_potentials(kot_ctx* ctx, const kot_problem* pb, const kot_params*
 
 kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass) {
   KCHK(check_ctx(ctx));
+  Profiler* side = ctx->side ? &ctx->side->c->prof : nullptr;  // launches of the extragradient branch
   if (enable) {
     ctx->prof.clear();
     ctx->prof.on = true;
+    if (side) side->clear();
     return KOT_OK;
   }
   ctx->prof.on = false;
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (side) {
+    side->on = false;
+    HIPCHK(hipStreamSynchronize(ctx->side->c->stream));
+  }
   if (out) {
     for (int c = 0; c < nclass * 4; ++c) out[c] = 0.0;
-    for (const auto& r : ctx->prof.recs) {
-      if (r.cls >= nclass || !r.a || !r.b) continue;
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
-      out[4 * r.cls + 0] += 1.0;
-      out[4 * r.cls + 1] += ms;
-      out[4 * r.cls + 2] += r.flops;
-      out[4 * r.cls + 3] += r.bytes;
+    for (const Profiler* pf : {(const Profiler*)&ctx->prof, (const Profiler*)side}) {
+      if (!pf) continue;
+      for (const auto& r : pf->recs) {
+        if (r.cls >= nclass || !r.a || !r.b) continue;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        out[4 * r.cls + 0] += 1.0;
+        out[4 * r.cls + 1] += ms;
+        out[4 * r.cls + 2] += r.flops;
+        out[4 * r.cls + 3] += r.bytes;
+      }
     }
   }
   ctx->prof.clear();
+  if (side) side->clear();
   return KOT_OK;
 }
 

@@ -39,7 +39,7 @@ class KotParams(C.Structure):
                 ("theta_min", C.c_double), ("theta_max", C.c_double), ("eg_step", C.c_double),
                 ("precision", C.c_int), ("safeguard", C.c_int), ("null_step", C.c_int),
                 ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int), ("lift_x0", C.c_int), ("ws_F", C.c_int),
-                ("ws_H", C.c_int), ("ws_theta", C.c_void_p)]
+                ("ws_H", C.c_int), ("ws_theta", C.c_void_p), ("overlap", C.c_int)]
 
 
 class KotProblem(C.Structure):
