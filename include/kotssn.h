@@ -73,10 +73,12 @@ typedef struct kot_params {
                           0.02 x the mean positive y_i set to 0; 0 = X0 = 0 */
   int ws_F, ws_H;      /* warm-start network sizes (features, width) when ws_theta is set */
   const float* ws_theta; /* device, kot_mlp layout; non-NULL: kot_solve predicts gamma0 with the network */
-  int overlap;         /* 1 (default): with safeguard EG and l >= 128, the extragradient branch of each iteration
-                          (its step and the residual at v_{k+1}) runs on a second stream driven by a second host
-                          thread, concurrently with the Newton direction and the trial residual; the iterates are
-                          the same as with 0 (one stream), bit for bit.  Not used by kot_solve_batched lanes. */
+  int overlap;         /* 1 (default), for l >= 128: a second stream driven by a second host thread runs the
+                          setup work that does not need R (mean embeddings, q^2, z, the network's start) while
+                          the Cholesky factorization runs, and, with safeguard EG, the extragradient branch of
+                          each iteration (its step and the residual at v_{k+1}) while the Newton direction and
+                          the trial residual run.  Results are those of 0 (one stream), bit for bit.  Not used
+                          by kot_solve_batched lanes. */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:

@@ -261,29 +261,46 @@ __global__ __launch_bounds__(64) void apply_kernel(int l, int np, double* __rest
   else apply_V_slab(l, V, round, nb, list, Ub, flag, P, ((int)blockIdx.x - np) * SLOT);
 }
 
-// Squared Frobenius norms of the 8 x 8 blocks (b1, b2), b1 <= b2 (A symmetric): boff = off-diagonal part,
-// ball = all entries, counted twice for b1 < b2 so that the sums over b1 <= b2 are the norms of A.
-// bpos[b] counts the positive diagonal entries of block b (the eigenvalues once A is diagonal).
-__global__ __launch_bounds__(64) void block_norm_kernel(int l, int nb, const double* __restrict__ A,
-                                                        double* __restrict__ boff, double* __restrict__ ball,
-                                                        double* __restrict__ bpos) {
-  const int b1 = blockIdx.y, b2 = blockIdx.x;
-  if (b2 < b1) return;
+// Sums of squares of A over the BSZ x BSZ blocks (b1, b2 >= b1): off-diagonal entries (boff), all entries,
+// doubled off the block diagonal for the mirrored block (ball), and per diagonal block the number of positive
+// diagonal entries (bpos); the diagonal itself goes to dg.  Workgroup (chunk, b1): the BSZ rows of block row b1
+// over 256 consecutive columns, one column per thread, so every row segment is one coalesced 2 KB read.
+__global__ __launch_bounds__(256) void block_norm_kernel(int l, int nb, const double* __restrict__ A,
+                                                         double* __restrict__ boff, double* __restrict__ ball,
+                                                         double* __restrict__ bpos, double* __restrict__ dg) {
+  const int b1 = blockIdx.y;
+  if ((int)blockIdx.x * (256 / BSZ) + (256 / BSZ) - 1 < b1) return;  // the chunk lies left of the diagonal
   const int t = threadIdx.x;
-  const int i = b1 * BSZ + (t >> 3), j = b2 * BSZ + (t & 7);
-  const double v = (i < l && j < l) ? A[(long long)i * l + j] : 0.0;
-  double off = (i != j) ? v * v : 0.0;
-  double all = (b1 < b2 ? 2.0 : 1.0) * v * v;
-  double pos = (i == j && v > 0.0) ? 1.0 : 0.0;
+  const int j = blockIdx.x * 256 + t;
+  const int b2 = j / BSZ;
+  const bool need = b2 >= b1 && b2 < nb;
+  double v[BSZ];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int r = 0; r < BSZ; ++r) {
+    const int i = b1 * BSZ + r;
+    v[r] = (need && i < l && j < l) ? A[(long long)i * l + j] : 0.0;
+  }
+  double off = 0.0, all = 0.0, pos = 0.0;
+#pragma unroll
+  for (int r = 0; r < BSZ; ++r) {
+    const double sq = v[r] * v[r];
+    all += sq;
+    if (b1 * BSZ + r != j) {
+      off += sq;
+    } else {
+      pos = v[r] > 0.0 ? 1.0 : 0.0;
+      if (j < l) dg[j] = v[r];
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < BSZ; o <<= 1) {  // the BSZ lanes of one block column are consecutive
     off += __shfl_xor(off, o);
     all += __shfl_xor(all, o);
     pos += __shfl_xor(pos, o);
   }
-  if (t == 0) {
+  if ((t & (BSZ - 1)) == 0 && need) {
     boff[(long long)b1 * nb + b2] = off;
-    ball[(long long)b1 * nb + b2] = all;
+    ball[(long long)b1 * nb + b2] = (b1 < b2 ? 2.0 : 1.0) * all;
     if (b1 == b2) bpos[b1] = pos;
   }
 }
@@ -294,20 +311,21 @@ __global__ void eye_kernel(int l, double* __restrict__ V) {
   V[u] = ((u / l) == (u % l)) ? 1.0 : 0.0;
 }
 
-// Ascending order of diag(A) by ranks: element i goes to position #{j : k_j < k_i, or k_j == k_i and j < i}
-// (keys ordered totally, NaN as +inf, so the positions are a permutation).  Workgroup b ranks elements
-// 64 b .. 64 b + 63; its four waves count over four quarters of the keys, staged in LDS (l <= 4096).
-__global__ __launch_bounds__(256) void rank_sort_kernel(int l, const double* __restrict__ A, double* __restrict__ w,
+// Ascending order of the diagonal dg by ranks: element i goes to position #{j : k_j < k_i, or k_j == k_i and
+// j < i} (keys ordered totally, NaN as +inf, so the positions are a permutation); w[rank] = value, perm[rank] =
+// index.  Workgroup b ranks elements 16 b .. 16 b + 15, each counted by 16 threads over a sixteenth of the keys,
+// staged in LDS (l <= 4096).
+__global__ __launch_bounds__(256) void rank_sort_kernel(int l, const double* __restrict__ dg, double* __restrict__ w,
                                                         int* __restrict__ perm) {
   __shared__ double key[4096];
-  __shared__ int cnt[4][64];
+  __shared__ int cnt[16][16];
   const int t = threadIdx.x;
   for (int j0 = 0; j0 < l; j0 += 4 * 256) {
     double v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = j0 + t + 256 * q;
-      v[q] = (j < l) ? A[(long long)j * l + j] : 0.0;
+      v[q] = (j < l) ? dg[j] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -316,19 +334,19 @@ __global__ __launch_bounds__(256) void rank_sort_kernel(int l, const double* __r
     }
   }
   __syncthreads();
-  const int il = t & 63, part = t >> 6;
-  const int i = blockIdx.x * 64 + il;
+  const int il = t & 15, part = t >> 4;
+  const int i = blockIdx.x * 16 + il;
   const double ki = (i < l) ? key[i] : 0.0;
-  const int per = (l + 3) / 4;
+  const int per = (l + 15) / 16;
   const int jb = part * per, je = min(l, jb + per);
   int c = 0;
   int j = jb;
-  for (; j + 16 <= je; j += 16) {  // sixteen LDS reads in flight per pass
-    double kj[16];
+  for (; j + 8 <= je; j += 8) {
+    double kj[8];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) kj[q] = key[j + q];
+    for (int q = 0; q < 8; ++q) kj[q] = key[j + q];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) c += (kj[q] < ki || (kj[q] == ki && j + q < i)) ? 1 : 0;
+    for (int q = 0; q < 8; ++q) c += (kj[q] < ki || (kj[q] == ki && j + q < i)) ? 1 : 0;
   }
   for (; j < je; ++j) {
     const double kj = key[j];
@@ -336,9 +354,11 @@ __global__ __launch_bounds__(256) void rank_sort_kernel(int l, const double* __r
   }
   cnt[part][il] = c;
   __syncthreads();
-  if (part == 0 && i < l) {
-    const int r = cnt[0][il] + cnt[1][il] + cnt[2][il] + cnt[3][il];
-    w[r] = A[(long long)i * l + i];
+  if (t < 16 && i < l) {
+    int r = 0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) r += cnt[p][il];
+    w[r] = dg[i];
     perm[r] = i;
   }
 }
@@ -361,14 +381,18 @@ struct EigWork {
   bool graph_failed = false;
   double* U = nullptr;        // device [npairs_max * 256]
   int* flag = nullptr;        // device [npairs_max]
-  double* norms = nullptr;    // device [4]: slot 2 = rotation threshold
-  double* hnorms = nullptr;   // pinned host [4]
   int* perm = nullptr;        // device [lmax]
+  double* dg = nullptr;       // device [lmax]: the diagonal of A at the last block-norm pass
   double* hb = nullptr;       // block norms: off-diagonal part [nbmax^2], all entries [nbmax^2], positive diagonal
                               // counts [nbmax]; pinned, mapped and coherent host memory written by the kernel
   double* boff = nullptr;     // device address of hb
-  int2* list = nullptr;       // device pair lists of a threshold sweep [(nbmax - 1) * nbmax / 2]
-  int2* hlist = nullptr;      // pinned host staging of the lists
+  // uploads: [0] the rotation threshold, [2..] the pair lists of a threshold sweep [(nbmax - 1) * nbmax / 2];
+  // device copy, host staging (pinned, mapped and coherent) and its device address, copied by a kernel
+  double* up = nullptr;
+  double* hup = nullptr;
+  double* hup_dev = nullptr;
+  int2* list = nullptr;       // up + 2
+  int2* hlist = nullptr;      // hup + 2
   std::vector<int> round_k;   // active pairs per round of the current threshold sweep
 };
 static int block_count(int l) {
@@ -387,23 +411,27 @@ EigWork* eig_work_create(int lmax) {
   const size_t nlist = (size_t)(nbmax - 1) * npm;
   bool ok = hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256) == hipSuccess &&
             hipMalloc(&w->flag, sizeof(int) * (size_t)npm) == hipSuccess &&
-            hipMalloc(&w->norms, sizeof(double) * 4) == hipSuccess &&
-            hipHostMalloc(&w->hnorms, sizeof(double) * 4) == hipSuccess &&
             hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess &&
+            hipMalloc(&w->dg, sizeof(double) * (size_t)lmax) == hipSuccess &&
             hipHostMalloc(&w->hb, sizeof(double) * (2 * nb2 + nbmax), hipHostMallocMapped | hipHostMallocCoherent) ==
                 hipSuccess &&
             hipHostGetDevicePointer(reinterpret_cast<void**>(&w->boff), w->hb, 0) == hipSuccess &&
-            hipMalloc(&w->list, sizeof(int2) * nlist) == hipSuccess &&
-            hipHostMalloc(&w->hlist, sizeof(int2) * nlist) == hipSuccess;
+            hipMalloc(&w->up, sizeof(double) * (2 + nlist)) == hipSuccess &&
+            hipHostMalloc(&w->hup, sizeof(double) * (2 + nlist), hipHostMallocMapped | hipHostMallocCoherent) ==
+                hipSuccess &&
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&w->hup_dev), w->hup, 0) == hipSuccess;
   if (!ok) { eig_work_destroy(w); return nullptr; }
+  static_assert(sizeof(int2) == sizeof(double), "pair lists travel as doubles");
+  w->list = reinterpret_cast<int2*>(w->up + 2);
+  w->hlist = reinterpret_cast<int2*>(w->hup + 2);
   return w;
 }
 
 void eig_work_destroy(EigWork* w) {
   if (!w) return;
   if (w->graph) hipGraphExecDestroy(w->graph);
-  hipFree(w->U); hipFree(w->flag); hipFree(w->norms); hipHostFree(w->hnorms); hipFree(w->perm);
-  hipHostFree(w->hb); hipFree(w->list); hipHostFree(w->hlist);
+  hipFree(w->U); hipFree(w->flag); hipFree(w->perm); hipFree(w->dg);
+  hipHostFree(w->hb); hipFree(w->up); hipHostFree(w->hup);
   delete w;
 }
 
@@ -412,8 +440,8 @@ void eig_work_destroy(EigWork* w) {
 static hipError_t block_norms(EigWork* w, int l, int nb, const double* A, hipStream_t st, double* off, double* all,
                               int* npos) {
   const size_t nb2 = (size_t)nb * nb;
-  hipLaunchKernelGGL(block_norm_kernel, dim3(nb, nb), dim3(64), 0, st, l, nb, A, w->boff, w->boff + nb2,
-                     w->boff + 2 * nb2);
+  hipLaunchKernelGGL(block_norm_kernel, dim3((nb * BSZ + 255) / 256, nb), dim3(256), 0, st, l, nb, A, w->boff,
+                     w->boff + nb2, w->boff + 2 * nb2, w->dg);
   KOT_HIP_TRY(hipGetLastError());
   KOT_HIP_TRY(hipStreamSynchronize(st));
   double so = 0.0, sa = 0.0, sp = 0.0;
@@ -536,7 +564,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   const double thresh_rel = 1e-18;
   auto launch_round = [&](hipStream_t s_, int r, const int2* list, int kact) -> hipError_t {
     hipLaunchKernelGGL(pair_solve_kernel, dim3(np), dim3(64), 0, s_, l, A, r, nb, list, kact, w->U, w->flag,
-                       w->norms + 2, 8);
+                       w->up, 8);
     KOT_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(apply_kernel, dim3(np + nslab, np), dim3(64), 0, s_, l, np, A, V, r, nb, list, w->U, w->flag);
     return hipGetLastError();
@@ -549,15 +577,14 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * nslab * np);
   const double npairs = 0.5 * nb * (nb + 1.0);
   while (off > tol * all && s < max_sweeps) {
-    w->hnorms[2] = thresh_rel * all;
-    KOT_HIP_TRY(hipMemcpyAsync(w->norms + 2, w->hnorms + 2, sizeof(double), hipMemcpyHostToDevice, st));
+    w->hup[0] = thresh_rel * all;  // the stream is idle here (block_norms synchronized it)
     Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
     // threshold sweep over the block pairs above tau; if every pair is at or below tau, then
     // off(A)^2 <= npairs tau^2 = (tol |A|_F / 2)^2, so the stopping test is met
     const double tau2 = 0.25 * tol * tol * all * all / npairs;
     if (threshold_schedule(w, nb, tau2)) {
       const int R = (int)w->round_k.size();
-      KOT_HIP_TRY(hipMemcpyAsync(w->list, w->hlist, sizeof(int2) * (size_t)R * np, hipMemcpyHostToDevice, st));
+      KOT_HIP_TRY(vec_copy(2 + R * np, w->hup_dev, w->up, st));  // threshold and pair lists
       double fl = 0.0;
       for (int r = 0; r < R; ++r) {
         const double k = w->round_k[r];
@@ -567,6 +594,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       for (int r = 0; r < R; ++r) KOT_HIP_TRY(launch_round(st, 0, w->list + (size_t)r * np, w->round_k[r]));
       if (pf) pf->end(st);
     } else {
+      KOT_HIP_TRY(vec_copy(2, w->hup_dev, w->up, st));  // threshold
       if (!w->graph_failed && (w->graph == nullptr || w->graph_l != l || w->graph_tmp != tmp)) {
         if (w->graph) { hipGraphExecDestroy(w->graph); w->graph = nullptr; }
         hipGraph_t gr = nullptr;
@@ -598,7 +626,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   *rel_off = (all > 0.0) ? off / all : 0.0;
   if (npos) *npos = pos;
   if (l > 4096) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 63) / 64), dim3(256), 0, st, l, A, wv, w->perm);
+  hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 15) / 16), dim3(256), 0, st, l, w->dg, wv, w->perm);
   KOT_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, V, w->perm, P);
   return hipGetLastError();

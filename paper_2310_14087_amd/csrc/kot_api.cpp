@@ -51,7 +51,11 @@ struct CoreView {  // dual data of Eq. (3.4) on the device
   double q2 = 0.0;
   double lam1 = 0.0, lam2 = 0.0;
   double* KK = nullptr;  // (R^T R) o (R^T R)
-  double kb_eps = -1.0;  // >= 0: the context's K buffer holds K from the setup; R^T R = K + kb_eps I
+  int kb_state = 0;      // the context's K buffer: 0 unrelated, 1 holds R^T R = K + eps I, 2 and KK is formed
+};
+
+struct Prelude {  // setup results computed on the second stream while the factorization runs
+  double q2 = 0.0, eta = 0.0, zz = 0.0;
 };
 
 struct SideRunner;
@@ -544,10 +548,10 @@ kot_status prepare_core(kot_ctx* ctx, CoreView& cv) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
   // KK = (R^T R) o (R^T R); after the setup R^T R = K + eps I is at hand without the product
-  if (cv.kb_eps >= 0.0) HIPCHK(add_diag(l, cv.kb_eps, ctx->Kb, st));
-  else HIPCHK(mm(st, 1, 0, l, l, l, 1.0, cv.R, l, nullptr, cv.R, l, 0.0, ctx->Kb, l, TRI_A_LOWER | TRI_B_UPPER, true));
-  cv.kb_eps = -1.0;  // Kb now holds R^T R
-  HIPCHK(hadamard_square(l * l, ctx->Kb, ctx->KKb, st));
+  if (cv.kb_state == 0)
+    HIPCHK(mm(st, 1, 0, l, l, l, 1.0, cv.R, l, nullptr, cv.R, l, 0.0, ctx->Kb, l, TRI_A_LOWER | TRI_B_UPPER, true));
+  if (cv.kb_state < 2) HIPCHK(hadamard_square(l * l, ctx->Kb, ctx->KKb, st));
+  cv.kb_state = 2;
   cv.KK = ctx->KKb;
   return KOT_OK;
 }
@@ -560,8 +564,11 @@ kot_status default_eta_launch(kot_ctx* ctx, const CoreView& cv) {
   HIPCHK(rowsum_abs_max(l, cv.KK, false, ctx->dsc + SL_ETA + 1, ctx->part, ctx->stream));
   return KOT_OK;
 }
+double default_eta_value(double qmax, double kkmax, double lam2) {
+  return 0.5 / (qmax / (2.0 * lam2) + std::sqrt(kkmax));
+}
 double default_eta_read(kot_ctx* ctx, const CoreView& cv) {
-  return 0.5 / (ctx->hsc[SL_ETA] / (2.0 * cv.lam2) + std::sqrt(ctx->hsc[SL_ETA + 1]));
+  return default_eta_value(ctx->hsc[SL_ETA], ctx->hsc[SL_ETA + 1], cv.lam2);
 }
 
 kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
@@ -656,11 +663,13 @@ kot_status mlp_loss_grad_impl(kot_ctx* ctx, int n, const MlpView& w, const float
 }
 
 // gamma0 = lambda1 * f(features) for the prepared core (KK must be set).
-kot_status predict_gamma0(kot_ctx* ctx, const CoreView& cv, int F, int H, const float* theta, double* gamma0) {
+// K: the buffer holding R^T R (K + eps I)
+kot_status predict_gamma0(kot_ctx* ctx, const CoreView& cv, const double* K, int F, int H, const float* theta,
+                          double* gamma0) {
   const int l = cv.l;
   if (F != kFeatures) return fail(ctx, KOT_ERR_ARG, "the feature map has %d features (got F=%d)", kFeatures, F);
   KCHK(ensure_mlp(ctx, l, H, l));
-  HIPCHK(features(l, cv.Q, cv.z, cv.wsum, ctx->Kb, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + SL_POOL, ctx->fX, ctx->stream));
+  HIPCHK(features(l, cv.Q, cv.z, cv.wsum, K, cv.KK, cv.lam1, ctx->rs3, ctx->dsc + SL_POOL, ctx->fX, ctx->stream));
   KCHK(mlp_forward_impl(ctx, l, mlp_view(F, H, theta), ctx->fX, ctx->fout));
   HIPCHK(f32_to_f64_scaled(l, ctx->fout, cv.lam1, gamma0, ctx->stream));
   return KOT_OK;
@@ -721,7 +730,7 @@ void side_loop(SideRunner* s) {
   }
 }
 
-kot_status side_ensure(kot_ctx* ctx, int l) {
+kot_status side_ensure(kot_ctx* ctx, int l, int nmax) {
   if (!ctx->side) {
     SideRunner* s = new SideRunner();
     kot_ctx* c = nullptr;
@@ -742,7 +751,7 @@ kot_status side_ensure(kot_ctx* ctx, int l) {
   kot_ctx* c = ctx->side->c;
   c->tuned = ctx->tuned;
   if (ctx->tuned) std::copy(ctx->tune, ctx->tune + kTuneBuckets, c->tune);
-  const kot_status st = ensure_ws(c, l, 0);
+  const kot_status st = ensure_ws(c, l, nmax);
   bind_thread(ctx);  // ensure_ws binds the calling thread to the context it sizes
   if (st < 0) return fail(ctx, st, "side workspace: %s", c->err.c_str());
   return KOT_OK;
@@ -768,7 +777,7 @@ kot_status side_join(kot_ctx* ctx) {
   while (s->state.load(std::memory_order_acquire) != 2) __builtin_ia32_pause();
   s->state.store(0, std::memory_order_relaxed);
   s->job = nullptr;
-  if (s->rc < 0) return fail(ctx, s->rc, "extragradient branch: %s", s->c->err.c_str());
+  if (s->rc < 0) return fail(ctx, s->rc, "second stream: %s", s->c->err.c_str());
   return KOT_OK;
 }
 
@@ -789,21 +798,29 @@ void side_destroy(kot_ctx* ctx) {
 
 constexpr int kOverlapMinL = 128;
 
+bool overlap_ok(const kot_ctx* ctx, const kot_params* p, int l) {
+  return p->overlap && l >= kOverlapMinL && !ctx->is_lane;
+}
+
 // Algorithm 2 on a prepared core.
-kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const double* gamma0, kot_result* res) {
+// pre: the setup already formed KK, the default step's bounds, |z|^2 and the network's start (in S[1].g).
+kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const double* gamma0, kot_result* res,
+                    const Prelude* pre = nullptr) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
   HIPCHK(hipEventRecord(ctx->ev0, st));
   KCHK(prepare_core(ctx, cv));
   double eta = p->eg_step;
   const bool eta_default = !(eta > 0.0);
-  if (eta_default) KCHK(default_eta_launch(ctx, cv));       // read with the first residual's norms
-  if (gamma0 || p->ws_theta) HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + SL_ZZ, ctx->part, st));
+  if (!pre) {
+    if (eta_default) KCHK(default_eta_launch(ctx, cv));       // read with the first residual's norms
+    if (gamma0 || p->ws_theta) HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + SL_ZZ, ctx->part, st));
+  }
   State* W = &ctx->S[0];
   State* T = &ctx->S[1];
   State* V = &ctx->S[2];
   if (p->ws_theta && !gamma0) {  // learned start
-    KCHK(predict_gamma0(ctx, cv, p->ws_F, p->ws_H, p->ws_theta, ctx->S[1].g));
+    if (!pre) KCHK(predict_gamma0(ctx, cv, ctx->Kb, p->ws_F, p->ws_H, p->ws_theta, ctx->S[1].g));
     gamma0 = ctx->S[1].g;
   }
   if (gamma0) HIPCHK(vec_copy(l, gamma0, W->g, st));
@@ -820,11 +837,11 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   }
   int sweeps = 0;
   KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
-  if (eta_default) eta = default_eta_read(ctx, cv);
+  if (eta_default) eta = pre ? pre->eta : default_eta_read(ctx, cv);
   res->warm_used = 0;
   if (gamma0) {
     // fallback: the cold start w = (0, 0) has |R| = |z|/(2 lam2) (Pi(-lambda1 I) = 0); keep the better one
-    const double cold = std::sqrt(ctx->hsc[SL_ZZ]) / (2.0 * cv.lam2);
+    const double cold = std::sqrt(pre ? pre->zz : ctx->hsc[SL_ZZ]) / (2.0 * cv.lam2);
     if (!(W->rn <= cold)) {
       HIPCHK(vec_fill(l, 0.0, W->g, st));
       HIPCHK(vec_fill(l * l, 0.0, W->X, st));
@@ -834,9 +851,9 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     }
   }
   const bool use_eg = p->safeguard == KOT_SAFEGUARD_EG;
-  const bool overlap = use_eg && p->overlap && l >= kOverlapMinL && !ctx->is_lane;
+  const bool overlap = use_eg && overlap_ok(ctx, p, l);
   int side_sweeps = 0;
-  if (overlap) KCHK(side_ensure(ctx, l));
+  if (overlap) KCHK(side_ensure(ctx, l, 0));
   if (use_eg) KCHK(copy_state(ctx, l, *W, *V));
   double theta = p->theta0;
   int k = 0, cg_total = 0, eg_acc = 0, nulls = 0;
@@ -950,14 +967,64 @@ kot_status setup_impl(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, 
   const int l = pb->l, d = pb->d;
   hipStream_t st = ctx->stream;
   HIPCHK(gram_build(l, d, pb->xf, pb->yf, p->sigma, Q, ctx->Kb, st));
+  HIPCHK(add_diag(l, p->eps_jitter, ctx->Kb, st));  // K + eps I = R^T R from here on
   HIPCHK(mean_embedding(pb->n_src, l, d, pb->xs, pb->xf, p->sigma, ctx->wmu, st));
   HIPCHK(mean_embedding(pb->n_tgt, l, d, pb->ys, pb->yf, p->sigma, ctx->wnu, st));
   HIPCHK(mean_gram(pb->n_src, d, pb->xs, p->sigma, ctx->dsc + 0, ctx->part, st));
   HIPCHK(mean_gram(pb->n_tgt, d, pb->ys, p->sigma, ctx->dsc + 1, ctx->part, st));
   HIPCHK(build_z(l, d, pb->xf, pb->yf, ctx->wmu, ctx->wnu, p->lambda2, z, wsum, st));
-  HIPCHK(cholesky_upper(l, ctx->Kb, p->eps_jitter, R, ctx->T1, ctx->dint, st));
+  HIPCHK(cholesky_upper(l, ctx->Kb, 0.0, R, ctx->T1, ctx->dint, st));
   KCHK(sync_read(ctx, 2, 1));
   *q2 = ctx->hsc[0] + ctx->hsc[1];
+  if (ctx->hint[0] != 0)
+    return fail(ctx, KOT_ERR_FACTOR, "K + eps I is not positive definite (pivot %d)", ctx->hint[0]);
+  return KOT_OK;
+}
+
+// The setup work that does not need the factor R (mean embeddings, q^2, z, KK, the default step's bounds,
+// |z|^2 and the network's start), run on the second stream while the calling thread factorizes K + eps I.
+// ctx: the side context; own: the calling context, whose buffers receive the results.
+kot_status setup_side(kot_ctx* ctx, kot_ctx* own, const kot_problem* pb, const kot_params* p, bool predict,
+                      Prelude* pre) {
+  const int l = pb->l, d = pb->d;
+  hipStream_t st = ctx->stream;
+  HIPCHK(mean_embedding(pb->n_src, l, d, pb->xs, pb->xf, p->sigma, own->wmu, st));
+  HIPCHK(mean_embedding(pb->n_tgt, l, d, pb->ys, pb->yf, p->sigma, own->wnu, st));
+  HIPCHK(mean_gram(pb->n_src, d, pb->xs, p->sigma, ctx->dsc + 0, ctx->part, st));
+  HIPCHK(mean_gram(pb->n_tgt, d, pb->ys, p->sigma, ctx->dsc + 1, ctx->part, st));
+  HIPCHK(build_z(l, d, pb->xf, pb->yf, own->wmu, own->wnu, p->lambda2, own->zb, own->wsumb, st));
+  HIPCHK(hadamard_square(l * l, own->Kb, own->KKb, st));
+  HIPCHK(rowsum_abs_max(l, own->Qb, false, ctx->dsc + SL_ETA, ctx->part, st));
+  HIPCHK(rowsum_abs_max(l, own->KKb, false, ctx->dsc + SL_ETA + 1, ctx->part, st));
+  HIPCHK(dot(l, own->zb, own->zb, ctx->dsc + SL_ZZ, ctx->part, st));
+  if (predict) {
+    CoreView cv;
+    cv.l = l; cv.Q = own->Qb; cv.z = own->zb; cv.wsum = own->wsumb; cv.KK = own->KKb;
+    cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+    KCHK(predict_gamma0(ctx, cv, own->Kb, p->ws_F, p->ws_H, p->ws_theta, own->S[1].g));
+  }
+  KCHK(sync_read(ctx));
+  pre->q2 = ctx->hsc[0] + ctx->hsc[1];
+  pre->eta = default_eta_value(ctx->hsc[SL_ETA], ctx->hsc[SL_ETA + 1], p->lambda2);
+  pre->zz = ctx->hsc[SL_ZZ];
+  return KOT_OK;
+}
+
+// setup_impl with the factorization on the calling stream and setup_side beside it; the core buffers of ctx
+// hold Q, z, R, w_mu + w_nu, K + eps I and KK on return.
+kot_status setup_overlapped(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, bool predict, Prelude* pre) {
+  const int l = pb->l, d = pb->d;
+  hipStream_t st = ctx->stream;
+  KCHK(side_ensure(ctx, l, std::max(pb->n_src, pb->n_tgt)));
+  HIPCHK(gram_build(l, d, pb->xf, pb->yf, p->sigma, ctx->Qb, ctx->Kb, st));
+  HIPCHK(add_diag(l, p->eps_jitter, ctx->Kb, st));  // K + eps I = R^T R from here on; read-only below
+  KCHK(side_post(ctx, [ctx, pb, p, predict, pre]() { return setup_side(ctx->side->c, ctx, pb, p, predict, pre); }));
+  const hipError_t e = cholesky_upper(l, ctx->Kb, 0.0, ctx->Rb, ctx->T1, ctx->dint, st);
+  const kot_status rc = e != hipSuccess ? fail(ctx, KOT_ERR_HIP, "cholesky_upper: %s", hipGetErrorString(e))
+                                        : sync_read(ctx);
+  const kot_status rs = side_join(ctx);  // joined even when the factorization failed
+  KCHK(rc);
+  KCHK(rs);
   if (ctx->hint[0] != 0)
     return fail(ctx, KOT_ERR_FACTOR, "K + eps I is not positive definite (pivot %d)", ctx->hint[0]);
   return KOT_OK;
@@ -1098,11 +1165,21 @@ kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, c
   KCHK(check_params(ctx, p, true));
   if (!res || !res->gamma) return fail(ctx, KOT_ERR_ARG, "result or result->gamma is NULL");
   KCHK(ensure_ws(ctx, pb->l, std::max(pb->n_src, pb->n_tgt)));
+  CoreView cv;
+  cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb;
+  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  if (overlap_ok(ctx, p, pb->l)) {
+    Prelude pre;
+    KCHK(setup_overlapped(ctx, pb, p, p->ws_theta && !gamma0, &pre));
+    cv.q2 = pre.q2;
+    cv.kb_state = 2;
+    cv.KK = ctx->KKb;
+    return run_alg2(ctx, cv, p, gamma0, res, &pre);
+  }
   double q2 = 0.0;
   KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2));
-  CoreView cv;
-  cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb; cv.q2 = q2;
-  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2; cv.kb_eps = p->eps_jitter;
+  cv.q2 = q2;
+  cv.kb_state = 1;
   return run_alg2(ctx, cv, p, gamma0, res);
 }
 
@@ -1396,9 +1473,9 @@ kot_status kot_warmstart(kot_ctx* ctx, const kot_problem* pb, const kot_params* 
   KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2));
   CoreView cv;
   cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb; cv.q2 = q2;
-  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2; cv.kb_eps = p->eps_jitter;
+  cv.lam1 = p->lambda1; cv.lam2 = p->lambda2; cv.kb_state = 1;
   KCHK(prepare_core(ctx, cv));
-  KCHK(predict_gamma0(ctx, cv, F, H, theta, gamma0));
+  KCHK(predict_gamma0(ctx, cv, ctx->Kb, F, H, theta, gamma0));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;
 }

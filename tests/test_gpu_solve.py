@@ -93,24 +93,33 @@ def test_pure_extragradient_trajectory(gpu_ctx):
     np.testing.assert_allclose(_n(g), ref["gamma"], atol=1e-9 * np.abs(ref["gamma"]).max())
 
 
-@pytest.mark.parametrize("name,l,n,seed,precision", [("mix1000", 257, 800, 3, 0), ("batch", 160, 500, 8, 3),
-                                                     ("mix256", 128, 400, 2, 1)])
-def test_overlapped_branches_match_one_stream(gpu_ctx, name, l, n, seed, precision):
-    """The extragradient branch on the second stream (overlap=1) changes no iterate: gamma, X, both residual
-    histories and the counters agree bit for bit with the one-stream run (overlap=0), twice in a row (the
-    second run reuses the side context and its thread)."""
+@pytest.mark.parametrize("name,l,n,seed,precision,warm", [("mix1000", 257, 800, 3, 0, False),
+                                                          ("batch", 160, 500, 8, 3, False),
+                                                          ("mix256", 128, 400, 2, 1, False),
+                                                          ("mix1000", 300, 1000, 5, 3, True)])
+def test_overlapped_branches_match_one_stream(gpu_ctx, name, l, n, seed, precision, warm):
+    """The second stream (overlap=1: setup beside the factorization, extragradient branch beside the Newton
+    branch) changes no iterate: gamma, X, both residual histories and the counters agree bit for bit with
+    the one-stream run (overlap=0), twice in a row (the second run reuses the side context and its thread);
+    with the learned start too."""
     import torch
     from paper_2310_14087_amd import kotssn
     p = make_problem(name, seed, l=l, n=n)
-    print(f"[case] overlap on/off {name} seed={seed} l={p.l} precision={precision}", flush=True)
+    print(f"[case] overlap on/off {name} seed={seed} l={p.l} precision={precision} warm={warm}", flush=True)
     args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+    extra = {}
+    if warm:
+        from paper_2310_14087_amd import warmstart
+        theta, F, H, _ = warmstart.load()
+        th = torch.from_numpy(theta).to("cuda:0")
+        extra = dict(ws_F=F, ws_H=H, ws_theta=th.data_ptr())
     runs = []
     for ov in (0, 1, 1):
         prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=precision,
-                                    overlap=ov)
+                                    overlap=ov, **extra)
         runs.append(gpu_ctx.solve(*args, prm, want_X=True, hist_cap=256))
     g0, X0, r0 = runs[0]
-    assert r0.status == kotssn.KOT_OK and r0.iters >= 2
+    assert r0.status == kotssn.KOT_OK and r0.iters >= (1 if warm else 2)
     for g1, X1, r1 in runs[1:]:
         assert torch.equal(g0, g1) and torch.equal(X0, X1)
         assert (r1.iters, r1.cg_iters_total, r1.eg_accepts, r1.null_steps, r1.eig_sweeps_total) == \
@@ -118,4 +127,4 @@ def test_overlapped_branches_match_one_stream(gpu_ctx, name, l, n, seed, precisi
         k = r0.iters + 1
         np.testing.assert_array_equal(r1.res_hist[:k], r0.res_hist[:k])
         np.testing.assert_array_equal(r1.res_v_hist[:k], r0.res_v_hist[:k])
-        assert r1.ot == r0.ot
+        assert r1.ot == r0.ot and r1.warm_used == r0.warm_used
