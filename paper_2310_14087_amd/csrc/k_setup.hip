@@ -152,9 +152,11 @@ __global__ void z_kernel(int l, int d, const double* __restrict__ xf, const doub
 }
 
 // ---------------------------------------------------------------------------------------------------------
-// Blocked right-looking Cholesky on a working copy W (lower triangle), panel width CB.  One launch per panel
-// factors the diagonal block and solves the rows below it; the trailing update is an MFMA GEMM restricted
-// to the lower triangle.
+// Blocked right-looking Cholesky on a working copy W (lower triangle), panel width CB, one launch per panel
+// with a one-panel look-ahead.  Launch s factors panel s (columns k0 = s CB ..) and, in the same grid,
+// applies the previous panel's L21 to the trailing lower triangle beyond panel s; the previous panel's
+// contribution to panel s itself is applied by the panel workgroups just before they factor it.  Panel s
+// therefore never waits for the trailing update of step s - 1, which runs beside it.
 constexpr int CB = 32;
 
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
@@ -164,100 +166,166 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One wavefront per workgroup.  Every workgroup factors the CB x CB diagonal block W[k0.., k0..] in
-// registers (lane i holds row i; the column entries L_cj reach the other rows through v_readlane, so the
-// factorization has no barrier and no LDS traffic); workgroup 0 writes L11 back (zeros above the diagonal)
-// and reports a non-positive pivot through info.  Workgroup b >= 1 takes the 64 panel rows starting at
-// k0 + nb + 64 (b - 1) and solves L21 L11^T = A21 by forward substitution, one row per lane held in
-// registers, L11 broadcast from LDS.  Loads and stores are staged through LDS to run along the rows.
-__global__ __launch_bounds__(64) void chol_panel_kernel(int l, int k0, int nb, double* __restrict__ W, int* info) {
-  __shared__ double L11[CB][CB + 1];
-  __shared__ double P[64][CB + 1];
-  __shared__ double inv_d[CB];
+// Panel workgroups (one wavefront each): lanes 0..31 hold the rows of the CB x CB diagonal block (every
+// workgroup factors it; workgroup 0 writes it back and reports a non-positive pivot through info), lanes
+// 32..63 the CB panel rows k0 + nb + 32 b ..; the right-looking factorization of this 64-row tall panel
+// turns the lower rows into L21 with no separate triangular solve.  At step j the pivot reaches every lane
+// through v_readlane (the next pivot is formed on its own lane ahead of the rest of the update) and the new
+// column L_.j through LDS.
+// Update workgroups: the 32 x 32 tiles (tr >= tc) of W[k0 + CB.., k0 + CB..] get -= L_r L_c^T over the
+// previous panel's columns, staged in LDS; each lane accumulates a 4 x 4 block.
+__global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, int npb, double* __restrict__ W,
+                                                       int* info) {
+  __shared__ double S[64][2 * CB + 1];  // panel: the workgroup's rows over both panels; update: the two L tiles
+  __shared__ double colb[2][CB];
+  double (*Lb)[2 * CB + 1] = S;
+  double (*Lc)[2 * CB + 1] = S + CB;
   const int t = threadIdx.x;
-  {
-    // all sixteen loads of a lane in flight together (register buffer), then staged in LDS
-    double v[CB * CB / 64];
+  const int kp = k0 - CB;  // first column of the previous panel (< 0: none)
+  if ((int)blockIdx.x >= npb) {
+    // ---- trailing update with the previous panel: tile u of the lower triangle beyond panel s
+    int u = (int)blockIdx.x - npb, tr = 0;
+    while (u > tr) { u -= tr + 1; ++tr; }
+    const int tc = u;
+    const int o = k0 + CB, R0 = o + CB * tr, C0 = o + CB * tc;
+    // stage L[R0.., kp..] and L[C0.., kp..] (rows past l read as zero), and fetch this lane's 4 x 4 block of the
+    // tile: all loads of a lane in flight together, from clamped (in-bounds) addresses
+    const int ri = (t >> 3) * 4, ci = (t & 7) * 4;
+    double cv[4][4];
+    {
+      double vb[CB * CB / 64], vc[CB * CB / 64];
 #pragma unroll
-    for (int q = 0; q < CB * CB / 64; ++q) {
-      const int u = t + 64 * q, i = u >> 5, j = u & 31;
-      if (i < nb && j < nb) v[q] = (j <= i) ? W[(long long)(k0 + i) * l + k0 + j] : 0.0;
-      else v[q] = (i == j) ? 1.0 : 0.0;  // pad a short last block with the identity
+      for (int q = 0; q < CB * CB / 64; ++q) {
+        const int e = t + 64 * q, r = e >> 5, k = e & 31;
+        vb[q] = W[(long long)min(R0 + r, l - 1) * l + kp + k];
+        vc[q] = W[(long long)min(C0 + r, l - 1) * l + kp + k];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          cv[p][q] = W[(long long)min(R0 + ri + p, l - 1) * l + min(C0 + ci + q, l - 1)];
+#pragma unroll
+      for (int q = 0; q < CB * CB / 64; ++q) {
+        const int e = t + 64 * q, r = e >> 5, k = e & 31;
+        Lb[r][k] = (R0 + r < l) ? vb[q] : 0.0;
+        Lc[r][k] = (C0 + r < l) ? vc[q] : 0.0;
+      }
+    }
+    __syncthreads();
+    double acc[4][4] = {};
+#pragma unroll 8
+    for (int k = 0; k < CB; ++k) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        av[p] = Lb[ri + p][k];
+        bv[p] = Lc[ci + p][k];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
     }
 #pragma unroll
-    for (int q = 0; q < CB * CB / 64; ++q) {
-      const int u = t + 64 * q;
-      L11[u >> 5][u & 31] = v[q];
-    }
-  }
-  __syncthreads();
-  const int i = t & 31;  // lanes 32..63 mirror rows 0..31
-  double a[CB];
+    for (int p = 0; p < 4; ++p) {
+      const int r = R0 + ri + p;
 #pragma unroll
-  for (int c = 0; c < CB; ++c) a[c] = L11[i][c];
-  int bad = 0;
-#pragma unroll
-  for (int j = 0; j < CB; ++j) {
-    double piv = readlane_f64(a[j], j);
-    if (!(piv > 0.0)) {
-      if (j < nb && !bad) bad = k0 + j + 1;
-      piv = 1.0;
-    }
-    const double dj = sqrt(piv), rdj = 1.0 / dj;
-    const double lij = a[j] * rdj;  // L_ij on lanes i > j
-#pragma unroll
-    for (int c = j + 1; c < CB; ++c) a[c] -= lij * readlane_f64(lij, c);  // entries c > i are never used
-    a[j] = (i == j) ? dj : lij;
-    if (t == 0) inv_d[j] = rdj;
-  }
-  __syncthreads();  // all rows read from L11 before it is overwritten
-  if (t < CB)
-#pragma unroll
-    for (int c = 0; c < CB; ++c) L11[i][c] = (c <= i) ? a[c] : 0.0;
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    if (t == 0 && bad) atomicCAS(info, 0, bad);
-    for (int u = t; u < nb * CB; u += 64) {
-      const int r = u >> 5, j = u & 31;
-      if (j < nb) W[(long long)(k0 + r) * l + k0 + j] = L11[r][j];
+      for (int q = 0; q < 4; ++q) {
+        const int cc = C0 + ci + q;
+        if (r < l && cc <= r) W[(long long)r * l + cc] = cv[p][q] - acc[p][q];  // cc <= r < l
+      }
     }
     return;
   }
-  // panel rows (nb == CB here: only the last panel is short, and it has no rows below it)
-  const int rbase = k0 + nb + ((int)blockIdx.x - 1) * 64;
-  double x[CB];
+  // ---- panel s
+  const bool diag = t < CB;
+  const int row = diag ? k0 + t : k0 + nb + (int)blockIdx.x * CB + (t - CB);
+  const bool live = diag ? t < nb : row < l;
+  // stage the 64 rows of this workgroup over the column window [k0 - CB, k0 + CB) (the previous panel, then
+  // this one) in LDS: each load instruction reads one row segment, lane t column t of the window
+  {
+    const int w0 = kp >= 0 ? kp : k0;
+    const int wn = kp >= 0 ? 2 * CB : CB;
+    const int wc = min(wn, k0 + nb - w0);  // columns of the window inside the matrix
+    // clamped addresses keep every load in bounds without a branch; the entries they fill for rows past l or
+    // columns past the window are finite copies of real entries, and nothing that is stored depends on them
+    const int tc = min(t, wc - 1);
+    double v[64];
 #pragma unroll
-  for (int q = 0; q < CB; ++q) {
-    const int u = t + 64 * q, r = u >> 5, j = u & 31;
-    x[q] = (rbase + r < l) ? W[(long long)(rbase + r) * l + k0 + j] : 0.0;
-  }
+    for (int q = 0; q < 64; ++q) {
+      const int r = q < CB ? k0 + q : k0 + nb + (int)blockIdx.x * CB + (q - CB);
+      v[q] = W[(long long)min(r, l - 1) * l + w0 + tc];
+    }
 #pragma unroll
-  for (int q = 0; q < CB; ++q) {
-    const int u = t + 64 * q;
-    P[u >> 5][u & 31] = x[q];
+    for (int q = 0; q < 64; ++q) S[q][t] = v[q];
   }
   __syncthreads();
+  const int ca = kp >= 0 ? CB : 0;  // column of this panel inside the staged window
+  double a[CB];
 #pragma unroll
-  for (int c = 0; c < CB; ++c) x[c] = P[t][c];
-  // column-oriented substitution: once x_j is final it is eliminated from every later entry, so the
-  // dependent chain is one multiply-add per column and the updates of one step are independent
+  for (int c = 0; c < CB; ++c) {
+    const double v = S[t][ca + c];
+    a[c] = diag ? (live ? ((c <= t) ? v : 0.0) : ((t == c) ? 1.0 : 0.0)) : v;  // short block: identity pad
+  }
+  if (kp >= 0) {
+    // the previous panel's contribution to this panel's columns: a[c] -= sum_k L(row, kp + k) L(k0 + c, kp + k),
+    // the L rows of the diagonal block being S[c][0..CB) (k outermost: the 32 updates of one k are independent)
+#pragma unroll 1
+    for (int k0c = 0; k0c < CB; k0c += 4) {  // a rolled loop over chunks of four k: bounded live ranges
+#pragma unroll
+      for (int k = k0c; k < k0c + 4; ++k) {
+        const double xk = live ? S[t][k] : 0.0;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) a[c] = fma(-xk, S[c][k], a[c]);
+      }
+    }
+  }
+  int bad = 0;
+  double pnext = readlane_f64(a[0], 0);
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
-    x[j] *= inv_d[j];
+    double piv = pnext;
+    // a valid pivot is a positive normal number: high word in [0x00100000, 0x7ff00000) (a scalar test)
+    const unsigned hw = (unsigned)((unsigned long long)__double_as_longlong(piv) >> 32);
+    if (hw - 0x00100000u >= 0x7fe00000u) {  // reported, then replaced by 1
+      if (j < nb && !bad) bad = k0 + j + 1;
+      piv = 1.0;
+    }
+    // 1/sqrt(piv): hardware estimate y0 refined by one third-order step y0 (1 + e/2 + 3 e^2/8), e = 1 - piv y0^2
+    const double y0 = __builtin_amdgcn_rsq(piv);
+    const double e = fma(-piv * y0, y0, 1.0);
+    const double rdj = fma(y0 * e, fma(0.375, e, 0.5), y0);
+    const double dj = piv * rdj;
+    const double lij = a[j] * rdj;  // L_ij on rows below j
+    // the next pivot from its own lane (its entry minus its L entry squared), ahead of the LDS exchange
+    if (j + 1 < CB) pnext = readlane_f64(fma(-lij, lij, a[j + 1]), j + 1);
+    if (diag) colb[j & 1][t] = lij;
+    __syncthreads();
 #pragma unroll
-    for (int c = j + 1; c < CB; ++c) x[c] -= x[j] * L11[c][j];
+    for (int c = j + 1; c < CB; ++c) a[c] -= lij * colb[j & 1][c];  // entries c > t of diagonal rows unused
+    a[j] = (diag && t == j) ? dj : lij;
+#pragma unroll
+    for (int c = j + 1; c < CB; ++c) asm volatile("" : "+v"(a[c]));  // keep each update inside its step
   }
+  if (diag) {
+    if (blockIdx.x == 0) {
+      if (t == 0 && bad) atomicCAS(info, 0, bad);
+      if (live)
 #pragma unroll
-  for (int c = 0; c < CB; ++c) P[t][c] = x[c];
-  __syncthreads();
-  for (int u = t; u < 64 * CB; u += 64) {
-    const int r = u >> 5, j = u & 31;
-    if (rbase + r < l) W[(long long)(rbase + r) * l + k0 + j] = P[r][j];
+        for (int c = 0; c < CB; ++c)
+          if (c < nb) W[(long long)row * l + k0 + c] = (c <= t) ? a[c] : 0.0;
+    }
+  } else if (live) {
+#pragma unroll
+    for (int c = 0; c < CB; ++c) W[(long long)row * l + k0 + c] = a[c];
   }
 }
 
-__global__ void copy_jitter_kernel(int l, const double* __restrict__ A, double eps, double* __restrict__ W) {
+__global__ void copy_jitter_kernel(int l, const double* __restrict__ A, double eps, double* __restrict__ W,
+                                   int* __restrict__ info) {
   const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u == 0) *info = 0;
   if (u >= (long long)l * l) return;
   const int i = (int)(u / l), j = (int)(u % l);
   W[u] = A[u] + ((i == j) ? eps : 0.0);
@@ -390,25 +458,17 @@ hipError_t build_z(int l, int d, const double* xf, const double* yf, const doubl
 hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double* W, int* info, hipStream_t st) {
   const long long nn = (long long)l * l;
   const int eb = (int)((nn + 255) / 256);
-  KOT_HIP_TRY(hipMemsetAsync(info, 0, sizeof(int), st));
-  hipLaunchKernelGGL(copy_jitter_kernel, dim3(eb), dim3(256), 0, st, l, A, eps, W);
+  hipLaunchKernelGGL(copy_jitter_kernel, dim3(eb), dim3(256), 0, st, l, A, eps, W, info);
   KOT_HIP_TRY(hipGetLastError());
   for (int k0 = 0; k0 < l; k0 += CB) {
     const int nb = (l - k0 < CB) ? (l - k0) : CB;
     const int rest = l - k0 - nb;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(1 + (rest + 63) / 64), dim3(64), 0, st, l, k0, nb, W, info);
+    const int npb = rest > 0 ? (rest + CB - 1) / CB : 1;
+    // trailing tiles beyond panel s that the previous panel still has to update
+    const int m = (k0 > 0 && l > k0 + CB) ? (l - k0 - CB + CB - 1) / CB : 0;
+    const int ntiles = m * (m + 1) / 2;
+    hipLaunchKernelGGL(chol_step_kernel, dim3(npb + ntiles), dim3(64), 0, st, l, k0, nb, npb, W, info);
     KOT_HIP_TRY(hipGetLastError());
-    if (rest <= 0) break;
-    // W22 -= L21 L21^T on the lower triangle
-    GemmArgs g{};
-    g.transa = 0; g.transb = 1; g.m = rest; g.n = rest; g.k = nb;
-    g.alpha = -1.0; g.beta = 1.0;
-    g.A = W + (long long)(k0 + nb) * l + k0; g.lda = l;
-    g.B = W + (long long)(k0 + nb) * l + k0; g.ldb = l;
-    g.C = W + (long long)(k0 + nb) * l + (k0 + nb); g.ldc = l;
-    g.batch = 1;
-    g.lower = 1;
-    KOT_HIP_TRY(gemm_f64(g, st));
   }
   hipLaunchKernelGGL(lower_to_upper_kernel, dim3(eb), dim3(256), 0, st, l, W, R);
   return hipGetLastError();

@@ -115,7 +115,7 @@ def test_eigh_degenerate(gpu_ctx):
     assert np.abs(P.T @ P - np.eye(48)).max() <= 1e-12
 
 
-@pytest.mark.parametrize("l", [1, 31, 32, 33, 100, 257, 1000])
+@pytest.mark.parametrize("l", [1, 31, 32, 33, 64, 65, 97, 100, 257, 513, 1000])
 def test_cholesky(gpu_ctx, l):
     _case(f"kot_cholesky l={l}")
     rng = np.random.default_rng(l + 7)
@@ -125,14 +125,17 @@ def test_cholesky(gpu_ctx, l):
     np.testing.assert_allclose(R, np.linalg.cholesky(S).T, rtol=1e-12, atol=1e-12)
 
 
-def test_cholesky_not_pd(gpu_ctx):
+@pytest.mark.parametrize("l,bad", [(10, 3), (100, 70), (300, 299)])
+def test_cholesky_not_pd(gpu_ctx, l, bad):
+    """A non-positive pivot in the first, a middle or the last panel is reported with its (1-based) index."""
     from paper_2310_14087_amd import kotssn
-    _case("kot_cholesky indefinite l=10")
-    S = np.eye(10)
-    S[3, 3] = -1.0
+    _case(f"kot_cholesky indefinite l={l} pivot {bad}")
+    S = np.eye(l)
+    S[bad, bad] = -1.0
     with pytest.raises(kotssn.KotError) as e:
         gpu_ctx.cholesky(_t(S), 0.0)
     assert e.value.status == kotssn.KOT_ERR_FACTOR
+    assert f"pivot {bad + 1})" in str(e.value)
 
 
 def _core_case(name, l, n, seed=0):
