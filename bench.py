@@ -239,7 +239,8 @@ def main():
         conv = sum(1 for r in results if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
         out_arms[arm] = dict(solves_per_s=a.steps / el, ms_per_solve=1e3 * el / a.steps, converged=conv,
                              iters=[r.iters for r in results], eig_sweeps=[r.eig_sweeps_total for r in results],
-                             cg_iters=[r.cg_iters_total for r in results], ot=[r.ot for r in results])
+                             cg_iters=[r.cg_iters_total for r in results],
+                             lowp_directions=[r.lowp_directions for r in results], ot=[r.ot for r in results])
         if arm == arms[-1]:
             elapsed, prof, final = el, pr, arm
         _log(f"{arm}: {a.steps / el:.2f} solves/s, {conv}/{a.steps} converged")

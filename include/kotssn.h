@@ -79,6 +79,10 @@ typedef struct kot_params {
                           each iteration (its step and the residual at v_{k+1}) while the Newton direction and
                           the trial residual run.  Results are those of 0 (one stream), bit for bit.  Not used
                           by kot_solve_batched lanes. */
+  int lowp_min_rows;   /* with a reduced precision: the Newton direction runs the reduced-precision chain and
+                          iterative refinement only when the chain has at least this many eigen-rows
+                          (min(|alpha|, l - |alpha|)); below it the chain's products are too small to gain from
+                          lower precision and the FP64 CG runs instead (default 64; 0 = always) */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:
@@ -109,6 +113,7 @@ typedef struct kot_result {
   int eig_sweeps_total;
   int alpha_last;      /* number of positive eigenvalues of Z at the returned iterate */
   int warm_used;       /* 1 if the start from gamma0 was kept (it had |R(w0)| <= |R(0,0)|), else 0 */
+  int lowp_directions; /* Newton directions computed with the reduced-precision chain (see lowp_min_rows) */
   double time_ms;      /* wall time of the solve on the device stream */
 } kot_result;
 

@@ -400,6 +400,7 @@ struct DirInfo {
   int cg_iters = 0;
   double cg_res = 0.0;
   int sweeps = 0;
+  bool lowp = false;  // the reduced-precision chain ran
 };
 
 // Algorithm 1 at state s with regularization mu: writes ctx->dg, ctx->dX.
@@ -422,7 +423,8 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   const double rnorm = s.rn;
   int it = 0;
   double rr = 0.0;
-  if (p->precision == KOT_FP64) {
+  info->lowp = p->precision != KOT_FP64 && tp.m >= p->lowp_min_rows;
+  if (!info->lowp) {
     HIPCHK(vec_fill(l, 0.0, x, st));
     HIPCHK(vec_copy(l, ctx->a1, r, st));
     HIPCHK(vec_copy(l, ctx->a1, pp, st));
@@ -581,6 +583,7 @@ kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
     return fail(ctx, KOT_ERR_ARG, "unknown precision %d", p->precision);
   if (p->safeguard != KOT_SAFEGUARD_EG && p->safeguard != KOT_SAFEGUARD_NONE && p->safeguard != KOT_SAFEGUARD_EG_ONLY)
     return fail(ctx, KOT_ERR_ARG, "unknown safeguard %d", p->safeguard);
+  if (p->lowp_min_rows < 0) return fail(ctx, KOT_ERR_ARG, "lowp_min_rows must be >= 0");
   return KOT_OK;
 }
 
@@ -856,7 +859,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   if (overlap) KCHK(side_ensure(ctx, l, 0));
   if (use_eg) KCHK(copy_state(ctx, l, *W, *V));
   double theta = p->theta0;
-  int k = 0, cg_total = 0, eg_acc = 0, nulls = 0;
+  int k = 0, cg_total = 0, eg_acc = 0, nulls = 0, lowp_dirs = 0;
   kot_status status = KOT_NOT_CONVERGED;
   bool warm_e = false;
   for (k = 0;; ++k) {
@@ -900,6 +903,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     auto newton = [&]() -> kot_status {
       KCHK(ssn_direction(ctx, cv, *W, mu, p, &di));
       cg_total += di.cg_iters;
+      lowp_dirs += di.lowp ? 1 : 0;
       HIPCHK(vec_lincomb(l, 1.0, W->g, 1.0, ctx->dg, T->g, st));
       HIPCHK(vec_lincomb(l * l, 1.0, W->X, 1.0, ctx->dX, T->X, st));
       KCHK(residual_state(ctx, cv, *T, p->warm_eig ? W->P : nullptr, p, &sweeps, SL_TN, true));
@@ -943,6 +947,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   }
   res->iters = k;
   res->cg_iters_total = cg_total;
+  res->lowp_directions = lowp_dirs;
   res->eg_accepts = eg_acc;
   res->null_steps = nulls;
   res->eig_sweeps_total = sweeps;
@@ -1098,6 +1103,7 @@ void kot_params_default(kot_params* p) {
   p->ws_H = 0;
   p->ws_theta = nullptr;
   p->overlap = 1;
+  p->lowp_min_rows = 64;
 }
 
 kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {

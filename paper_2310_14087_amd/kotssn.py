@@ -39,7 +39,8 @@ class KotParams(C.Structure):
                 ("theta_min", C.c_double), ("theta_max", C.c_double), ("eg_step", C.c_double),
                 ("precision", C.c_int), ("safeguard", C.c_int), ("null_step", C.c_int),
                 ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int), ("lift_x0", C.c_int), ("ws_F", C.c_int),
-                ("ws_H", C.c_int), ("ws_theta", C.c_void_p), ("overlap", C.c_int)]
+                ("ws_H", C.c_int), ("ws_theta", C.c_void_p), ("overlap", C.c_int),
+                ("lowp_min_rows", C.c_int)]
 
 
 class KotProblem(C.Structure):
@@ -52,7 +53,7 @@ class KotResult(C.Structure):
                 ("hist_cap", C.c_int), ("ot", C.c_double), ("residual", C.c_double), ("iters", C.c_int),
                 ("cg_iters_total", C.c_int), ("eg_accepts", C.c_int), ("null_steps", C.c_int),
                 ("eig_sweeps_total", C.c_int), ("alpha_last", C.c_int), ("warm_used", C.c_int),
-                ("time_ms", C.c_double)]
+                ("lowp_directions", C.c_int), ("time_ms", C.c_double)]
 
 
 _lib = None
@@ -156,6 +157,7 @@ class SolveResult:
     eig_sweeps_total: int
     alpha_last: int
     warm_used: int
+    lowp_directions: int
     time_ms: float
     res_hist: np.ndarray
     res_v_hist: np.ndarray
@@ -226,7 +228,7 @@ class Context:
     def _pack(st, res, rh, rvh) -> SolveResult:
         n = min(res.iters + 1, len(rh))
         return SolveResult(st, res.ot, res.residual, res.iters, res.cg_iters_total, res.eg_accepts, res.null_steps,
-                           res.eig_sweeps_total, res.alpha_last, res.warm_used, res.time_ms, rh[:n].copy(),
+                           res.eig_sweeps_total, res.alpha_last, res.warm_used, res.lowp_directions, res.time_ms, rh[:n].copy(),
                            rvh[:n].copy())
 
     def solve(self, xs, ys, xf, yf, prm: KotParams, gamma0=None, want_X=False, hist_cap=1024):

@@ -50,13 +50,14 @@ def test_batched_fp32_cg(gpu_ctx):
     probs = _problems()[:4]
     print("[case] kot_solve_batched FP32 CG, 2 lanes", flush=True)
     dev = [(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf)) for p in probs]
-    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=1)
-            for p in probs]
+    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=1,
+                                  lowp_min_rows=0) for p in probs]
     out = gpu_ctx.solve_batched(dev, prms, lanes=2)
     for p, (g, r) in zip(probs, out):
         core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
         ref = ko.solve(core, ko.Params(tol=p.tol))
         assert r.status == kotssn.KOT_OK and abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
+        assert r.lowp_directions == r.iters  # every Newton direction ran the FP32 chain
 
 
 def test_autotune_table(gpu_ctx, tmp_path):

@@ -68,12 +68,36 @@ def test_solve_reduced_precision_cg(gpu_ctx, precision, name, l, n, seed):
     print(f"[case] kot_solve precision={precision} {name} seed={seed} l={p.l}", flush=True)
     core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
     ref = ko.solve(core, ko.Params(tol=p.tol))
-    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=precision)
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=precision,
+                                lowp_min_rows=0)
     gamma, X, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, want_X=True)
     assert r.status == kotssn.KOT_OK and r.residual <= p.tol
+    assert r.lowp_directions == r.iters  # every Newton direction ran the reduced-precision chain
     assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
     _, _, rn, _ = ko.residual(core, _n(gamma), _n(X))
     assert rn <= 1.01 * p.tol
+
+
+@pytest.mark.parametrize("name,l,n,seed", [("mix1000", 257, 800, 3), ("batch", 150, 500, 8)])
+def test_small_chain_directions_are_fp64(gpu_ctx, name, l, n, seed):
+    """With the default lowp_min_rows, a direction whose chain has fewer eigen-rows runs the FP64 CG: when
+    no direction of a solve reaches the threshold, the reduced-precision setting reproduces the FP64 solve
+    bit for bit; otherwise it still reaches the oracle's estimate."""
+    import torch
+    from paper_2310_14087_amd import kotssn
+    p = make_problem(name, seed, l=l, n=n)
+    print(f"[case] lowp threshold {name} seed={seed} l={p.l}", flush=True)
+    args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+    out = {}
+    for prec in (0, 3):
+        prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=prec)
+        out[prec] = gpu_ctx.solve(*args, prm, want_X=True)
+    (g0, X0, r0), (g3, X3, r3) = out[0], out[3]
+    assert r0.lowp_directions == 0 and r3.status == kotssn.KOT_OK and r3.residual <= p.tol
+    if r3.lowp_directions == 0:
+        assert torch.equal(g0, g3) and torch.equal(X0, X3) and r0.iters == r3.iters
+    else:
+        assert abs(r3.ot - r0.ot) <= 1e-6 * abs(r0.ot)
 
 
 def test_pure_extragradient_trajectory(gpu_ctx):
