@@ -100,8 +100,21 @@ struct Tile {
   }
 };
 
+// K range [klo, khi) of output tile (m0, n0) where the triangular operands (bits of tri) can be nonzero,
+// klo aligned down to BK.
+__device__ __forceinline__ void tri_k_range(int tri, int k, int m0, int n0, int& klo, int& khi) {
+  klo = 0;
+  khi = k;
+  if (tri & 1) klo = max(klo, m0);            // op(A) upper: op(A)[m][k] = 0 for k < m
+  if (tri & 8) klo = max(klo, n0);            // op(B) lower: op(B)[k][n] = 0 for k < n
+  if (tri & 2) khi = min(khi, m0 + BM);       // op(A) lower: zero for k > m
+  if (tri & 4) khi = min(khi, n0 + BN);       // op(B) upper: zero for k > n
+  klo &= ~(BK - 1);
+}
+
 // blockIdx.z = batch * splits + split.  With splits > 1 the workgroup covers K slices
-// [split*kchunk, (split+1)*kchunk) and writes its raw partial tile to part (layout [batch][split][m][n]).
+// [split*kchunk, (split+1)*kchunk) and writes its raw partial tile to part (layout [batch][split][m][n]); a
+// split that misses the tile's K range writes nothing (the reduction skips it the same way).
 template <bool TA, bool TB, bool SC, int FM, int FN>
 __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(GemmArgs g, int splits, int kchunk,
                                                                              double* __restrict__ part) {
@@ -120,15 +133,12 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave / WN, wn = wave % WN;
   // K range of this split, narrowed to where the triangular operands can be nonzero for this tile
-  int klo = 0, khi = g.k;
-  if (g.tri & 1) klo = max(klo, m0);            // op(A) upper: op(A)[m][k] = 0 for k < m
-  if (g.tri & 8) klo = max(klo, n0);            // op(B) lower: op(B)[k][n] = 0 for k < n
-  if (g.tri & 2) khi = min(khi, m0 + BM);       // op(A) lower: zero for k > m
-  if (g.tri & 4) khi = min(khi, n0 + BN);       // op(B) upper: zero for k > n
-  klo &= ~(BK - 1);
+  int klo, khi;
+  tri_k_range(g.tri, g.k, m0, n0, klo, khi);
   const int kbeg = max(sp * kchunk, klo);
   const int kend = min(min(g.k, sp * kchunk + kchunk), khi);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (splits > 1 && nk == 0) return;  // nothing of this tile in this split (uniform per workgroup)
   using T = Tile<TA, TB, SC, NT>;
 
   dbl4 acc[FM][FN];
@@ -192,17 +202,21 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
       }
 }
 
-// C = alpha * sum_s part[b][s] + beta * C, summed in split order.
-__global__ void splitk_reduce_kernel(GemmArgs g, int splits, const double* __restrict__ part) {
+// C = alpha * sum_s part[b][s] + beta * C, summed in split order over the splits that met the element's tile.
+__global__ void splitk_reduce_kernel(GemmArgs g, int splits, int kchunk, const double* __restrict__ part) {
   const long long mn = (long long)g.m * g.n;
   const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int bz = blockIdx.y;
   if (u >= mn) return;
+  const int row = (int)(u / g.n), col = (int)(u % g.n);
+  const int m0 = (row / BM) * BM, n0 = (col / BN) * BN;
+  if (g.lower && n0 > m0 + BM - 1) return;  // tile above the diagonal: not computed
+  int klo, khi;
+  tri_k_range(g.tri, g.k, m0, n0, klo, khi);
   const double* p = part + (long long)bz * splits * mn + u;
   double s = 0.0;
-  for (int q = 0; q < splits; ++q) s += p[q * mn];
-  const int row = (int)(u / g.n), col = (int)(u % g.n);
-  if (g.lower && (col / BN) * BN > (row / BM) * BM + BM - 1) return;  // partial tile was not written
+  for (int q = 0; q < splits; ++q)
+    if (max(q * kchunk, klo) < min(min(g.k, q * kchunk + kchunk), khi)) s += p[q * mn];
   double* c = g.C + bz * g.sC + (long long)row * g.ldc + col;
   *c = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*c);
   if (g.mirror && (col / BN) < (row / BM)) {
@@ -377,7 +391,7 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
   if (splits > 1) {
     const long long mn = (long long)g.m * g.n;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((mn + 255) / 256), g.batch), dim3(256), 0, st, g, splits,
-                       (const double*)part);
+                       kchunk, (const double*)part);
   }
   if (pf) pf->end(st);
   return hipGetLastError();

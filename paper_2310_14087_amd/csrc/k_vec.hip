@@ -162,6 +162,127 @@ __global__ void cg_step_kernel(int n, double rr, const double* __restrict__ pAp,
   x[i] = alpha * p[i] + x[i];
   r[i] = -alpha * Ap[i] + r[i];
 }
+// ---- conjugate gradients with the scalars on the device ------------------------------------------------------
+// st: [CG_RR] r.r, [CG_XX] x.x, [CG_DONE] 0 running / 1 stopped, [CG_IT] iterations done.  The stopping test is
+// Eq. (4.5)'s: |r| <= thr with thr = tau min(1, kr |x|) (kr = kappa |R(w)|), or a fixed thr when fixed > 0; an
+// iteration count reaching cap, or a non-positive p.Ap, stops as well.  Iterations queued after the stop leave
+// every vector unchanged, so the host may queue several before it looks.
+constexpr int CG_RR = 0, CG_XX = 1, CG_DONE = 2, CG_IT = 3;
+
+// Sums of three values over a 1024-thread workgroup, the same on every thread (shuffles inside each wavefront,
+// then the sixteen wavefront partials in a fixed order).
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double (*sh)[16]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+    c += __shfl_xor(c, o);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();  // earlier readers of sh are done
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = a;
+    sh[1][w] = b;
+    sh[2][w] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    a += sh[0][k];
+    b += sh[1][k];
+    c += sh[2][k];
+  }
+}
+
+__device__ __forceinline__ bool cg_stop(double rr, double xx, double tau, double kr, double fixed) {
+  const double thr = fixed > 0.0 ? fixed : tau * fmin(1.0, kr * sqrt(xx));
+  return sqrt(rr) <= thr;
+}
+
+// x = 0, r = p = b, r.r, and the stopping test at the start.
+__global__ __launch_bounds__(1024) void cg_init_kernel(int n, const double* __restrict__ b, double* __restrict__ x,
+                                                       double* __restrict__ r, double* __restrict__ p,
+                                                       double* __restrict__ st, double tau, double kr, double fixed,
+                                                       int cap) {
+  __shared__ double sh[3][16];
+  double rr = 0.0, z1 = 0.0, z2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = threadIdx.x + 1024 * q;
+    if (i < n) {
+      const double v = b[i];
+      x[i] = 0.0;
+      r[i] = v;
+      p[i] = v;
+      rr += v * v;
+    }
+  }
+  block_sum3(rr, z1, z2, sh);
+  if (threadIdx.x == 0) {
+    st[CG_RR] = rr;
+    st[CG_XX] = 0.0;
+    st[CG_IT] = 0.0;
+    st[CG_DONE] = (cap <= 0 || cg_stop(rr, 0.0, tau, kr, fixed)) ? 1.0 : 0.0;
+  }
+}
+
+// The vector part of one iteration, Ap (+ addmu p) given:  alpha = r.r / p.Ap;  x += alpha p;  r -= alpha Ap;
+// p = r + (r'.r' / r.r) p; then the stopping test on the new r and x.
+__global__ __launch_bounds__(1024) void cg_tail_kernel(int n, double* __restrict__ st, double* __restrict__ p,
+                                                       const double* __restrict__ Ap, double addmu,
+                                                       double* __restrict__ x, double* __restrict__ r, double tau,
+                                                       double kr, double fixed, int cap) {
+  __shared__ double sh[3][16];
+  if (st[CG_DONE] != 0.0) return;
+  const double rr = st[CG_RR];
+  double pv[8], av[8];
+  double pap = 0.0, z1 = 0.0, z2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = threadIdx.x + 1024 * q;
+    pv[q] = (i < n) ? p[i] : 0.0;
+    av[q] = (i < n) ? addmu * pv[q] + Ap[i] : 0.0;
+    pap += pv[q] * av[q];
+  }
+  block_sum3(pap, z1, z2, sh);
+  if (!(pap > 0.0)) {  // breakdown: stop with x and r as they are
+    if (threadIdx.x == 0) st[CG_DONE] = 1.0;
+    return;
+  }
+  const double alpha = rr / pap;
+  double rv[8];
+  double rs = 0.0, xs = 0.0, z3 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = threadIdx.x + 1024 * q;
+    rv[q] = 0.0;
+    if (i < n) {
+      const double xn = alpha * pv[q] + x[i];
+      const double rn = -alpha * av[q] + r[i];
+      x[i] = xn;
+      r[i] = rn;
+      rv[q] = rn;
+      rs += rn * rn;
+      xs += xn * xn;
+    }
+  }
+  block_sum3(rs, xs, z3, sh);
+  const double beta = rs / rr;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = threadIdx.x + 1024 * q;
+    if (i < n) p[i] = beta * pv[q] + rv[q];
+  }
+  if (threadIdx.x == 0) {
+    const double it = st[CG_IT] + 1.0;
+    st[CG_IT] = it;
+    st[CG_RR] = rs;
+    st[CG_XX] = xs;
+    if (it >= (double)cap || cg_stop(rs, xs, tau, kr, fixed)) st[CG_DONE] = 1.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void rowsum_abs_kernel(int l, const double* __restrict__ A, int sq, double* __restrict__ rows) {
   __shared__ double red[256];
   const int i = blockIdx.x;
@@ -362,6 +483,20 @@ hipError_t form_z(int l, const double* X, double a, const double* T, double c, d
   hipLaunchKernelGGL(form_z_kernel, dim3(nt, nt), dim3(256), 0, st, l, X, a, T, c, Z);
   return hipGetLastError();
 }
+hipError_t cg_init(int n, const double* b, double* x, double* r, double* p, double* st, double tau, double kr,
+                   double fixed, int cap, hipStream_t st_) {
+  if (n > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(1024), 0, st_, n, b, x, r, p, st, tau, kr, fixed, cap);
+  return hipGetLastError();
+}
+
+hipError_t cg_tail(int n, double* st, double* p, const double* Ap, double addmu, double* x, double* r, double tau,
+                   double kr, double fixed, int cap, hipStream_t st_) {
+  if (n > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cg_tail_kernel, dim3(1), dim3(1024), 0, st_, n, st, p, Ap, addmu, x, r, tau, kr, fixed, cap);
+  return hipGetLastError();
+}
+
 hipError_t cg_step(int n, double rr, const double* pAp, const double* p, const double* Ap, double* x, double* r,
                    hipStream_t st) {
   hipLaunchKernelGGL(cg_step_kernel, dim3(nblk(n)), dim3(256), 0, st, n, rr, pAp, p, Ap, x, r);

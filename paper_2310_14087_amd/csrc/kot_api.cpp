@@ -25,10 +25,10 @@ namespace {
 constexpr int kScalarDoubles = 64, kScalarInts = 16;
 constexpr size_t kScalarBytes = kScalarDoubles * sizeof(double) + kScalarInts * sizeof(int);
 // scalar slots: 0-3 per-call temporaries; residual norms (|r1|^2, |r2|^2) of the EG point 4-5 and of the trial
-// 6-7; the theta-rule dots 8-11; inputs of the default EG step 12-13; |z|^2 14; CG scalars 16-19; pooled
-// feature statistics 24-25
+// 6-7; the theta-rule dots 8-11; inputs of the default EG step 12-13; |z|^2 14; refinement scalars 16-19;
+// pooled feature statistics 24-25; the device-resident CG state 32-35
 enum : int { SL_TMP = 0, SL_VN = 4, SL_TN = 6, SL_THETA = 8, SL_ETA = 12, SL_ZZ = 14, SL_RR = 16, SL_PAP = 17,
-             SL_XX = 18, SL_POOL = 24 };
+             SL_XX = 18, SL_POOL = 24, SL_CG = 32 };
 
 struct State {  // an iterate w = (gamma, X) with its residual and the spectral data of Z
   double* g = nullptr;
@@ -103,8 +103,10 @@ struct kot_ctx {
   // split-K targets per size bucket (autotuner)
   int tune[kTuneBuckets];
   bool tuned = false;
-  // second stream and host thread for the extragradient branch of Algorithm 2 (created on first use)
+  // second and third streams, each with a host thread, for the extragradient branch of Algorithm 2 (created on
+  // first use)
   SideRunner* side = nullptr;
+  SideRunner* side2 = nullptr;  // the extragradient step's second projection
   bool is_lane = false;  // a child context of kot_solve_batched
 };
 
@@ -424,31 +426,29 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   int it = 0;
   double rr = 0.0;
   info->lowp = p->precision != KOT_FP64 && tp.m >= p->lowp_min_rows;
-  if (!info->lowp) {
-    HIPCHK(vec_fill(l, 0.0, x, st));
-    HIPCHK(vec_copy(l, ctx->a1, r, st));
-    HIPCHK(vec_copy(l, ctx->a1, pp, st));
-    HIPCHK(dot(l, r, r, ctx->dsc + SL_RR, ctx->part, st));
-    KCHK(sync_read(ctx));
-    rr = ctx->hsc[SL_RR];
-    double xx = 0.0;
-    // one host synchronization per iteration: the step length stays on the device, the host reads
-    // (p.Ap, r.r, x.x) after the update and decides on Eq. (4.5)
-    while (it < p->cg_max_iter) {
-      const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
-      if (std::sqrt(rr) <= thr) break;
-      KCHK(schur_matvec(ctx, cv, tp, pp, Ap));
-      HIPCHK(dot(l, pp, Ap, ctx->dsc + SL_PAP, ctx->part, st));
-      HIPCHK(cg_step(l, rr, ctx->dsc + SL_PAP, pp, Ap, x, r, st));
-      HIPCHK(dot2(l, r, r, ctx->dsc + SL_RR, x, x, ctx->dsc + SL_XX, ctx->part, st));
+  double* cs = ctx->dsc + SL_CG;        // device CG state
+  const double* hcs = ctx->hsc + SL_CG;
+  const double kr = p->kappa * rnorm;
+  const int cap = std::max(0, p->cg_max_iter);
+  // CG on the device: iterations go out in batches between host checks of the stop flag (those queued past
+  // the stop change nothing); one synchronization per batch instead of one per iteration
+  auto run_cg = [&](auto&& matvec, const double* b, double* xo, double* ro, double* po, double* Apo, double fixed,
+                    int capc) -> kot_status {
+    HIPCHK(cg_init(l, b, xo, ro, po, cs, p->tau, kr, fixed, capc, st));
+    for (int batch = 2;; batch = 3) {
+      for (int q = 0; q < batch; ++q) {
+        KCHK(matvec(po, Apo));
+        HIPCHK(cg_tail(l, cs, po, Apo, 0.0, xo, ro, p->tau, kr, fixed, capc, st));
+      }
       KCHK(sync_read(ctx));
-      if (!(ctx->hsc[SL_PAP] > 0.0)) break;  // the device skipped the update
-      const double rr_new = ctx->hsc[SL_RR];
-      xx = ctx->hsc[SL_XX];
-      HIPCHK(vec_axpby(l, 1.0, r, rr_new / rr, pp, st));
-      rr = rr_new;
-      ++it;
+      if (hcs[kCgDone] != 0.0) return KOT_OK;
     }
+  };
+  if (!info->lowp) {
+    KCHK(run_cg([&](const double* v, double* y) { return schur_matvec(ctx, cv, tp, v, y); }, ctx->a1, x, r, pp, Ap,
+                0.0, cap));
+    it = (int)hcs[kCgIt];
+    rr = hcs[kCgRR];
   } else {
     // Iterative refinement: each sweep solves M~ d = r with CG whose chain runs in reduced precision, then
     // x += d and the true residual r = a1 - M x is recomputed in FP64; Eq. 4.5 is checked on that residual.
@@ -464,32 +464,14 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
       KCHK(sync_read(ctx));
       rr = ctx->hsc[SL_RR];
       xx = ctx->hsc[SL_XX];
-      const double thr = p->tau * std::min(1.0, p->kappa * rnorm * std::sqrt(xx));
+      const double thr = p->tau * std::min(1.0, kr * std::sqrt(xx));
       if (std::sqrt(rr) <= thr || sweeps >= 8 || it >= 4 * std::max(1, p->cg_max_iter)) break;
-      // inner CG from d = 0 on the reduced-precision operator
-      double* d = ctx->lx;
-      double* ri = ctx->lr;
-      double* pi = ctx->lp;
-      double* Api = ctx->lAp;
-      HIPCHK(vec_fill(l, 0.0, d, st));
-      HIPCHK(vec_copy(l, r, ri, st));
-      HIPCHK(vec_copy(l, r, pi, st));
-      double rri = rr;
+      // inner CG from d = 0 on the reduced-precision operator, to a fixed threshold
       const double stop_in = std::max(inner_rel * std::sqrt(rr), 0.5 * thr);
-      for (int j = 0; j < std::max(1, p->cg_max_iter); ++j) {
-        if (std::sqrt(rri) <= stop_in) break;
-        KCHK(schur_matvec_lowp(ctx, cv, tp, pi, Api, mode));
-        HIPCHK(dot(l, pi, Api, ctx->dsc + SL_PAP, ctx->part, st));
-        HIPCHK(cg_step(l, rri, ctx->dsc + SL_PAP, pi, Api, d, ri, st));
-        HIPCHK(dot(l, ri, ri, ctx->dsc + SL_TMP, ctx->part, st));
-        KCHK(sync_read(ctx));
-        if (!(ctx->hsc[SL_PAP] > 0.0)) break;
-        const double rr_new = ctx->hsc[SL_TMP];
-        HIPCHK(vec_axpby(l, 1.0, ri, rr_new / rri, pi, st));
-        rri = rr_new;
-        ++it;
-      }
-      HIPCHK(vec_axpby(l, 1.0, d, 1.0, x, st));
+      KCHK(run_cg([&](const double* v, double* y) { return schur_matvec_lowp(ctx, cv, tp, v, y, mode); }, r,
+                  ctx->lx, ctx->lr, ctx->lp, ctx->lAp, stop_in, std::max(1, p->cg_max_iter)));
+      it += (int)hcs[kCgIt];
+      HIPCHK(vec_axpby(l, 1.0, ctx->lx, 1.0, x, st));
       KCHK(schur_matvec(ctx, cv, tp, x, Ap));                 // FP64 residual
       HIPCHK(vec_lincomb(l, 1.0, ctx->a1, -1.0, Ap, r, st));
       ++sweeps;
@@ -515,22 +497,30 @@ kot_status proj_psd(kot_ctx* ctx, int l, double* Y, double* Pbasis, double* wbuf
   return KOT_OK;
 }
 
-// One extragradient step on Eq. (4.1) from (g, X) with r1(g, X) given; writes (gn, Xn).
+// Pi(X - eta (Phi*(gs) + lam1 I)) into out, through the eigendecomposition (warm basis Pbasis, eigenvalues sbuf).
+kot_status eg_proj(kot_ctx* ctx, const CoreView& cv, const double* gs, const double* X, double eta, double* Pbasis,
+                   double* sbuf, bool warm, double* out, const kot_params* p, int* sweeps_acc) {
+  const int l = cv.l;
+  KCHK(phi_star(ctx, cv, gs, ctx->T1));
+  HIPCHK(form_z(l, X, eta, ctx->T1, -eta * cv.lam1, ctx->Z, ctx->stream));
+  KCHK(proj_psd(ctx, l, ctx->Z, Pbasis, sbuf, warm, out, p, sweeps_acc));
+  return KOT_OK;
+}
+
+// One extragradient step on Eq. (4.1) from (g, X) with r1(g, X) given; writes (gn, Xn):
+//   gh = g - eta r1(g, X),  Xh = Pi(X - eta (Phi*(g) + lam1 I)),  gn = g - eta r1(gh, Xh),
+//   Xn = Pi(X - eta (Phi*(gh) + lam1 I)).
+// The X-part of the operator depends on gamma alone, so Xn needs gh but not Xh: the two projections are
+// independent (the overlapped iteration runs them on two streams).
 kot_status eg_step_impl(kot_ctx* ctx, const CoreView& cv, const double* g, const double* X, const double* r1,
                         double eta, double* gn, double* Xn, bool warm, const kot_params* p, int* sweeps_acc) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
-  // half step: gh = g - eta r1(g,X);  Xh = Pi(X - eta (Phi*(g) + lam1 I))
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, r1, ctx->gh, st));
-  KCHK(phi_star(ctx, cv, g, ctx->T1));
-  HIPCHK(form_z(l, X, eta, ctx->T1, -eta * cv.lam1, ctx->Z, st));
-  KCHK(proj_psd(ctx, l, ctx->Z, ctx->Pe1, ctx->s_e1, warm, ctx->Xh, p, sweeps_acc));
-  // full step with F at the half point
+  KCHK(eg_proj(ctx, cv, g, X, eta, ctx->Pe1, ctx->s_e1, warm, ctx->Xh, p, sweeps_acc));
   KCHK(r1_op(ctx, cv, ctx->gh, ctx->Xh, ctx->r1h, ctx->T1));
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, ctx->r1h, gn, st));
-  KCHK(phi_star(ctx, cv, ctx->gh, ctx->T1));
-  HIPCHK(form_z(l, X, eta, ctx->T1, -eta * cv.lam1, ctx->Z, st));
-  KCHK(proj_psd(ctx, l, ctx->Z, ctx->Pe2, ctx->s_e2, warm, Xn, p, sweeps_acc));
+  KCHK(eg_proj(ctx, cv, ctx->gh, X, eta, ctx->Pe2, ctx->s_e2, warm, Xn, p, sweeps_acc));
   return KOT_OK;
 }
 
@@ -733,25 +723,25 @@ void side_loop(SideRunner* s) {
   }
 }
 
-kot_status side_ensure(kot_ctx* ctx, int l, int nmax) {
-  if (!ctx->side) {
+kot_status runner_ensure(kot_ctx* ctx, SideRunner** slot, int l, int nmax) {
+  if (!*slot) {
     SideRunner* s = new SideRunner();
     kot_ctx* c = nullptr;
     const kot_status st = kot_create(&c, ctx->device, nullptr);
     if (st != KOT_OK) {
       delete s;
-      return fail(ctx, st, "could not create the side context");
+      return fail(ctx, st, "could not create a side context");
     }
     s->c = c;
     if (hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess) {
       kot_destroy(c);
       delete s;
-      return fail(ctx, KOT_ERR_HIP, "could not create the side event");
+      return fail(ctx, KOT_ERR_HIP, "could not create a side event");
     }
     s->th = std::thread(side_loop, s);
-    ctx->side = s;
+    *slot = s;
   }
-  kot_ctx* c = ctx->side->c;
+  kot_ctx* c = (*slot)->c;
   c->tuned = ctx->tuned;
   if (ctx->tuned) std::copy(ctx->tune, ctx->tune + kTuneBuckets, c->tune);
   const kot_status st = ensure_ws(c, l, nmax);
@@ -760,8 +750,13 @@ kot_status side_ensure(kot_ctx* ctx, int l, int nmax) {
   return KOT_OK;
 }
 
-kot_status side_post(kot_ctx* ctx, std::function<kot_status()> f) {
-  SideRunner* s = ctx->side;
+kot_status side_ensure(kot_ctx* ctx, int l, int nmax) {
+  KCHK(runner_ensure(ctx, &ctx->side, l, nmax));
+  return runner_ensure(ctx, &ctx->side2, l, 0);
+}
+
+// Queues f on runner s, ordered after the work queued so far on ctx's stream.
+kot_status runner_post(kot_ctx* ctx, SideRunner* s, std::function<kot_status()> f) {
   HIPCHK(hipEventRecord(s->ready, ctx->stream));
   s->c->prof.on = ctx->prof.on;
   {
@@ -772,20 +767,20 @@ kot_status side_post(kot_ctx* ctx, std::function<kot_status()> f) {
   s->cvar.notify_one();
   return KOT_OK;
 }
+kot_status side_post(kot_ctx* ctx, std::function<kot_status()> f) { return runner_post(ctx, ctx->side, std::move(f)); }
 
-// Waits for the posted job; on return the side stream has finished all of the job's work (the job ends with a
-// host synchronization of that stream).
-kot_status side_join(kot_ctx* ctx) {
-  SideRunner* s = ctx->side;
+// Waits for the job posted on s (from whichever thread posted it); on return the side stream has finished all
+// of the job's work (every job ends with a host synchronization of its stream).  Errors are reported on ctx.
+kot_status runner_join(kot_ctx* ctx, SideRunner* s) {
   while (s->state.load(std::memory_order_acquire) != 2) __builtin_ia32_pause();
   s->state.store(0, std::memory_order_relaxed);
   s->job = nullptr;
   if (s->rc < 0) return fail(ctx, s->rc, "second stream: %s", s->c->err.c_str());
   return KOT_OK;
 }
+kot_status side_join(kot_ctx* ctx) { return runner_join(ctx, ctx->side); }
 
-void side_destroy(kot_ctx* ctx) {
-  SideRunner* s = ctx->side;
+void runner_destroy(SideRunner*& s) {
   if (!s) return;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -796,7 +791,11 @@ void side_destroy(kot_ctx* ctx) {
   if (s->ready) hipEventDestroy(s->ready);
   kot_destroy(s->c);
   delete s;
-  ctx->side = nullptr;
+  s = nullptr;
+}
+void side_destroy(kot_ctx* ctx) {
+  runner_destroy(ctx->side);
+  runner_destroy(ctx->side2);
 }
 
 constexpr int kOverlapMinL = 128;
@@ -855,7 +854,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   }
   const bool use_eg = p->safeguard == KOT_SAFEGUARD_EG;
   const bool overlap = use_eg && overlap_ok(ctx, p, l);
-  int side_sweeps = 0;
+  int side_sweeps = 0, side2_sweeps = 0;
   if (overlap) KCHK(side_ensure(ctx, l, 0));
   if (use_eg) KCHK(copy_state(ctx, l, *W, *V));
   double theta = p->theta0;
@@ -879,15 +878,35 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     }
     // (1) safeguard: one EG step on v, then R(v_{k+1}); on the side stream when overlapped
     if (use_eg && overlap) {
+      // gh on this stream, then the projection for Xn on the third stream and the rest of the branch (the
+      // projection for Xh, gn, the residual at v_{k+1} once Xn is in) on the second
       const bool warm_v = warm_e && p->warm_eig;
-      KCHK(side_post(ctx, [ctx, &cv, V, eta, warm_v, p, &side_sweeps]() -> kot_status {
+      State* H = &ctx->S[3];
+      HIPCHK(vec_lincomb(l, 1.0, V->g, -eta, V->r1, ctx->gh, st));
+      KCHK(runner_post(ctx, ctx->side2, [ctx, &cv, V, H, eta, warm_v, p, &side2_sweeps]() -> kot_status {
+        kot_ctx* c = ctx->side2->c;
+        KCHK(eg_proj(c, cv, ctx->gh, V->X, eta, c->Pe2, c->s_e2, warm_v, H->X, p, &side2_sweeps));
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, KOT_ERR_HIP, "stream synchronization");
+        return KOT_OK;
+      }));
+      const kot_status rp = side_post(ctx, [ctx, &cv, V, H, eta, warm_v, p, &side_sweeps]() -> kot_status {
         kot_ctx* c = ctx->side->c;
-        State* H = &ctx->S[3];
-        KCHK(eg_step_impl(c, cv, V->g, V->X, V->r1, eta, H->g, H->X, warm_v, p, &side_sweeps));
+        const int n = cv.l;
+        const kot_status r0 = eg_proj(c, cv, V->g, V->X, eta, c->Pe1, c->s_e1, warm_v, c->Xh, p, &side_sweeps);
+        kot_status r1 = r0 < 0 ? r0 : r1_op(c, cv, ctx->gh, c->Xh, c->r1h, c->T1);
+        if (r1 >= 0 && vec_lincomb(n, 1.0, V->g, -eta, c->r1h, H->g, c->stream) != hipSuccess)
+          r1 = fail(c, KOT_ERR_HIP, "vec_lincomb");
+        const kot_status r2 = runner_join(c, ctx->side2);  // Xn (joined even after a failure)
+        KCHK(r1);
+        KCHK(r2);
         std::swap(H->g, V->g);
         std::swap(H->X, V->X);
         return residual_state(c, cv, *V, p->warm_eig ? V->P : nullptr, p, &side_sweeps, SL_VN, false);
-      }));
+      });
+      if (rp < 0) {  // the third stream's job is already out: wait for it before returning
+        (void)runner_join(ctx, ctx->side2);
+        return rp;
+      }
       warm_e = true;
     } else if (use_eg) {
       State* H = &ctx->S[3];
@@ -918,8 +937,8 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     const kot_status rc_newton = newton();
     if (use_eg && overlap) {
       const kot_status rc_side = side_join(ctx);  // joined even when the Newton branch failed
-      sweeps += side_sweeps;
-      side_sweeps = 0;
+      sweeps += side_sweeps + side2_sweeps;
+      side_sweeps = side2_sweeps = 0;
       KCHK(rc_newton);
       KCHK(rc_side);
     }
@@ -1520,22 +1539,26 @@ kot_status kot_potentials(kot_ctx* ctx, const kot_problem* pb, const kot_params*
 
 kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass) {
   KCHK(check_ctx(ctx));
-  Profiler* side = ctx->side ? &ctx->side->c->prof : nullptr;  // launches of the extragradient branch
+  // launches of the second and third streams count with the context's own
+  Profiler* side = ctx->side ? &ctx->side->c->prof : nullptr;
+  Profiler* side2 = ctx->side2 ? &ctx->side2->c->prof : nullptr;
   if (enable) {
     ctx->prof.clear();
     ctx->prof.on = true;
     if (side) side->clear();
+    if (side2) side2->clear();
     return KOT_OK;
   }
   ctx->prof.on = false;
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  if (side) {
-    side->on = false;
-    HIPCHK(hipStreamSynchronize(ctx->side->c->stream));
+  for (SideRunner* s : {ctx->side, ctx->side2}) {
+    if (!s) continue;
+    s->c->prof.on = false;
+    HIPCHK(hipStreamSynchronize(s->c->stream));
   }
   if (out) {
     for (int c = 0; c < nclass * 4; ++c) out[c] = 0.0;
-    for (const Profiler* pf : {(const Profiler*)&ctx->prof, (const Profiler*)side}) {
+    for (const Profiler* pf : {(const Profiler*)&ctx->prof, (const Profiler*)side, (const Profiler*)side2}) {
       if (!pf) continue;
       for (const auto& r : pf->recs) {
         if (r.cls >= nclass || !r.a || !r.b) continue;
@@ -1550,6 +1573,7 @@ kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass) {
   }
   ctx->prof.clear();
   if (side) side->clear();
+  if (side2) side2->clear();
   return KOT_OK;
 }
 

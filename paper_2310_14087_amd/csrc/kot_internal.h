@@ -107,6 +107,15 @@ hipError_t dot2(long long n, const double* x1, const double* y1, double* o1, con
 // Z = (M + M^T)/2 + c I with M = X - a T (l x l; Z must not alias X or T)
 hipError_t form_z(int l, const double* X, double a, const double* T, double c, double* Z, hipStream_t st);
 // CG update with a device step length: alpha = rr / pAp[0] (0 when pAp[0] <= 0); x += alpha p; r -= alpha Ap.
+// Conjugate gradients with the scalars on the device (n <= 8192, one workgroup per call).  st holds r.r, x.x,
+// a stop flag and the iteration count (indices below).  cg_init: x = 0, r = p = b and the test at the start;
+// cg_tail: the vector part of one iteration given Ap (Ap + addmu p is the operator's product), a no-op once
+// stopped.  Stop: |r| <= tau min(1, kr |x|) (or |r| <= fixed when fixed > 0), cap iterations, or p.Ap <= 0.
+constexpr int kCgRR = 0, kCgXX = 1, kCgDone = 2, kCgIt = 3;
+hipError_t cg_init(int n, const double* b, double* x, double* r, double* p, double* st, double tau, double kr,
+                   double fixed, int cap, hipStream_t s);
+hipError_t cg_tail(int n, double* st, double* p, const double* Ap, double addmu, double* x, double* r, double tau,
+                   double kr, double fixed, int cap, hipStream_t s);
 hipError_t cg_step(int n, double rr, const double* pAp, const double* p, const double* Ap, double* x, double* r,
                    hipStream_t st);
 // out[0] = max_i sum_j |A_ij| (row-sum norm)
