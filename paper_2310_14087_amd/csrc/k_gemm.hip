@@ -2,6 +2,9 @@
 // column-dot reduction used for Phi(X)_i = R[:,i]^T (X R)[:,i] and the diagonal extract of the CG matvec.
 #include "kot_internal.h"
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace kot {
 
@@ -115,19 +118,34 @@ __device__ __forceinline__ void tri_k_range(int tri, int k, int m0, int n0, int&
 // blockIdx.z = batch * splits + split.  With splits > 1 the workgroup covers K slices
 // [split*kchunk, (split+1)*kchunk) and writes its raw partial tile to part (layout [batch][split][m][n]); a
 // split that misses the tile's K range writes nothing (the reduction skips it the same way).
+// With a work list (units != null, a 1D grid) workgroup i takes entry i: (tile row << 16) | (tile col << 8) | K
+// slice, or -1 for nothing.
 template <bool TA, bool TB, bool SC, int FM, int FN>
 __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(GemmArgs g, int splits, int kchunk,
-                                                                             double* __restrict__ part) {
+                                                                             double* __restrict__ part,
+                                                                             const int* __restrict__ units) {
   constexpr int WN = 4 / FN;                   // waves along n
   constexpr int NT = 64 * (4 / FM) * WN;
   __shared__ double As[TILE_D];
   __shared__ double Bs[TILE_D];
-  const int bz = blockIdx.z / splits, sp = blockIdx.z % splits;
+  int bz, sp, m0, n0;
+  if (units) {
+    const int u = units[blockIdx.x];
+    if (u < 0) return;
+    bz = 0;
+    sp = u & 255;
+    m0 = (u >> 16) * BM;
+    n0 = ((u >> 8) & 255) * BN;
+  } else {
+    bz = blockIdx.z / splits;
+    sp = blockIdx.z % splits;
+    m0 = blockIdx.y * BM;
+    n0 = blockIdx.x * BN;
+  }
   const double* __restrict__ A = g.A + bz * g.sA;
   const double* __restrict__ B = g.B + bz * g.sB;
   const double* __restrict__ S = SC ? g.s + bz * g.sS : nullptr;
   double* __restrict__ C = g.C + bz * g.sC;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   if (g.lower && n0 > m0 + BM - 1) return;  // tile strictly above the diagonal (uniform per workgroup)
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -323,6 +341,79 @@ static double gemm_work_flops(const GemmArgs& g) {
 
 hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) { return gemm_f64_cfg(g, st, 0, 0); }
 
+// ---- work lists for products with uneven tiles ----------------------------------------------------------
+// Workgroup i of a launch runs on XCD i mod 8, so a grid in tile order gives each XCD whatever tiles land on
+// it: with a lower-only result or triangular operands (work per tile from the full K down to one slice) some
+// XCDs get several times the work of others.  The work list deals the (tile, K slice) units, longest first,
+// each to the XCD with the least work so far, and lays them out so that entry i belongs to XCD i mod 8.  One
+// list per shape, built on first use and kept for the life of the process (a few KB each).
+constexpr int kXcds = 8;
+struct UnitKey {
+  int m, n, k, tri, lower, kchunk;
+  bool operator<(const UnitKey& o) const {
+    return std::tie(m, n, k, tri, lower, kchunk) < std::tie(o.m, o.n, o.k, o.tri, o.lower, o.kchunk);
+  }
+};
+struct UnitList {
+  int* dev = nullptr;
+  int len = 0;
+};
+static std::mutex g_units_mu;
+static std::map<UnitKey, UnitList>* g_units = nullptr;
+
+static hipError_t unit_list(const GemmArgs& g, int kchunk, const UnitList** out) {
+  const UnitKey key{g.m, g.n, g.k, g.tri, g.lower, kchunk};
+  std::lock_guard<std::mutex> lk(g_units_mu);
+  if (!g_units) g_units = new std::map<UnitKey, UnitList>();
+  auto it = g_units->find(key);
+  if (it != g_units->end()) {
+    *out = &it->second;
+    return hipSuccess;
+  }
+  struct U { int code, work; };
+  std::vector<U> us;
+  for (int m0 = 0; m0 < g.m; m0 += BM)
+    for (int n0 = 0; n0 < g.n; n0 += BN) {
+      if (g.lower && n0 > m0 + BM - 1) continue;
+      int klo = 0, khi = g.k;
+      if (g.tri & 1) klo = std::max(klo, m0);
+      if (g.tri & 8) klo = std::max(klo, n0);
+      if (g.tri & 2) khi = std::min(khi, m0 + BM);
+      if (g.tri & 4) khi = std::min(khi, n0 + BN);
+      klo &= ~(BK - 1);
+      const int code = ((m0 / BM) << 16) | ((n0 / BN) << 8);
+      if (khi <= klo) {  // an empty K range still writes its tile (alpha * 0 + beta * C) when not split
+        if (kchunk >= g.k) us.push_back({code, 1});
+        continue;
+      }
+      for (int sp = klo / kchunk; sp * kchunk < khi; ++sp) {
+        const int w = std::min(khi, sp * kchunk + kchunk) - std::max(klo, sp * kchunk);
+        us.push_back({code | sp, w + BK});  // + a slice's fixed cost
+      }
+    }
+  std::stable_sort(us.begin(), us.end(), [](const U& a, const U& b) { return a.work > b.work; });
+  std::vector<std::vector<int>> bins(kXcds);
+  std::vector<long long> load(kXcds, 0);
+  for (const U& u : us) {
+    int b = 0;
+    for (int x = 1; x < kXcds; ++x)
+      if (load[x] < load[b]) b = x;
+    bins[b].push_back(u.code);
+    load[b] += u.work;
+  }
+  size_t rows = 0;
+  for (const auto& b : bins) rows = std::max(rows, b.size());
+  std::vector<int> host(rows * kXcds, -1);
+  for (int x = 0; x < kXcds; ++x)
+    for (size_t r = 0; r < bins[x].size(); ++r) host[r * kXcds + x] = bins[x][r];
+  UnitList ul;
+  ul.len = (int)host.size();
+  KOT_HIP_TRY(hipMalloc(&ul.dev, host.size() * sizeof(int)));
+  KOT_HIP_TRY(hipMemcpy(ul.dev, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
+  *out = &((*g_units)[key] = ul);
+  return hipSuccess;
+}
+
 hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits_req) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return hipSuccess;
   if (g.k <= 0) {  // C = beta C
@@ -344,29 +435,63 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
   // 16 waves per workgroup: measured fastest on every solver shape (four waves per SIMD at one tile per CU)
   if (waves == 0) waves = 16;
   int splits = 1;
+  int kchunk = g.k;
   if (splits_req > 0) {
     splits = std::min(splits_req, std::max(1, g.k / BK));
   } else {
-    // K split: aim for `target` workgroups (one per CU by default, twice that when triangular operands make
-    // the K ranges of the tiles uneven; per size bucket from the autotuner's table), at least 64 of K each
+    // K split: aim for `target` workgroups (one per CU by default; per size bucket from the autotuner's table)
     int target = g_gemm_tune ? g_gemm_tune[gemm_tune_bucket(std::max(g.m, g.n))] : 256;
-    if (g.tri) target *= 2;
     const int computed = g.lower ? (tiles + ((g.n + BN - 1) / BN) * g.batch) / 2 : tiles;
-    if (target > 0 && computed < target && g.k >= 128) {
+    if (g.tri || g.lower) {
+      // uneven or halved work: count the (tile, K slice) work units of a slice width, and take the widest
+      // slice (a multiple of BK, at least 64) that yields 1.5 x target units, so that the longest K ranges
+      // are cut into pieces and every CU gets work
+      auto units = [&](int kc) {
+        long long u = 0;
+        for (int m0 = 0; m0 < g.m; m0 += BM)
+          for (int n0 = 0; n0 < g.n; n0 += BN) {
+            if (g.lower && n0 > m0 + BM - 1) continue;
+            int klo = 0, khi = g.k;
+            if (g.tri & 1) klo = std::max(klo, m0);
+            if (g.tri & 8) klo = std::max(klo, n0);
+            if (g.tri & 2) khi = std::min(khi, m0 + BM);
+            if (g.tri & 4) khi = std::min(khi, n0 + BN);
+            klo &= ~(BK - 1);
+            if (khi > klo) u += (khi - 1) / kc - klo / kc + 1;
+          }
+        return u * g.batch;
+      };
+      if (target > 0 && g.k >= 128) {
+        const long long want = (long long)target * 3 / 2;
+        int kc = (g.k + BK - 1) / BK * BK;
+        while (kc > 64 && units(kc) < want) kc = std::max(64, (kc / 2 + BK - 1) / BK * BK);
+        kchunk = kc;
+        splits = (g.k + kchunk - 1) / kchunk;
+      }
+    } else if (target > 0 && computed < target && g.k >= 128) {
       splits = (target + computed - 1) / computed;
       splits = std::min(splits, std::min(8, g.k / 64));
     }
   }
   if (splits > 1) {
     const size_t need = (size_t)splits * g.batch * (size_t)g.m * g.n;
-    if (!g_gemm_ws || need > g_gemm_ws_cap) splits = 1;
+    if (!g_gemm_ws || need > g_gemm_ws_cap) {
+      splits = 1;
+      kchunk = g.k;
+    }
   }
-  int kchunk = g.k;
-  if (splits > 1) {
+  if (splits > 1 && kchunk == g.k) {
     kchunk = ((g.k + splits - 1) / splits + BK - 1) / BK * BK;
     splits = (g.k + kchunk - 1) / kchunk;
   }
   dim3 grid((g.n + BN - 1) / BN, (g.m + BM - 1) / BM, g.batch * splits);
+  const int* units = nullptr;
+  if ((g.tri || g.lower) && g.batch == 1 && g.m <= 64 * BM && g.n <= 64 * BN && splits <= 255) {
+    const UnitList* ul = nullptr;
+    KOT_HIP_TRY(unit_list(g, splits > 1 ? kchunk : g.k, &ul));
+    units = ul->dev;
+    grid = dim3(ul->len, 1, 1);
+  }
   const bool sc = g.s != nullptr;
   Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
   // work of the product (2mnk flops, less the skipped tiles and K ranges); bytes = each operand and C once
@@ -377,7 +502,7 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
 #define KOT_GEMM_CASE(TA, TB, SC_, FM, FN)                                                                       \
   if (!launched && g.transa == TA && g.transb == TB && sc == SC_ && waves == (4 / FM) * (4 / FN)) {               \
     hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, SC_, FM, FN>), grid, dim3(64 * (4 / FM) * (4 / FN)), 0, st, g,    \
-                       splits, kchunk, part);                                                                      \
+                       splits, kchunk, part, units);                                                               \
     launched = true;                                                                                               \
   }
 #define KOT_GEMM_WAVES(FM, FN)                                                                                     \

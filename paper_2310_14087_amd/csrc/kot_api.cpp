@@ -79,7 +79,7 @@ struct kot_ctx {
   int* hint = nullptr;
   double* part = nullptr;      // reduction partials (>= max(kRedBlocks, kDiagParts*l, n, q^2 tile pairs))
   size_t part_cap = 0;
-  double* gemm_ws = nullptr;   // split-K partial tiles (4 l^2 doubles)
+  double* gemm_ws = nullptr;   // split-K partial tiles (16 l^2 doubles: up to 16 K slices of an l x l product)
   size_t gemm_ws_cap = 0;
   // matrices (cap x cap)
   double *Qb, *Rb, *Kb, *KKb, *Z, *T1, *T2, *T3, *T4, *Bm, *dX, *Mr, *eigtmp, *Pe1, *Pe2, *Xh;
@@ -181,10 +181,10 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   }
   if (!(ctx->part = alloc(need_part * sizeof(double)))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   ctx->part_cap = need_part;
-  if (!(ctx->gemm_ws = alloc(4 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  if (!(ctx->gemm_ws = alloc(16 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   if (!(ctx->Bf = (float*)alloc(mm / 2)) || !(ctx->Cf = (float*)alloc(mm / 2)) || !(ctx->Ef = (float*)alloc(mm / 2)))
     return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
-  ctx->gemm_ws_cap = 4 * (size_t)cap * cap;
+  ctx->gemm_ws_cap = 16 * (size_t)cap * cap;
   g_gemm_ws = ctx->gemm_ws;
   g_gemm_ws_cap = ctx->gemm_ws_cap;
   ctx->eig = eig_work_create(cap);
