@@ -126,8 +126,8 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
                                                                              const int* __restrict__ units) {
   constexpr int WN = 4 / FN;                   // waves along n
   constexpr int NT = 64 * (4 / FM) * WN;
-  __shared__ double As[TILE_D];
-  __shared__ double Bs[TILE_D];
+  __shared__ double As2[2][TILE_D];  // two K slices in LDS: one feeds the matrix cores while the next is stored
+  __shared__ double Bs2[2][TILE_D];
   int bz, sp, m0, n0;
   if (units) {
     const int u = units[blockIdx.x];
@@ -169,11 +169,13 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
   GemmArgs gk = g;
   gk.k = kend;  // bounds for the loads of this split
   tile.load(gk, A, B, S, m0, n0, kbeg, t);
-  tile.store(As, Bs, t);
+  tile.store(As2[0], Bs2[0], t);
   __syncthreads();
   const int r16 = lane & 15, k4 = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
     const bool more = kt + 1 < nk;
+    const double* As = As2[kt & 1];
+    const double* Bs = Bs2[kt & 1];
     if (more) tile.load(gk, A, B, S, m0, n0, kbeg + (kt + 1) * BK, t);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
@@ -188,9 +190,10 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // the next slice goes to the other buffer; one barrier then both publishes it and ends every read of this
+    // one, which the slice after next overwrites
     if (more) {
-      __syncthreads();
-      tile.store(As, Bs, t);
+      tile.store(As2[(kt + 1) & 1], Bs2[(kt + 1) & 1], t);
       __syncthreads();
     }
   }
