@@ -165,18 +165,22 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  T tile;
+  // Two register sets of loads in flight: slice kt + 2 is requested while slice kt feeds the matrix cores and
+  // slice kt + 1 (requested one slice earlier) goes to the other LDS buffer, so each global load has two
+  // slices of compute to arrive.
+  T tile0, tile1;
   GemmArgs gk = g;
   gk.k = kend;  // bounds for the loads of this split
-  tile.load(gk, A, B, S, m0, n0, kbeg, t);
-  tile.store(As2[0], Bs2[0], t);
+  tile0.load(gk, A, B, S, m0, n0, kbeg, t);
+  tile0.store(As2[0], Bs2[0], t);
+  if (nk > 1) tile1.load(gk, A, B, S, m0, n0, kbeg + BK, t);
   __syncthreads();
   const int r16 = lane & 15, k4 = lane >> 4;
-  for (int kt = 0; kt < nk; ++kt) {
-    const bool more = kt + 1 < nk;
+  // spare: its slice kt is in LDS already, so it takes the request for slice kt + 2; next holds slice kt + 1
+  auto step = [&](int kt, T& spare, T& next) {
     const double* As = As2[kt & 1];
     const double* Bs = Bs2[kt & 1];
-    if (more) tile.load(gk, A, B, S, m0, n0, kbeg + (kt + 1) * BK, t);
+    if (kt + 2 < nk) spare.load(gk, A, B, S, m0, n0, kbeg + (kt + 2) * BK, t);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double a[FM], b[FN];
@@ -190,12 +194,16 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    // the next slice goes to the other buffer; one barrier then both publishes it and ends every read of this
-    // one, which the slice after next overwrites
-    if (more) {
-      tile.store(As2[(kt + 1) & 1], Bs2[(kt + 1) & 1], t);
+    // slice kt + 1 goes to the other buffer; one barrier then both publishes it and ends every read of this
+    // one, which slice kt + 2 overwrites
+    if (kt + 1 < nk) {
+      next.store(As2[(kt + 1) & 1], Bs2[(kt + 1) & 1], t);
       __syncthreads();
     }
+  };
+  for (int kt = 0; kt < nk; kt += 2) {  // two slices per pass, so that each register set stays in place
+    step(kt, tile0, tile1);
+    if (kt + 1 < nk) step(kt + 1, tile1, tile0);
   }
   // ---- epilogue ----
   const int M = g.m, N = g.n;

@@ -107,6 +107,11 @@ struct kot_ctx {
   // first use)
   SideRunner* side = nullptr;
   SideRunner* side2 = nullptr;  // the extragradient step's second projection
+  // the triangular inverse of the lift as one graph (about thirty small launches), per (l, buffers)
+  hipGraphExec_t trtri_graph = nullptr;
+  int trtri_l = 0;
+  const void* trtri_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool trtri_graph_failed = false;
   bool is_lane = false;  // a child context of kot_solve_batched
 };
 
@@ -805,6 +810,42 @@ bool overlap_ok(const kot_ctx* ctx, const kot_params* p, int l) {
 }
 
 // Algorithm 2 on a prepared core.
+// Y = R^-1 (W: workspace) through a HIP graph of the launches of trtri_upper, captured on the first call for
+// these buffers (that call runs them directly, which also builds any GEMM work list they need) and replayed
+// afterwards.  With the profiler on, or when capture fails, the launches go out one by one.
+kot_status trtri_cached(kot_ctx* ctx, int l, const double* R, double* Y, double* W) {
+  hipStream_t st = ctx->stream;
+  const void* key[4] = {R, Y, W, g_gemm_ws};
+  const bool same = ctx->trtri_graph && ctx->trtri_l == l && std::equal(key, key + 4, ctx->trtri_key);
+  if (same && !(g_prof && g_prof->on)) {
+    HIPCHK(hipGraphLaunch(ctx->trtri_graph, st));
+    return KOT_OK;
+  }
+  HIPCHK(trtri_upper(l, R, Y, W, st));
+  if (ctx->trtri_graph_failed || (g_prof && g_prof->on)) return KOT_OK;
+  if (ctx->trtri_graph) {
+    hipGraphExecDestroy(ctx->trtri_graph);
+    ctx->trtri_graph = nullptr;
+  }
+  hipGraph_t gr = nullptr;
+  bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const hipError_t le = trtri_upper(l, R, Y, W, st);
+    ok = hipStreamEndCapture(st, &gr) == hipSuccess && le == hipSuccess && gr != nullptr;
+  }
+  if (ok) ok = hipGraphInstantiate(&ctx->trtri_graph, gr, nullptr, nullptr, 0) == hipSuccess;
+  if (gr) hipGraphDestroy(gr);
+  if (!ok) {
+    (void)hipGetLastError();
+    ctx->trtri_graph = nullptr;
+    ctx->trtri_graph_failed = true;
+    return KOT_OK;
+  }
+  ctx->trtri_l = l;
+  std::copy(key, key + 4, ctx->trtri_key);
+  return KOT_OK;
+}
+
 // pre: the setup already formed KK, the default step's bounds, |z|^2 and the network's start (in S[1].g).
 kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const double* gamma0, kot_result* res,
                     const Prelude* pre = nullptr) {
@@ -830,7 +871,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   if (gamma0 && p->lift_x0) {
     // X0 = R^-T diag(y) R^-1 with y = (Q gamma0 - z)/(2 lam2) (stationarity's value of Phi(X)) on the
     // constraints predicted active, small entries dropped, so that Phi(X0) = y
-    HIPCHK(trtri_upper(l, cv.R, ctx->T1, ctx->T2, st));
+    KCHK(trtri_cached(ctx, l, cv.R, ctx->T1, ctx->T2));
     HIPCHK(mm(st, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, W->g, 1, 0.0, ctx->vtmp, 1));
     HIPCHK(lift_diag(l, ctx->vtmp, cv.z, W->g, cv.lam1, cv.lam2, 0.02, ctx->dg, ctx->part, st));
     HIPCHK(mm(st, 1, 0, l, l, l, 1.0, ctx->T1, l, ctx->dg, ctx->T1, l, 0.0, W->X, l, TRI_A_LOWER | TRI_B_UPPER, true));
@@ -856,7 +897,11 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   const bool overlap = use_eg && overlap_ok(ctx, p, l);
   int side_sweeps = 0, side2_sweeps = 0;
   if (overlap) KCHK(side_ensure(ctx, l, 0));
-  if (use_eg) KCHK(copy_state(ctx, l, *W, *V));
+  // v_0 = w_0 without a copy: the first extragradient step reads w_0's buffers (which nothing writes before the
+  // accept test) and writes v_1 into V's own; only the host-side norms are copied
+  if (use_eg) {
+    V->a = W->a; V->r1n = W->r1n; V->r2n = W->r2n; V->rn = W->rn; V->has_eig = W->has_eig;
+  }
   double theta = p->theta0;
   int k = 0, cg_total = 0, eg_acc = 0, nulls = 0, lowp_dirs = 0;
   kot_status status = KOT_NOT_CONVERGED;
@@ -877,31 +922,34 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
       continue;
     }
     // (1) safeguard: one EG step on v, then R(v_{k+1}); on the side stream when overlapped
+    // the extragradient step reads v_k (w_0 at k = 0) and its eigenbasis
+    const State* Vs = k == 0 ? W : V;
+    const double* Pv = p->warm_eig ? Vs->P : nullptr;
     if (use_eg && overlap) {
       // gh on this stream, then the projection for Xn on the third stream and the rest of the branch (the
       // projection for Xh, gn, the residual at v_{k+1} once Xn is in) on the second
       const bool warm_v = warm_e && p->warm_eig;
       State* H = &ctx->S[3];
-      HIPCHK(vec_lincomb(l, 1.0, V->g, -eta, V->r1, ctx->gh, st));
-      KCHK(runner_post(ctx, ctx->side2, [ctx, &cv, V, H, eta, warm_v, p, &side2_sweeps]() -> kot_status {
+      HIPCHK(vec_lincomb(l, 1.0, Vs->g, -eta, Vs->r1, ctx->gh, st));
+      KCHK(runner_post(ctx, ctx->side2, [ctx, &cv, Vs, H, eta, warm_v, p, &side2_sweeps]() -> kot_status {
         kot_ctx* c = ctx->side2->c;
-        KCHK(eg_proj(c, cv, ctx->gh, V->X, eta, c->Pe2, c->s_e2, warm_v, H->X, p, &side2_sweeps));
+        KCHK(eg_proj(c, cv, ctx->gh, Vs->X, eta, c->Pe2, c->s_e2, warm_v, H->X, p, &side2_sweeps));
         if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, KOT_ERR_HIP, "stream synchronization");
         return KOT_OK;
       }));
-      const kot_status rp = side_post(ctx, [ctx, &cv, V, H, eta, warm_v, p, &side_sweeps]() -> kot_status {
+      const kot_status rp = side_post(ctx, [ctx, &cv, Vs, V, H, Pv, eta, warm_v, p, &side_sweeps]() -> kot_status {
         kot_ctx* c = ctx->side->c;
         const int n = cv.l;
-        const kot_status r0 = eg_proj(c, cv, V->g, V->X, eta, c->Pe1, c->s_e1, warm_v, c->Xh, p, &side_sweeps);
+        const kot_status r0 = eg_proj(c, cv, Vs->g, Vs->X, eta, c->Pe1, c->s_e1, warm_v, c->Xh, p, &side_sweeps);
         kot_status r1 = r0 < 0 ? r0 : r1_op(c, cv, ctx->gh, c->Xh, c->r1h, c->T1);
-        if (r1 >= 0 && vec_lincomb(n, 1.0, V->g, -eta, c->r1h, H->g, c->stream) != hipSuccess)
+        if (r1 >= 0 && vec_lincomb(n, 1.0, Vs->g, -eta, c->r1h, H->g, c->stream) != hipSuccess)
           r1 = fail(c, KOT_ERR_HIP, "vec_lincomb");
         const kot_status r2 = runner_join(c, ctx->side2);  // Xn (joined even after a failure)
         KCHK(r1);
         KCHK(r2);
         std::swap(H->g, V->g);
         std::swap(H->X, V->X);
-        return residual_state(c, cv, *V, p->warm_eig ? V->P : nullptr, p, &side_sweeps, SL_VN, false);
+        return residual_state(c, cv, *V, Pv, p, &side_sweeps, SL_VN, false);
       });
       if (rp < 0) {  // the third stream's job is already out: wait for it before returning
         (void)runner_join(ctx, ctx->side2);
@@ -910,11 +958,11 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
       warm_e = true;
     } else if (use_eg) {
       State* H = &ctx->S[3];
-      KCHK(eg_step_impl(ctx, cv, V->g, V->X, V->r1, eta, H->g, H->X, warm_e && p->warm_eig, p, &sweeps));
+      KCHK(eg_step_impl(ctx, cv, Vs->g, Vs->X, Vs->r1, eta, H->g, H->X, warm_e && p->warm_eig, p, &sweeps));
       warm_e = true;
       std::swap(H->g, V->g);
       std::swap(H->X, V->X);
-      KCHK(residual_state(ctx, cv, *V, p->warm_eig ? V->P : nullptr, p, &sweeps, SL_VN, true));
+      KCHK(residual_state(ctx, cv, *V, Pv, p, &sweeps, SL_VN, true));
     }
     // (2) regularized SSN trial
     const double mu = theta * W->rn;
@@ -1157,6 +1205,7 @@ kot_status kot_destroy(kot_ctx* ctx) {
   hipSetDevice(ctx->device);
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   side_destroy(ctx);
+  if (ctx->trtri_graph) hipGraphExecDestroy(ctx->trtri_graph);
   for (kot_ctx* ln : ctx->lanes) kot_destroy(ln);
   ctx->lanes.clear();
   free_ws(ctx);
