@@ -191,9 +191,11 @@ kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, co
                        double* gamma_out, double* X_out);
 
 /* Upper Cholesky factor R (device, l x l) of the symmetric positive definite A (device, l x l) + eps I:
- * R^T R = A + eps I; strictly lower triangle written as 0.  Returns KOT_ERR_FACTOR on a non-positive
- * pivot. */
-kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double* R);
+ * R^T R = A + eps I; strictly lower triangle written as 0.  Rit (device, l x l) may be NULL; else it
+ * receives R^-T, lower triangular with zeros above, formed by the same launches one block row behind the
+ * factor (the lifted start of Section 5 needs it).  Returns KOT_ERR_FACTOR on a non-positive pivot (Rit
+ * then undefined). */
+kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double* R, double* Rit);
 
 /* General FP64 product on the device (MFMA): C = alpha op(A) diag(s) op(B) + beta C, op = transpose if
  * trans* != 0; s (device, length k) may be NULL.  C is m x n with leading dimension ldc. */

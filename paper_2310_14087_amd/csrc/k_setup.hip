@@ -166,6 +166,130 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// ---- the inverse X = L^-1 (lower, CB-blocked) beside the factorization ------------------------------------
+// Forward substitution L X = I by block rows: X_rr = L_rr^-1 and X_rj = -L_rr^-1 C_rj, C_rj = sum over
+// m = j .. r-1 of L_rm X_mj, accumulated right-looking in X's own storage (zero on entry).  Launch s, where
+// block rows <= s - 1 of L are final, finishes row r = s - 1 (adding the m = r - 1 term itself, as the panel
+// workgroups do for the factor) and adds the m = s - 2 term to the rows k >= s.  Tiles of 32 x 32 live in the
+// four quadrants of the workgroup's LDS array (row stride 2 CB + 1).
+#define QT(q, i, k) S[((q) >> 1) * CB + (i)][((q) & 1) * CB + (k)]
+
+// Block (rb, cb) of the l x l row-major M into LDS quadrant q; entries past l read as zero, or as the
+// identity when pad_eye (a short last diagonal block).  All loads of a lane in flight together.
+__device__ __forceinline__ void load_quad(const double* __restrict__ M, int l, int rb, int cb, int q, bool pad_eye,
+                                          double (*S)[2 * CB + 1], int t) {
+  double v[CB * CB / 64];
+#pragma unroll
+  for (int e = 0; e < CB * CB / 64; ++e) {
+    const int u = t + 64 * e, i = u >> 5, k = u & 31;
+    v[e] = M[(long long)min(rb * CB + i, l - 1) * l + min(cb * CB + k, l - 1)];
+  }
+#pragma unroll
+  for (int e = 0; e < CB * CB / 64; ++e) {
+    const int u = t + 64 * e, i = u >> 5, k = u & 31;
+    const bool in = rb * CB + i < l && cb * CB + k < l;
+    QT(q, i, k) = in ? v[e] : ((pad_eye && i == k) ? 1.0 : 0.0);
+  }
+}
+
+// Launch s, block (r, j), j <= r, r = s - 1: X_rj from C_rj + L_{r,r-1} X_{r-1,j} (j < r) or the identity (j = r).
+__device__ void inv_row_block(int l, int r, int j, const double* __restrict__ W, double* __restrict__ Y,
+                              double (*S)[2 * CB + 1], double* invd, int t) {
+  load_quad(W, l, r, r, 0, true, S, t);             // L_rr
+  if (j < r) {
+    load_quad(W, l, r, r - 1, 1, false, S, t);      // L_{r,r-1}
+    load_quad(Y, l, r - 1, j, 2, false, S, t);      // X_{r-1,j}
+    load_quad(Y, l, r, j, 3, false, S, t);          // C_rj
+  }
+  __syncthreads();
+  if (t < CB) invd[t] = 1.0 / QT(0, t, t);
+  if (j < r) {
+    // B = -(C_rj + L_{r,r-1} X_{r-1,j}), each lane a 4 x 4 block
+    const int ri = (t >> 3) * 4, ci = (t & 7) * 4;
+    double acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] = QT(3, ri + p, ci + q);
+#pragma unroll 8
+    for (int k = 0; k < CB; ++k) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        av[p] = QT(1, ri + p, k);
+        bv[p] = QT(2, k, ci + p);
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
+    }
+    __syncthreads();  // every read of quadrant 3 done
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) QT(3, ri + p, ci + q) = -acc[p][q];
+  }
+  __syncthreads();
+  if (t >= CB) return;
+  // L_rr x = b for column t of B (or of the identity): once x_q is final it leaves every later entry
+  double x[CB];
+#pragma unroll
+  for (int i = 0; i < CB; ++i) x[i] = (j < r) ? QT(3, i, t) : (i == t ? 1.0 : 0.0);
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    x[q] *= invd[q];
+#pragma unroll
+    for (int i = q + 1; i < CB; ++i) x[i] = fma(-QT(0, i, q), x[q], x[i]);
+#pragma unroll
+    for (int i = q; i < CB; ++i) asm volatile("" : "+v"(x[i]));  // each step in order (else it spills)
+  }
+  const int col = j * CB + t;
+  if (col < l)
+#pragma unroll
+    for (int i = 0; i < CB; ++i)
+      if (r * CB + i < l) Y[(long long)(r * CB + i) * l + col] = x[i];
+}
+
+// Launch s, tile u of the rows k >= s and columns j <= m = s - 2: C_kj += L_km X_mj.
+__device__ void inv_update_block(int l, int s, int u, const double* __restrict__ W, double* __restrict__ Y,
+                                 double (*S)[2 * CB + 1], int t) {
+  const int m = s - 2;
+  const int k = s + u / (m + 1), j = u % (m + 1);
+  const int ri = (t >> 3) * 4, ci = (t & 7) * 4;
+  double cv[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cv[p][q] = Y[(long long)min(k * CB + ri + p, l - 1) * l + min(j * CB + ci + q, l - 1)];
+  load_quad(W, l, k, m, 0, false, S, t);  // L_km
+  load_quad(Y, l, m, j, 1, false, S, t);  // X_mj
+  __syncthreads();
+#pragma unroll 8
+  for (int q = 0; q < CB; ++q) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      av[p] = QT(0, ri + p, q);
+      bv[p] = QT(1, q, ci + p);
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cv[p][e] = fma(av[p], bv[e], cv[p][e]);
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int rr = k * CB + ri + p;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int cc = j * CB + ci + e;
+      if (rr < l && cc < l) Y[(long long)rr * l + cc] = cv[p][e];
+    }
+  }
+}
+#undef QT
+
 // Panel workgroups (one wavefront each): lanes 0..31 hold the rows of the CB x CB diagonal block (every
 // workgroup factors it; workgroup 0 writes it back and reports a non-positive pivot through info), lanes
 // 32..63 the CB panel rows k0 + nb + 32 b ..; the right-looking factorization of this 64-row tall panel
@@ -174,17 +298,25 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
 // column L_.j through LDS.
 // Update workgroups: the 32 x 32 tiles (tr >= tc) of W[k0 + CB.., k0 + CB..] get -= L_r L_c^T over the
 // previous panel's columns, staged in LDS; each lane accumulates a 4 x 4 block.
-__global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, int npb, double* __restrict__ W,
-                                                       int* info) {
+__global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, int npb, int ntiles, int nir,
+                                                       double* __restrict__ W, int* info, double* __restrict__ Y) {
   __shared__ double S[64][2 * CB + 1];  // panel: the workgroup's rows over both panels; update: the two L tiles
   __shared__ double colb[2][CB];
   double (*Lb)[2 * CB + 1] = S;
   double (*Lc)[2 * CB + 1] = S + CB;
   const int t = threadIdx.x;
   const int kp = k0 - CB;  // first column of the previous panel (< 0: none)
-  if ((int)blockIdx.x >= npb) {
+  const int bid = (int)blockIdx.x;
+  if (bid >= npb + ntiles) {
+    // ---- the inverse X = L^-1, one block row behind the factorization (launch s: row s - 1)
+    const int s = k0 / CB;
+    if (bid < npb + ntiles + nir) inv_row_block(l, s - 1, bid - npb - ntiles, W, Y, S, colb[0], t);
+    else inv_update_block(l, s, bid - npb - ntiles - nir, W, Y, S, t);
+    return;
+  }
+  if (bid >= npb) {
     // ---- trailing update with the previous panel: tile u of the lower triangle beyond panel s
-    int u = (int)blockIdx.x - npb, tr = 0;
+    int u = bid - npb, tr = 0;
     while (u > tr) { u -= tr + 1; ++tr; }
     const int tc = u;
     const int o = k0 + CB, R0 = o + CB * tr, C0 = o + CB * tc;
@@ -323,10 +455,11 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
 }
 
 __global__ void copy_jitter_kernel(int l, const double* __restrict__ A, double eps, double* __restrict__ W,
-                                   int* __restrict__ info) {
+                                   int* __restrict__ info, double* __restrict__ Y) {
   const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (u == 0) *info = 0;
   if (u >= (long long)l * l) return;
+  if (Y) Y[u] = 0.0;
   const int i = (int)(u / l), j = (int)(u % l);
   W[u] = A[u] + ((i == j) ? eps : 0.0);
 }
@@ -455,19 +588,31 @@ hipError_t build_z(int l, int d, const double* xf, const double* yf, const doubl
   return hipGetLastError();
 }
 
-hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double* W, int* info, hipStream_t st) {
+hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double* W, int* info, hipStream_t st,
+                          double* Linv) {
   const long long nn = (long long)l * l;
   const int eb = (int)((nn + 255) / 256);
-  hipLaunchKernelGGL(copy_jitter_kernel, dim3(eb), dim3(256), 0, st, l, A, eps, W, info);
+  hipLaunchKernelGGL(copy_jitter_kernel, dim3(eb), dim3(256), 0, st, l, A, eps, W, info, Linv);
   KOT_HIP_TRY(hipGetLastError());
-  for (int k0 = 0; k0 < l; k0 += CB) {
-    const int nb = (l - k0 < CB) ? (l - k0) : CB;
-    const int rest = l - k0 - nb;
-    const int npb = rest > 0 ? (rest + CB - 1) / CB : 1;
-    // trailing tiles beyond panel s that the previous panel still has to update
-    const int m = (k0 > 0 && l > k0 + CB) ? (l - k0 - CB + CB - 1) / CB : 0;
-    const int ntiles = m * (m + 1) / 2;
-    hipLaunchKernelGGL(chol_step_kernel, dim3(npb + ntiles), dim3(64), 0, st, l, k0, nb, npb, W, info);
+  const int nbk = (l + CB - 1) / CB;  // block rows
+  for (int s = 0; s <= nbk; ++s) {
+    const int k0 = s * CB;
+    int npb = 0, ntiles = 0, nir = 0, niu = 0, nb = 0;
+    if (s < nbk) {
+      nb = (l - k0 < CB) ? (l - k0) : CB;
+      const int rest = l - k0 - nb;
+      npb = rest > 0 ? (rest + CB - 1) / CB : 1;
+      // trailing tiles beyond panel s that the previous panel still has to update
+      const int m = (k0 > 0 && l > k0 + CB) ? (l - k0 - CB + CB - 1) / CB : 0;
+      ntiles = m * (m + 1) / 2;
+    }
+    if (Linv) {
+      if (s >= 1) nir = s;                                  // row s - 1, blocks 0 .. s - 1
+      if (s >= 2 && s < nbk) niu = (nbk - s) * (s - 1);    // rows s .. nbk - 1, blocks 0 .. s - 2
+    }
+    if (npb + ntiles + nir + niu == 0) continue;
+    hipLaunchKernelGGL(chol_step_kernel, dim3(npb + ntiles + nir + niu), dim3(64), 0, st, l, k0, nb, npb, ntiles,
+                       nir, W, info, Linv);
     KOT_HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(lower_to_upper_kernel, dim3(eb), dim3(256), 0, st, l, W, R);

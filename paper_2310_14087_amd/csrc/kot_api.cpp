@@ -51,6 +51,7 @@ struct CoreView {  // dual data of Eq. (3.4) on the device
   double q2 = 0.0;
   double lam1 = 0.0, lam2 = 0.0;
   double* KK = nullptr;  // (R^T R) o (R^T R)
+  const double* Linv = nullptr;  // R^-T when the factorization produced it (else the lift inverts R itself)
   int kb_state = 0;      // the context's K buffer: 0 unrelated, 1 holds R^T R = K + eps I, 2 and KK is formed
 };
 
@@ -871,10 +872,15 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   if (gamma0 && p->lift_x0) {
     // X0 = R^-T diag(y) R^-1 with y = (Q gamma0 - z)/(2 lam2) (stationarity's value of Phi(X)) on the
     // constraints predicted active, small entries dropped, so that Phi(X0) = y
-    KCHK(trtri_cached(ctx, l, cv.R, ctx->T1, ctx->T2));
+    if (!cv.Linv) KCHK(trtri_cached(ctx, l, cv.R, ctx->T1, ctx->T2));
     HIPCHK(mm(st, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, W->g, 1, 0.0, ctx->vtmp, 1));
     HIPCHK(lift_diag(l, ctx->vtmp, cv.z, W->g, cv.lam1, cv.lam2, 0.02, ctx->dg, ctx->part, st));
-    HIPCHK(mm(st, 1, 0, l, l, l, 1.0, ctx->T1, l, ctx->dg, ctx->T1, l, 0.0, W->X, l, TRI_A_LOWER | TRI_B_UPPER, true));
+    if (cv.Linv)
+      HIPCHK(mm(st, 0, 1, l, l, l, 1.0, cv.Linv, l, ctx->dg, cv.Linv, l, 0.0, W->X, l, TRI_A_LOWER | TRI_B_UPPER,
+                true));
+    else
+      HIPCHK(mm(st, 1, 0, l, l, l, 1.0, ctx->T1, l, ctx->dg, ctx->T1, l, 0.0, W->X, l, TRI_A_LOWER | TRI_B_UPPER,
+                true));
   } else {
     HIPCHK(vec_fill(l * l, 0.0, W->X, st));
   }
@@ -1034,8 +1040,9 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   return status;
 }
 
+// Linv (optional): receives R^-T from the factorization.
 kot_status setup_impl(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, double* Q, double* z, double* R,
-                      double* wsum, double* q2) {
+                      double* wsum, double* q2, double* Linv = nullptr) {
   const int l = pb->l, d = pb->d;
   hipStream_t st = ctx->stream;
   HIPCHK(gram_build(l, d, pb->xf, pb->yf, p->sigma, Q, ctx->Kb, st));
@@ -1045,7 +1052,7 @@ kot_status setup_impl(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, 
   HIPCHK(mean_gram(pb->n_src, d, pb->xs, p->sigma, ctx->dsc + 0, ctx->part, st));
   HIPCHK(mean_gram(pb->n_tgt, d, pb->ys, p->sigma, ctx->dsc + 1, ctx->part, st));
   HIPCHK(build_z(l, d, pb->xf, pb->yf, ctx->wmu, ctx->wnu, p->lambda2, z, wsum, st));
-  HIPCHK(cholesky_upper(l, ctx->Kb, 0.0, R, ctx->T1, ctx->dint, st));
+  HIPCHK(cholesky_upper(l, ctx->Kb, 0.0, R, ctx->T1, ctx->dint, st, Linv));
   KCHK(sync_read(ctx, 2, 1));
   *q2 = ctx->hsc[0] + ctx->hsc[1];
   if (ctx->hint[0] != 0)
@@ -1083,15 +1090,16 @@ kot_status setup_side(kot_ctx* ctx, kot_ctx* own, const kot_problem* pb, const k
 }
 
 // setup_impl with the factorization on the calling stream and setup_side beside it; the core buffers of ctx
-// hold Q, z, R, w_mu + w_nu, K + eps I and KK on return.
-kot_status setup_overlapped(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, bool predict, Prelude* pre) {
+// hold Q, z, R, w_mu + w_nu, K + eps I and KK on return (and Linv, when given, R^-T).
+kot_status setup_overlapped(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, bool predict, Prelude* pre,
+                            double* Linv) {
   const int l = pb->l, d = pb->d;
   hipStream_t st = ctx->stream;
   KCHK(side_ensure(ctx, l, std::max(pb->n_src, pb->n_tgt)));
   HIPCHK(gram_build(l, d, pb->xf, pb->yf, p->sigma, ctx->Qb, ctx->Kb, st));
   HIPCHK(add_diag(l, p->eps_jitter, ctx->Kb, st));  // K + eps I = R^T R from here on; read-only below
   KCHK(side_post(ctx, [ctx, pb, p, predict, pre]() { return setup_side(ctx->side->c, ctx, pb, p, predict, pre); }));
-  const hipError_t e = cholesky_upper(l, ctx->Kb, 0.0, ctx->Rb, ctx->T1, ctx->dint, st);
+  const hipError_t e = cholesky_upper(l, ctx->Kb, 0.0, ctx->Rb, ctx->T1, ctx->dint, st, Linv);
   const kot_status rc = e != hipSuccess ? fail(ctx, KOT_ERR_HIP, "cholesky_upper: %s", hipGetErrorString(e))
                                         : sync_read(ctx);
   const kot_status rs = side_join(ctx);  // joined even when the factorization failed
@@ -1242,16 +1250,20 @@ kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, c
   CoreView cv;
   cv.l = pb->l; cv.Q = ctx->Qb; cv.z = ctx->zb; cv.R = ctx->Rb; cv.wsum = ctx->wsumb;
   cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  // the lifted start needs R^-T: the factorization forms it beside R (the buffer is free until the first
+  // extragradient step)
+  double* Linv = (gamma0 || p->ws_theta) && p->lift_x0 ? ctx->Xh : nullptr;
+  cv.Linv = Linv;
   if (overlap_ok(ctx, p, pb->l)) {
     Prelude pre;
-    KCHK(setup_overlapped(ctx, pb, p, p->ws_theta && !gamma0, &pre));
+    KCHK(setup_overlapped(ctx, pb, p, p->ws_theta && !gamma0, &pre, Linv));
     cv.q2 = pre.q2;
     cv.kb_state = 2;
     cv.KK = ctx->KKb;
     return run_alg2(ctx, cv, p, gamma0, res, &pre);
   }
   double q2 = 0.0;
-  KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2));
+  KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2, Linv));
   cv.q2 = q2;
   cv.kb_state = 1;
   return run_alg2(ctx, cv, p, gamma0, res);
@@ -1347,11 +1359,11 @@ kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, co
   return KOT_OK;
 }
 
-kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double* R) {
+kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double* R, double* Rit) {
   KCHK(check_ctx(ctx));
   if (l < 1 || l > 4096 || !A || !R || !(eps >= 0.0)) return fail(ctx, KOT_ERR_ARG, "invalid argument");
   KCHK(ensure_ws(ctx, l, 0));
-  HIPCHK(cholesky_upper(l, A, eps, R, ctx->T1, ctx->dint, ctx->stream));
+  HIPCHK(cholesky_upper(l, A, eps, R, ctx->T1, ctx->dint, ctx->stream, Rit));
   KCHK(sync_read(ctx, 0, 1));
   if (ctx->hint[0] != 0) return fail(ctx, KOT_ERR_FACTOR, "matrix is not positive definite (pivot %d)", ctx->hint[0]);
   return KOT_OK;

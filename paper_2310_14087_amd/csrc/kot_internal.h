@@ -73,7 +73,9 @@ hipError_t build_z(int l, int d, const double* xf, const double* yf, const doubl
                    double lam2, double* z, double* wsum, hipStream_t st);
 
 // ---- Cholesky: R^T R = A + eps I (R upper). info[0] != 0 on a non-positive pivot. ----------------------------
-hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double* work, int* info, hipStream_t st);
+// Linv (optional, l x l): receives X = L^-1 = R^-T (lower triangle, zeros above), computed beside the factor.
+hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double* work, int* info, hipStream_t st,
+                          double* Linv = nullptr);
 
 // ---- symmetric eigensolver (block Jacobi) ------------------------------------------------------------------
 struct EigWork;

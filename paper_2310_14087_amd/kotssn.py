@@ -82,7 +82,7 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
         "kot_residual": (i, [vp, i, vp, vp, vp, vp, vp, P(KotParams), vp, vp, P(d)]),
         "kot_ssn_direction": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp, P(d)]),
         "kot_eg_step": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp]),
-        "kot_cholesky": (i, [vp, i, vp, d, vp]),
+        "kot_cholesky": (i, [vp, i, vp, d, vp, vp]),
         "kot_gemm": (i, [vp, i, i, i, i, i, d, vp, i, vp, vp, i, d, vp, i]),
         "kot_profile": (i, [vp, i, vp, i]),
         "kot_mlp_params": (i, [i, i]),
@@ -309,11 +309,14 @@ class Context:
                                          C.byref(prm), _ptr(go), _ptr(Xo)))
         return go, Xo
 
-    def cholesky(self, A, eps=0.0):
+    def cholesky(self, A, eps=0.0, inverse=False):
+        """R with R^T R = A + eps I; with inverse, (R, R^-T)."""
         import torch
         R = torch.empty_like(A)
-        self._check(self.lib.kot_cholesky(self.h, A.shape[0], _ptr(A), float(eps), _ptr(R)))
-        return R
+        Rit = torch.empty_like(A) if inverse else None
+        self._check(self.lib.kot_cholesky(self.h, A.shape[0], _ptr(A), float(eps), _ptr(R),
+                                          _ptr(Rit) if inverse else None))
+        return (R, Rit) if inverse else R
 
     # ---- warm-start network ----
     def features(self, Q, z, R, wsum, q2, prm: KotParams):

@@ -125,6 +125,33 @@ def test_cholesky(gpu_ctx, l):
     np.testing.assert_allclose(R, np.linalg.cholesky(S).T, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("l", [1, 32, 33, 64, 65, 97, 257, 1000])
+@pytest.mark.parametrize("kind", ["wishart", "gauss_kernel"])
+def test_cholesky_inverse(gpu_ctx, l, kind):
+    """R^-T formed beside the factor: R unchanged bit for bit, exact zeros above the diagonal, and the
+    componentwise residual of a triangular inverse, |X R^T - I| <= c l u |X| |R^T| (cond-independent)."""
+    _case(f"kot_cholesky inverse {kind} l={l}")
+    rng = np.random.default_rng(l + 11)
+    if kind == "wishart":
+        A = rng.standard_normal((l, l))
+        S = A @ A.T + l * np.eye(l)
+    else:  # the Gaussian kernel matrix of Section 5 with a small jitter: condition number ~1e8 and beyond
+        x = rng.standard_normal((l, 2))
+        S = np.exp(-((x[:, None, :] - x[None, :, :]) ** 2).sum(-1) / 2.0) + 1e-6 * np.eye(l)
+    R0 = _n(gpu_ctx.cholesky(_t(S), 0.0))
+    R, X = gpu_ctx.cholesky(_t(S), 0.0, inverse=True)
+    R, X = _n(R), _n(X)
+    assert np.array_equal(R, R0)
+    assert np.all(np.triu(X, 1) == 0.0)
+    L = R.T
+    res = np.abs(X @ L - np.eye(l))
+    bound = 4 * l * np.finfo(float).eps * (np.abs(X) @ np.abs(L))
+    assert np.all(res <= bound + 1e-300)
+    if kind == "wishart":  # well conditioned: also close to the inverse of the reference factor
+        Xr = np.linalg.inv(np.linalg.cholesky(S))
+        np.testing.assert_allclose(X, Xr, rtol=0, atol=1e-12 * np.abs(Xr).max())
+
+
 @pytest.mark.parametrize("l,bad", [(10, 3), (100, 70), (300, 299)])
 def test_cholesky_not_pd(gpu_ctx, l, bad):
     """A non-positive pivot in the first, a middle or the last panel is reported with its (1-based) index."""
