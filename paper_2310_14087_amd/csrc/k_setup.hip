@@ -5,6 +5,8 @@
 namespace kot {
 namespace {
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 // Q = K_X + K_Y, K = K_X o K_Y (the Gaussian on the concatenated point), one thread per entry.
 __global__ __launch_bounds__(256) void gram_kernel(int l, int d, const double* __restrict__ xf, const double* __restrict__ yf,
                                                     double inv2s2, double* __restrict__ Q, double* __restrict__ K) {
@@ -393,6 +395,38 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
     for (int q = 0; q < 64; ++q) S[q][t] = v[q];
   }
   __syncthreads();
+  if (kp >= 0) {
+    // the previous panel's contribution to this panel's columns, S[r][CB + c] -= sum_k S[r][k] S[c][k] (rows
+    // c < CB of S are the diagonal block's), as a 64 x 32 x 32 product on the matrix cores: operand lane L
+    // supplies A[L%16][L/16] and B[L/16][L%16], the accumulator lane L holds D[L/16 + 4 v][L%16].  With
+    // B = A^T of the diagonal rows, both operands come from the same fragments.  Rows that are not live
+    // are updated too: they are replaced (diagonal padding) or never stored.
+    const int r16 = t & 15, k4 = t >> 4;
+    double f[4][CB / 4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int ks = 0; ks < CB / 4; ++ks) f[rb][ks] = S[rb * 16 + r16][ks * 4 + k4];
+    dbl4 acc[4][2];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < CB / 4; ++ks)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[rb][ks], f[cb][ks], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[rb * 16 + k4 + 4 * v][CB + cb * 16 + r16] -= acc[rb][cb][v];
+    __syncthreads();
+  }
   const int ca = kp >= 0 ? CB : 0;  // column of this panel inside the staged window
   double a[CB];
 #pragma unroll
@@ -400,21 +434,17 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
     const double v = S[t][ca + c];
     a[c] = diag ? (live ? ((c <= t) ? v : 0.0) : ((t == c) ? 1.0 : 0.0)) : v;  // short block: identity pad
   }
-  if (kp >= 0) {
-    // the previous panel's contribution to this panel's columns: a[c] -= sum_k L(row, kp + k) L(k0 + c, kp + k),
-    // the L rows of the diagonal block being S[c][0..CB) (k outermost: the 32 updates of one k are independent)
-#pragma unroll 1
-    for (int k0c = 0; k0c < CB; k0c += 4) {  // a rolled loop over chunks of four k: bounded live ranges
-#pragma unroll
-      for (int k = k0c; k < k0c + 4; ++k) {
-        const double xk = live ? S[t][k] : 0.0;
-#pragma unroll
-        for (int c = 0; c < CB; ++c) a[c] = fma(-xk, S[c][k], a[c]);
-      }
-    }
-  }
+  // Right-looking factorization of the 64 x CB panel, pipelined: step j's update reaches columns j + 1 and
+  // j + 2 at once, through the L entries of rows k0 + j + 1 and k0 + j + 2 read from their lanes; the rest of
+  // it (columns >= j + 3, new column through LDS) is applied during step j + 1, so the LDS round trip and
+  // that bulk of FMAs overlap the next pivot's chain.  Every column has all earlier steps' terms before it
+  // becomes a pivot column.
   int bad = 0;
   double pnext = readlane_f64(a[0], 0);
+  double lprev = 0.0;  // L(row, k0 + j - 1)
+  double cbuf[CB];     // L(k0 + c, k0 + j - 1) for c >= j + 2, read from LDS in the previous step
+#pragma unroll
+  for (int c = 0; c < CB; ++c) cbuf[c] = 0.0;
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
     double piv = pnext;
@@ -430,12 +460,20 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
     const double rdj = fma(y0 * e, fma(0.375, e, 0.5), y0);
     const double dj = piv * rdj;
     const double lij = a[j] * rdj;  // L_ij on rows below j
-    // the next pivot from its own lane (its entry minus its L entry squared), ahead of the LDS exchange
-    if (j + 1 < CB) pnext = readlane_f64(fma(-lij, lij, a[j + 1]), j + 1);
     if (diag) colb[j & 1][t] = lij;
-    __syncthreads();
+    if (j + 1 < CB) {
+      a[j + 1] = fma(-lij, readlane_f64(lij, j + 1), a[j + 1]);
+      pnext = readlane_f64(a[j + 1], j + 1);
+    }
+    if (j + 2 < CB) a[j + 2] = fma(-lij, readlane_f64(lij, j + 2), a[j + 2]);
+    // the bulk of step j - 1
+    if (j >= 1)
 #pragma unroll
-    for (int c = j + 1; c < CB; ++c) a[c] -= lij * colb[j & 1][c];  // entries c > t of diagonal rows unused
+      for (int c = j + 2; c < CB; ++c) a[c] = fma(-lprev, cbuf[c], a[c]);
+    __builtin_amdgcn_wave_barrier();  // (one wavefront: LDS operations complete in issue order)
+#pragma unroll
+    for (int c = j + 3; c < CB; ++c) cbuf[c] = colb[j & 1][c];
+    lprev = lij;
     a[j] = (diag && t == j) ? dj : lij;
 #pragma unroll
     for (int c = j + 1; c < CB; ++c) asm volatile("" : "+v"(a[c]));  // keep each update inside its step
