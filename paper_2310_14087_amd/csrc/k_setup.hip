@@ -206,31 +206,37 @@ __device__ void inv_row_block(int l, int r, int j, const double* __restrict__ W,
   __syncthreads();
   if (t < CB) invd[t] = 1.0 / QT(0, t, t);
   if (j < r) {
-    // B = -(C_rj + L_{r,r-1} X_{r-1,j}), each lane a 4 x 4 block
-    const int ri = (t >> 3) * 4, ci = (t & 7) * 4;
-    double acc[4][4];
+    // B = -(C_rj + L_{r,r-1} X_{r-1,j}) on the matrix cores (operand lane L: A[L%16][L/16], B[L/16][L%16];
+    // accumulator lane L: D[L/16 + 4 v][L%16]); each lane rewrites the entries of C it read
+    const int r16 = t & 15, k4 = t >> 4;
+    dbl4 acc[2][2];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] = QT(3, ri + p, ci + q);
-#pragma unroll 8
-    for (int k = 0; k < CB; ++k) {
-      double av[4], bv[4];
+      for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        av[p] = QT(1, ri + p, k);
-        bv[p] = QT(2, k, ci + p);
+        for (int v = 0; v < 4; ++v) acc[rb][cb][v] = QT(3, rb * 16 + k4 + 4 * v, cb * 16 + r16);
+    double fa[2][CB / 4], fb[2][CB / 4];
+#pragma unroll
+    for (int ks = 0; ks < CB / 4; ++ks)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        fa[h][ks] = QT(1, h * 16 + r16, ks * 4 + k4);
+        fb[h][ks] = QT(2, ks * 4 + k4, h * 16 + r16);
       }
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+    for (int ks = 0; ks < CB / 4; ++ks)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
-    }
-    __syncthreads();  // every read of quadrant 3 done
+      for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+        for (int cb = 0; cb < 2; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[rb][ks], fb[cb][ks], acc[rb][cb], 0, 0, 0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) QT(3, ri + p, ci + q) = -acc[p][q];
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) QT(3, rb * 16 + k4 + 4 * v, cb * 16 + r16) = -acc[rb][cb][v];
   }
   __syncthreads();
   if (t >= CB) return;
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
   // it (columns >= j + 3, new column through LDS) is applied during step j + 1, so the LDS round trip and
   // that bulk of FMAs overlap the next pivot's chain.  Every column has all earlier steps' terms before it
   // becomes a pivot column.
-  int bad = 0;
+  unsigned badmask = 0;  // bit j: the pivot of step j was not a positive normal number
   double pnext = readlane_f64(a[0], 0);
   double lprev = 0.0;  // L(row, k0 + j - 1)
   double cbuf[CB];     // L(k0 + c, k0 + j - 1) for c >= j + 2, read from LDS in the previous step
@@ -450,10 +456,11 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
     double piv = pnext;
     // a valid pivot is a positive normal number: high word in [0x00100000, 0x7ff00000) (a scalar test)
     const unsigned hw = (unsigned)((unsigned long long)__double_as_longlong(piv) >> 32);
-    if (hw - 0x00100000u >= 0x7fe00000u) {  // reported, then replaced by 1
-      if (j < nb && !bad) bad = k0 + j + 1;
+    if (hw - 0x00100000u >= 0x7fe00000u) {  // recorded, then replaced by 1
+      badmask |= 1u << j;
       piv = 1.0;
     }
+    asm volatile("" : "+v"(badmask));  // kept in step (left to itself the compiler defers it past the loop)
     // 1/sqrt(piv): hardware estimate y0 refined by one third-order step y0 (1 + e/2 + 3 e^2/8), e = 1 - piv y0^2
     const double y0 = __builtin_amdgcn_rsq(piv);
     const double e = fma(-piv * y0, y0, 1.0);
@@ -478,14 +485,17 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
 #pragma unroll
     for (int c = j + 1; c < CB; ++c) asm volatile("" : "+v"(a[c]));  // keep each update inside its step
   }
+  if (blockIdx.x == 0 && t == 0) {
+    const unsigned m = badmask & (nb >= 32 ? ~0u : ((1u << nb) - 1u));
+    if (m) atomicCAS(info, 0, k0 + __ffs((int)m));  // the first non-positive pivot, 1-based
+  }
+  // stores: lane t writes its row of the panel (the diagonal block, zeros above the diagonal, from
+  // workgroup 0 only); the column offsets are immediates of the store instructions
   if (diag) {
-    if (blockIdx.x == 0) {
-      if (t == 0 && bad) atomicCAS(info, 0, bad);
-      if (live)
+    if (blockIdx.x == 0 && live)
 #pragma unroll
-        for (int c = 0; c < CB; ++c)
-          if (c < nb) W[(long long)row * l + k0 + c] = (c <= t) ? a[c] : 0.0;
-    }
+      for (int c = 0; c < CB; ++c)
+        if (c < nb) W[(long long)row * l + k0 + c] = (c <= t) ? a[c] : 0.0;
   } else if (live) {
 #pragma unroll
     for (int c = 0; c < CB; ++c) W[(long long)row * l + k0 + c] = a[c];
