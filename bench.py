@@ -161,6 +161,9 @@ def main():
                     help="solves of the final arm in the roofline pass (after the timed run)")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
                     help="1: extragradient branch on a second stream (the default of the library)")
+    ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi"],
+                    help="Schur-system CG as in the paper (none) or Jacobi-preconditioned; auto: none on the "
+                         "plain fp64 arm, jacobi on the accelerated arms")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the metric line: time kot_solve_batched on this many 'batch' problems")
     ap.add_argument("--lanes", type=int, default=4)
@@ -202,7 +205,9 @@ def main():
         theta_dev = torch.from_numpy(theta).to(dev)
 
     def params(i, arm):
-        kw = dict(base[i], overlap=a.overlap)
+        jac = a.precond == "jacobi" or (a.precond == "auto" and arm != "fp64")
+        kw = dict(base[i], overlap=a.overlap,
+                  precond=kotssn.KOT_PRECOND_JACOBI if jac else kotssn.KOT_PRECOND_NONE)
         if arm != "fp64":
             kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
         if arm == "mixed":
@@ -283,7 +288,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: n=5000/side, d=10, two 4-component mixtures, l=1000, "
                                f"sigma^2=0.005 on unit-cube data, lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
-                   "arm": final, "instances": n_inst, "overlap": a.overlap, "arms": out_arms},
+                   "arm": final, "instances": n_inst, "overlap": a.overlap, "precond": a.precond,
+                   "arms": out_arms},
     }
     if prof:
         dom = max(prof, key=lambda c: prof[c]["ms"])

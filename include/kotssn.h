@@ -43,6 +43,11 @@ typedef enum { KOT_FP64 = 0, KOT_FP32 = 1, KOT_MIXED_BF16 = 2, KOT_MIXED_BF16X3 
 /* Algorithm 2 with its extragradient safeguard (EG), the regularized SSN steps alone (NONE), or the safeguard
  * alone: pure extragradient iterations on Eq. (4.1), the comparison method of Appendix F (EG_ONLY). */
 typedef enum { KOT_SAFEGUARD_EG = 0, KOT_SAFEGUARD_NONE = 1, KOT_SAFEGUARD_EG_ONLY = 2 } kot_safeguard;
+/* CG on the Schur system of Algorithm 1 as the paper runs it (NONE), or preconditioned with the inverse of the
+ * system's diagonal (JACOBI), one of the variants Section 4.3 names for it:
+ * M_ii = Q_ii/(2 lambda2) + mu + [(B o B)^T Psi (B o B)]_ii with B = P^T R.  Eq. (4.5) is checked on the
+ * unpreconditioned residual either way. */
+typedef enum { KOT_PRECOND_NONE = 0, KOT_PRECOND_JACOBI = 1 } kot_precond;
 
 /* Parameters of Algorithm 2 and the inexactness rule Eq. (4.5).  kot_params_default fills the values
  * used throughout: tol 1e-6, max_iter 200, cg_max_iter 20 (Remark 4.5), tau = kappa = 0.5,
@@ -83,6 +88,7 @@ typedef struct kot_params {
                           iterative refinement only when the chain has at least this many eigen-rows
                           (min(|alpha|, l - |alpha|)); below it the chain's products are too small to gain from
                           lower precision and the FP64 CG runs instead (default 64; 0 = always) */
+  int precond;         /* kot_precond of the Schur-system CG (default KOT_PRECOND_NONE) */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:

@@ -42,7 +42,7 @@ import numpy as np
 __all__ = [
     "Params", "Core", "gaussian_gram", "mean_embedding", "mean_gram", "setup", "core_from_arrays",
     "phi", "phi_star", "eig_sym", "proj_psd", "residual", "pair_norm", "pair_dot", "omega_matrix",
-    "psi_matrix", "t_apply", "schur_matvec", "cg", "ssn_direction", "eg_operator", "eg_step",
+    "psi_matrix", "t_apply", "schur_matvec", "schur_diag", "cg", "pcg", "ssn_direction", "eg_operator", "eg_step",
     "default_eg_step", "theta_update", "solve", "ot_estimate", "kkt_report",
 ]
 
@@ -70,6 +70,8 @@ class Params:
                                    # (pure extragradient, the comparison method of Appendix F)
     null_step: bool = True         # reading: keep w_k when it beats both the trial and v_{k+1}
     eps_jitter: float = 1e-10
+    precond: str = "none"          # "none" (CG as the paper runs it) or "jacobi" (diagonal preconditioner, a
+                                   # variant Section 4.3 names for the Schur system)
 
 
 @dataclass
@@ -242,6 +244,47 @@ def schur_matvec(core: Core, P, Psi, mu: float, v: np.ndarray) -> np.ndarray:
     return core.Q @ v / (2.0 * core.lam2) + mu * v + phi(core.R, t_apply(P, Psi, phi_star(core.R, v)))
 
 
+def schur_diag(core: Core, P, Psi, mu: float) -> np.ndarray:
+    """Diagonal of the Schur operator M = Q/(2 lambda2) + mu I + Phi T Phi* of Algorithm 1.
+
+    With b = P^T R_i (R_i the i-th column of R), (Phi T Phi* e_i)_i = R_i^T P (Psi o (b b^T)) P^T R_i
+    = sum_{r,s} Psi_rs b_r^2 b_s^2, so M_ii = Q_ii/(2 lambda2) + mu + [(B o B)^T Psi (B o B)]_ii, B = P^T R.
+    """
+    B = P.T @ core.R
+    B2 = B * B
+    return np.diag(core.Q) / (2.0 * core.lam2) + mu + np.einsum("ri,rs,si->i", B2, Psi, B2)
+
+
+def pcg(matvec, b: np.ndarray, dinv: np.ndarray, stop, max_iter: int):
+    """Preconditioned conjugate gradients with the diagonal preconditioner D (dinv = 1/diag(D)) from x = 0:
+    z = D^-1 r, alpha = r.z / p.Ap, beta = r'.z' / r.z, p = z + beta p.  ``stop(res_norm, x)`` sees the
+    unpreconditioned residual, as Eq. (4.5) asks."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = dinv * r
+    p = z.copy()
+    rr = float(r @ r)
+    rz = float(r @ z)
+    it = 0
+    while it < max_iter:
+        if stop(math.sqrt(rr), x):
+            break
+        Ap = matvec(p)
+        pAp = float(p @ Ap)
+        if pAp <= 0.0:
+            break
+        alpha = rz / pAp
+        x = x + alpha * p
+        r = r - alpha * Ap
+        z = dinv * r
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        rr = float(r @ r)
+        it += 1
+    return x, it, math.sqrt(rr)
+
+
 def cg(matvec, b: np.ndarray, stop, max_iter: int):
     """Conjugate gradients from x = 0; ``stop(res_norm, x)`` decides termination (Eq. 4.5)."""
     x = np.zeros_like(b)
@@ -276,7 +319,12 @@ def ssn_direction(core: Core, r1, r2, eig, mu: float, prm: Params):
     rnorm = pair_norm(r1, r2)
     mv = lambda v: schur_matvec(core, P, Psi, mu, v)
     stop = lambda res, x: res <= prm.tau * min(1.0, prm.kappa * rnorm * float(np.linalg.norm(x)))
-    at1, it, res = cg(mv, a1, stop, prm.cg_max_iter)
+    if prm.precond == "jacobi":
+        at1, it, res = pcg(mv, a1, 1.0 / schur_diag(core, P, Psi, mu), stop, prm.cg_max_iter)
+    elif prm.precond == "none":
+        at1, it, res = cg(mv, a1, stop, prm.cg_max_iter)
+    else:
+        raise ValueError(f"unknown preconditioner {prm.precond!r}")
     at2 = (a2 + T(a2)) / (mu + 1.0)
     dg = at1
     dX = at2 - T(phi_star(core.R, at1))

@@ -163,11 +163,13 @@ __global__ void cg_step_kernel(int n, double rr, const double* __restrict__ pAp,
   r[i] = -alpha * Ap[i] + r[i];
 }
 // ---- conjugate gradients with the scalars on the device ------------------------------------------------------
-// st: [CG_RR] r.r, [CG_XX] x.x, [CG_DONE] 0 running / 1 stopped, [CG_IT] iterations done.  The stopping test is
-// Eq. (4.5)'s: |r| <= thr with thr = tau min(1, kr |x|) (kr = kappa |R(w)|), or a fixed thr when fixed > 0; an
-// iteration count reaching cap, or a non-positive p.Ap, stops as well.  Iterations queued after the stop leave
-// every vector unchanged, so the host may queue several before it looks.
-constexpr int CG_RR = 0, CG_XX = 1, CG_DONE = 2, CG_IT = 3;
+// st: [CG_RR] r.r, [CG_XX] x.x, [CG_DONE] 0 running / 1 stopped, [CG_IT] iterations done, [CG_RZ] r.D^-1 r
+// with a diagonal preconditioner D (dinv = D^-1 non-null; preconditioned CG: z = D^-1 r, alpha = r.z / p.Ap,
+// beta = r'.z' / r.z, p = z + beta p).  The stopping test is Eq. (4.5)'s on the unpreconditioned residual:
+// |r| <= thr with thr = tau min(1, kr |x|) (kr = kappa |R(w)|), or a fixed thr when fixed > 0; an iteration
+// count reaching cap, or a non-positive p.Ap, stops as well.  Iterations queued after the stop leave every
+// vector unchanged, so the host may queue several before it looks.
+constexpr int CG_RR = 0, CG_XX = 1, CG_DONE = 2, CG_IT = 3, CG_RZ = 4;
 
 // Sums of three values over a 1024-thread workgroup, the same on every thread (shuffles inside each wavefront,
 // then the sixteen wavefront partials in a fixed order).
@@ -200,27 +202,30 @@ __device__ __forceinline__ bool cg_stop(double rr, double xx, double tau, double
   return sqrt(rr) <= thr;
 }
 
-// x = 0, r = p = b, r.r, and the stopping test at the start.
+// x = 0, r = b, p = D^-1 b (b without a preconditioner), r.r, r.z, and the stopping test at the start.
 __global__ __launch_bounds__(1024) void cg_init_kernel(int n, const double* __restrict__ b, double* __restrict__ x,
                                                        double* __restrict__ r, double* __restrict__ p,
                                                        double* __restrict__ st, double tau, double kr, double fixed,
-                                                       int cap) {
+                                                       int cap, const double* __restrict__ dinv) {
   __shared__ double sh[3][16];
-  double rr = 0.0, z1 = 0.0, z2 = 0.0;
+  double rr = 0.0, rz = 0.0, z2 = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int i = threadIdx.x + 1024 * q;
     if (i < n) {
       const double v = b[i];
+      const double z = dinv ? dinv[i] * v : v;
       x[i] = 0.0;
       r[i] = v;
-      p[i] = v;
+      p[i] = z;
       rr += v * v;
+      rz += v * z;
     }
   }
-  block_sum3(rr, z1, z2, sh);
+  block_sum3(rr, rz, z2, sh);
   if (threadIdx.x == 0) {
     st[CG_RR] = rr;
+    st[CG_RZ] = rz;
     st[CG_XX] = 0.0;
     st[CG_IT] = 0.0;
     st[CG_DONE] = (cap <= 0 || cg_stop(rr, 0.0, tau, kr, fixed)) ? 1.0 : 0.0;
@@ -232,10 +237,12 @@ __global__ __launch_bounds__(1024) void cg_init_kernel(int n, const double* __re
 __global__ __launch_bounds__(1024) void cg_tail_kernel(int n, double* __restrict__ st, double* __restrict__ p,
                                                        const double* __restrict__ Ap, double addmu,
                                                        double* __restrict__ x, double* __restrict__ r, double tau,
-                                                       double kr, double fixed, int cap) {
+                                                       double kr, double fixed, int cap,
+                                                       const double* __restrict__ dinv) {
   __shared__ double sh[3][16];
   if (st[CG_DONE] != 0.0) return;
   const double rr = st[CG_RR];
+  const double rz = dinv ? st[CG_RZ] : rr;
   double pv[8], av[8];
   double pap = 0.0, z1 = 0.0, z2 = 0.0;
 #pragma unroll
@@ -250,9 +257,9 @@ __global__ __launch_bounds__(1024) void cg_tail_kernel(int n, double* __restrict
     if (threadIdx.x == 0) st[CG_DONE] = 1.0;
     return;
   }
-  const double alpha = rr / pap;
+  const double alpha = rz / pap;
   double rv[8];
-  double rs = 0.0, xs = 0.0, z3 = 0.0;
+  double rs = 0.0, xs = 0.0, rzn = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int i = threadIdx.x + 1024 * q;
@@ -262,13 +269,14 @@ __global__ __launch_bounds__(1024) void cg_tail_kernel(int n, double* __restrict
       const double rn = -alpha * av[q] + r[i];
       x[i] = xn;
       r[i] = rn;
-      rv[q] = rn;
+      rv[q] = dinv ? dinv[i] * rn : rn;  // z = D^-1 r
       rs += rn * rn;
       xs += xn * xn;
+      rzn += rn * rv[q];
     }
   }
-  block_sum3(rs, xs, z3, sh);
-  const double beta = rs / rr;
+  block_sum3(rs, xs, rzn, sh);
+  const double beta = dinv ? rzn / rz : rs / rr;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int i = threadIdx.x + 1024 * q;
@@ -279,8 +287,24 @@ __global__ __launch_bounds__(1024) void cg_tail_kernel(int n, double* __restrict
     st[CG_IT] = it;
     st[CG_RR] = rs;
     st[CG_XX] = xs;
+    st[CG_RZ] = rzn;
     if (it >= (double)cap || cg_stop(rs, xs, tau, kr, fixed)) st[CG_DONE] = 1.0;
   }
+}
+
+// d_i = cq Q_ii + mu + ckk KK_ii (KK may be null): the Schur operator's diagonal outside its eigen-chain term.
+__global__ void schur_diag_base_kernel(int l, const double* __restrict__ Q, double cq, double mu,
+                                       const double* __restrict__ KK, double ckk, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= l) return;
+  const long long ii = (long long)i * l + i;
+  d[i] = cq * Q[ii] + mu + (KK ? ckk * KK[ii] : 0.0);
+}
+
+// out_i = 1 / d_i
+__global__ void recip_kernel(int n, const double* __restrict__ d, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = 1.0 / d[i];
 }
 
 __global__ __launch_bounds__(256) void rowsum_abs_kernel(int l, const double* __restrict__ A, int sq, double* __restrict__ rows) {
@@ -484,22 +508,32 @@ hipError_t form_z(int l, const double* X, double a, const double* T, double c, d
   return hipGetLastError();
 }
 hipError_t cg_init(int n, const double* b, double* x, double* r, double* p, double* st, double tau, double kr,
-                   double fixed, int cap, hipStream_t st_) {
+                   double fixed, int cap, hipStream_t st_, const double* dinv) {
   if (n > 8192) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(1024), 0, st_, n, b, x, r, p, st, tau, kr, fixed, cap);
+  hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(1024), 0, st_, n, b, x, r, p, st, tau, kr, fixed, cap, dinv);
   return hipGetLastError();
 }
 
 hipError_t cg_tail(int n, double* st, double* p, const double* Ap, double addmu, double* x, double* r, double tau,
-                   double kr, double fixed, int cap, hipStream_t st_) {
+                   double kr, double fixed, int cap, hipStream_t st_, const double* dinv) {
   if (n > 8192) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cg_tail_kernel, dim3(1), dim3(1024), 0, st_, n, st, p, Ap, addmu, x, r, tau, kr, fixed, cap);
+  hipLaunchKernelGGL(cg_tail_kernel, dim3(1), dim3(1024), 0, st_, n, st, p, Ap, addmu, x, r, tau, kr, fixed, cap,
+                     dinv);
   return hipGetLastError();
 }
 
 hipError_t cg_step(int n, double rr, const double* pAp, const double* p, const double* Ap, double* x, double* r,
                    hipStream_t st) {
   hipLaunchKernelGGL(cg_step_kernel, dim3(nblk(n)), dim3(256), 0, st, n, rr, pAp, p, Ap, x, r);
+  return hipGetLastError();
+}
+hipError_t schur_diag_base(int l, const double* Q, double cq, double mu, const double* KK, double ckk, double* d,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(schur_diag_base_kernel, dim3((l + 255) / 256), dim3(256), 0, st, l, Q, cq, mu, KK, ckk, d);
+  return hipGetLastError();
+}
+hipError_t vec_recip(int n, const double* d, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(recip_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, d, out);
   return hipGetLastError();
 }
 hipError_t rowsum_abs_max(int l, const double* A, bool square_entries, double* out, double* part, hipStream_t st) {

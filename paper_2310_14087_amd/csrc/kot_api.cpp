@@ -26,7 +26,7 @@ constexpr int kScalarDoubles = 64, kScalarInts = 16;
 constexpr size_t kScalarBytes = kScalarDoubles * sizeof(double) + kScalarInts * sizeof(int);
 // scalar slots: 0-3 per-call temporaries; residual norms (|r1|^2, |r2|^2) of the EG point 4-5 and of the trial
 // 6-7; the theta-rule dots 8-11; inputs of the default EG step 12-13; |z|^2 14; refinement scalars 16-19;
-// pooled feature statistics 24-25; the device-resident CG state 32-35
+// pooled feature statistics 24-25; the device-resident CG state 32-36
 enum : int { SL_TMP = 0, SL_VN = 4, SL_TN = 6, SL_THETA = 8, SL_ETA = 12, SL_ZZ = 14, SL_RR = 16, SL_PAP = 17,
              SL_XX = 18, SL_POOL = 24, SL_CG = 32 };
 
@@ -85,7 +85,7 @@ struct kot_ctx {
   // matrices (cap x cap)
   double *Qb, *Rb, *Kb, *KKb, *Z, *T1, *T2, *T3, *T4, *Bm, *dX, *Mr, *eigtmp, *Pe1, *Pe2, *Xh;
   // vectors (cap)
-  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
+  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *cdinv, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
   float *Bf = nullptr, *Cf = nullptr, *Ef = nullptr;  // reduced-precision chain operands
   State S[4];  // 0: w, 1: trial, 2: v, 3: scratch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -175,7 +175,7 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
     if (!(*m = alloc(mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed (l=%d)", cap);
   if (!(ctx->eigtmp = alloc(2 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   double** vecs[] = {&ctx->zb, &ctx->wsumb, &ctx->wmu, &ctx->wnu, &ctx->dg, &ctx->a1, &ctx->cx, &ctx->cr, &ctx->cp,
-                     &ctx->cAp, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
+                     &ctx->cAp, &ctx->cdinv, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
                      &ctx->lAp};
   for (double** v : vecs)
     if (!(*v = alloc(vv))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
@@ -381,6 +381,29 @@ kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const
   return KOT_OK;
 }
 
+// Jacobi (diagonal) preconditioner of the Schur system, one of the CG variants Section 4.3 names: the diagonal
+// of M = Q/(2 lam2) + mu I + Phi T Phi* is M_ii = Q_ii/(2 lam2) + mu + [(B o B)^T Psi (B o B)]_ii (B = P^T R),
+// formed with the matvec's eigen-row chain: E = H (B o B), H the chain's Psi weights (cross block doubled),
+// then +/- sum over the chain's rows r of (B o B)_ri E_ri, and (1/mu) (K o K)_ii in the complement form.
+// dinv receives 1 / M_ii.  Uses T1, T3, T4.
+kot_status schur_dinv(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, double* dinv) {
+  const int l = cv.l;
+  hipStream_t st = ctx->stream;
+  HIPCHK(schur_diag_base(l, cv.Q, 1.0 / (2.0 * cv.lam2), tp.mu, tp.comp ? cv.KK : nullptr, 1.0 / tp.mu, dinv, st));
+  if (tp.m > 0) {
+    double* D2 = ctx->T1;
+    double* H = ctx->T3;
+    double* E = ctx->T4;
+    HIPCHK(hadamard_square(l * l, ctx->Bm, D2, st));
+    HIPCHK(mat_fill(tp.m, l, 1.0, H, l, st));
+    HIPCHK(psi_hadamard(l, tp.a, tp.r0, tp.m, tp.mu, tp.w, H, l, tp.comp, 1.0, 2.0, st));
+    HIPCHK(mm(st, 0, 0, tp.m, l, l, 1.0, H, l, nullptr, D2, l, 0.0, E, l));
+    HIPCHK(diag_dot(0, tp.m, l, tp.comp ? -1.0 : 1.0, D2 + (long long)tp.r0 * l, l, E, l, 1.0, dinv, ctx->part, st));
+  }
+  HIPCHK(vec_recip(l, dinv, dinv, st));
+  return KOT_OK;
+}
+
 // Same operator with the chain in reduced precision (Bf holds B in FP32): FP32/BF16 products, FP32
 // accumulation, FP64 for the Q and (K o K) terms.
 kot_status schur_matvec_lowp(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const double* v, double* y, int mode) {
@@ -423,7 +446,12 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   HIPCHK(vec_lincomb(l * l, 1.0, s.r2, 1.0, ctx->T1, ctx->Mr, st));
   HIPCHK(vec_copy(l, s.r1, ctx->a1, st));
   KCHK(phi_op(ctx, cv, ctx->Mr, -1.0 / (mu + 1.0), -1.0, ctx->a1, ctx->T2));
-  // CG on the Schur system from x = 0 (Eq. 4.5 on the CG residual)
+  const double* dinv = nullptr;
+  if (p->precond == KOT_PRECOND_JACOBI) {
+    KCHK(schur_dinv(ctx, cv, tp, ctx->cdinv));
+    dinv = ctx->cdinv;
+  }
+  // CG on the Schur system from x = 0 (Eq. 4.5 on the CG residual), preconditioned when dinv is set
   double* x = ctx->cx;
   double* r = ctx->cr;
   double* pp = ctx->cp;
@@ -440,11 +468,11 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   // the stop change nothing); one synchronization per batch instead of one per iteration
   auto run_cg = [&](auto&& matvec, const double* b, double* xo, double* ro, double* po, double* Apo, double fixed,
                     int capc) -> kot_status {
-    HIPCHK(cg_init(l, b, xo, ro, po, cs, p->tau, kr, fixed, capc, st));
+    HIPCHK(cg_init(l, b, xo, ro, po, cs, p->tau, kr, fixed, capc, st, dinv));
     for (int batch = 2;; batch = 3) {
       for (int q = 0; q < batch; ++q) {
         KCHK(matvec(po, Apo));
-        HIPCHK(cg_tail(l, cs, po, Apo, 0.0, xo, ro, p->tau, kr, fixed, capc, st));
+        HIPCHK(cg_tail(l, cs, po, Apo, 0.0, xo, ro, p->tau, kr, fixed, capc, st, dinv));
       }
       KCHK(sync_read(ctx));
       if (hcs[kCgDone] != 0.0) return KOT_OK;
@@ -580,6 +608,8 @@ kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
   if (p->safeguard != KOT_SAFEGUARD_EG && p->safeguard != KOT_SAFEGUARD_NONE && p->safeguard != KOT_SAFEGUARD_EG_ONLY)
     return fail(ctx, KOT_ERR_ARG, "unknown safeguard %d", p->safeguard);
   if (p->lowp_min_rows < 0) return fail(ctx, KOT_ERR_ARG, "lowp_min_rows must be >= 0");
+  if (p->precond != KOT_PRECOND_NONE && p->precond != KOT_PRECOND_JACOBI)
+    return fail(ctx, KOT_ERR_ARG, "precond must be KOT_PRECOND_NONE or KOT_PRECOND_JACOBI");
   return KOT_OK;
 }
 
@@ -1179,6 +1209,7 @@ void kot_params_default(kot_params* p) {
   p->ws_theta = nullptr;
   p->overlap = 1;
   p->lowp_min_rows = 64;
+  p->precond = KOT_PRECOND_NONE;
 }
 
 kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {

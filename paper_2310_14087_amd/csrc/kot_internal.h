@@ -113,11 +113,16 @@ hipError_t form_z(int l, const double* X, double a, const double* T, double c, d
 // a stop flag and the iteration count (indices below).  cg_init: x = 0, r = p = b and the test at the start;
 // cg_tail: the vector part of one iteration given Ap (Ap + addmu p is the operator's product), a no-op once
 // stopped.  Stop: |r| <= tau min(1, kr |x|) (or |r| <= fixed when fixed > 0), cap iterations, or p.Ap <= 0.
-constexpr int kCgRR = 0, kCgXX = 1, kCgDone = 2, kCgIt = 3;
+// dinv (n, may be null): the inverse of a diagonal preconditioner (preconditioned CG; the test stays on r).
+constexpr int kCgRR = 0, kCgXX = 1, kCgDone = 2, kCgIt = 3, kCgRZ = 4;
 hipError_t cg_init(int n, const double* b, double* x, double* r, double* p, double* st, double tau, double kr,
-                   double fixed, int cap, hipStream_t s);
+                   double fixed, int cap, hipStream_t s, const double* dinv = nullptr);
 hipError_t cg_tail(int n, double* st, double* p, const double* Ap, double addmu, double* x, double* r, double tau,
-                   double kr, double fixed, int cap, hipStream_t s);
+                   double kr, double fixed, int cap, hipStream_t s, const double* dinv = nullptr);
+// d_i = cq Q_ii + mu + ckk KK_ii (KK may be null); out_i = 1 / d_i
+hipError_t schur_diag_base(int l, const double* Q, double cq, double mu, const double* KK, double ckk, double* d,
+                           hipStream_t st);
+hipError_t vec_recip(int n, const double* d, double* out, hipStream_t st);
 hipError_t cg_step(int n, double rr, const double* pAp, const double* p, const double* Ap, double* x, double* r,
                    hipStream_t st);
 // out[0] = max_i sum_j |A_ij| (row-sum norm)
