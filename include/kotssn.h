@@ -48,6 +48,10 @@ typedef enum { KOT_SAFEGUARD_EG = 0, KOT_SAFEGUARD_NONE = 1, KOT_SAFEGUARD_EG_ON
  * M_ii = Q_ii/(2 lambda2) + mu + [(B o B)^T Psi (B o B)]_ii with B = P^T R.  Eq. (4.5) is checked on the
  * unpreconditioned residual either way. */
 typedef enum { KOT_PRECOND_NONE = 0, KOT_PRECOND_JACOBI = 1 } kot_precond;
+/* Solver of that Schur system: conjugate gradients (the paper's choice) or symmetric QMR (Freund and
+ * Nachtigal's simplified QMR, the other Krylov method Section 4.3 names), with the same preconditioner choice,
+ * iteration cap and Eq. (4.5) test (on the true residual b - M x). */
+typedef enum { KOT_SCHUR_CG = 0, KOT_SCHUR_SQMR = 1 } kot_schur_solver;
 
 /* Parameters of Algorithm 2 and the inexactness rule Eq. (4.5).  kot_params_default fills the values
  * used throughout: tol 1e-6, max_iter 200, cg_max_iter 20 (Remark 4.5), tau = kappa = 0.5,
@@ -88,7 +92,8 @@ typedef struct kot_params {
                           iterative refinement only when the chain has at least this many eigen-rows
                           (min(|alpha|, l - |alpha|)); below it the chain's products are too small to gain from
                           lower precision and the FP64 CG runs instead (default 64; 0 = always) */
-  int precond;         /* kot_precond of the Schur-system CG (default KOT_PRECOND_NONE) */
+  int precond;         /* kot_precond of the Schur-system solver (default KOT_PRECOND_NONE) */
+  int schur_solver;    /* a kot_schur_solver value; default KOT_SCHUR_CG */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:

@@ -42,7 +42,7 @@ import numpy as np
 __all__ = [
     "Params", "Core", "gaussian_gram", "mean_embedding", "mean_gram", "setup", "core_from_arrays",
     "phi", "phi_star", "eig_sym", "proj_psd", "residual", "pair_norm", "pair_dot", "omega_matrix",
-    "psi_matrix", "t_apply", "schur_matvec", "schur_diag", "cg", "pcg", "ssn_direction", "eg_operator", "eg_step",
+    "psi_matrix", "t_apply", "schur_matvec", "schur_diag", "cg", "pcg", "sqmr", "ssn_direction", "eg_operator", "eg_step",
     "default_eg_step", "theta_update", "solve", "ot_estimate", "kkt_report",
 ]
 
@@ -72,6 +72,7 @@ class Params:
     eps_jitter: float = 1e-10
     precond: str = "none"          # "none" (CG as the paper runs it) or "jacobi" (diagonal preconditioner, a
                                    # variant Section 4.3 names for the Schur system)
+    schur_solver: str = "cg"       # "cg" (the paper's choice) or "sqmr" (symmetric QMR, the other solver it names)
 
 
 @dataclass
@@ -285,6 +286,51 @@ def pcg(matvec, b: np.ndarray, dinv: np.ndarray, stop, max_iter: int):
     return x, it, math.sqrt(rr)
 
 
+def sqmr(matvec, b: np.ndarray, dinv, stop, max_iter: int):
+    """Symmetric QMR (Freund and Nachtigal's simplified QMR for symmetric systems) with the symmetric diagonal
+    preconditioner D (dinv = 1/diag(D), or None for none), from x = 0.
+
+    Lanczos-type vectors: r (the BCG residual), q the search direction, rho = r^T D^-1 r.  Quasi-minimal
+    residual: theta_k = |r_k|_{D^-1} / tau_{k-1}, c_k = 1/sqrt(1 + theta_k^2), tau_k = tau_{k-1} theta_k c_k,
+    d_k = c_k^2 theta_{k-1}^2 d_{k-1} + c_k^2 alpha_k q_{k-1}, x_k = x_{k-1} + d_k.  The true residual
+    s_k = b - A x_k is carried by s_k = s_{k-1} - A d_k with A d_k formed by the same recurrence, and
+    ``stop(|s_k|, x_k)`` decides termination (Eq. 4.5)."""
+    dv = np.ones_like(b) if dinv is None else dinv
+    x = np.zeros_like(b)
+    d = np.zeros_like(b)
+    e = np.zeros_like(b)          # A d
+    s = b.copy()                  # b - A x
+    r = b.copy()
+    q = dv * r
+    rho = float(r @ q)
+    tau = math.sqrt(rho)
+    theta = 0.0
+    it = 0
+    while it < max_iter:
+        if stop(float(np.linalg.norm(s)), x):
+            break
+        t = matvec(q)
+        sigma = float(q @ t)
+        if sigma <= 0.0 or rho <= 0.0:
+            break
+        alpha = rho / sigma
+        r = r - alpha * t
+        u = dv * r
+        rho_new = float(r @ u)
+        theta_old = theta
+        theta = math.sqrt(rho_new) / tau
+        c2 = 1.0 / (1.0 + theta * theta)
+        tau = tau * theta * math.sqrt(c2)
+        d = (c2 * theta_old * theta_old) * d + (c2 * alpha) * q
+        e = (c2 * theta_old * theta_old) * e + (c2 * alpha) * t
+        x = x + d
+        s = s - e
+        q = u + (rho_new / rho) * q
+        rho = rho_new
+        it += 1
+    return x, it, float(np.linalg.norm(s))
+
+
 def cg(matvec, b: np.ndarray, stop, max_iter: int):
     """Conjugate gradients from x = 0; ``stop(res_norm, x)`` decides termination (Eq. 4.5)."""
     x = np.zeros_like(b)
@@ -319,12 +365,17 @@ def ssn_direction(core: Core, r1, r2, eig, mu: float, prm: Params):
     rnorm = pair_norm(r1, r2)
     mv = lambda v: schur_matvec(core, P, Psi, mu, v)
     stop = lambda res, x: res <= prm.tau * min(1.0, prm.kappa * rnorm * float(np.linalg.norm(x)))
-    if prm.precond == "jacobi":
-        at1, it, res = pcg(mv, a1, 1.0 / schur_diag(core, P, Psi, mu), stop, prm.cg_max_iter)
-    elif prm.precond == "none":
-        at1, it, res = cg(mv, a1, stop, prm.cg_max_iter)
-    else:
+    if prm.precond not in ("none", "jacobi"):
         raise ValueError(f"unknown preconditioner {prm.precond!r}")
+    dinv = 1.0 / schur_diag(core, P, Psi, mu) if prm.precond == "jacobi" else None
+    if prm.schur_solver == "sqmr":
+        at1, it, res = sqmr(mv, a1, dinv, stop, prm.cg_max_iter)
+    elif prm.schur_solver != "cg":
+        raise ValueError(f"unknown Schur-system solver {prm.schur_solver!r}")
+    elif dinv is not None:
+        at1, it, res = pcg(mv, a1, dinv, stop, prm.cg_max_iter)
+    else:
+        at1, it, res = cg(mv, a1, stop, prm.cg_max_iter)
     at2 = (a2 + T(a2)) / (mu + 1.0)
     dg = at1
     dX = at2 - T(phi_star(core.R, at1))

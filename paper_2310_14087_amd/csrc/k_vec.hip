@@ -292,6 +292,125 @@ __global__ __launch_bounds__(1024) void cg_tail_kernel(int n, double* __restrict
   }
 }
 
+// ---- symmetric QMR (Freund and Nachtigal's simplified QMR) with the scalars on the device ------------------
+// st as for CG ([CG_RR] holds s.s of the true residual s = b - A x, [CG_RZ] rho = r.D^-1 r) plus [SQ_TAU] tau and
+// [SQ_THETA] theta.  Vectors: x, r (the Lanczos / BCG residual), q (direction, the operand of the product),
+// d (the last update of x), e = A d, s = b - A x.  Same stopping test as CG, on s.
+constexpr int SQ_TAU = 5, SQ_THETA = 6;
+
+__global__ __launch_bounds__(1024) void sqmr_init_kernel(int n, const double* __restrict__ b, double* __restrict__ x,
+                                                         double* __restrict__ r, double* __restrict__ q,
+                                                         double* __restrict__ d, double* __restrict__ e,
+                                                         double* __restrict__ s, double* __restrict__ st, double tau,
+                                                         double kr, double fixed, int cap,
+                                                         const double* __restrict__ dinv) {
+  __shared__ double sh[3][16];
+  double bb = 0.0, rho = 0.0, z2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int i = threadIdx.x + 1024 * k;
+    if (i < n) {
+      const double v = b[i];
+      const double u = dinv ? dinv[i] * v : v;
+      x[i] = 0.0;
+      d[i] = 0.0;
+      e[i] = 0.0;
+      r[i] = v;
+      s[i] = v;
+      q[i] = u;
+      bb += v * v;
+      rho += v * u;
+    }
+  }
+  block_sum3(bb, rho, z2, sh);
+  if (threadIdx.x == 0) {
+    st[CG_RR] = bb;
+    st[CG_XX] = 0.0;
+    st[CG_IT] = 0.0;
+    st[CG_RZ] = rho;
+    st[SQ_TAU] = sqrt(rho);
+    st[SQ_THETA] = 0.0;
+    st[CG_DONE] = (cap <= 0 || cg_stop(bb, 0.0, tau, kr, fixed)) ? 1.0 : 0.0;
+  }
+}
+
+// One iteration given t = A q.  A non-positive q.t or rho stops (the operator is SPD; neither happens in exact
+// arithmetic).
+__global__ __launch_bounds__(1024) void sqmr_tail_kernel(int n, double* __restrict__ st, double* __restrict__ q,
+                                                         const double* __restrict__ t, double* __restrict__ x,
+                                                         double* __restrict__ r, double* __restrict__ d,
+                                                         double* __restrict__ e, double* __restrict__ s, double tau,
+                                                         double kr, double fixed, int cap,
+                                                         const double* __restrict__ dinv) {
+  __shared__ double sh[3][16];
+  if (st[CG_DONE] != 0.0) return;
+  const double rho = st[CG_RZ];
+  double qv[8], tv[8];
+  double sigma = 0.0, z1 = 0.0, z2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int i = threadIdx.x + 1024 * k;
+    qv[k] = (i < n) ? q[i] : 0.0;
+    tv[k] = (i < n) ? t[i] : 0.0;
+    sigma += qv[k] * tv[k];
+  }
+  block_sum3(sigma, z1, z2, sh);
+  if (!(sigma > 0.0) || !(rho > 0.0)) {
+    if (threadIdx.x == 0) st[CG_DONE] = 1.0;
+    return;
+  }
+  const double alpha = rho / sigma;
+  double rv[8], uv[8];
+  double rho_n = 0.0, z3 = 0.0, z4 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int i = threadIdx.x + 1024 * k;
+    rv[k] = 0.0;
+    uv[k] = 0.0;
+    if (i < n) {
+      rv[k] = -alpha * tv[k] + r[i];
+      uv[k] = dinv ? dinv[i] * rv[k] : rv[k];
+      r[i] = rv[k];
+      rho_n += rv[k] * uv[k];
+    }
+  }
+  block_sum3(rho_n, z3, z4, sh);
+  const double theta_o = st[SQ_THETA];
+  const double theta = sqrt(rho_n) / st[SQ_TAU];
+  const double c2 = 1.0 / (1.0 + theta * theta);
+  const double taun = st[SQ_TAU] * theta * sqrt(c2);
+  const double fd = c2 * theta_o * theta_o, fq = c2 * alpha, beta = rho_n / rho;
+  double ss = 0.0, xx = 0.0, z5 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int i = threadIdx.x + 1024 * k;
+    if (i < n) {
+      const double dn = fd * d[i] + fq * qv[k];
+      const double en = fd * e[i] + fq * tv[k];
+      const double xn = x[i] + dn;
+      const double sn = s[i] - en;
+      d[i] = dn;
+      e[i] = en;
+      x[i] = xn;
+      s[i] = sn;
+      q[i] = uv[k] + beta * qv[k];
+      ss += sn * sn;
+      xx += xn * xn;
+    }
+  }
+  block_sum3(ss, xx, z5, sh);
+  if (threadIdx.x == 0) {
+    const double it = st[CG_IT] + 1.0;
+    st[CG_IT] = it;
+    st[CG_RR] = ss;
+    st[CG_XX] = xx;
+    st[CG_RZ] = rho_n;
+    st[SQ_TAU] = taun;
+    st[SQ_THETA] = theta;
+    if (it >= (double)cap || cg_stop(ss, xx, tau, kr, fixed)) st[CG_DONE] = 1.0;
+  }
+}
+
 // d_i = cq Q_ii + mu + ckk KK_ii (KK may be null): the Schur operator's diagonal outside its eigen-chain term.
 __global__ void schur_diag_base_kernel(int l, const double* __restrict__ Q, double cq, double mu,
                                        const double* __restrict__ KK, double ckk, double* __restrict__ d) {
@@ -525,6 +644,20 @@ hipError_t cg_tail(int n, double* st, double* p, const double* Ap, double addmu,
 hipError_t cg_step(int n, double rr, const double* pAp, const double* p, const double* Ap, double* x, double* r,
                    hipStream_t st) {
   hipLaunchKernelGGL(cg_step_kernel, dim3(nblk(n)), dim3(256), 0, st, n, rr, pAp, p, Ap, x, r);
+  return hipGetLastError();
+}
+hipError_t sqmr_init(int n, const double* b, double* x, double* r, double* q, double* d, double* e, double* s,
+                     double* st, double tau, double kr, double fixed, int cap, hipStream_t st_, const double* dinv) {
+  if (n > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sqmr_init_kernel, dim3(1), dim3(1024), 0, st_, n, b, x, r, q, d, e, s, st, tau, kr, fixed, cap,
+                     dinv);
+  return hipGetLastError();
+}
+hipError_t sqmr_tail(int n, double* st, double* q, const double* t, double* x, double* r, double* d, double* e,
+                     double* s, double tau, double kr, double fixed, int cap, hipStream_t st_, const double* dinv) {
+  if (n > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sqmr_tail_kernel, dim3(1), dim3(1024), 0, st_, n, st, q, t, x, r, d, e, s, tau, kr, fixed, cap,
+                     dinv);
   return hipGetLastError();
 }
 hipError_t schur_diag_base(int l, const double* Q, double cq, double mu, const double* KK, double ckk, double* d,

@@ -26,7 +26,7 @@ constexpr int kScalarDoubles = 64, kScalarInts = 16;
 constexpr size_t kScalarBytes = kScalarDoubles * sizeof(double) + kScalarInts * sizeof(int);
 // scalar slots: 0-3 per-call temporaries; residual norms (|r1|^2, |r2|^2) of the EG point 4-5 and of the trial
 // 6-7; the theta-rule dots 8-11; inputs of the default EG step 12-13; |z|^2 14; refinement scalars 16-19;
-// pooled feature statistics 24-25; the device-resident CG state 32-36
+// pooled feature statistics 24-25; the device-resident CG / QMR state 32-38
 enum : int { SL_TMP = 0, SL_VN = 4, SL_TN = 6, SL_THETA = 8, SL_ETA = 12, SL_ZZ = 14, SL_RR = 16, SL_PAP = 17,
              SL_XX = 18, SL_POOL = 24, SL_CG = 32 };
 
@@ -85,7 +85,7 @@ struct kot_ctx {
   // matrices (cap x cap)
   double *Qb, *Rb, *Kb, *KKb, *Z, *T1, *T2, *T3, *T4, *Bm, *dX, *Mr, *eigtmp, *Pe1, *Pe2, *Xh;
   // vectors (cap)
-  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *cdinv, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
+  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *cdinv, *qd, *qe, *qs, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
   float *Bf = nullptr, *Cf = nullptr, *Ef = nullptr;  // reduced-precision chain operands
   State S[4];  // 0: w, 1: trial, 2: v, 3: scratch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -175,7 +175,7 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
     if (!(*m = alloc(mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed (l=%d)", cap);
   if (!(ctx->eigtmp = alloc(2 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   double** vecs[] = {&ctx->zb, &ctx->wsumb, &ctx->wmu, &ctx->wnu, &ctx->dg, &ctx->a1, &ctx->cx, &ctx->cr, &ctx->cp,
-                     &ctx->cAp, &ctx->cdinv, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
+                     &ctx->cAp, &ctx->cdinv, &ctx->qd, &ctx->qe, &ctx->qs, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
                      &ctx->lAp};
   for (double** v : vecs)
     if (!(*v = alloc(vv))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
@@ -466,13 +466,19 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   const int cap = std::max(0, p->cg_max_iter);
   // CG on the device: iterations go out in batches between host checks of the stop flag (those queued past
   // the stop change nothing); one synchronization per batch instead of one per iteration
+  // With schur_solver SQMR the same loop runs symmetric QMR (po is its direction q, Apo its product).
+  const bool sqmr = p->schur_solver == KOT_SCHUR_SQMR;
   auto run_cg = [&](auto&& matvec, const double* b, double* xo, double* ro, double* po, double* Apo, double fixed,
                     int capc) -> kot_status {
-    HIPCHK(cg_init(l, b, xo, ro, po, cs, p->tau, kr, fixed, capc, st, dinv));
+    if (sqmr) HIPCHK(sqmr_init(l, b, xo, ro, po, ctx->qd, ctx->qe, ctx->qs, cs, p->tau, kr, fixed, capc, st, dinv));
+    else HIPCHK(cg_init(l, b, xo, ro, po, cs, p->tau, kr, fixed, capc, st, dinv));
     for (int batch = 2;; batch = 3) {
       for (int q = 0; q < batch; ++q) {
         KCHK(matvec(po, Apo));
-        HIPCHK(cg_tail(l, cs, po, Apo, 0.0, xo, ro, p->tau, kr, fixed, capc, st, dinv));
+        if (sqmr)
+          HIPCHK(sqmr_tail(l, cs, po, Apo, xo, ro, ctx->qd, ctx->qe, ctx->qs, p->tau, kr, fixed, capc, st, dinv));
+        else
+          HIPCHK(cg_tail(l, cs, po, Apo, 0.0, xo, ro, p->tau, kr, fixed, capc, st, dinv));
       }
       KCHK(sync_read(ctx));
       if (hcs[kCgDone] != 0.0) return KOT_OK;
@@ -610,6 +616,8 @@ kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
   if (p->lowp_min_rows < 0) return fail(ctx, KOT_ERR_ARG, "lowp_min_rows must be >= 0");
   if (p->precond != KOT_PRECOND_NONE && p->precond != KOT_PRECOND_JACOBI)
     return fail(ctx, KOT_ERR_ARG, "precond must be KOT_PRECOND_NONE or KOT_PRECOND_JACOBI");
+  if (p->schur_solver != KOT_SCHUR_CG && p->schur_solver != KOT_SCHUR_SQMR)
+    return fail(ctx, KOT_ERR_ARG, "schur_solver must be KOT_SCHUR_CG or KOT_SCHUR_SQMR");
   return KOT_OK;
 }
 
@@ -1210,6 +1218,7 @@ void kot_params_default(kot_params* p) {
   p->overlap = 1;
   p->lowp_min_rows = 64;
   p->precond = KOT_PRECOND_NONE;
+  p->schur_solver = KOT_SCHUR_CG;
 }
 
 kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {

@@ -119,6 +119,13 @@ hipError_t cg_init(int n, const double* b, double* x, double* r, double* p, doub
                    double fixed, int cap, hipStream_t s, const double* dinv = nullptr);
 hipError_t cg_tail(int n, double* st, double* p, const double* Ap, double addmu, double* x, double* r, double tau,
                    double kr, double fixed, int cap, hipStream_t s, const double* dinv = nullptr);
+// Symmetric QMR with the scalars on the device (same st layout, tests and limits as CG; st also holds tau and
+// theta).  sqmr_init: x = d = e = 0, r = s = b, q = D^-1 b; sqmr_tail: one iteration given t = A q.  s is the
+// true residual b - A x; the stopping test runs on it.
+hipError_t sqmr_init(int n, const double* b, double* x, double* r, double* q, double* d, double* e, double* s,
+                     double* st, double tau, double kr, double fixed, int cap, hipStream_t s_, const double* dinv);
+hipError_t sqmr_tail(int n, double* st, double* q, const double* t, double* x, double* r, double* d, double* e,
+                     double* s, double tau, double kr, double fixed, int cap, hipStream_t s_, const double* dinv);
 // d_i = cq Q_ii + mu + ckk KK_ii (KK may be null); out_i = 1 / d_i
 hipError_t schur_diag_base(int l, const double* Q, double cq, double mu, const double* KK, double ckk, double* d,
                            hipStream_t st);

@@ -21,6 +21,7 @@ KOT_ERR_ARG, KOT_ERR_HIP, KOT_ERR_OOM, KOT_ERR_FACTOR, KOT_ERR_NUMERIC, KOT_ERR_
 KOT_FP64, KOT_FP32, KOT_MIXED_BF16, KOT_MIXED_BF16X3 = 0, 1, 2, 3
 KOT_SAFEGUARD_EG, KOT_SAFEGUARD_NONE, KOT_SAFEGUARD_EG_ONLY = 0, 1, 2
 KOT_PRECOND_NONE, KOT_PRECOND_JACOBI = 0, 1
+KOT_SCHUR_CG, KOT_SCHUR_SQMR = 0, 1
 
 STATUS_NAMES = {0: "KOT_OK", 1: "KOT_NOT_CONVERGED", -1: "KOT_ERR_ARG", -2: "KOT_ERR_HIP", -3: "KOT_ERR_OOM",
                 -4: "KOT_ERR_FACTOR", -5: "KOT_ERR_NUMERIC", -6: "KOT_ERR_EIG"}
@@ -41,7 +42,8 @@ class KotParams(C.Structure):
                 ("precision", C.c_int), ("safeguard", C.c_int), ("null_step", C.c_int),
                 ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int), ("lift_x0", C.c_int), ("ws_F", C.c_int),
                 ("ws_H", C.c_int), ("ws_theta", C.c_void_p), ("overlap", C.c_int),
-                ("lowp_min_rows", C.c_int), ("precond", C.c_int)]
+                ("lowp_min_rows", C.c_int), ("precond", C.c_int),
+                ("schur_solver", C.c_int)]
 
 
 class KotProblem(C.Structure):

@@ -45,12 +45,13 @@ def test_params_default_host_only(lib):
     assert p.beta1 == pytest.approx(1 / 1.2)
     assert p.null_step == 1 and p.safeguard == kotssn.KOT_SAFEGUARD_EG and p.precision == kotssn.KOT_FP64
     assert p.overlap == 1 and p.lowp_min_rows == 64 and p.precond == kotssn.KOT_PRECOND_NONE
+    assert p.schur_solver == kotssn.KOT_SCHUR_CG
 
 
 def test_struct_layouts_match_header():
     """ctypes mirrors of the C structs have the sizes the header implies (field order / padding)."""
     from paper_2310_14087_amd import kotssn
-    assert C.sizeof(kotssn.KotParams) == 8 * 5 + 4 * 2 + 8 * 11 + 4 * 8 + 8 + 8 + 8  # precond + padding
+    assert C.sizeof(kotssn.KotParams) == 8 * 5 + 4 * 2 + 8 * 11 + 4 * 8 + 8 + 8 + 8  # precond, schur_solver
     assert C.sizeof(kotssn.KotProblem) == 16 + 4 * 8
     assert C.sizeof(kotssn.KotResult) == 8 * 4 + 8 + 8 + 8 + 4 * 8 + 8
 

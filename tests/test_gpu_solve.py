@@ -99,6 +99,24 @@ def test_solve_jacobi_preconditioned(gpu_ctx, precision, name, l, n, seed):
     assert rn <= 1.01 * p.tol
 
 
+@pytest.mark.parametrize("precision,precond", [(0, 0), (0, 1), (2, 1)])
+@pytest.mark.parametrize("name,l,n,seed", [("mix1000", 150, 600, 0), ("mix256", 64, 300, 1)])
+def test_solve_sqmr(gpu_ctx, precision, precond, name, l, n, seed):
+    """Full solves with symmetric QMR on the Schur system reach the oracle's minimizer and estimate."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem(name, seed, l=l, n=n)
+    print(f"[case] kot_solve sqmr precision={precision} precond={precond} {name} seed={seed} l={p.l}", flush=True)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=p.tol, schur_solver="sqmr", precond="jacobi" if precond else "none"))
+    assert ref["status"] == "converged"
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=precision,
+                                lowp_min_rows=0, precond=precond, schur_solver=kotssn.KOT_SCHUR_SQMR)
+    gamma, X, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, want_X=True)
+    assert r.status == kotssn.KOT_OK and r.residual <= p.tol
+    assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
+    np.testing.assert_allclose(_n(gamma), ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
+
+
 @pytest.mark.parametrize("name,l,n,seed", [("mix1000", 257, 800, 3), ("batch", 150, 500, 8)])
 def test_small_chain_directions_are_fp64(gpu_ctx, name, l, n, seed):
     """With the default lowp_min_rows, a direction whose chain has fewer eigen-rows runs the FP64 CG: when

@@ -252,6 +252,31 @@ def test_ssn_direction_jacobi(gpu_ctx, name, l, n, mu, sign):
         np.testing.assert_allclose(_n(dX), odX, atol=1e-8 * np.abs(odX).max())
 
 
+@pytest.mark.parametrize("precond", [0, 1])
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+@pytest.mark.parametrize("name,l,n,mu", [("tiny", None, None, 0.3), ("mix1000", 130, 400, 0.05)])
+def test_ssn_direction_sqmr(gpu_ctx, name, l, n, mu, sign, precond):
+    """Symmetric QMR on the Schur system vs the oracle's: the iterate after four steps (where it differs from
+    CG's), then the converged direction."""
+    from paper_2310_14087_amd import kotssn
+    p, core = _core_case(name, l, n)
+    _case(f"kot_ssn_direction sqmr precond={precond} {name} l={core.l} mu={mu} sign={sign}")
+    g, X = _random_iterate(core.l, 37)
+    X = sign * X
+    o1, o2, on, eig = ko.residual(core, g, X)
+    for cap, tol in ((4, 1e-300), (400, 1e-13)):
+        prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2, cg_max_iter=cap, tau=tol, kappa=tol,
+                                    precond=precond, schur_solver=kotssn.KOT_SCHUR_SQMR)
+        dg, dX, info = gpu_ctx.ssn_direction(_t(core.Q), _t(core.z), _t(core.R), _t(g), _t(X), mu, prm)
+        odg, odX, oinfo = ko.ssn_direction(core, o1, o2, eig, mu,
+                                           ko.Params(cg_max_iter=cap, tau=tol, kappa=tol, schur_solver="sqmr",
+                                                     precond="jacobi" if precond else "none"))
+        if cap == 4:
+            assert info["cg_iters"] == oinfo["cg_iters"] == 4
+        np.testing.assert_allclose(_n(dg), odg, atol=1e-8 * np.abs(odg).max())
+        np.testing.assert_allclose(_n(dX), odX, atol=1e-8 * np.abs(odX).max())
+
+
 @pytest.mark.parametrize("name,l,n", [("tiny", None, None), ("mix1000", 100, 300)])
 def test_eg_step(gpu_ctx, name, l, n):
     from paper_2310_14087_amd import kotssn

@@ -73,3 +73,51 @@ def test_solve_with_jacobi_reaches_the_same_minimizer():
     assert a["status"] == "converged" and b["status"] == "converged"
     np.testing.assert_allclose(b["gamma"], a["gamma"], atol=1e-6 * np.abs(a["gamma"]).max())
     assert abs(b["ot"] - a["ot"]) <= 1e-7 * abs(a["ot"])
+
+
+@pytest.mark.parametrize("scaled", [False, True])
+def test_sqmr_true_residual_and_solution(scaled):
+    """Symmetric QMR: the carried residual s_k equals b - A x_k at every step, and the iterate reaches
+    np.linalg.solve (plain, and with the diagonal preconditioner on a badly scaled system)."""
+    rng = np.random.default_rng(5)
+    n = 40
+    C = rng.standard_normal((n, n))
+    A = C @ C.T / n + 0.2 * np.eye(n)
+    if scaled:
+        sc = 10.0 ** rng.uniform(-2, 2, n)
+        A = (sc[:, None] * A) * sc[None, :]
+    b = rng.standard_normal(n)
+    dinv = 1.0 / np.diag(A) if scaled else None
+    seen = []
+
+    def stop(res, x):
+        seen.append((res, x.copy()))
+        return res <= 1e-11 * np.linalg.norm(b)
+
+    x, it, res = ko.sqmr(lambda v: A @ v, b, dinv, stop, 400)
+    for rk, xk in seen:
+        assert abs(rk - np.linalg.norm(b - A @ xk)) <= 1e-8 * np.linalg.norm(b)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-8 * np.abs(np.linalg.solve(A, b)).max())
+
+
+def test_sqmr_one_step_is_the_minimal_residual_point():
+    """After one step the QMR iterate minimizes |b - A x| over x in span{b} (exact arithmetic identity)."""
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((12, 12))
+    A = A @ A.T + np.eye(12)
+    b = rng.standard_normal(12)
+    x, it, _ = ko.sqmr(lambda v: A @ v, b, None, lambda r_, x_: False, 1)
+    Ab = A @ b
+    t = float(b @ Ab) / float(Ab @ Ab)
+    assert it == 1
+    np.testing.assert_allclose(x, t * b, rtol=1e-12, atol=1e-14)
+
+
+def test_solve_with_sqmr_reaches_the_same_minimizer():
+    p = make_problem("mix256", 1, l=64, n=300)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    a = ko.solve(core, ko.Params(tol=1e-9))
+    b = ko.solve(core, ko.Params(tol=1e-9, schur_solver="sqmr", precond="jacobi"))
+    assert a["status"] == "converged" and b["status"] == "converged"
+    np.testing.assert_allclose(b["gamma"], a["gamma"], atol=1e-6 * np.abs(a["gamma"]).max())
+    assert abs(b["ot"] - a["ot"]) <= 1e-7 * abs(a["ot"])
