@@ -111,6 +111,52 @@ def copy_calibrate(mb):
                                            "copies": 3}}), flush=True)
 
 
+def sweep_bench(a):
+    """Section 5's synthetic sweep, SSN side: 3- vs 5-Gaussian mixtures in d = 2, 5, 10 with Sobol filling points
+    and l = n in {100, 200, 500, 1000}, stopped at |R(w)| < 0.005; mean wall time per solve for the paper's FP64
+    SSN (plain CG) and for the accelerated configuration (Jacobi CG, BF16x3 chain, learned start)."""
+    import numpy as np
+    import torch
+    from paper_2310_14087_amd import kotssn, warmstart
+    from paper_2310_14087_amd.inputs import make_problem
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    theta, F, H, _ = warmstart.load()
+    theta_dev = torch.from_numpy(theta).to(dev)
+    ctx = kotssn.Context(0)
+    reps = max(1, a.steps // 2)
+    rows = []
+    for d in (2, 5, 10):
+        for l in (100, 200, 500, 1000):
+            probs = [make_problem(f"sweep_d{d}", s, l=l, n=l) for s in range(reps)]
+            inputs = [(t(p.xs), t(p.ys), t(p.xf), t(p.yf)) for p in probs]
+            row = dict(d=d, l=l, n=l)
+            for arm in ("fp64", "fast"):
+                def prm(p):
+                    kw = dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+                    if arm == "fast":
+                        kw.update(precond=kotssn.KOT_PRECOND_JACOBI, precision=kotssn.KOT_MIXED_BF16X3,
+                                  ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
+                    return kotssn.default_params(**kw)
+                ctx.solve(*inputs[0], prm(probs[0]))  # warm-up (workspace sizing)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = [ctx.solve(*inputs[i], prm(p))[2] for i, p in enumerate(probs)]
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / len(probs)
+                row[arm] = dict(ms=1e3 * dt, iters=[r.iters for r in out], residual=max(r.residual for r in out),
+                                converged=sum(1 for r in out if r.status == kotssn.KOT_OK))
+                _log(f"sweep d={d} l={l} {arm}: {1e3 * dt:.2f} ms/solve iters={row[arm]['iters']}")
+            rows.append(row)
+    ctx.close()
+    print(json.dumps({"metric": "mean SSN solve time to |R(w)| < 0.005 on Section 5's synthetic sweep",
+                      "unit": "ms/solve", "higher_is_better": False, "data": "synthetic",
+                      "config": {"workload": "sweep: mixtures of 3 vs 5 Gaussians, d in {2,5,10}, Sobol filling, "
+                                             "sigma^2=0.005, lambda1=1/l, lambda2=1/sqrt(n), n=l",
+                                 "instances_per_point": reps},
+                      "rows": rows}), flush=True)
+
+
 def batch_bench(a):
     """Uneven batch (n ~ U{200..2000}, l ~ U{100..400}, d ~ U{2..10}): solves/s through kot_solve_batched with
     `lanes` concurrent streams vs one lane; FP32 CG chain, FP64 projections."""
@@ -153,7 +199,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mix1000")
+    ap.add_argument("--workload", default="mix1000",
+                    help="mix1000 (the metric line) or sweep (Section 5's synthetic sweep, its own JSON line)")
     ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed32", "mixed16", "mixed", "all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the roofline pass")
@@ -186,6 +233,8 @@ def main():
     dev = torch.device("cuda:0")
     if a.batch:
         return batch_bench(a)
+    if a.workload == "sweep":
+        return sweep_bench(a)
     if a.copy_calibrate > 0:
         return copy_calibrate(a.copy_calibrate)
     n_inst = max(1, a.steps)

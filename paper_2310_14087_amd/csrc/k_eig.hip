@@ -606,6 +606,12 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
         if (ok) ok = hipGraphInstantiate(&w->graph, gr, nullptr, nullptr, 0) == hipSuccess;
         if (gr) hipGraphDestroy(gr);
         if (!ok) {
+          hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;  // a failed capture must not stay open
+          if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(st, &g2);
+            if (g2) hipGraphDestroy(g2);
+          }
           (void)hipGetLastError();
           w->graph = nullptr;
           w->graph_failed = true;

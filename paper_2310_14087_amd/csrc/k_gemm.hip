@@ -360,9 +360,9 @@ hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) { return gemm_f64_cfg(g, 
 // list per shape, built on first use and kept for the life of the process (a few KB each).
 constexpr int kXcds = 8;
 struct UnitKey {
-  int m, n, k, tri, lower, kchunk;
+  int dev, m, n, k, tri, lower, kchunk;
   bool operator<(const UnitKey& o) const {
-    return std::tie(m, n, k, tri, lower, kchunk) < std::tie(o.m, o.n, o.k, o.tri, o.lower, o.kchunk);
+    return std::tie(dev, m, n, k, tri, lower, kchunk) < std::tie(o.dev, o.m, o.n, o.k, o.tri, o.lower, o.kchunk);
   }
 };
 struct UnitList {
@@ -371,9 +371,22 @@ struct UnitList {
 };
 static std::mutex g_units_mu;
 static std::map<UnitKey, UnitList>* g_units = nullptr;
+// The lists live in one device pool reserved outside any solve (gemm_reserve, from context creation): building
+// a list in the middle of a solve then needs no allocation and no copy on the legacy stream, which could
+// disturb a graph capture running on another thread's stream.
+constexpr size_t kUnitPool = size_t(1) << 20;  // ints per device
+constexpr int kMaxDevices = 64;
+static int* g_unit_pool[kMaxDevices] = {};
+static size_t g_unit_used[kMaxDevices] = {};
 
-static hipError_t unit_list(const GemmArgs& g, int kchunk, const UnitList** out) {
-  const UnitKey key{g.m, g.n, g.k, g.tri, g.lower, kchunk};
+// *out = null when no list can be built (pool full, or the stream is being captured): the caller then runs
+// the plain tile grid.
+static hipError_t unit_list(const GemmArgs& g, int kchunk, hipStream_t st, const UnitList** out) {
+  int dev = 0;
+  KOT_HIP_TRY(hipGetDevice(&dev));
+  const UnitKey key{dev, g.m, g.n, g.k, g.tri, g.lower, kchunk};
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipSuccess;
   std::lock_guard<std::mutex> lk(g_units_mu);
   if (!g_units) g_units = new std::map<UnitKey, UnitList>();
   auto it = g_units->find(key);
@@ -381,6 +394,10 @@ static hipError_t unit_list(const GemmArgs& g, int kchunk, const UnitList** out)
     *out = &it->second;
     return hipSuccess;
   }
+  if (!g_unit_pool[dev]) return hipSuccess;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  KOT_HIP_TRY(hipStreamIsCapturing(st, &cap));
+  if (cap != hipStreamCaptureStatusNone) return hipSuccess;
   struct U { int code, work; };
   std::vector<U> us;
   for (int m0 = 0; m0 < g.m; m0 += BM)
@@ -417,12 +434,24 @@ static hipError_t unit_list(const GemmArgs& g, int kchunk, const UnitList** out)
   std::vector<int> host(rows * kXcds, -1);
   for (int x = 0; x < kXcds; ++x)
     for (size_t r = 0; r < bins[x].size(); ++r) host[r * kXcds + x] = bins[x][r];
+  if (g_unit_used[dev] + host.size() > kUnitPool) return hipSuccess;
   UnitList ul;
   ul.len = (int)host.size();
-  KOT_HIP_TRY(hipMalloc(&ul.dev, host.size() * sizeof(int)));
-  KOT_HIP_TRY(hipMemcpy(ul.dev, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice));
+  ul.dev = g_unit_pool[dev] + g_unit_used[dev];
+  KOT_HIP_TRY(hipMemcpyAsync(ul.dev, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  KOT_HIP_TRY(hipStreamSynchronize(st));  // host is a local vector
+  g_unit_used[dev] += host.size();
   *out = &((*g_units)[key] = ul);
   return hipSuccess;
+}
+
+hipError_t gemm_reserve() {
+  int dev = 0;
+  KOT_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return hipSuccess;  // such a device runs without work lists
+  std::lock_guard<std::mutex> lk(g_units_mu);
+  if (g_unit_pool[dev]) return hipSuccess;
+  return hipMalloc(&g_unit_pool[dev], kUnitPool * sizeof(int));
 }
 
 hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits_req) {
@@ -499,9 +528,11 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
   const int* units = nullptr;
   if ((g.tri || g.lower) && g.batch == 1 && g.m <= 64 * BM && g.n <= 64 * BN && splits <= 255) {
     const UnitList* ul = nullptr;
-    KOT_HIP_TRY(unit_list(g, splits > 1 ? kchunk : g.k, &ul));
-    units = ul->dev;
-    grid = dim3(ul->len, 1, 1);
+    KOT_HIP_TRY(unit_list(g, splits > 1 ? kchunk : g.k, st, &ul));
+    if (ul) {
+      units = ul->dev;
+      grid = dim3(ul->len, 1, 1);
+    }
   }
   const bool sc = g.s != nullptr;
   Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;

@@ -875,6 +875,12 @@ kot_status trtri_cached(kot_ctx* ctx, int l, const double* R, double* Y, double*
   if (ok) ok = hipGraphInstantiate(&ctx->trtri_graph, gr, nullptr, nullptr, 0) == hipSuccess;
   if (gr) hipGraphDestroy(gr);
   if (!ok) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;  // a failed capture must not stay open
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(st, &g2);
+      if (g2) hipGraphDestroy(g2);
+    }
     (void)hipGetLastError();
     ctx->trtri_graph = nullptr;
     ctx->trtri_graph_failed = true;
@@ -1235,7 +1241,7 @@ kot_status kot_create(kot_ctx** out, int device, void* hip_stream) {
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return KOT_ERR_HIP; }
     ctx->own_stream = true;
   }
-  bool ok = hipMalloc(&ctx->dsc, kScalarBytes) == hipSuccess &&
+  bool ok = gemm_reserve() == hipSuccess && hipMalloc(&ctx->dsc, kScalarBytes) == hipSuccess &&
             hipHostMalloc(&ctx->hsc, kScalarBytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
             hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->hsc_dev), ctx->hsc, 0) == hipSuccess &&
             hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess;

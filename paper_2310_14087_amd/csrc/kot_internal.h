@@ -42,6 +42,8 @@ struct GemmArgs {
   int batch;
   int lower, mirror, tri;
 };
+// Reserves the current device's pool of GEMM work lists (once per device and process; call outside any solve).
+hipError_t gemm_reserve();
 hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
 // Same with an explicit launch shape: waves per workgroup (4, 8 or 16; 0 = default) and K splits (0 = from
 // the split-K target of the size bucket).

@@ -31,10 +31,11 @@ import numpy as np
 
 __all__ = ["Problem", "make_problem", "make_custom", "median_pairwise_distance", "WORKLOADS"]
 
-WORKLOADS = ("tiny", "gauss500", "mix1000", "batch", "mix256")
+WORKLOADS = ("tiny", "gauss500", "mix1000", "batch", "mix256", "sweep_d2", "sweep_d5", "sweep_d10", "cells48")
 
 # Seed offsets per workload: seed = base + s.
-_SEED_BASE = {"tiny": 1000, "gauss500": 2000, "mix1000": 3000, "batch": 4000, "mix256": 5000}
+_SEED_BASE = {"tiny": 1000, "gauss500": 2000, "mix1000": 3000, "batch": 4000, "mix256": 5000, "sweep_d2": 6000,
+              "sweep_d5": 7000, "sweep_d10": 8000, "cells48": 9000}
 
 
 @dataclass
@@ -108,6 +109,67 @@ def _mixture(rng: np.random.Generator, means: np.ndarray, n: int) -> np.ndarray:
     return means[lab] + rng.standard_normal((n, means.shape[1]))
 
 
+def sobol_filling(rng: np.random.Generator, l: int, d: int):
+    """l filling points (x~_i, y~_i) from a scrambled Sobol sequence in [0, 1]^(2d), split into the x- and
+    y-halves (the joint points of Section 5's synthetic setup)."""
+    import warnings
+    from scipy.stats import qmc
+    with warnings.catch_warnings():  # balance is exact only for powers of two; any l is accepted
+        warnings.simplefilter("ignore", UserWarning)
+        pts = qmc.Sobol(d=2 * d, scramble=True, seed=rng).random(l)
+    return np.ascontiguousarray(pts[:, :d]), np.ascontiguousarray(pts[:, d:])
+
+
+def _sweep(rng: np.random.Generator, name: str, seed: int, d: int, l_: int, n_: int, meta: dict) -> Problem:
+    """Section 5's synthetic setup: mu a mixture of 3 and nu a mixture of 5 Gaussians in R^d (equal weights,
+    identity covariance, means uniform in [-2, 2]^d), the samples scaled jointly into the unit cube, l filling
+    points from a 2d-dimensional Sobol sequence, sigma^2 = 0.005, lambda1 = 1/l, lambda2 = 1/sqrt(n), stop at
+    |R(w)| < 0.005."""
+    mx = rng.uniform(-2.0, 2.0, size=(3, d))
+    my = rng.uniform(-2.0, 2.0, size=(5, d))
+    xs = _mixture(rng, mx, n_)
+    ys = _mixture(rng, my, n_)
+    xs, ys = _unit_cube(xs, ys)
+    xf, yf = sobol_filling(rng, l_, d)
+    meta.update(components=(3, 5))
+    return Problem(name, seed, xs, ys, xf, yf, sigma=PAPER_SIGMA, lam1=1.0 / l_, lam2=1.0 / np.sqrt(n_),
+                   tol=0.005, meta=meta)
+
+
+def _cells48(rng: np.random.Generator, name: str, seed: int, l_: int, n_: int, meta: dict) -> Problem:
+    """Synthetic stand-in with the shapes of the single-cell comparison (48 features, 256 filling points): an
+    'unperturbed' population of 6 clusters with random anisotropic covariances and a 'perturbed' one in which
+    every cluster is shifted and rescaled and the cluster weights change; the samples are scaled jointly into
+    the unit cube, the filling points come from a 96-dimensional Sobol sequence and the bandwidth is a third of
+    the median pairwise distance (at the median itself the iteration stalls near |R| ~ 1e-5 at these sizes; no
+    cell measurements are used)."""
+    d, k = 48, 6
+    means = rng.uniform(-1.0, 1.0, size=(k, d))
+    facs = [rng.standard_normal((d, d)) / np.sqrt(d) * rng.uniform(0.2, 0.6) for _ in range(k)]
+    wx = rng.dirichlet(np.ones(k))
+    wy = rng.dirichlet(np.ones(k))
+    shift = 0.4 * rng.standard_normal((k, d)) / np.sqrt(d) * 4.0
+    scale = rng.uniform(0.7, 1.3, size=k)
+
+    def draw(w, perturbed):
+        lab = rng.choice(k, size=n_, p=w)
+        z = rng.standard_normal((n_, d))
+        out = np.empty((n_, d))
+        for j in range(k):
+            idx = lab == j
+            v = z[idx] @ facs[j].T
+            out[idx] = means[j] + (shift[j] + scale[j] * v if perturbed else v)
+        return out
+
+    xs = draw(wx, False)
+    ys = draw(wy, True)
+    xs, ys = _unit_cube(xs, ys)
+    xf, yf = sobol_filling(rng, l_, d)
+    meta.update(clusters=k)
+    return Problem(name, seed, xs, ys, xf, yf, sigma=median_pairwise_distance(xs, ys) / 3.0, lam1=1.0 / l_,
+                   lam2=1.0 / np.sqrt(n_), tol=1e-6, meta=meta)
+
+
 def make_problem(name: str, s: int = 0, *, l: int | None = None, n: int | None = None) -> Problem:
     """Draw problem number ``s`` of workload ``name``.  ``l``/``n`` override the sizes (for scaled-down tests);
     the draw order is fixed so that an override changes only the affected arrays' lengths."""
@@ -116,6 +178,11 @@ def make_problem(name: str, s: int = 0, *, l: int | None = None, n: int | None =
     seed = _SEED_BASE[name] + s
     rng = np.random.default_rng(seed)
     meta: dict = {}
+    if name.startswith("sweep_d"):
+        l_ = l or 500
+        return _sweep(rng, name, seed, int(name[len("sweep_d"):]), l_, n or l_, meta)
+    if name == "cells48":
+        return _cells48(rng, name, seed, l or 256, n or 1000, meta)
     if name == "tiny":
         n_ = n or 100
         l_ = l or 50
