@@ -44,7 +44,7 @@ typedef enum { KOT_FP64 = 0, KOT_FP32 = 1, KOT_MIXED_BF16 = 2, KOT_MIXED_BF16X3 
  * alone: pure extragradient iterations on Eq. (4.1), the comparison method of Appendix F (EG_ONLY). */
 typedef enum { KOT_SAFEGUARD_EG = 0, KOT_SAFEGUARD_NONE = 1, KOT_SAFEGUARD_EG_ONLY = 2 } kot_safeguard;
 /* CG on the Schur system of Algorithm 1 as the paper runs it (NONE), or preconditioned with the inverse of the
- * system's diagonal (JACOBI), one of the variants Section 4.3 names for it:
+ * system's diagonal (JACOBI; not in the paper, which runs plain CG):
  * M_ii = Q_ii/(2 lambda2) + mu + [(B o B)^T Psi (B o B)]_ii with B = P^T R.  Eq. (4.5) is checked on the
  * unpreconditioned residual either way. */
 typedef enum { KOT_PRECOND_NONE = 0, KOT_PRECOND_JACOBI = 1 } kot_precond;

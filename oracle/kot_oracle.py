@@ -70,8 +70,8 @@ class Params:
                                    # (pure extragradient, the comparison method of Appendix F)
     null_step: bool = True         # reading: keep w_k when it beats both the trial and v_{k+1}
     eps_jitter: float = 1e-10
-    precond: str = "none"          # "none" (CG as the paper runs it) or "jacobi" (diagonal preconditioner, a
-                                   # variant Section 4.3 names for the Schur system)
+    precond: str = "none"          # "none" (CG as the paper runs it) or "jacobi" (diagonal preconditioner of the
+                                   # Schur system; an addition, the paper names none)
     schur_solver: str = "cg"       # "cg" (the paper's choice) or "sqmr" (symmetric QMR, the other solver it names)
 
 

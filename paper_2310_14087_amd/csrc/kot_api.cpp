@@ -381,7 +381,7 @@ kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const
   return KOT_OK;
 }
 
-// Jacobi (diagonal) preconditioner of the Schur system, one of the CG variants Section 4.3 names: the diagonal
+// Jacobi (diagonal) preconditioner of the Schur system (an addition; the paper runs plain CG): the diagonal
 // of M = Q/(2 lam2) + mu I + Phi T Phi* is M_ii = Q_ii/(2 lam2) + mu + [(B o B)^T Psi (B o B)]_ii (B = P^T R),
 // formed with the matvec's eigen-row chain: E = H (B o B), H the chain's Psi weights (cross block doubled),
 // then +/- sum over the chain's rows r of (B o B)_ri E_ri, and (1/mu) (K o K)_ii in the complement form.

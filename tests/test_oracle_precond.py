@@ -1,7 +1,8 @@
 """Pins of the oracle's Jacobi-preconditioned CG for the Schur system of Algorithm 1 (no GPU).
 
-Section 4.3 names preconditioning among the ways to solve the Schur system; the oracle's diagonal is written as a
-closed form (schur_diag) and is pinned here against the operator itself, probed with unit vectors.
+Section 4.3 solves the Schur system by CG or symmetric QMR; the diagonal preconditioner is an addition.  The
+oracle's diagonal is written as a closed form (schur_diag) and is pinned here against the operator itself, probed
+with unit vectors.
 """
 import numpy as np
 import pytest
