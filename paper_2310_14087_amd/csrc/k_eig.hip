@@ -265,6 +265,38 @@ __global__ __launch_bounds__(64) void apply_kernel(int l, int np, double* __rest
 // doubled off the block diagonal for the mirrored block (ball), and per diagonal block the number of positive
 // diagonal entries (bpos); the diagonal itself goes to dg.  Workgroup (chunk, b1): the BSZ rows of block row b1
 // over 256 consecutive columns, one column per thread, so every row segment is one coalesced 2 KB read.
+// Warm-basis check without the second product: with V = Z P0 and d_i = P0_i . V_i (the diagonal of
+// A = P0^T Z P0), off(A) = |V - P0 diag(d)|_F and |A|_F = |V|_F for orthogonal P0.  Workgroup r sums row r
+// (fixed tree) into out[r], out[l + r], and flags d_r > 0 in out[2 l + r].
+__global__ __launch_bounds__(256) void warm_check_kernel(int l, const double* __restrict__ P0,
+                                                         const double* __restrict__ V, const double* __restrict__ d,
+                                                         double* __restrict__ out) {
+  __shared__ double so_s[256], sa_s[256];
+  const int r = blockIdx.x, t = threadIdx.x;
+  double so = 0.0, sa = 0.0;
+  for (int i = t; i < l; i += 256) {
+    const double v = V[(long long)r * l + i];
+    const double e = v - P0[(long long)r * l + i] * d[i];
+    so += e * e;
+    sa += v * v;
+  }
+  so_s[t] = so;
+  sa_s[t] = sa;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      so_s[t] += so_s[t + h];
+      sa_s[t] += sa_s[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[r] = so_s[0];
+    out[l + r] = sa_s[0];
+    out[2 * l + r] = d[r] > 0.0 ? 1.0 : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void block_norm_kernel(int l, int nb, const double* __restrict__ A,
                                                          double* __restrict__ boff, double* __restrict__ ball,
                                                          double* __restrict__ bpos, double* __restrict__ dg) {
@@ -393,6 +425,8 @@ struct EigWork {
   double* hup_dev = nullptr;
   int2* list = nullptr;       // up + 2
   int2* hlist = nullptr;      // hup + 2
+  double* wh = nullptr;       // mapped host: per-row sums of the warm-basis check (3 lmax)
+  double* wdev = nullptr;     // its device alias
   std::vector<int> round_k;   // active pairs per round of the current threshold sweep
 };
 static int block_count(int l) {
@@ -419,7 +453,10 @@ EigWork* eig_work_create(int lmax) {
             hipMalloc(&w->up, sizeof(double) * (2 + nlist)) == hipSuccess &&
             hipHostMalloc(&w->hup, sizeof(double) * (2 + nlist), hipHostMallocMapped | hipHostMallocCoherent) ==
                 hipSuccess &&
-            hipHostGetDevicePointer(reinterpret_cast<void**>(&w->hup_dev), w->hup, 0) == hipSuccess;
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&w->hup_dev), w->hup, 0) == hipSuccess &&
+            hipHostMalloc(&w->wh, sizeof(double) * 3 * (size_t)lmax, hipHostMallocMapped | hipHostMallocCoherent) ==
+                hipSuccess &&
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&w->wdev), w->wh, 0) == hipSuccess;
   if (!ok) { eig_work_destroy(w); return nullptr; }
   static_assert(sizeof(int2) == sizeof(double), "pair lists travel as doubles");
   w->list = reinterpret_cast<int2*>(w->up + 2);
@@ -431,7 +468,7 @@ void eig_work_destroy(EigWork* w) {
   if (!w) return;
   if (w->graph) hipGraphExecDestroy(w->graph);
   hipFree(w->U); hipFree(w->flag); hipFree(w->perm); hipFree(w->dg);
-  hipHostFree(w->hb); hipFree(w->up); hipHostFree(w->hup);
+  hipHostFree(w->hb); hipFree(w->up); hipHostFree(w->hup); hipHostFree(w->wh);
   delete w;
 }
 
@@ -539,12 +576,41 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   double* V = tmp + (long long)l * l;
   const long long nn = (long long)l * l;
   const int eb = (int)((nn + 255) / 256);
+  // ascending eigenvalues from w->dg and the columns of V permuted to match into P
+  auto finish = [&]() -> hipError_t {
+    if (l > 4096) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 15) / 16), dim3(256), 0, st, l, w->dg, wv, w->perm);
+    KOT_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, V, w->perm, P);
+    return hipGetLastError();
+  };
   if (P0) {
     // A = P0^T Z P0 (Z P0 staged in V; P0 may alias the output P), then V = P0
     GemmArgs g{};
     g.transa = 0; g.transb = 0; g.m = l; g.n = l; g.k = l; g.alpha = 1.0; g.beta = 0.0;
     g.A = Z; g.lda = l; g.B = P0; g.ldb = l; g.C = V; g.ldc = l; g.batch = 1;
     KOT_HIP_TRY(gemm_f64(g, st));
+    if (l >= kDiagParts) {
+      // Once the iteration settles the warm basis often diagonalizes Z to the tolerance already: test that from
+      // V alone (A's buffer serves as the column dots' workspace) and skip the second product and the sweeps.
+      KOT_HIP_TRY(diag_dot(0, l, l, 1.0, P0, l, V, l, 0.0, w->dg, A, st));
+      hipLaunchKernelGGL(warm_check_kernel, dim3(l), dim3(256), 0, st, l, P0, V, w->dg, w->wdev);
+      KOT_HIP_TRY(hipGetLastError());
+      KOT_HIP_TRY(hipStreamSynchronize(st));
+      double so = 0.0, sa = 0.0, sp = 0.0;
+      for (int r = 0; r < l; ++r) {
+        so += w->wh[r];
+        sa += w->wh[l + r];
+        sp += w->wh[2 * l + r];
+      }
+      if (std::sqrt(so) <= tol * std::sqrt(sa)) {
+        KOT_HIP_TRY(vec_copy((int)nn, P0, V, st));
+        *sweeps = 0;
+        *rel_off = (sa > 0.0) ? std::sqrt(so) / std::sqrt(sa) : 0.0;
+        if (npos) *npos = (int)sp;
+        return finish();
+      }
+    }
     g.transa = 1; g.A = P0; g.B = V; g.C = A;
     g.lower = 1; g.mirror = 1;  // symmetric result: lower tiles, mirrored
     KOT_HIP_TRY(gemm_f64(g, st));
@@ -631,11 +697,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   *sweeps = s;
   *rel_off = (all > 0.0) ? off / all : 0.0;
   if (npos) *npos = pos;
-  if (l > 4096) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 15) / 16), dim3(256), 0, st, l, w->dg, wv, w->perm);
-  KOT_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, V, w->perm, P);
-  return hipGetLastError();
+  return finish();
 }
 
 }  // namespace kot
