@@ -209,10 +209,13 @@ kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, co
 kot_status kot_cholesky(kot_ctx* ctx, int l, const double* A, double eps, double* R, double* Rit);
 
 /* General FP64 product on the device (MFMA): C = alpha op(A) diag(s) op(B) + beta C, op = transpose if
- * trans* != 0; s (device, length k) may be NULL.  C is m x n with leading dimension ldc. */
+ * trans* != 0; s (device, length k) may be NULL.  C is m x n with leading dimension ldc.  The solver's product
+ * modes, exposed for testing: tri declares known zero triangles (bit 1: op(A) upper triangular, 2: op(A) lower,
+ * 4: op(B) upper, 8: op(B) lower; the skipped entries must be zero), sym declares a symmetric result (m == n,
+ * and C symmetric when beta != 0): only the lower tiles are computed and mirrored.  KOT_ERR_ARG otherwise. */
 kot_status kot_gemm(kot_ctx* ctx, int transa, int transb, int m, int n, int k, double alpha,
                     const double* A, int lda, const double* s, const double* B, int ldb, double beta,
-                    double* C, int ldc);
+                    double* C, int ldc, int tri, int sym);
 
 /* ---- Learned warm start (not in the paper: a network predicting the start dual) ----------------------------
  * Network: f(x) = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3 applied to each row x of a feature matrix.

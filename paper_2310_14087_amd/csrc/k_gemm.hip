@@ -207,6 +207,10 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
   }
   // ---- epilogue ----
   const int M = g.m, N = g.n;
+  // strictly lower tile of a symmetric result: the transpose goes out through LDS, row segments again
+  const bool mir = splits == 1 && g.mirror && n0 < m0;
+  double* Tt = &As2[0][0];  // 64 x 65 staging tile (the K loop's buffers are free once every wave is past it)
+  if (mir) __syncthreads();
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -222,35 +226,76 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
             double* p = C + (long long)row * g.ldc + col;
             const double r = g.alpha * acc[i][j][v];
             *p = (g.beta == 0.0) ? r : r + g.beta * (*p);
-            if (g.mirror && n0 < m0) {  // strictly lower tile of a symmetric result: write the transpose too
-              double* q = C + (long long)col * g.ldc + row;
-              *q = (g.beta == 0.0) ? r : r + g.beta * (*q);
-            }
+            if (mir) Tt[(row - m0) * (BN + 1) + (col - n0)] = r;
           }
         }
       }
+  if (mir) {
+    __syncthreads();
+    for (int e = (int)threadIdx.x; e < BM * BN; e += NT) {
+      const int a = e / BM, b = e % BM;  // C[n0 + a][m0 + b] = tile[b][a]
+      if (n0 + a < N && m0 + b < M) {
+        double* q = C + (long long)(n0 + a) * g.ldc + (m0 + b);
+        const double r = Tt[b * (BN + 1) + a];
+        *q = (g.beta == 0.0) ? r : r + g.beta * (*q);
+      }
+    }
+  }
 }
 
-// C = alpha * sum_s part[b][s] + beta * C, summed in split order over the splits that met the element's tile.
-__global__ void splitk_reduce_kernel(GemmArgs g, int splits, int kchunk, const double* __restrict__ part) {
-  const long long mn = (long long)g.m * g.n;
-  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int bz = blockIdx.y;
-  if (u >= mn) return;
-  const int row = (int)(u / g.n), col = (int)(u % g.n);
-  const int m0 = (row / BM) * BM, n0 = (col / BN) * BN;
-  if (g.lower && n0 > m0 + BM - 1) return;  // tile above the diagonal: not computed
+// C = alpha * sum_s part[b][s] + beta * C, summed in split order over the splits that met the tile's K range;
+// one 16-row slab of a 64 x 64 tile per workgroup (row segments in and out; many workgroups keep enough loads
+// in flight), the transpose of a slab of a strictly lower tile of a symmetric result written through LDS as
+// 128-byte row segments too.
+constexpr int RS = 16;  // rows per reduction slab
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int splits, int kchunk,
+                                                            const double* __restrict__ part) {
+  __shared__ double Tt[RS][BN + 1];
+  const int s0 = blockIdx.y * RS, n0 = blockIdx.x * BN, bz = blockIdx.z;
+  const int m0 = (s0 / BM) * BM;  // the slab's GEMM tile row
+  if (g.lower && n0 > m0 + BM - 1) return;  // tile above the diagonal: not computed (uniform per workgroup)
   int klo, khi;
   tri_k_range(g.tri, g.k, m0, n0, klo, khi);
-  const double* p = part + (long long)bz * splits * mn + u;
-  double s = 0.0;
-  for (int q = 0; q < splits; ++q)
-    if (max(q * kchunk, klo) < min(min(g.k, q * kchunk + kchunk), khi)) s += p[q * mn];
-  double* c = g.C + bz * g.sC + (long long)row * g.ldc + col;
-  *c = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*c);
-  if (g.mirror && (col / BN) < (row / BM)) {
-    double* q = g.C + bz * g.sC + (long long)col * g.ldc + row;
-    *q = (g.beta == 0.0) ? g.alpha * s : g.alpha * s + g.beta * (*q);
+  const long long mn = (long long)g.m * g.n;
+  const double* pb = part + (long long)bz * splits * mn;
+  double* Cb = g.C + bz * g.sC;
+  const int t = threadIdx.x, cc = t & (BN - 1);
+  const bool mir = g.mirror && n0 < m0;
+  const int col = n0 + cc, colc = min(col, g.n - 1);
+  constexpr int E = RS / 4;  // elements per thread
+  double s[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) s[q] = 0.0;
+  for (int sp = 0; sp < splits; ++sp) {
+    if (!(max(sp * kchunk, klo) < min(min(g.k, sp * kchunk + kchunk), khi))) continue;  // uniform
+    const double* ps = pb + sp * mn;
+    double v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = ps[(long long)min(s0 + (t >> 6) + 4 * q, g.m - 1) * g.n + colc];
+#pragma unroll
+    for (int q = 0; q < E; ++q) s[q] += v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int rr = (t >> 6) + 4 * q;
+    const int row = s0 + rr;
+    if (row < g.m && col < g.n) {
+      double* c = Cb + (long long)row * g.ldc + col;
+      const double r = g.alpha * s[q];
+      *c = (g.beta == 0.0) ? r : r + g.beta * (*c);
+      if (mir) Tt[rr][cc] = r;
+    }
+  }
+  if (!mir) return;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int a = (t >> 4) + 16 * q, b = t & (RS - 1);  // C[n0 + a][s0 + b] = slab[b][a]
+    if (n0 + a < g.n && s0 + b < g.m) {
+      double* d = Cb + (long long)(n0 + a) * g.ldc + (s0 + b);
+      const double r = Tt[b][a];
+      *d = (g.beta == 0.0) ? r : r + g.beta * (*d);
+    }
   }
 }
 
@@ -556,9 +601,8 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
 #undef KOT_GEMM_CASE
   if (!launched) return hipErrorInvalidValue;
   if (splits > 1) {
-    const long long mn = (long long)g.m * g.n;
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((mn + 255) / 256), g.batch), dim3(256), 0, st, g, splits,
-                       kchunk, (const double*)part);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((g.n + BN - 1) / BN, (g.m + RS - 1) / RS, g.batch), dim3(256), 0,
+                       st, g, splits, kchunk, (const double*)part);
   }
   if (pf) pf->end(st);
   return hipGetLastError();

@@ -1685,11 +1685,14 @@ kot_status kot_profile(kot_ctx* ctx, int enable, double* out, int nclass) {
 }
 
 kot_status kot_gemm(kot_ctx* ctx, int transa, int transb, int m, int n, int k, double alpha, const double* A, int lda,
-                    const double* s, const double* B, int ldb, double beta, double* C, int ldc) {
+                    const double* s, const double* B, int ldb, double beta, double* C, int ldc, int tri, int sym) {
   KCHK(check_ctx(ctx));
   if (m < 0 || n < 0 || k < 1 || !A || !B || !C) return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  if (tri < 0 || tri > 15 || (tri & 3) == 3 || (tri & 12) == 12 || (sym && m != n))
+    return fail(ctx, KOT_ERR_ARG, "invalid tri / sym");
   if (std::max(m, n) <= 4096) KCHK(ensure_ws(ctx, std::max(std::max(m, n), 1), 0));  // split-K workspace
-  HIPCHK(mm(ctx->stream, transa ? 1 : 0, transb ? 1 : 0, m, n, k, alpha, A, lda, s, B, ldb, beta, C, ldc));
+  HIPCHK(mm(ctx->stream, transa ? 1 : 0, transb ? 1 : 0, m, n, k, alpha, A, lda, s, B, ldb, beta, C, ldc, tri,
+            sym != 0));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;
 }

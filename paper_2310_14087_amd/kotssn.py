@@ -86,7 +86,7 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
         "kot_ssn_direction": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp, P(d)]),
         "kot_eg_step": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp]),
         "kot_cholesky": (i, [vp, i, vp, d, vp, vp]),
-        "kot_gemm": (i, [vp, i, i, i, i, i, d, vp, i, vp, vp, i, d, vp, i]),
+        "kot_gemm": (i, [vp, i, i, i, i, i, d, vp, i, vp, vp, i, d, vp, i, i, i]),
         "kot_profile": (i, [vp, i, vp, i]),
         "kot_mlp_params": (i, [i, i]),
         "kot_features": (i, [vp, i, vp, vp, vp, vp, d, P(KotParams), vp]),
@@ -388,7 +388,7 @@ class Context:
         return {c: dict(launches=int(buf[4 * i]), ms=buf[4 * i + 1], flops=buf[4 * i + 2], bytes=buf[4 * i + 3])
                 for i, c in enumerate(self.PROFILE_CLASSES)}
 
-    def gemm(self, A, B, transa=False, transb=False, s=None, alpha=1.0, beta=0.0, Cm=None):
+    def gemm(self, A, B, transa=False, transb=False, s=None, alpha=1.0, beta=0.0, Cm=None, tri=0, sym=False):
         import torch
         m = A.shape[1] if transa else A.shape[0]
         k = A.shape[0] if transa else A.shape[1]
@@ -396,5 +396,6 @@ class Context:
         if Cm is None:
             Cm = torch.zeros((m, n), device=A.device, dtype=torch.float64)
         self._check(self.lib.kot_gemm(self.h, int(transa), int(transb), m, n, k, float(alpha), _ptr(A), A.shape[1],
-                                      _ptr(s), _ptr(B), B.shape[1], float(beta), _ptr(Cm), Cm.shape[1]))
+                                      _ptr(s), _ptr(B), B.shape[1], float(beta), _ptr(Cm), Cm.shape[1], int(tri),
+                                      int(bool(sym))))
         return Cm

@@ -43,6 +43,45 @@ def test_gemm_f64(gpu_ctx, m, n, k, ta, tb, scaled):
     np.testing.assert_allclose(_n(out), ref, rtol=1e-12, atol=1e-12 * k)
 
 
+@pytest.mark.parametrize("l", [33, 64, 257, 1000])
+@pytest.mark.parametrize("mode", ["phi_star", "xr", "ptr", "sym_beta", "proj"])
+def test_gemm_f64_modes(gpu_ctx, l, mode):
+    """The solver's product modes against numpy: zero triangles of R skipped (tri), symmetric results from the
+    lower tiles mirrored (sym), with the work lists and split-K of the large shapes."""
+    _case(f"kot_gemm mode={mode} l={l}")
+    rng = np.random.default_rng(l * 7 + len(mode))
+    R = np.triu(rng.standard_normal((l, l)))
+    g = rng.standard_normal(l)
+    X = rng.standard_normal((l, l))
+    X = X + X.T
+    a = max(1, l // 3)
+    P = rng.standard_normal((l, a))
+    if mode == "phi_star":      # R diag(g) R^T: op(A) upper, op(B) lower, symmetric
+        ref = (R * g) @ R.T
+        out = gpu_ctx.gemm(_t(R), _t(R), transb=True, s=_t(g), tri=1 | 8, sym=True)
+    elif mode == "xr":          # X R with R upper
+        ref = X @ R
+        out = gpu_ctx.gemm(_t(X), _t(R), tri=4)
+    elif mode == "ptr":         # P^T R (square P) with R upper
+        Pq = rng.standard_normal((l, l))
+        ref = Pq.T @ R
+        out = gpu_ctx.gemm(_t(Pq), _t(R), transa=True, tri=4)
+    elif mode == "sym_beta":    # alpha Y^T Y + beta C, C symmetric
+        Y = rng.standard_normal((l, l))
+        C0 = rng.standard_normal((l, l))
+        C0 = C0 + C0.T
+        ref = 0.5 * Y.T @ Y - 2.0 * C0
+        out = gpu_ctx.gemm(_t(Y), _t(Y), transa=True, alpha=0.5, beta=-2.0, Cm=_t(C0), sym=True)
+    else:                       # P diag(w) P^T, inner size a
+        w = rng.standard_normal(a)
+        ref = (P * w) @ P.T
+        out = gpu_ctx.gemm(_t(P), _t(P), transb=True, s=_t(w), sym=True)
+    o = _n(out)
+    np.testing.assert_allclose(o, ref, rtol=1e-12, atol=1e-12 * l * max(1.0, np.abs(ref).max()))
+    if mode in ("phi_star", "sym_beta", "proj"):  # mirrored tiles exact; diagonal tiles up to rounding
+        np.testing.assert_allclose(o, o.T, rtol=0, atol=1e-13 * l * max(1.0, np.abs(ref).max()))
+
+
 @pytest.mark.parametrize("name,l,n", [("tiny", None, None), ("gauss500", 120, 400), ("mix1000", 200, 700),
                                       ("mix256", 97, 300)])
 def test_setup(gpu_ctx, name, l, n):
