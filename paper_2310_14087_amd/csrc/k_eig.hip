@@ -576,12 +576,12 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   double* V = tmp + (long long)l * l;
   const long long nn = (long long)l * l;
   const int eb = (int)((nn + 255) / 256);
-  // ascending eigenvalues from w->dg and the columns of V permuted to match into P
-  auto finish = [&]() -> hipError_t {
+  // ascending eigenvalues from w->dg and the columns of src (the basis) permuted to match into P
+  auto finish = [&](const double* src) -> hipError_t {
     if (l > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 15) / 16), dim3(256), 0, st, l, w->dg, wv, w->perm);
     KOT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, V, w->perm, P);
+    hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, src, w->perm, P);
     return hipGetLastError();
   };
   if (P0) {
@@ -604,11 +604,11 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
         sp += w->wh[2 * l + r];
       }
       if (std::sqrt(so) <= tol * std::sqrt(sa)) {
-        KOT_HIP_TRY(vec_copy((int)nn, P0, V, st));
+        if (P0 == P) KOT_HIP_TRY(vec_copy((int)nn, P0, V, st));  // the permutation cannot run in place
         *sweeps = 0;
         *rel_off = (sa > 0.0) ? std::sqrt(so) / std::sqrt(sa) : 0.0;
         if (npos) *npos = (int)sp;
-        return finish();
+        return finish(P0 == P ? V : P0);
       }
     }
     g.transa = 1; g.A = P0; g.B = V; g.C = A;
@@ -697,7 +697,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   *sweeps = s;
   *rel_off = (all > 0.0) ? off / all : 0.0;
   if (npos) *npos = pos;
-  return finish();
+  return finish(V);
 }
 
 }  // namespace kot

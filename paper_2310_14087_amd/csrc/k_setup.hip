@@ -418,19 +418,22 @@ __global__ __launch_bounds__(64) void chol_step_kernel(int l, int k0, int nb, in
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // (block rb = 0, cb = 1 lies above the diagonal of the diagonal block: not needed)
 #pragma unroll
     for (int ks = 0; ks < CB / 4; ++ks)
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
-          acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[rb][ks], f[cb][ks], acc[rb][cb], 0, 0, 0);
+          if (rb > 0 || cb == 0)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[rb][ks], f[cb][ks], acc[rb][cb], 0, 0, 0);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb)
+        if (rb > 0 || cb == 0)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) S[rb * 16 + k4 + 4 * v][CB + cb * 16 + r16] -= acc[rb][cb][v];
+          for (int v = 0; v < 4; ++v) S[rb * 16 + k4 + 4 * v][CB + cb * 16 + r16] -= acc[rb][cb][v];
     __syncthreads();
   }
   const int ca = kp >= 0 ? CB : 0;  // column of this panel inside the staged window
