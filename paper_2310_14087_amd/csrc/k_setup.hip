@@ -7,22 +7,52 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Q = K_X + K_Y, K = K_X o K_Y (the Gaussian on the concatenated point), one thread per entry.
-__global__ __launch_bounds__(256) void gram_kernel(int l, int d, const double* __restrict__ xf, const double* __restrict__ yf,
-                                                    double inv2s2, double* __restrict__ Q, double* __restrict__ K) {
-  const int j = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
-  if (i >= l || j >= l) return;
-  double dx = 0.0, dy = 0.0;
-  for (int k = 0; k < d; ++k) {
-    const double a = xf[(long long)i * d + k] - xf[(long long)j * d + k];
-    const double b = yf[(long long)i * d + k] - yf[(long long)j * d + k];
-    dx += a * a;
-    dy += b * b;
+// Q = K_X + K_Y, K = K_X o K_Y (the Gaussian on the concatenated point) on one 32 x 32 tile pair (bi <= bj) per
+// workgroup: both results are symmetric, so each pair of exponentials is evaluated once and the tile of the
+// lower triangle goes out transposed through LDS as row segments ((a - b)^2 = (b - a)^2 exactly, so the
+// mirrored entry is the one a direct evaluation would give).
+__global__ __launch_bounds__(256) void gram_sym_kernel(int l, int d, const double* __restrict__ xf,
+                                                       const double* __restrict__ yf, double inv2s2,
+                                                       double* __restrict__ Q, double* __restrict__ K) {
+  __shared__ double tq[32][33], tk[32][33];
+  const int nt = (l + 31) / 32;
+  int u = blockIdx.x, bi = 0;
+  while (u >= nt - bi) {  // row bi of the upper triangle holds nt - bi tiles
+    u -= nt - bi;
+    ++bi;
   }
-  const double kx = exp(-dx * inv2s2), ky = exp(-dy * inv2s2);
-  Q[(long long)i * l + j] = kx + ky;
-  K[(long long)i * l + j] = kx * ky;
+  const int bj = bi + u;
+  const int t = threadIdx.x, tc = t & 31, tr = t >> 5;
+  const int j = bj * 32 + tc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ii = tr + 8 * q, i = bi * 32 + ii;
+    if (i < l && j < l) {
+      double dx = 0.0, dy = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const double a = xf[(long long)i * d + k] - xf[(long long)j * d + k];
+        const double b = yf[(long long)i * d + k] - yf[(long long)j * d + k];
+        dx += a * a;
+        dy += b * b;
+      }
+      const double kx = exp(-dx * inv2s2), ky = exp(-dy * inv2s2);
+      Q[(long long)i * l + j] = kx + ky;
+      K[(long long)i * l + j] = kx * ky;
+      tq[ii][tc] = kx + ky;
+      tk[ii][tc] = kx * ky;
+    }
+  }
+  if (bi == bj) return;  // uniform per workgroup
+  __syncthreads();
+  const int i2 = bi * 32 + tc;  // column of the transposed write
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int jj = tr + 8 * q, j2 = bj * 32 + jj;
+    if (i2 < l && j2 < l) {
+      Q[(long long)j2 * l + i2] = tq[tc][jj];
+      K[(long long)j2 * l + i2] = tk[tc][jj];
+    }
+  }
 }
 
 // w[i] = (1/n) sum_j exp(-|s_j - p_i|^2 inv2s2): 4 points per workgroup, samples strided over 256 threads,
@@ -606,8 +636,9 @@ hipError_t trtri_upper(int l, const double* R, double* Y, double* T, hipStream_t
 
 hipError_t gram_build(int l, int d, const double* xf, const double* yf, double sigma, double* Q, double* K,
                       hipStream_t st) {
-  dim3 grid((l + 15) / 16, (l + 15) / 16);
-  hipLaunchKernelGGL(gram_kernel, grid, dim3(256), 0, st, l, d, xf, yf, 1.0 / (2.0 * sigma * sigma), Q, K);
+  const int nt = (l + 31) / 32;
+  hipLaunchKernelGGL(gram_sym_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, l, d, xf, yf,
+                     1.0 / (2.0 * sigma * sigma), Q, K);
   return hipGetLastError();
 }
 
