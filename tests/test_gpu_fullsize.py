@@ -1,0 +1,93 @@
+"""Parity at the bench's full size: mix1000 (l = 1000 filling points, n = 5000 samples per side, d = 10), in the
+configurations bench.py times (the plain FP64 arm, and the accelerated arm: learned start, split-BF16 chain,
+Jacobi CG, the extragradient branch on its own streams).
+
+Setup outputs are checked on sampled entries the oracle evaluates one by one; the solves against the oracle's
+own full solve of the same instance and against properties the oracle evaluates on the GPU's output (the
+residual of Eq. 4.2, the estimate, the feasibility of Eq. 3.4's constraint)."""
+import numpy as np
+import pytest
+
+from oracle import kot_oracle as ko
+from paper_2310_14087_amd.inputs import make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def full():
+    p = make_problem("mix1000", 0)
+    assert (p.l, p.n_src, p.d) == (1000, 5000, 10)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=p.tol))
+    assert ref["status"] == "converged"
+    return p, core, ref
+
+
+def test_full_setup_sampled_entries(gpu_ctx, full):
+    from paper_2310_14087_amd import kotssn
+    p, core, _ = full
+    print("[case] kot_setup mix1000 full size, sampled entries", flush=True)
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2)
+    Q, z, R, wsum, q2 = gpu_ctx.setup(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm)
+    Q, z, R, wsum = _n(Q), _n(z), _n(R), _n(wsum)
+    rng = np.random.default_rng(0)
+    inv = 1.0 / (2.0 * p.sigma ** 2)
+    for i, j in rng.integers(0, p.l, size=(200, 2)):
+        kx = np.exp(-np.sum((p.xf[i] - p.xf[j]) ** 2) * inv)
+        ky = np.exp(-np.sum((p.yf[i] - p.yf[j]) ** 2) * inv)
+        assert abs(Q[i, j] - (kx + ky)) <= 1e-14
+    for i in rng.integers(0, p.l, size=40):
+        wmu = np.mean(np.exp(-np.sum((p.xs - p.xf[i]) ** 2, axis=1) * inv))
+        wnu = np.mean(np.exp(-np.sum((p.ys - p.yf[i]) ** 2, axis=1) * inv))
+        assert abs(wsum[i] - (wmu + wnu)) <= 1e-12 * abs(wmu + wnu) + 1e-14
+        zi = wmu + wnu - p.lam2 * np.sum((p.xf[i] - p.yf[i]) ** 2)
+        assert abs(z[i] - zi) <= 1e-12 * abs(zi) + 1e-14
+    assert abs(q2 - core.q2) <= 1e-11 * abs(core.q2)
+    # the factor: R^T R = K + eps I on sampled entries, R upper triangular
+    K = core.R.T @ core.R
+    for i, j in rng.integers(0, p.l, size=(200, 2)):
+        assert abs(R[:, i] @ R[:, j] - K[i, j]) <= 1e-12
+    assert np.all(np.tril(R, -1) == 0.0)
+
+
+@pytest.mark.parametrize("arm", ["fp64", "mixed"])
+def test_full_solve(gpu_ctx, full, arm):
+    from paper_2310_14087_amd import kotssn, warmstart
+    import torch
+    p, core, ref = full
+    print(f"[case] kot_solve mix1000 full size arm={arm}", flush=True)
+    kw = dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+    theta = None
+    if arm == "mixed":
+        th, F, H, _ = warmstart.load()
+        theta = torch.from_numpy(th).to("cuda:0")
+        kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta.data_ptr(), precision=kotssn.KOT_MIXED_BF16X3,
+                  precond=kotssn.KOT_PRECOND_JACOBI)
+    prm = kotssn.default_params(**kw)
+    gamma, X, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, want_X=True)
+    assert r.status == kotssn.KOT_OK and r.residual <= p.tol
+    if arm == "fp64":
+        assert r.iters == ref["iters"]
+    g, Xn = _n(gamma), _n(X)
+    r1, r2, rn, (s, _) = ko.residual(core, g, Xn)
+    assert rn <= 1.01 * p.tol
+    assert abs(rn - r.residual) <= 1e-9
+    assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
+    assert abs(r.ot - ko.ot_estimate(core, g)) <= 1e-12 * abs(r.ot)
+    if arm == "fp64":  # the oracle's own trajectory: agreement to rounding
+        np.testing.assert_allclose(g, ref["gamma"], atol=1e-5 * np.abs(ref["gamma"]).max())
+    else:  # another path to |R| <= tol: the two approximate minimizers agree to the tolerance
+        np.testing.assert_allclose(g, ref["gamma"], rtol=0, atol=p.tol)
+    # Eq. 3.4's constraint R diag(gamma) R^T + lambda1 I >= 0 holds up to the residual
+    S = core.R @ np.diag(g) @ core.R.T + p.lam1 * np.eye(p.l)
+    assert np.linalg.eigvalsh(0.5 * (S + S.T)).min() >= -10 * p.tol
