@@ -197,7 +197,7 @@ def batch_bench(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=24)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mix1000",
                     help="mix1000 (the metric line) or sweep (Section 5's synthetic sweep, its own JSON line)")
