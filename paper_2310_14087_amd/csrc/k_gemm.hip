@@ -555,7 +555,7 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
       }
     } else if (target > 0 && computed < target && g.k >= 128) {
       splits = (target + computed - 1) / computed;
-      splits = std::min(splits, std::min(8, g.k / 64));
+      splits = std::min(splits, std::min(16, g.k / 64));
     }
   }
   if (splits > 1) {
