@@ -207,6 +207,35 @@ __global__ __launch_bounds__(64 * (4 / FM) * (4 / FN)) void gemm_f64_kernel(Gemm
   }
   // ---- epilogue ----
   const int M = g.m, N = g.n;
+  if (g.D) {
+    // column-dot mode: sum_i D_ij (alpha acc)_ij over this tile's rows, per column, into part[(tile row, split)]:
+    // over each lane's rows, then the four lanes of a column (k4), then the row-group waves in order
+    __shared__ double dsum[4 / FM][BN];
+    double cs[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      cs[j] = 0.0;
+      const int col = n0 + wn * 16 * FN + j * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = m0 + wm * 16 * FM + i * 16 + k4 + 4 * v;
+          if (row < M && col < N) cs[j] += g.D[(long long)row * g.ldd + col] * (g.alpha * acc[i][j][v]);
+        }
+      cs[j] += __shfl_xor(cs[j], 16);
+      cs[j] += __shfl_xor(cs[j], 32);
+      if (k4 == 0) dsum[wm][wn * 16 * FN + j * 16 + r16] = cs[j];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < BN && n0 + (int)threadIdx.x < N) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4 / FM; ++w) s += dsum[w][threadIdx.x];
+      part[((long long)(m0 / BM) * splits + sp) * N + n0 + threadIdx.x] = s;
+    }
+    return;
+  }
   // strictly lower tile of a symmetric result: the transpose goes out through LDS, row segments again
   const bool mir = splits == 1 && g.mirror && n0 < m0;
   double* Tt = &As2[0][0];  // 64 x 65 staging tile (the K loop's buffers are free once every wave is past it)
@@ -299,6 +328,24 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int spli
   }
 }
 
+// Column-dot mode's sum: y_j = dalpha sum over tile rows and the splits that met each tile's K range (fixed
+// order) of part + dbeta y_j.
+__global__ __launch_bounds__(256) void coldot_final_kernel(GemmArgs g, int splits, int kchunk,
+                                                           const double* __restrict__ part) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= g.n) return;
+  const int n0 = (col / BN) * BN, mt = (g.m + BM - 1) / BM;
+  double s = 0.0;
+  for (int t = 0; t < mt; ++t) {
+    int klo, khi;
+    tri_k_range(g.tri, g.k, t * BM, n0, klo, khi);
+    for (int sp = 0; sp < splits; ++sp)
+      if (max(sp * kchunk, klo) < min(min(g.k, sp * kchunk + kchunk), khi))
+        s += part[((long long)t * splits + sp) * g.n + col];
+  }
+  g.y[col] = (g.dbeta == 0.0) ? g.dalpha * s : g.dalpha * s + g.dbeta * g.y[col];
+}
+
 // y[r] = alpha * sum_k A[r][k] s[k] x[k] + beta * y[r]: one wavefront per row (loads along k), fixed-order
 // lane partials and a butterfly reduction, so the result does not depend on the launch.
 __global__ __launch_bounds__(256) void gemv_f64_kernel(int m, int k, double alpha, const double* __restrict__ A, int lda,
@@ -308,12 +355,22 @@ __global__ __launch_bounds__(256) void gemv_f64_kernel(int m, int k, double alph
   const int lane = threadIdx.x & 63;
   if (row >= m) return;  // uniform per wavefront
   const double* __restrict__ a = A + (long long)row * lda;
-  double acc = 0.0;
-  if (s) {
-    for (int c = lane; c < k; c += 64) acc += a[c] * (s[c] * x[(long long)c * incx]);
-  } else {
-    for (int c = lane; c < k; c += 64) acc += a[c] * x[(long long)c * incx];
+  // four independent lane partials (four loads of the row in flight), combined in a fixed order
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  int c = lane;
+  for (; c + 192 < k; c += 256) {
+    double av[4], xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = a[c + 64 * u];
+      const long long cx = (long long)(c + 64 * u);
+      xv[u] = s ? s[cx] * x[cx * incx] : x[cx * incx];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] += av[u] * xv[u];
   }
+  for (; c < k; c += 64) q[0] += a[c] * (s ? s[c] * x[(long long)c * incx] : x[(long long)c * incx]);
+  double acc = (q[0] + q[1]) + (q[2] + q[3]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) {
@@ -505,7 +562,8 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
     // handled by a k=1 launch with alpha = 0 would read A; do it explicitly instead
     return hipErrorInvalidValue;
   }
-  if (g.n == 1 && g.batch == 1 && !g.transa) {
+  if (g.D && (g.batch != 1 || g.lower || g.mirror || !g.y)) return hipErrorInvalidValue;
+  if (g.n == 1 && g.batch == 1 && !g.transa && !g.D) {
     // x[c] = op(B)[c][0]: B[c*ldb] (k x 1) or B[c] (1 x k, transposed)
     const int incx = g.transb ? 1 : g.ldb;
     Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
@@ -584,7 +642,9 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
   // work of the product (2mnk flops, less the skipped tiles and K ranges); bytes = each operand and C once
   if (pf) pf->begin(st, PROF_GEMM_F64, gemm_work_flops(g),
                     8.0 * g.batch * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
-  double* part = splits > 1 ? g_gemm_ws : nullptr;
+  if (g.D && (!g_gemm_ws || (size_t)((g.m + BM - 1) / BM) * splits * g.n > g_gemm_ws_cap))
+    return hipErrorInvalidValue;
+  double* part = (splits > 1 || g.D) ? g_gemm_ws : nullptr;
   bool launched = false;
 #define KOT_GEMM_CASE(TA, TB, SC_, FM, FN)                                                                       \
   if (!launched && g.transa == TA && g.transb == TB && sc == SC_ && waves == (4 / FM) * (4 / FN)) {               \
@@ -600,7 +660,10 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
 #undef KOT_GEMM_WAVES
 #undef KOT_GEMM_CASE
   if (!launched) return hipErrorInvalidValue;
-  if (splits > 1) {
+  if (g.D) {
+    hipLaunchKernelGGL(coldot_final_kernel, dim3((g.n + 255) / 256), dim3(256), 0, st, g, splits, kchunk,
+                       (const double*)part);
+  } else if (splits > 1) {
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((g.n + BN - 1) / BN, (g.m + RS - 1) / RS, g.batch), dim3(256), 0,
                        st, g, splits, kchunk, (const double*)part);
   }

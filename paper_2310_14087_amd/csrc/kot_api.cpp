@@ -229,6 +229,21 @@ hipError_t mm(hipStream_t st, int ta, int tb, int m, int n, int k, double alpha,
 
 constexpr int TRI_A_UPPER = 1, TRI_A_LOWER = 2, TRI_B_UPPER = 4, TRI_B_LOWER = 8;
 
+// y_j = dalpha sum_i D_ij (alpha op(A) diag(s) op(B))_ij + dbeta y_j, the product never written out (its column
+// dots against D are taken in the GEMM's epilogue).  D is m x n with leading dimension ldd.
+hipError_t mm_coldot(hipStream_t st, int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda,
+                     const double* s, const double* B, int ldb, int tri, const double* D, int ldd, double dalpha,
+                     double dbeta, double* y) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (k <= 0) return hipErrorInvalidValue;
+  GemmArgs g{};
+  g.transa = ta; g.transb = tb; g.m = m; g.n = n; g.k = k; g.alpha = alpha; g.beta = 0.0;
+  g.A = A; g.lda = lda; g.s = s; g.B = B; g.ldb = ldb; g.C = nullptr; g.ldc = n; g.batch = 1;
+  g.tri = tri;
+  g.D = D; g.ldd = ldd; g.y = y; g.dalpha = dalpha; g.dbeta = dbeta;
+  return gemm_f64(g, st);
+}
+
 // out = Phi*(g) = R diag(g) R^T  (R upper: the k-th term touches only rows and columns <= k)
 kot_status phi_star(kot_ctx* ctx, const CoreView& cv, const double* g, double* out) {
   const int l = cv.l;
@@ -236,21 +251,20 @@ kot_status phi_star(kot_ctx* ctx, const CoreView& cv, const double* g, double* o
   return KOT_OK;
 }
 
-// y = alpha*Phi(X) + beta*y, Phi(X)_i = R[:,i]^T X R[:,i]; uses tmp (l x l)
-kot_status phi_op(kot_ctx* ctx, const CoreView& cv, const double* X, double alpha, double beta, double* y, double* tmp) {
+// y = alpha*Phi(X) + beta*y, Phi(X)_i = R[:,i]^T X R[:,i] = sum_r R_ri (X R)_ri (X R never written out)
+kot_status phi_op(kot_ctx* ctx, const CoreView& cv, const double* X, double alpha, double beta, double* y) {
   const int l = cv.l;
-  HIPCHK(mm(ctx->stream, 0, 0, l, l, l, 1.0, X, l, nullptr, cv.R, l, 0.0, tmp, l, TRI_B_UPPER));
-  HIPCHK(diag_dot(0, l, l, alpha, cv.R, l, tmp, l, beta, y, ctx->part, ctx->stream));
+  HIPCHK(mm_coldot(ctx->stream, 0, 0, l, l, l, 1.0, X, l, nullptr, cv.R, l, TRI_B_UPPER, cv.R, l, alpha, beta, y));
   return KOT_OK;
 }
 
 // r1 = (Q g - z)/(2 lam2) - Phi(X)
-kot_status r1_op(kot_ctx* ctx, const CoreView& cv, const double* g, const double* X, double* r1, double* tmp) {
+kot_status r1_op(kot_ctx* ctx, const CoreView& cv, const double* g, const double* X, double* r1) {
   const int l = cv.l;
   // r1 = Q g  (as an l x 1 product)
   HIPCHK(mm(ctx->stream, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, g, 1, 0.0, r1, 1));
   HIPCHK(vec_axpby(l, -1.0 / (2.0 * cv.lam2), cv.z, 1.0 / (2.0 * cv.lam2), r1, ctx->stream));
-  KCHK(phi_op(ctx, cv, X, -1.0, 1.0, r1, tmp));
+  KCHK(phi_op(ctx, cv, X, -1.0, 1.0, r1));
   return KOT_OK;
 }
 
@@ -300,7 +314,7 @@ kot_status residual_state(kot_ctx* ctx, const CoreView& cv, State& s, const doub
   KCHK(eig_run(ctx, l, ctx->Z, P0, s.P, s.s, p, sweeps_acc, &s.a));
   KCHK(proj_from_eig(ctx, l, ctx->Z, s.P, s.s, s.a, ctx->T1));
   HIPCHK(mat_sub(l * l, s.X, ctx->T1, s.r2, st));
-  KCHK(r1_op(ctx, cv, s.g, s.X, s.r1, ctx->T2));
+  KCHK(r1_op(ctx, cv, s.g, s.X, s.r1));
   HIPCHK(dot(l, s.r1, s.r1, ctx->dsc + slot, ctx->part, st));
   HIPCHK(dot2((long long)l * l, s.r2, s.r2, ctx->dsc + slot + 1, nullptr, nullptr, nullptr, ctx->part, st));
   s.has_eig = true;
@@ -369,15 +383,12 @@ kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const
   if (tp.m == 0) return KOT_OK;
   const double* Bs = ctx->Bm + (long long)tp.r0 * l;
   double* C = ctx->T3;
-  double* E = ctx->T4;
   // C = B_set diag(v) B^T   (m x l)
   HIPCHK(mm(st, 0, 1, tp.m, l, l, 1.0, Bs, l, v, ctx->Bm, l, 0.0, C, l));
   // H = [Psi o C] with the cross block doubled
   HIPCHK(psi_hadamard(l, tp.a, tp.r0, tp.m, tp.mu, tp.w, C, l, tp.comp, 1.0, 2.0, st));
-  // E = H B
-  HIPCHK(mm(st, 0, 0, tp.m, l, l, 1.0, C, l, nullptr, ctx->Bm, l, 0.0, E, l));
-  // y_i += (+/-) sum_{r in set} B_ri E_ri
-  HIPCHK(diag_dot(0, tp.m, l, tp.comp ? -1.0 : 1.0, Bs, l, E, l, 1.0, y, ctx->part, st));
+  // y_i += (+/-) sum_{r in set} B_ri E_ri with E = H B (E's column dots taken in the product's epilogue)
+  HIPCHK(mm_coldot(st, 0, 0, tp.m, l, l, 1.0, C, l, nullptr, ctx->Bm, l, 0, Bs, l, tp.comp ? -1.0 : 1.0, 1.0, y));
   return KOT_OK;
 }
 
@@ -385,7 +396,7 @@ kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const
 // of M = Q/(2 lam2) + mu I + Phi T Phi* is M_ii = Q_ii/(2 lam2) + mu + [(B o B)^T Psi (B o B)]_ii (B = P^T R),
 // formed with the matvec's eigen-row chain: E = H (B o B), H the chain's Psi weights (cross block doubled),
 // then +/- sum over the chain's rows r of (B o B)_ri E_ri, and (1/mu) (K o K)_ii in the complement form.
-// dinv receives 1 / M_ii.  Uses T1, T3, T4.
+// dinv receives 1 / M_ii.  Uses T1 and T3.
 kot_status schur_dinv(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, double* dinv) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
@@ -393,12 +404,11 @@ kot_status schur_dinv(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, double*
   if (tp.m > 0) {
     double* D2 = ctx->T1;
     double* H = ctx->T3;
-    double* E = ctx->T4;
     HIPCHK(hadamard_square(l * l, ctx->Bm, D2, st));
     HIPCHK(mat_fill(tp.m, l, 1.0, H, l, st));
     HIPCHK(psi_hadamard(l, tp.a, tp.r0, tp.m, tp.mu, tp.w, H, l, tp.comp, 1.0, 2.0, st));
-    HIPCHK(mm(st, 0, 0, tp.m, l, l, 1.0, H, l, nullptr, D2, l, 0.0, E, l));
-    HIPCHK(diag_dot(0, tp.m, l, tp.comp ? -1.0 : 1.0, D2 + (long long)tp.r0 * l, l, E, l, 1.0, dinv, ctx->part, st));
+    HIPCHK(mm_coldot(st, 0, 0, tp.m, l, l, 1.0, H, l, nullptr, D2, l, 0, D2 + (long long)tp.r0 * l, l,
+                     tp.comp ? -1.0 : 1.0, 1.0, dinv));
   }
   HIPCHK(vec_recip(l, dinv, dinv, st));
   return KOT_OK;
@@ -445,7 +455,7 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   KCHK(t_apply(ctx, tp, s.r2, ctx->T1));
   HIPCHK(vec_lincomb(l * l, 1.0, s.r2, 1.0, ctx->T1, ctx->Mr, st));
   HIPCHK(vec_copy(l, s.r1, ctx->a1, st));
-  KCHK(phi_op(ctx, cv, ctx->Mr, -1.0 / (mu + 1.0), -1.0, ctx->a1, ctx->T2));
+  KCHK(phi_op(ctx, cv, ctx->Mr, -1.0 / (mu + 1.0), -1.0, ctx->a1));
   const double* dinv = nullptr;
   if (p->precond == KOT_PRECOND_JACOBI) {
     KCHK(schur_dinv(ctx, cv, tp, ctx->cdinv));
@@ -558,7 +568,7 @@ kot_status eg_step_impl(kot_ctx* ctx, const CoreView& cv, const double* g, const
   hipStream_t st = ctx->stream;
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, r1, ctx->gh, st));
   KCHK(eg_proj(ctx, cv, g, X, eta, ctx->Pe1, ctx->s_e1, warm, ctx->Xh, p, sweeps_acc));
-  KCHK(r1_op(ctx, cv, ctx->gh, ctx->Xh, ctx->r1h, ctx->T1));
+  KCHK(r1_op(ctx, cv, ctx->gh, ctx->Xh, ctx->r1h));
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, ctx->r1h, gn, st));
   KCHK(eg_proj(ctx, cv, ctx->gh, X, eta, ctx->Pe2, ctx->s_e2, warm, Xn, p, sweeps_acc));
   return KOT_OK;
@@ -991,7 +1001,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
         kot_ctx* c = ctx->side->c;
         const int n = cv.l;
         const kot_status r0 = eg_proj(c, cv, Vs->g, Vs->X, eta, c->Pe1, c->s_e1, warm_v, c->Xh, p, &side_sweeps);
-        kot_status r1 = r0 < 0 ? r0 : r1_op(c, cv, ctx->gh, c->Xh, c->r1h, c->T1);
+        kot_status r1 = r0 < 0 ? r0 : r1_op(c, cv, ctx->gh, c->Xh, c->r1h);
         if (r1 >= 0 && vec_lincomb(n, 1.0, Vs->g, -eta, c->r1h, H->g, c->stream) != hipSuccess)
           r1 = fail(c, KOT_ERR_HIP, "vec_lincomb");
         const kot_status r2 = runner_join(c, ctx->side2);  // Xn (joined even after a failure)
@@ -1399,7 +1409,7 @@ kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, co
   KCHK(check_upper(ctx, l, R));
   CoreView cv;
   cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
-  KCHK(r1_op(ctx, cv, gamma, X, ctx->vtmp, ctx->T2));
+  KCHK(r1_op(ctx, cv, gamma, X, ctx->vtmp));
   KCHK(eg_step_impl(ctx, cv, gamma, X, ctx->vtmp, eta, gamma_out, X_out, false, p, nullptr));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KOT_OK;

@@ -41,6 +41,10 @@ struct GemmArgs {
   double* C; int ldc; long long sC;
   int batch;
   int lower, mirror, tri;
+  // column-dot mode (D non-null, batch 1, no lower/mirror): instead of C, y_j = dalpha sum_i D_ij
+  // (alpha op(A) diag(s) op(B))_ij + dbeta y_j, D m x n with leading dimension ldd; C is not touched
+  const double* D = nullptr; int ldd = 0;
+  double* y = nullptr; double dalpha = 1.0, dbeta = 0.0;
 };
 // Reserves the current device's pool of GEMM work lists (once per device and process; call outside any solve).
 hipError_t gemm_reserve();
