@@ -328,22 +328,29 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int spli
   }
 }
 
-// Column-dot mode's sum: y_j = dalpha sum over tile rows and the splits that met each tile's K range (fixed
-// order) of part + dbeta y_j.
+// Column-dot mode's sum: y_j = dalpha sum over tile rows and the splits that met each tile's K range of part +
+// dbeta y_j.  64 columns per workgroup; the (tile row, split) terms of a column are dealt round-robin to four
+// thread groups and the four group sums added in order (a fixed order throughout).
 __global__ __launch_bounds__(256) void coldot_final_kernel(GemmArgs g, int splits, int kchunk,
                                                            const double* __restrict__ part) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= g.n) return;
-  const int n0 = (col / BN) * BN, mt = (g.m + BM - 1) / BM;
+  __shared__ double gs[4][64];
+  const int t = threadIdx.x, c = t & 63, grp = t >> 6;
+  const int col = blockIdx.x * 64 + c;
+  const int n0 = blockIdx.x * 64, mt = (g.m + BM - 1) / BM;
+  const int colc = min(col, g.n - 1);
   double s = 0.0;
-  for (int t = 0; t < mt; ++t) {
+  for (int q = grp; q < mt * splits; q += 4) {
+    const int tr = q / splits, sp = q - tr * splits;
     int klo, khi;
-    tri_k_range(g.tri, g.k, t * BM, n0, klo, khi);
-    for (int sp = 0; sp < splits; ++sp)
-      if (max(sp * kchunk, klo) < min(min(g.k, sp * kchunk + kchunk), khi))
-        s += part[((long long)t * splits + sp) * g.n + col];
+    tri_k_range(g.tri, g.k, tr * BM, n0, klo, khi);
+    if (max(sp * kchunk, klo) < min(min(g.k, sp * kchunk + kchunk), khi)) s += part[(long long)q * g.n + colc];
   }
-  g.y[col] = (g.dbeta == 0.0) ? g.dalpha * s : g.dalpha * s + g.dbeta * g.y[col];
+  gs[grp][c] = s;
+  __syncthreads();
+  if (grp == 0 && col < g.n) {
+    const double v = (gs[0][c] + gs[1][c]) + (gs[2][c] + gs[3][c]);
+    g.y[col] = (g.dbeta == 0.0) ? g.dalpha * v : g.dalpha * v + g.dbeta * g.y[col];
+  }
 }
 
 // y[r] = alpha * sum_k A[r][k] s[k] x[k] + beta * y[r]: one wavefront per row (loads along k), fixed-order
@@ -661,7 +668,7 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
 #undef KOT_GEMM_CASE
   if (!launched) return hipErrorInvalidValue;
   if (g.D) {
-    hipLaunchKernelGGL(coldot_final_kernel, dim3((g.n + 255) / 256), dim3(256), 0, st, g, splits, kchunk,
+    hipLaunchKernelGGL(coldot_final_kernel, dim3((g.n + 63) / 64), dim3(256), 0, st, g, splits, kchunk,
                        (const double*)part);
   } else if (splits > 1) {
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((g.n + BN - 1) / BN, (g.m + RS - 1) / RS, g.batch), dim3(256), 0,
