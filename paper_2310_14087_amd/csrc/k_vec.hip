@@ -89,6 +89,60 @@ __global__ __launch_bounds__(256) void dot2_final_kernel(int nb, const double* _
     if (o2) o2[0] = red[1][0];
   }
 }
+// out = X - Y with the block partials of |out|^2 (the layout of dot2_part's first sum), in one pass.
+__global__ __launch_bounds__(256) void sub_sq_part_kernel(long long n, const double* __restrict__ X,
+                                                          const double* __restrict__ Y, double* __restrict__ out,
+                                                          double* __restrict__ part) {
+  __shared__ double red[256];
+  double a = 0.0;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i0 = (long long)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    double u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long i = i0 + q * stride;
+      u[q] = 0.0;
+      if (i < n) {
+        const double d = X[i] - Y[i];
+        out[i] = d;
+        u[q] = d * d;
+      }
+    }
+    a += (u[0] + u[1]) + (u[2] + u[3]);
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = red[0]; part[2 * blockIdx.x + 1] = 0.0; }
+}
+
+// o1 = |r1|^2 (length l) and o2 = the sum of the nb first-sum partials, fixed order throughout.
+__global__ __launch_bounds__(256) void resid_final_kernel(int nb, const double* __restrict__ part, int l,
+                                                          const double* __restrict__ r1, double* __restrict__ o1,
+                                                          double* __restrict__ o2) {
+  __shared__ double red[2][256];
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 768 < l; i += 1024)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] += r1[i + 256 * u] * r1[i + 256 * u];
+  for (; i < l; i += 256) q[0] += r1[i] * r1[i];
+  red[0][threadIdx.x] = (q[0] + q[1]) + (q[2] + q[3]);
+  red[1][threadIdx.x] = (threadIdx.x < nb) ? part[2 * threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) { red[0][threadIdx.x] += red[0][threadIdx.x + h]; red[1][threadIdx.x] += red[1][threadIdx.x + h]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    o1[0] = red[0][0];
+    o2[0] = red[1][0];
+  }
+}
+
 // Short vectors (n <= kSmallDot): one workgroup, eight loads in flight per thread, fixed order.
 constexpr int kSmallDot = 8192;
 __global__ __launch_bounds__(1024) void dot2_small_kernel(int n, const double* __restrict__ x1, const double* __restrict__ y1,
@@ -616,6 +670,18 @@ hipError_t dot2(long long n, const double* x1, const double* y1, double* o1, con
   hipLaunchKernelGGL(dot2_part_kernel, dim3((unsigned)nb), dim3(256), 0, st, n, x1, y1, x2, y2, part);
   KOT_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(dot2_final_kernel, dim3(1), dim3(256), 0, st, (int)nb, part, o1, o2);
+  return hipGetLastError();
+}
+int mat_sub_sq(long long n, const double* X, const double* Y, double* out, double* part, hipStream_t st) {
+  long long nb = (n + 4 * 256 - 1) / (4 * 256);
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(sub_sq_part_kernel, dim3((unsigned)nb), dim3(256), 0, st, n, X, Y, out, part);
+  return hipGetLastError() == hipSuccess ? (int)nb : -1;
+}
+hipError_t resid_norms_final(int nb, const double* part, int l, const double* r1, double* o1, double* o2,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(resid_final_kernel, dim3(1), dim3(256), 0, st, nb, part, l, r1, o1, o2);
   return hipGetLastError();
 }
 hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st) {

@@ -313,10 +313,11 @@ kot_status residual_state(kot_ctx* ctx, const CoreView& cv, State& s, const doub
   HIPCHK(form_z(l, s.X, 1.0, ctx->T1, -cv.lam1, ctx->Z, st));
   KCHK(eig_run(ctx, l, ctx->Z, P0, s.P, s.s, p, sweeps_acc, &s.a));
   KCHK(proj_from_eig(ctx, l, ctx->Z, s.P, s.s, s.a, ctx->T1));
-  HIPCHK(mat_sub(l * l, s.X, ctx->T1, s.r2, st));
+  // r2 = X - Pi(Z) with its squared norm's partials in the same pass; |r1|^2 and |r2|^2 land in (slot, slot + 1)
+  const int nb = mat_sub_sq((long long)l * l, s.X, ctx->T1, s.r2, ctx->part, st);
+  if (nb < 0) return fail(ctx, KOT_ERR_HIP, "mat_sub_sq: launch failed");
   KCHK(r1_op(ctx, cv, s.g, s.X, s.r1));
-  HIPCHK(dot(l, s.r1, s.r1, ctx->dsc + slot, ctx->part, st));
-  HIPCHK(dot2((long long)l * l, s.r2, s.r2, ctx->dsc + slot + 1, nullptr, nullptr, nullptr, ctx->part, st));
+  HIPCHK(resid_norms_final(nb, ctx->part, l, s.r1, ctx->dsc + slot, ctx->dsc + slot + 1, st));
   s.has_eig = true;
   if (!defer) {
     KCHK(sync_read(ctx));

@@ -110,6 +110,11 @@ hipError_t symmetrize(int l, double* Z, hipStream_t st);
 // two dot products (x2 null: one) in the same launches.
 constexpr int kRedBlocks = 256;
 hipError_t dot(int n, const double* x, const double* y, double* out, double* part, hipStream_t st);
+// out = X - Y (n entries) with the block partials of |out|^2 into part; returns the number of partials (< 0 on a
+// launch error).  resid_norms_final: o1 = |r1|^2 (length l), o2 = the partials' sum (one workgroup).
+int mat_sub_sq(long long n, const double* X, const double* Y, double* out, double* part, hipStream_t st);
+hipError_t resid_norms_final(int nb, const double* part, int l, const double* r1, double* o1, double* o2,
+                             hipStream_t st);
 hipError_t dot2(long long n, const double* x1, const double* y1, double* o1, const double* x2, const double* y2,
                 double* o2, double* part, hipStream_t st);
 // Z = (M + M^T)/2 + c I with M = X - a T (l x l; Z must not alias X or T)
