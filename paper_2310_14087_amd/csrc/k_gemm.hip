@@ -386,6 +386,47 @@ __global__ __launch_bounds__(256) void gemv_f64_kernel(int m, int k, double alph
   }
 }
 
+// y_r = a (Q v)_r + b (K2 v)_r + c v_r (K2 may be null): the Schur operator's dense part in one pass, one
+// wavefront per row, four partial sums per lane for each product, combined in a fixed order.
+__global__ __launch_bounds__(256) void gemv2_f64_kernel(int m, const double* __restrict__ Q, double a,
+                                                         const double* __restrict__ K2, double b,
+                                                         const double* __restrict__ v, double c,
+                                                         double* __restrict__ y) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= m) return;  // uniform per wavefront
+  const double* __restrict__ q = Q + (long long)row * m;
+  const double* __restrict__ k2 = K2 ? K2 + (long long)row * m : nullptr;
+  double p[4] = {0.0, 0.0, 0.0, 0.0}, r[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = lane;
+  for (; j + 192 < m; j += 256) {
+    double qv[4], kv[4], vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      qv[u] = q[j + 64 * u];
+      kv[u] = k2 ? k2[j + 64 * u] : 0.0;
+      vv[u] = v[j + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      p[u] += qv[u] * vv[u];
+      r[u] += kv[u] * vv[u];
+    }
+  }
+  for (; j < m; j += 64) {
+    p[0] += q[j] * v[j];
+    if (k2) r[0] += k2[j] * v[j];
+  }
+  double sq = (p[0] + p[1]) + (p[2] + p[3]);
+  double sk = (r[0] + r[1]) + (r[2] + r[3]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sq += __shfl_xor(sq, off);
+    sk += __shfl_xor(sk, off);
+  }
+  if (lane == 0) y[row] = a * sq + (K2 ? b * sk : 0.0) + c * v[row];
+}
+
 // Column dots: partial sums over kDiagParts row slabs, then a fixed-order sum -> deterministic.
 __global__ __launch_bounds__(256) void diag_dot_part(int r0, int r1, int n, const double* __restrict__ A, int lda,
                                                       const double* __restrict__ B, int ldb, double* __restrict__ part) {
@@ -675,6 +716,12 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
                        st, g, splits, kchunk, (const double*)part);
   }
   if (pf) pf->end(st);
+  return hipGetLastError();
+}
+
+hipError_t gemv2(int m, const double* Q, double a, const double* K2, double b, const double* v, double c, double* y,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(gemv2_f64_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, m, Q, a, K2, b, v, c, y);
   return hipGetLastError();
 }
 

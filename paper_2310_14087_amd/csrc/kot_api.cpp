@@ -375,12 +375,8 @@ kot_status t_apply(kot_ctx* ctx, const TPlan& tp, const double* S, double* out) 
 kot_status schur_matvec(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const double* v, double* y) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
-  // y = Q v / (2 lam2) + mu v
-  HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / (2.0 * cv.lam2), cv.Q, l, nullptr, v, 1, 0.0, y, 1));
-  HIPCHK(vec_axpby(l, tp.mu, v, 1.0, y, st));
-  if (tp.comp) {  // + (1/mu) (K o K) v
-    HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / tp.mu, cv.KK, l, nullptr, v, 1, 1.0, y, 1));
-  }
+  // y = Q v / (2 lam2) + mu v (+ (1/mu) (K o K) v in the complement form), one pass
+  HIPCHK(gemv2(l, cv.Q, 1.0 / (2.0 * cv.lam2), tp.comp ? cv.KK : nullptr, 1.0 / tp.mu, v, tp.mu, y, st));
   if (tp.m == 0) return KOT_OK;
   const double* Bs = ctx->Bm + (long long)tp.r0 * l;
   double* C = ctx->T3;

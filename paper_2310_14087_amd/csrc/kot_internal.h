@@ -46,6 +46,9 @@ struct GemmArgs {
   const double* D = nullptr; int ldd = 0;
   double* y = nullptr; double dalpha = 1.0, dbeta = 0.0;
 };
+// y = a Q v + b K2 v + c v for square m x m row-major Q, K2 (K2 may be null; v, y device vectors)
+hipError_t gemv2(int m, const double* Q, double a, const double* K2, double b, const double* v, double c, double* y,
+                 hipStream_t st);
 // Reserves the current device's pool of GEMM work lists (once per device and process; call outside any solve).
 hipError_t gemm_reserve();
 hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
