@@ -7,7 +7,11 @@ samples per side, d = 10, two 4-component Gaussian mixtures, l = 1000 filling po
 seed.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--arm fp64|warm|mixed32|mixed16|mixed|all]
-                    [--no-cpu-baseline]
+                    [--lanes L] [--no-cpu-baseline]
+
+Each arm's K solves run twice: one at a time on one context, then as independent solves in flight together on
+L lanes of ``kot_solve_batched`` (child contexts with a stream and a host thread each; default 8).  The rates
+reported are those of the lanes pass (whole-job throughput); the one-at-a-time rate is kept beside them.
 
 Arms: ``fp64`` cold start, FP64 everywhere; ``warm`` learned warm start, FP64; ``mixed32``, ``mixed16`` and
 ``mixed``: learned warm start with the CG matvec chain in FP32, BF16 and split BF16 (three BF16 products per
@@ -213,7 +217,9 @@ def main():
                          "plain fp64 arm, jacobi on the accelerated arms")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the metric line: time kot_solve_batched on this many 'batch' problems")
-    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--lanes", type=int, default=8,
+                    help="independent solves in flight (kot_solve_batched lanes, one stream and host thread each); "
+                         "1: one solve at a time on the main context")
     ap.add_argument("--tune", default=None, help="autotune table to load (or create when missing)")
     ap.add_argument("--copy-calibrate", type=float, default=0.0,
                     help="instead of the metric line: copy this many MiB device-to-device three times")
@@ -268,6 +274,10 @@ def main():
         return kotssn.default_params(**kw)
 
     def run_arm(arm):
+        """The arm's `steps` solves one after another on the main context (`overlap` as given), then, with
+        lanes > 1, the same solves again through kot_solve_batched: independent instances on `lanes` child
+        contexts, each with its own stream and host thread.  Returns (sequential results, seconds), and the
+        lanes' (results, seconds) or None."""
         for w in range(a.warmup):
             _log(f"{arm} warmup {w}")
             ctx.solve(*dev_inputs[w % n_inst], params(w % n_inst, arm))
@@ -281,8 +291,25 @@ def main():
             _log(f"{arm} step {k}: instance {i} status={r.status} iters={r.iters} warm_used={r.warm_used} "
                  f"residual={r.residual:.2e} ot={r.ot:.10g} device_ms={r.time_ms:.1f}")
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        return results, t1 - t0
+        seq = (results, time.perf_counter() - t0)
+        if a.lanes <= 1:
+            return seq, None
+        idx = [k % n_inst for k in range(a.steps)]
+        batch_in = [dev_inputs[i] for i in idx]
+        batch_prm = [params(i, arm) for i in idx]
+        nw = min(a.lanes, a.steps)
+        for w in range(a.warmup):  # every lane gets a solve: its workspace and GEMM unit lists exist before timing
+            ctx.solve_batched(batch_in[:nw], batch_prm[:nw], lanes=a.lanes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.solve_batched(batch_in, batch_prm, lanes=a.lanes)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        lres = [r for _, r in out]
+        for k, r in enumerate(lres):
+            _log(f"{arm} lanes solve {k}: instance {idx[k]} status={r.status} iters={r.iters} "
+                 f"residual={r.residual:.2e} ot={r.ot:.10g}")
+        return seq, (lres, el)
 
     def roofline_pass(arm):
         """Per-class launch timing with HIP events around every launch, outside the timed loop and on one
@@ -302,18 +329,25 @@ def main():
     prof = None
     elapsed = None
     for arm in arms:
-        results, el = run_arm(arm)
-        conv = sum(1 for r in results if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
+        (sres, sel), lan = run_arm(arm)
+        results, el = lan if lan else (sres, sel)
+        ok = lambda rs: sum(1 for r in rs if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
+        conv = ok(results)
         out_arms[arm] = dict(solves_per_s=a.steps / el, ms_per_solve=1e3 * el / a.steps, converged=conv,
                              iters=[r.iters for r in results], eig_sweeps=[r.eig_sweeps_total for r in results],
                              cg_iters=[r.cg_iters_total for r in results],
                              lowp_directions=[r.lowp_directions for r in results], ot=[r.ot for r in results])
+        if lan:
+            out_arms[arm]["sequential"] = dict(
+                solves_per_s=a.steps / sel, ms_per_solve=1e3 * sel / a.steps, converged=ok(sres),
+                ot_max_abs_diff_vs_lanes=max(abs(x.ot - y.ot) for x, y in zip(sres, results)))
         if arm == arms[-1]:
             elapsed, final = el, arm
             if not a.no_profile:
                 _log(f"{arm}: roofline pass ({a.roofline_solves} solves, one stream, events on every launch)")
                 prof, prof_wall = roofline_pass(arm)
-        _log(f"{arm}: {a.steps / el:.2f} solves/s, {conv}/{a.steps} converged")
+        _log(f"{arm}: {a.steps / el:.2f} solves/s, {conv}/{a.steps} converged"
+             + (f" ({a.lanes} lanes; one at a time {a.steps / sel:.2f} solves/s)" if lan else ""))
     ctx.close()
     if "fp64" in out_arms:
         for arm in ("warm", "mixed32", "mixed16", "mixed"):
@@ -337,7 +371,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: n=5000/side, d=10, two 4-component mixtures, l=1000, "
                                f"sigma^2=0.005 on unit-cube data, lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
-                   "arm": final, "instances": n_inst, "overlap": a.overlap, "precond": a.precond,
+                   "arm": final, "instances": n_inst, "lanes": max(1, a.lanes), "overlap": a.overlap,
+                   "precond": a.precond,
                    "arms": out_arms},
     }
     if prof:

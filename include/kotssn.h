@@ -153,7 +153,7 @@ kot_status kot_solve(kot_ctx* ctx, const kot_problem* prob, const kot_params* pr
 /* Many independent problems (any mix of n_src, n_tgt, d, l): each is solved as by kot_solve.  prms holds
  * 1 entry (shared) or nprob entries; gamma0 (host array of nprob device pointers) may be NULL; results[i]
  * (gamma required) and status[i] (host) receive problem i's outputs.  The problems are spread over `lanes`
- * child contexts (0 = 4), each with its own HIP stream and workspace and driven by its own host thread, so
+ * child contexts (0 = 8), each with its own HIP stream and workspace and driven by its own host thread, so
  * kernels of different problems overlap on the device.  Returns the most severe error status if a problem
  * failed (KOT_NOT_CONVERGED is reported per problem only). */
 kot_status kot_solve_batched(kot_ctx* ctx, int nprob, const kot_problem* probs, const kot_params* prms, int nparams,

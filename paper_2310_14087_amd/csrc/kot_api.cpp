@@ -1433,7 +1433,7 @@ kot_status kot_solve_batched(kot_ctx* ctx, int nprob, const kot_problem* probs, 
     if (!results[i].gamma) return fail(ctx, KOT_ERR_ARG, "results[%d].gamma is NULL", i);
   }
   if (nprob == 0) return KOT_OK;
-  if (lanes <= 0) lanes = 4;  // hardware queues per process on this device class
+  if (lanes <= 0) lanes = 8;  // more lanes than hardware queues: a lane waiting on the host leaves room to others
   lanes = std::min(lanes, std::min(nprob, 16));
   while ((int)ctx->lanes.size() < lanes) {
     kot_ctx* c = nullptr;

@@ -60,6 +60,33 @@ def test_batched_fp32_cg(gpu_ctx):
         assert r.lowp_directions == r.iters  # every Newton direction ran the FP32 chain
 
 
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2310_14087_amd",
+                       "weights", "warmstart_mix256.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_lanes_mix1000_match_sequential(gpu_ctx):
+    """The throughput configuration of the l = 1000 workload (learned start, split-BF16 chain with FP64
+    refinement, Jacobi-preconditioned CG) on 8 lanes, two solves per lane: every gamma equals, bit for bit,
+    that of the same solve run alone on the main context with its extragradient branch on a second stream."""
+    import torch
+    from paper_2310_14087_amd import kotssn, warmstart
+    theta, F, H, meta = warmstart.load(WEIGHTS)
+    th = torch.from_numpy(theta).to("cuda:0")
+    probs = [make_problem("mix1000", s) for s in range(16)]
+    print("[case] mix1000 seeds 0..15 on 8 lanes vs one at a time", flush=True)
+    dev = [(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf)) for p in probs]
+    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, ws_F=F, ws_H=H,
+                                  ws_theta=th.data_ptr(), precision=kotssn.KOT_MIXED_BF16X3,
+                                  precond=kotssn.KOT_PRECOND_JACOBI) for p in probs]
+    out = gpu_ctx.solve_batched(dev, prms, lanes=8)
+    for d, prm, (g, r) in zip(dev, prms, out):
+        assert r.status == kotssn.KOT_OK and r.residual <= 1e-6
+        g1, _, r1 = gpu_ctx.solve(*d, prm)
+        assert np.array_equal(_n(g), _n(g1)), "lanes and sequential solves differ"
+        assert (r1.iters, r1.ot) == (r.iters, r.ot)
+
+
 def test_autotune_table(gpu_ctx, tmp_path):
     from paper_2310_14087_amd import kotssn
     print("[case] kot_autotune sizes 128, 300", flush=True)
