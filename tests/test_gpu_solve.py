@@ -191,3 +191,38 @@ def test_overlapped_branches_match_one_stream(gpu_ctx, name, l, n, seed, precisi
         np.testing.assert_array_equal(r1.res_hist[:k], r0.res_hist[:k])
         np.testing.assert_array_equal(r1.res_v_hist[:k], r0.res_v_hist[:k])
         assert r1.ot == r0.ot and r1.warm_used == r0.warm_used
+
+
+@pytest.mark.parametrize("name,seed,l,n", [("mix256", 3, 1, 40), ("mix256", 3, 2, 40), ("mix256", 3, 3, 40),
+                                           ("mix1000", 1, 5, 40), ("gauss500", 2, 1, 40), ("gauss500", 2, 2, 40),
+                                           ("mix256", 3, 4, 1), ("mix256", 3, 1, 1)])
+def test_degenerate_sizes_match_oracle(gpu_ctx, name, seed, l, n):
+    """The smallest problems: one to five filling points (a single partial tile everywhere, a 1x1 PSD cone)
+    and one sample per side."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem(name, seed, l=l, n=n)
+    print(f"[case] kot_solve degenerate {name} seed={seed} l={p.l} n={p.n_src} d={p.d}", flush=True)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=p.tol))
+    assert ref["status"] == "converged"
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+    gamma, X, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, want_X=True)
+    assert r.status == kotssn.KOT_OK and r.residual <= p.tol, r
+    assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
+    g = _n(gamma)
+    np.testing.assert_allclose(g, ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
+    _, _, rn, _ = ko.residual(core, g, _n(X))
+    assert rn <= 1.01 * p.tol
+
+
+@pytest.mark.parametrize("l,n,d", [(0, 10, 3), (4097, 10, 3), (5, 0, 3), (5, 10, 0), (5, 10, 65)])
+def test_invalid_sizes_rejected(gpu_ctx, l, n, d):
+    """Sizes outside 1 <= l <= 4096, 1 <= d <= 64, n >= 1 are rejected on the host before any launch."""
+    import torch
+    from paper_2310_14087_amd import kotssn
+    print(f"[case] kot_solve rejects l={l} n={n} d={d}", flush=True)
+    z = lambda r: torch.zeros((r, d), dtype=torch.float64, device="cuda:0")
+    prm = kotssn.default_params(sigma=1.0, lambda1=1e-3, lambda2=1e-3, tol=1e-6)
+    with pytest.raises(kotssn.KotError) as e:
+        gpu_ctx.solve(z(n), z(n), z(l), z(l), prm)
+    assert e.value.status == kotssn.KOT_ERR_ARG
