@@ -97,7 +97,8 @@ typedef struct kot_params {
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:
- * xs n_src x d, ys n_tgt x d, xf l x d, yf l x d. */
+ * xs n_src x d, ys n_tgt x d, xf l x d, yf l x d.  Accepted sizes: 1 <= l <= 4096, 1 <= d <= 64,
+ * 1 <= n_src, n_tgt <= 2^20; others are rejected with KOT_ERR_ARG before any launch. */
 typedef struct kot_problem {
   int n_src, n_tgt, d, l;
   const double* xs;

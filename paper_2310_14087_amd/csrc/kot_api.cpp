@@ -1176,6 +1176,8 @@ kot_status check_problem(kot_ctx* ctx, const kot_problem* pb) {
     return fail(ctx, KOT_ERR_ARG, "sizes must be >= 1 (l=%d d=%d n_src=%d n_tgt=%d)", pb->l, pb->d, pb->n_src, pb->n_tgt);
   if (pb->d > 64) return fail(ctx, KOT_ERR_ARG, "d must be <= 64");
   if (pb->l > 4096) return fail(ctx, KOT_ERR_ARG, "l must be <= 4096");
+  // the mean-Gram sum keeps one partial per 64 x 64 tile pair: (2^20 / 64)^2 doubles (2 GiB) at the cap
+  if (pb->n_src > (1 << 20) || pb->n_tgt > (1 << 20)) return fail(ctx, KOT_ERR_ARG, "n_src and n_tgt must be <= 2^20");
   if (!pb->xs || !pb->ys || !pb->xf || !pb->yf) return fail(ctx, KOT_ERR_ARG, "null point array");
   return KOT_OK;
 }

@@ -215,9 +215,9 @@ def test_degenerate_sizes_match_oracle(gpu_ctx, name, seed, l, n):
     assert rn <= 1.01 * p.tol
 
 
-@pytest.mark.parametrize("l,n,d", [(0, 10, 3), (4097, 10, 3), (5, 0, 3), (5, 10, 0), (5, 10, 65)])
+@pytest.mark.parametrize("l,n,d", [(0, 10, 3), (4097, 10, 3), (5, 0, 3), (5, 10, 0), (5, 10, 65), (5, (1 << 20) + 1, 1)])
 def test_invalid_sizes_rejected(gpu_ctx, l, n, d):
-    """Sizes outside 1 <= l <= 4096, 1 <= d <= 64, n >= 1 are rejected on the host before any launch."""
+    """Sizes outside 1 <= l <= 4096, 1 <= d <= 64, 1 <= n <= 2^20 are rejected on the host before any launch."""
     import torch
     from paper_2310_14087_amd import kotssn
     print(f"[case] kot_solve rejects l={l} n={n} d={d}", flush=True)
