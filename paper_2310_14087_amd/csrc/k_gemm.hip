@@ -386,6 +386,123 @@ __global__ __launch_bounds__(256) void gemv_f64_kernel(int m, int k, double alph
   }
 }
 
+// Row-vector products (m = 1): c_j = sum_k a_k s_k op(B)_kj with a_k = op(A)_0k.  The epilogue writes
+// C_0j = alpha c_j + beta C_0j, or in column-dot mode y_j = dalpha D_0j (alpha c_j) + dbeta y_j.
+__device__ __forceinline__ void rowvec_store(int j, double v, double alpha, double beta, double* __restrict__ C,
+                                             const double* __restrict__ D, double dalpha, double dbeta,
+                                             double* __restrict__ y) {
+  if (D) {
+    const double w = D[j] * (alpha * v);
+    y[j] = (dbeta == 0.0) ? dalpha * w : dalpha * w + dbeta * y[j];
+  } else {
+    C[j] = (beta == 0.0) ? alpha * v : alpha * v + beta * C[j];
+  }
+}
+
+// op(B)_kj = B[j * ldb + k] (k <= kRowvecMaxK): the workgroup stages x_k = s_k a_k in LDS once, then one
+// wavefront per output j reads its row of B along k with eight loads in flight per lane; the lane partials are
+// combined in a fixed order, then a butterfly.
+constexpr int kRowvecMaxK = 4096;
+__global__ __launch_bounds__(256) void rowvec_dot_kernel(int n, int k, const double* __restrict__ a, int inca,
+                                                         const double* __restrict__ s, const double* __restrict__ B,
+                                                         int ldb, double alpha, double beta, double* __restrict__ C,
+                                                         const double* __restrict__ D, double dalpha, double dbeta,
+                                                         double* __restrict__ y) {
+  __shared__ double xs[kRowvecMaxK];
+  for (int kk = threadIdx.x; kk < k; kk += 256)
+    xs[kk] = s ? s[kk] * a[(long long)kk * inca] : a[(long long)kk * inca];
+  __syncthreads();
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= n) return;  // uniform per wavefront (after the barrier)
+  const double* __restrict__ b = B + (long long)j * ldb;
+  double q[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int kk = lane;
+  for (; kk + 448 < k; kk += 512) {
+    double bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bv[u] = b[kk + 64 * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] += xs[kk + 64 * u] * bv[u];
+  }
+  for (; kk < k; kk += 64) q[0] += xs[kk] * b[kk];
+  double acc = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) rowvec_store(j, acc, alpha, beta, C, D, dalpha, dbeta, y);
+}
+
+// op(B)_kj = B[k * ldb + j]: workgroup (x, z) sums K slice z of 64 columns, the four thread groups taking every
+// fourth k of the slice (four loads in flight each), and writes part[z][j].
+__global__ __launch_bounds__(256) void rowvec_colsum_kernel(int n, int k, int kc, const double* __restrict__ a,
+                                                            int inca, const double* __restrict__ s,
+                                                            const double* __restrict__ B, int ldb,
+                                                            double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int t = threadIdx.x, c = t & 63, grp = t >> 6;
+  const int j = blockIdx.x * 64 + c;
+  const int k0 = blockIdx.y * kc, k1 = min(k, k0 + kc);
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < n) {
+    int kk = k0 + grp;
+    for (; kk + 12 < k1; kk += 16) {
+      double bv[4], xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kq = kk + 4 * u;
+        bv[u] = B[(long long)kq * ldb + j];
+        xv[u] = s ? s[kq] * a[(long long)kq * inca] : a[(long long)kq * inca];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] += xv[u] * bv[u];
+    }
+    for (; kk < k1; kk += 4) q[0] += (s ? s[kk] * a[(long long)kk * inca] : a[(long long)kk * inca]) * B[(long long)kk * ldb + j];
+  }
+  red[grp][c] = (q[0] + q[1]) + (q[2] + q[3]);
+  __syncthreads();
+  if (grp == 0 && j < n) part[(long long)blockIdx.y * n + j] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+// Sums the K slices of rowvec_colsum_kernel in slice order (ks <= kRowvecMaxSlices, every load issued before
+// the sum) and applies the epilogue.
+constexpr int kRowvecMaxSlices = 64;
+__global__ __launch_bounds__(256) void rowvec_final_kernel(int n, int ks, const double* __restrict__ part, double alpha,
+                                                           double beta, double* __restrict__ C,
+                                                           const double* __restrict__ D, double dalpha, double dbeta,
+                                                           double* __restrict__ y) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double pv[kRowvecMaxSlices];
+#pragma unroll
+  for (int z = 0; z < kRowvecMaxSlices; ++z) pv[z] = z < ks ? part[(long long)z * n + j] : 0.0;
+  double v = 0.0;
+#pragma unroll
+  for (int z = 0; z < kRowvecMaxSlices; ++z) v += pv[z];
+  rowvec_store(j, v, alpha, beta, C, D, dalpha, dbeta, y);
+}
+
+// Rank-one products (k = 1): C_ij = alpha op(A)_i0 s_0 op(B)_0j + beta C_ij over the whole matrix, or over its
+// lower triangle (lower), or over the lower triangle with each value also written to its mirror (lower and
+// mirror; beta = 0 there, so no element is read after another thread wrote it).
+__global__ __launch_bounds__(256) void rank1_kernel(int m, int n, double alpha, const double* __restrict__ A, int inca,
+                                                    const double* __restrict__ s, const double* __restrict__ B, int incb,
+                                                    double beta, double* __restrict__ C, int ldc, int lower,
+                                                    int mirror) {
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= m || j >= n) return;
+  const double s0 = s ? s[0] : 1.0;
+  if (lower && j > i) {
+    if (!mirror) return;
+    // the mirror of (j, i), which lies in the lower triangle (j < m since j > i and the product is square)
+    C[(long long)i * ldc + j] = alpha * ((A[(long long)j * inca] * s0) * B[(long long)i * incb]);
+    return;
+  }
+  const double v = alpha * ((A[(long long)i * inca] * s0) * B[(long long)j * incb]);
+  double* p = C + (long long)i * ldc + j;
+  *p = (beta == 0.0) ? v : v + beta * (*p);
+}
+
 // y_r = a (Q v)_r + b (K2 v)_r + c v_r (K2 may be null): the Schur operator's dense part in one pass, one
 // wavefront per row, four partial sums per lane for each product, combined in a fixed order.
 __global__ __launch_bounds__(256) void gemv2_f64_kernel(int m, const double* __restrict__ Q, double a,
@@ -621,6 +738,44 @@ hipError_t gemm_f64_cfg(const GemmArgs& g, hipStream_t st, int waves, int splits
                        g.lda, g.s, g.B, incx, g.beta, g.C, g.ldc);
     if (pf) pf->end(st);
     return hipGetLastError();
+  }
+  if (waves == 0 && splits_req == 0 && g.batch == 1 && !g.tri && (g.m == 1 || g.k == 1)) {
+    Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
+    if (g.m == 1 && !g.lower && !g.mirror) {
+      // row vector times a matrix: a matrix-vector product, bound by reading op(B)
+      const int inca = g.transa ? g.lda : 1;
+      const int ks = std::max(1, std::min(kRowvecMaxSlices, (g.k + 15) / 16));
+      const bool ws_ok = g_gemm_ws && (size_t)ks * g.n <= g_gemm_ws_cap;
+      const bool dot_ok = g.transb && g.k <= kRowvecMaxK;
+      if (pf && (dot_ok || (!g.transb && ws_ok)))
+        pf->begin(st, PROF_GEMV_F64, 2.0 * g.n * (double)g.k,
+                  8.0 * ((double)g.n * g.k + g.k + (g.D ? 3.0 : (g.beta != 0.0 ? 2.0 : 1.0)) * g.n));
+      if (dot_ok) {
+        hipLaunchKernelGGL(rowvec_dot_kernel, dim3((unsigned)((g.n + 3) / 4)), dim3(256), 0, st, g.n, g.k, g.A, inca,
+                           g.s, g.B, g.ldb, g.alpha, g.beta, g.C, g.D, g.dalpha, g.dbeta, g.y);
+        if (pf) pf->end(st);
+        return hipGetLastError();
+      }
+      if (!g.transb && ws_ok) {
+        const int kc = (g.k + ks - 1) / ks;
+        hipLaunchKernelGGL(rowvec_colsum_kernel, dim3((unsigned)((g.n + 63) / 64), (unsigned)ks), dim3(256), 0, st,
+                           g.n, g.k, kc, g.A, inca, g.s, g.B, g.ldb, g_gemm_ws);
+        KOT_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(rowvec_final_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, g.n, ks,
+                           (const double*)g_gemm_ws, g.alpha, g.beta, g.C, g.D, g.dalpha, g.dbeta, g.y);
+        if (pf) pf->end(st);
+        return hipGetLastError();
+      }
+    } else if (g.k == 1 && !g.D && (!g.mirror || (g.lower && g.m == g.n && g.beta == 0.0))) {
+      // outer product: bound by writing C
+      const int inca = g.transa ? 1 : g.lda;  // op(A)_i0
+      const int incb = g.transb ? g.ldb : 1;  // op(B)_0j
+      if (pf) pf->begin(st, PROF_GEMV_F64, 2.0 * g.m * (double)g.n, 8.0 * (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n);
+      hipLaunchKernelGGL(rank1_kernel, dim3((unsigned)((g.n + 63) / 64), (unsigned)((g.m + 3) / 4)), dim3(256), 0, st,
+                         g.m, g.n, g.alpha, g.A, inca, g.s, g.B, incb, g.beta, g.C, g.ldc, g.lower, g.mirror);
+      if (pf) pf->end(st);
+      return hipGetLastError();
+    }
   }
   const int tiles = ((g.n + BN - 1) / BN) * ((g.m + BM - 1) / BM) * g.batch;
   // 16 waves per workgroup: measured fastest on every solver shape (four waves per SIMD at one tile per CU)

@@ -25,7 +25,8 @@ def _case(msg):
 
 
 @pytest.mark.parametrize("m,n,k", [(64, 64, 16), (1, 1, 1), (37, 129, 70), (200, 3, 65), (130, 257, 300),
-                                   (300, 1, 257), (5, 1, 1000)])
+                                   (300, 1, 257), (5, 1, 1000), (1, 33, 64), (1, 257, 300), (1, 1000, 1000),
+                                   (120, 257, 1), (1000, 1000, 1)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 @pytest.mark.parametrize("scaled", [False, True])
 def test_gemm_f64(gpu_ctx, m, n, k, ta, tb, scaled):
@@ -44,7 +45,7 @@ def test_gemm_f64(gpu_ctx, m, n, k, ta, tb, scaled):
 
 
 @pytest.mark.parametrize("l", [33, 64, 257, 1000])
-@pytest.mark.parametrize("mode", ["phi_star", "xr", "ptr", "sym_beta", "proj"])
+@pytest.mark.parametrize("mode", ["phi_star", "xr", "ptr", "sym_beta", "proj", "proj_rank1"])
 def test_gemm_f64_modes(gpu_ctx, l, mode):
     """The solver's product modes against numpy: zero triangles of R skipped (tri), symmetric results from the
     lower tiles mirrored (sym), with the work lists and split-K of the large shapes."""
@@ -72,13 +73,16 @@ def test_gemm_f64_modes(gpu_ctx, l, mode):
         C0 = C0 + C0.T
         ref = 0.5 * Y.T @ Y - 2.0 * C0
         out = gpu_ctx.gemm(_t(Y), _t(Y), transa=True, alpha=0.5, beta=-2.0, Cm=_t(C0), sym=True)
-    else:                       # P diag(w) P^T, inner size a
+    else:                       # P diag(w) P^T, inner size a (one column: a rank-one update)
+        if mode == "proj_rank1":
+            a = 1
+            P = P[:, :1].copy()
         w = rng.standard_normal(a)
         ref = (P * w) @ P.T
         out = gpu_ctx.gemm(_t(P), _t(P), transb=True, s=_t(w), sym=True)
     o = _n(out)
     np.testing.assert_allclose(o, ref, rtol=1e-12, atol=1e-12 * l * max(1.0, np.abs(ref).max()))
-    if mode in ("phi_star", "sym_beta", "proj"):  # mirrored tiles exact; diagonal tiles up to rounding
+    if mode in ("phi_star", "sym_beta", "proj", "proj_rank1"):  # mirrored tiles exact; diagonal tiles up to rounding
         np.testing.assert_allclose(o, o.T, rtol=0, atol=1e-13 * l * max(1.0, np.abs(ref).max()))
 
 
