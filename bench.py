@@ -145,7 +145,10 @@ def sweep_bench(a):
                 ctx.solve(*inputs[0], prm(probs[0]))  # warm-up (workspace sizing)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                out = [ctx.solve(*inputs[i], prm(p))[2] for i, p in enumerate(probs)]
+                out = []
+                for i, p in enumerate(probs):
+                    out.append(ctx.solve(*inputs[i], prm(p))[2])
+                    _log(f"sweep d={d} l={l} {arm} instance {i}: iters={out[-1].iters} status={out[-1].status}")
                 torch.cuda.synchronize()
                 dt = (time.perf_counter() - t0) / len(probs)
                 row[arm] = dict(ms=1e3 * dt, iters=[r.iters for r in out], residual=max(r.residual for r in out),
