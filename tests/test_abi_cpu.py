@@ -80,3 +80,18 @@ def test_generator_shapes():
     assert p.xs.shape == (50, 10) and p.xf.shape == (40, 10) and p.lam1 == 1 / 40
     t = make_problem("tiny", 0)
     assert t.xs.shape == (100, 2) and t.l == 50 and t.sigma == 1.0 and t.lam1 == t.lam2 == 1e-3 and t.tol == 1e-8
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "4"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    """bench.py runs on one GPU: a request for more exits with status 2 and one JSON line saying so, before
+    it touches a device."""
+    import json
+    import subprocess
+    import sys
+    e = dict(os.environ, **env)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], capture_output=True, text=True,
+                       env=e, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
