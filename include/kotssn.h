@@ -56,9 +56,11 @@ typedef enum { KOT_SCHUR_CG = 0, KOT_SCHUR_SQMR = 1 } kot_schur_solver;
 /* Parameters of Algorithm 2 and the inexactness rule Eq. (4.5).  kot_params_default fills the values
  * used throughout: tol 1e-6, max_iter 200, cg_max_iter 20 (Remark 4.5), tau = kappa = 0.5,
  * alpha1 = 1e-6, alpha2 = 1, beta0 = 0.5, beta1 = 1/1.2, beta2 = 5 (Section 5 constants, with beta1 < 1
- * as Algorithm 2's input requires), theta0 = 1, theta in [1e-6, 1e6], eg_step = 0 (=> 0.5 / Lhat with
- * Lhat = |Q|_inf/(2 lambda2) + sqrt(|K o K|_inf)), null_step = 1 (keep w_k when it beats both the SSN trial
- * and the extragradient iterate), eps_jitter = 1e-10 (R^T R = K + eps I). */
+ * as Algorithm 2's input requires; Section 5 prints 1.2, which set here runs the printed value),
+ * theta0 = 1, theta in [1e-6, 1e6], eg_step = 0 (=> 0.5 / Lhat with
+ * Lhat = |Q|_inf/(2 lambda2) + sqrt(|K o K|_inf)), null_step = 0 (Algorithm 2's accept test as printed:
+ * w_{k+1} = SSN trial if |R(trial)| <= |R(v_{k+1})|, else v_{k+1}; 1 = opt-in variant that keeps w_k when
+ * the trial is worse than w_k and w_k beats v_{k+1}), eps_jitter = 1e-10 (R^T R = K + eps I). */
 typedef struct kot_params {
   double sigma;        /* Gaussian bandwidth: k(a,b) = exp(-|a-b|^2 / (2 sigma^2)) */
   double lambda1;      /* trace penalty (Eq. 3.2) */

@@ -26,7 +26,13 @@ Readings where the paper is silent or inconsistent (each is listed in the design
 * Eq. (4.5) is checked on the CG residual of the Schur system (the second block row of the full residual
   vanishes identically when the X-direction is formed as in Algorithm 1) against ``tau*min(1, kappa|r||a~1|)``
   (``|a~1| <= |dw|``, so the test is at least as strict).  CG stops at 20 iterations with its last iterate.
-* The constants of Section 5: alpha1=1e-6, alpha2=1, beta0=0.5, beta1=1.2, beta2=5.
+* The constants of Section 5: alpha1=1e-6, alpha2=1, beta0=0.5, beta2=5, and beta1 = 1/1.2: Section 5 prints
+  beta1 = 1.2 and the theta rule's text asks for beta1 > 1, while Algorithm 2's input line asks for beta1 < 1.
+  With 1.2, mu = theta |r| settles near alpha2 = 1 and the decoupled l = 1000 instances do not reach 1e-6 in
+  200 iterations (1/1.2: 10 iterations).  ``Params(beta1=1.2)`` runs the printed value.
+* Accept test as printed in Algorithm 2: w_{k+1} is the SSN trial when |R(trial)| <= |R(v_{k+1})|, else
+  v_{k+1}.  ``Params(null_step=True)`` is an opt-in variant that keeps w_k when the trial is worse than w_k
+  and w_k also beats v_{k+1}.
 * Extragradient: Korpelevich steps on the monotone operator of Eq. (4.1),
   ``F(gamma, X) = ((Q gamma - z)/(2 lambda2) - Phi(X),  Phi*(gamma) + lambda1 I)`` with projection onto
   ``R^l x S^l_+``; default step ``0.5 / (|Q|_inf/(2 lambda2) + sqrt(|K o K|_inf))`` (a bound on 1/L).
@@ -68,7 +74,8 @@ class Params:
     eg_step: float = 0.0           # 0 => default bound-based step
     safeguard: str = "eg"          # "eg" (Algorithm 2 as written), "none" (pure regularized SSN) or "eg_only"
                                    # (pure extragradient, the comparison method of Appendix F)
-    null_step: bool = True         # reading: keep w_k when it beats both the trial and v_{k+1}
+    null_step: bool = False        # False: Algorithm 2's accept test as printed; True: keep w_k when it beats
+                                   # both the trial and v_{k+1} (opt-in variant)
     eps_jitter: float = 1e-10
     precond: str = "none"          # "none" (CG as the paper runs it) or "jacobi" (diagonal preconditioner of the
                                    # Schur system; an addition, the paper names none)

@@ -1223,7 +1223,7 @@ void kot_params_default(kot_params* p) {
   p->eg_step = 0.0;
   p->precision = KOT_FP64;
   p->safeguard = KOT_SAFEGUARD_EG;
-  p->null_step = 1;
+  p->null_step = 0;
   p->eig_max_sweeps = 30;
   p->warm_eig = 1;
   p->lift_x0 = 1;

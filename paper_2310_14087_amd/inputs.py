@@ -9,6 +9,8 @@ lambda1 = 1/l, lambda2 = 1/sqrt(n_sample); the shapes below follow that recipe a
 * ``tiny``     n=100/side, d=2, N(0,I) vs N((1,1),I), l=50, sigma=1, lambda1=lambda2=1e-3, tol 1e-8.
 * ``gauss500`` n=2000/side, d=5, N(0,I) vs N(m, AA^T/5 + 0.1I), m ~ U[-1,1]^5, l=500.
 * ``mix1000``  n=5000/side, d=10, two 4-component unit-covariance mixtures, means ~ U[-2,2]^10, l=1000.
+* ``mix1000_median``  the same draw on raw coordinates with sigma = the median pooled pairwise distance (a
+               dense kernel: the coupled form of the l=1000 workload).
 * ``batch``    one problem of the uneven batch: n ~ U{200..2000}, l ~ U{100..400}, d ~ U{2..10},
                N(0,I) vs N(s, I), s ~ U[-1,1]^d.
 * ``mix256``   n=1000/side, d=8, two 3-component unit-covariance mixtures, means ~ U[-2,2]^8, l=256.
@@ -18,7 +20,7 @@ target samples (a point of X x Y, Section 3).
 
 Bandwidth and scale:
 * ``tiny``: raw coordinates, sigma = 1 (fixed by the workload's definition).
-* ``gauss500``: raw coordinates, sigma = median of all pooled pairwise Euclidean distances.
+* ``gauss500``, ``mix1000_median``: raw coordinates, sigma = median of all pooled pairwise Euclidean distances.
 * ``mix1000``, ``mix256``, ``batch`` (no bandwidth in their definition): the paper's own recipe (Section 5):
   samples affinely mapped into the unit cube (pooled bounding box, one common scale so the cost keeps its
   geometry), filling points uniform in the unit-cube boxes of each side, sigma^2 = 0.005.
@@ -31,10 +33,11 @@ import numpy as np
 
 __all__ = ["Problem", "make_problem", "make_custom", "median_pairwise_distance", "WORKLOADS"]
 
-WORKLOADS = ("tiny", "gauss500", "mix1000", "batch", "mix256", "sweep_d2", "sweep_d5", "sweep_d10", "cells48")
+WORKLOADS = ("tiny", "gauss500", "mix1000", "mix1000_median", "batch", "mix256", "sweep_d2", "sweep_d5", "sweep_d10",
+             "cells48")
 
 # Seed offsets per workload: seed = base + s.
-_SEED_BASE = {"tiny": 1000, "gauss500": 2000, "mix1000": 3000, "batch": 4000, "mix256": 5000, "sweep_d2": 6000,
+_SEED_BASE = {"tiny": 1000, "gauss500": 2000, "mix1000": 3000, "mix1000_median": 3000, "batch": 4000, "mix256": 5000, "sweep_d2": 6000,
               "sweep_d5": 7000, "sweep_d10": 8000, "cells48": 9000}
 
 
@@ -202,7 +205,7 @@ def make_problem(name: str, s: int = 0, *, l: int | None = None, n: int | None =
         L = np.linalg.cholesky(cov)
         xs = rng.standard_normal((n_, d))
         ys = m + rng.standard_normal((n_, d)) @ L.T
-    elif name == "mix1000":
+    elif name in ("mix1000", "mix1000_median"):
         n_ = n or 5000
         l_ = l or 1000
         d = 10
@@ -227,7 +230,7 @@ def make_problem(name: str, s: int = 0, *, l: int | None = None, n: int | None =
         shift = rng.uniform(-1.0, 1.0, size=d)
         xs = rng.standard_normal((n_, d))
         ys = shift + rng.standard_normal((n_, d))
-    if name == "gauss500":
+    if name in ("gauss500", "mix1000_median"):
         xf = _box_uniform(rng, xs, l_)
         yf = _box_uniform(rng, ys, l_)
         sigma = median_pairwise_distance(xs, ys)

@@ -43,7 +43,7 @@ def test_params_default_host_only(lib):
     assert p.tau == 0.5 and p.kappa == 0.5
     assert p.alpha1 == 1e-6 and p.alpha2 == 1.0 and p.beta0 == 0.5 and p.beta2 == 5.0
     assert p.beta1 == pytest.approx(1 / 1.2)
-    assert p.null_step == 1 and p.safeguard == kotssn.KOT_SAFEGUARD_EG and p.precision == kotssn.KOT_FP64
+    assert p.null_step == 0 and p.safeguard == kotssn.KOT_SAFEGUARD_EG and p.precision == kotssn.KOT_FP64
     assert p.overlap == 1 and p.lowp_min_rows == 64 and p.precond == kotssn.KOT_PRECOND_NONE
     assert p.schur_solver == kotssn.KOT_SCHUR_CG
 

@@ -40,7 +40,8 @@ def test_solve_converges_like_oracle(gpu_ctx, name, l, n, seed):
 
 @pytest.mark.parametrize("iters", [4, 8])
 def test_tiny_fixed_iterations(gpu_ctx, iters):
-    """The dense 'tiny' workload (sigma=1, lambda=1e-3), on which the method does not reach its tolerance:
+    """The dense 'tiny' workload (sigma=1, lambda=1e-3), on which the method does not reach its tolerance
+    from the cold start (a recorded limitation, pinned on the CPU):
     the first iterations of Algorithm 2 agree when both sides solve the Newton systems to convergence
     (with the 20-iteration CG cap the capped CG iterate of an ill-conditioned system depends on rounding
     order, so trajectories are compared with converged inner solves)."""
@@ -55,6 +56,25 @@ def test_tiny_fixed_iterations(gpu_ctx, iters):
     assert r.status == kotssn.KOT_NOT_CONVERGED and r.iters == iters
     hist = np.array([h["res"] for h in ref["history"]])
     np.testing.assert_allclose(r.res_hist, hist, rtol=1e-6)
+    np.testing.assert_allclose(_n(gamma), ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
+
+
+@pytest.mark.parametrize("beta1,null_step", [(1.2, 0), (1 / 1.2, 1), (1.2, 1)])
+def test_opt_in_readings_match_oracle(gpu_ctx, beta1, null_step):
+    """Section 5's printed beta1 = 1.2 and the null-step variant of the accept test, selected through the
+    parameters: the GPU follows the oracle run with the same reading to the same iteration count and estimate."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem("mix256", 0, l=64, n=300)
+    print(f"[case] kot_solve beta1={beta1:.4f} null_step={null_step} mix256 l=64", flush=True)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=p.tol, beta1=beta1, null_step=bool(null_step)))
+    assert ref["status"] == "converged"
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, beta1=beta1,
+                                null_step=null_step)
+    gamma, X, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, want_X=True)
+    assert r.status == kotssn.KOT_OK and r.residual <= p.tol
+    assert r.iters == ref["iters"]
+    assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
     np.testing.assert_allclose(_n(gamma), ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
 
 
