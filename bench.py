@@ -1,13 +1,17 @@
 #!/usr/bin/env python3
 """Throughput of the SSN kernel-OT solver on one MI355X.
 
-A step is one full solve of one synthetic problem with inputs resident in HBM: setup (Gram matrices, mean
-embeddings, q^2, Cholesky factor) and Algorithm 2 to |R(w)| <= 1e-6.  The workload is ``mix1000`` (n = 5000
-samples per side, d = 10, two 4-component Gaussian mixtures, l = 1000 filling points), one instance per
-seed.  Prints one JSON line.
+A step is one solve of one synthetic problem with inputs resident in HBM: setup (Gram matrices, mean embeddings,
+q^2, Cholesky factor) and Algorithm 2.  The default workload is ``mix1000_median`` (n = 5000 samples per side,
+d = 10, two 4-component Gaussian mixtures, l = 1000 filling points, raw coordinates, bandwidth = the median pooled
+pairwise distance): the kernel is dense, the eigen-row chain of the Schur matvec has about l/2 rows, and
+Algorithm 2 does not reach residual 1e-6 in any affordable number of iterations, so every solve is capped at
+``--iters`` outer iterations and the line reports outer iterations/s (with each solve's residual).  After it, the
+decoupled ``mix1000`` workload (the same draw on unit-cube data with sigma^2 = 0.005, where K is the identity to
+1e-14) is timed as solves to 1e-6 (solves/s), as a labelled secondary.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--arm fp64|warm|mixed32|mixed16|mixed|all]
-                    [--lanes L] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--iters N] [--workload mix1000_median|mix1000|sweep]
+                    [--arm fp64|warm|mixed32|mixed16|mixed|all] [--lanes L] [--no-decoupled] [--no-cpu-baseline]
 
 Each arm's K solves run twice: one at a time on one context, then as independent solves in flight together on
 L lanes of ``kot_solve_batched`` (child contexts with a stream and a host thread each; default 8).  The rates
@@ -16,7 +20,9 @@ reported are those of the lanes pass (whole-job throughput); the one-at-a-time r
 Arms: ``fp64`` cold start, FP64 everywhere; ``warm`` learned warm start, FP64; ``mixed32``, ``mixed16`` and
 ``mixed``: learned warm start with the CG matvec chain in FP32, BF16 and split BF16 (three BF16 products per
 FP32 product) on the matrix cores, FP32 accumulation, inside FP64 iterative refinement.  ``value`` is the rate
-of the last arm run (``mixed`` by default); every arm's rate is in ``config.arms``.
+of the last arm run (``mixed`` by default); every arm's rate is in ``config.arms``.  ``roofline`` covers the
+class with the most kernel time in the final arm's one-stream pass; ``roofline_chain`` the Schur matvec chain's
+products (FP64, FP32, BF16) in each arm.
 """
 from __future__ import annotations
 
@@ -30,8 +36,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_mix1000_traffic.md")
-GEMM_SOURCE = os.path.join(ROOT, "paper_2310_14087_amd", "csrc", "k_gemm.hip")
 
 PEAK = {  # MI355X published dense peaks
     "fp64_tflops": 78.6,
@@ -44,7 +48,9 @@ PEAK = {  # MI355X published dense peaks
 # profiler class -> (bound, published peak, unit)
 CLASS_ROOF = {
     "gemm_f64": ("mfma", PEAK["fp64_tflops"], "TFLOP/s"),
-    "eig_sweep": ("mfma", PEAK["fp64_tflops"], "TFLOP/s"),
+    "chain_f64": ("mfma", PEAK["fp64_tflops"], "TFLOP/s"),
+    # a Jacobi sweep's rounds read and write A and V (32 l^2 bytes per round) at 4 flops per byte: HBM-bound
+    "eig_sweep": ("hbm", PEAK["hbm_gbs"], "GB/s"),
     "gemv_f64": ("hbm", PEAK["hbm_gbs"], "GB/s"),
     "gemm_f32": ("mfma", PEAK["fp32_tflops"], "TFLOP/s"),
     "gemm_bf16": ("mfma", PEAK["bf16_tflops"], "TFLOP/s"),
@@ -56,22 +62,35 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(workload: str):
-    """Time the CPU oracle (as it stands) on one full solve of instance 0 of the same workload."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+def cpu_baseline(workload: str, iters=None):
+    """The CPU oracle as it stands, on instance 0 of the same workload (the GPU's first instance): with `iters`
+    (the fixed-count line) a bounded sample of `iters` outer iterations, else one full solve; timed with the
+    BLAS thread pool as found and again with one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import kot_oracle as ko
     from paper_2310_14087_amd.inputs import make_problem
 
     p = make_problem(workload, 0)
-    t0 = time.perf_counter()
-    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
-    res = ko.solve(core, ko.Params(tol=p.tol))
-    dt = time.perf_counter() - t0
+    n_it = iters if iters else 200
+
+    def run():
+        t0 = time.perf_counter()
+        core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+        res = ko.solve(core, ko.Params(tol=p.tol, max_iter=n_it), record=False)
+        return time.perf_counter() - t0, res
+
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return dict(value=1.0 / dt, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"1 full oracle solve (setup + Algorithm 2, {res['iters']} iterations, status "
-                       f"{res['status']}) of {workload} instance 0, {dt:.1f} s wall, numpy/OpenBLAS FP64",
+    dt, res = run()
+    with threadpool_limits(limits=1):
+        dt1, res1 = run()
+    per = (lambda d, r: r["iters"] / d) if iters else (lambda d, r: 1.0 / d)
+    unit = "iterations/s" if iters else "solves/s"
+    return dict(value=per(dt, res), unit=unit, cores=threads, kind="oracle",
+                value_1thread=per(dt1, res1),
+                sample=f"instance 0 of {workload}: setup + Algorithm 2 "
+                       + (f"capped at {iters} outer iterations" if iters else "to 1e-6")
+                       + f" ({res['iters']} iterations, status {res['status']}, residual {res['residual']:.3e}), "
+                       f"{dt:.1f} s wall on {threads} BLAS threads, {dt1:.1f} s on 1; numpy/OpenBLAS FP64",
                 cpu=_cpu_model())
 
 
@@ -86,19 +105,29 @@ def _cpu_model():
     return "unknown"
 
 
-def gemm_traffic():
-    """HBM bytes per FP64 GEMM call from the committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
-    plain copy of known size), or None when there is none or the GEMM source changed since it was taken."""
+# committed counter summaries per profiler class: (summary file, source file whose hash it was taken on)
+TRAFFIC = {
+    "gemm_f64": ("gemm_f64_mix1000_traffic.md", "k_gemm.hip"),
+    "eig_sweep": ("eig_jacobi_mix1000_median_traffic.md", "k_eig.hip"),
+}
+
+
+def class_traffic(cls):
+    """HBM bytes per launch of a profiler class from its committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy of known size), or None when there is none or the kernel source changed since."""
     import hashlib
+    if cls not in TRAFFIC:
+        return None
+    summary, src = TRAFFIC[cls]
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", summary)) as f:
             kv = dict(line.strip().lstrip("- ").split(": ", 1) for line in f if ": " in line)
-        with open(GEMM_SOURCE, "rb") as f:
+        with open(os.path.join(ROOT, "paper_2310_14087_amd", "csrc", src), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-        if kv.get("gemm_source_sha256") != sha:
+        if kv.get("source_sha256", kv.get("gemm_source_sha256")) != sha:
             return None
-        return float(kv["traffic_bytes_per_call"])
-    except (OSError, KeyError, ValueError):
+        return float(kv.get("traffic_bytes_per_launch", kv.get("traffic_bytes_per_call")))
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 
@@ -201,18 +230,35 @@ def batch_bench(a):
                       "results": res}), flush=True)
 
 
+WORKLOAD_TEXT = {
+    "mix1000_median": "mix1000_median: n=5000/side, d=10, two 4-component unit-covariance mixtures (means U[-2,2]^10), "
+                      "l=1000 filling points uniform in the per-side bounding boxes, raw coordinates, sigma = median "
+                      "pooled pairwise distance (dense, coupled kernel), lambda1=1/l, lambda2=1/sqrt(n)",
+    "mix1000": "mix1000 (decoupled): the same draw mapped to the unit cube with sigma^2=0.005 (the kernel K is the "
+               "identity to 1e-14, so the SDP nearly decouples), lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=24)
+    ap.add_argument("--steps", type=int, default=0,
+                    help="solves per arm (instances 0..steps-1); default 4 on mix1000_median, 24 on mix1000")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mix1000",
-                    help="mix1000 (the metric line) or sweep (Section 5's synthetic sweep, its own JSON line)")
+    ap.add_argument("--iters", type=int, default=10,
+                    help="outer iterations per solve on mix1000_median (Algorithm 2 does not reach 1e-6 there)")
+    ap.add_argument("--workload", default="mix1000_median",
+                    help="mix1000_median (the metric line: fixed outer-iteration solves, iterations/s), mix1000 "
+                         "(decoupled: solves to 1e-6, solves/s) or sweep (Section 5's synthetic sweep)")
+    ap.add_argument("--no-decoupled", action="store_true",
+                    help="skip the decoupled mix1000 secondary that runs after the mix1000_median line")
+    ap.add_argument("--decoupled-steps", type=int, default=24)
     ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed32", "mixed16", "mixed", "all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the roofline pass")
-    ap.add_argument("--roofline-solves", type=int, default=3,
-                    help="solves of the final arm in the roofline pass (after the timed run)")
+    ap.add_argument("--roofline-solves", type=int, default=0,
+                    help="solves of each arm in the roofline pass (after the timed run); default 1 on "
+                         "mix1000_median, 3 on mix1000")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
                     help="1: extragradient branch on a second stream (the default of the library)")
     ap.add_argument("--precond", default="auto", choices=["auto", "none", "jacobi"],
@@ -233,29 +279,91 @@ def main():
                                    "repeat independent solves per GPU and is not part of this build)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2310_14087_amd import kotssn
-    from paper_2310_14087_amd.inputs import make_problem
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
     if a.batch:
         return batch_bench(a)
     if a.workload == "sweep":
         return sweep_bench(a)
     if a.copy_calibrate > 0:
         return copy_calibrate(a.copy_calibrate)
-    n_inst = max(1, a.steps)
-    _log(f"generating {n_inst} {a.workload} instances")
-    probs = [make_problem(a.workload, s) for s in range(n_inst)]
+    if a.workload not in WORKLOAD_TEXT:
+        raise SystemExit(f"unknown workload {a.workload}")
+    coupled = a.workload == "mix1000_median"
+    arms = ["fp64", "warm", "mixed32", "mixed16", "mixed"] if a.arm == "all" else [a.arm]
+    steps = a.steps or (4 if coupled else 24)
+    nroof = a.roofline_solves or (1 if coupled else 3)
+    main_res = run_workload(a, a.workload, arms, steps, a.iters if coupled else 200, nroof)
+    final = arms[-1]
+    fa = main_res["arms"][final]
+    if coupled:
+        value = fa["iterations_per_s"]
+        metric = ("SSN outer iterations/s at l=1000 on the median-bandwidth (coupled) workload, fixed "
+                  f"{a.iters}-iteration solves: plain FP64 vs warm-start+mixed (Algorithm 2 does not reach "
+                  "residual 1e-6 on this workload; residual after the fixed count is reported per arm)")
+        unit = "iterations/s"
+        ms_per_step = fa["ms_per_solve"]
+    else:
+        value = fa["solves_per_s"]
+        metric = "SSN solves/s to residual<=1e-6 at l=1000: plain FP64 vs warm-start+mixed"
+        unit = "solves/s"
+        ms_per_step = fa["ms_per_solve"]
+    out = {
+        "metric": metric,
+        "value": value,
+        "unit": unit,
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[a.workload] + (f"; solves capped at {a.iters} outer iterations"
+                                                            if coupled else ""),
+                   "arm": final, "instances": steps, "lanes": max(1, a.lanes), "overlap": a.overlap,
+                   "precond": a.precond, "arms": main_res["arms"]},
+    }
+    if main_res.get("roofline"):
+        out["roofline"] = main_res["roofline"]
+        out["roofline_chain"] = main_res.get("roofline_chain", {})
+        out["profile"] = main_res["profile"]
+    if coupled and not a.no_decoupled:
+        _log("decoupled secondary: mix1000 solves to 1e-6")
+        dec_arms = ["fp64", "mixed"] if a.arm == "all" else arms
+        dec = run_workload(a, "mix1000", dec_arms, a.decoupled_steps, 200, 0)
+        out["config"]["decoupled"] = {
+            "workload": WORKLOAD_TEXT["mix1000"], "metric": "SSN solves/s to residual<=1e-6 (decoupled)",
+            "arms": {k: {q: v[q] for q in ("solves_per_s", "ms_per_solve", "converged", "iters",
+                                          "lowp_directions", "warm_used") if q in v}
+                     for k, v in dec["arms"].items() if isinstance(v, dict)},
+            "speedup_mixed_vs_fp64": dec["arms"].get("speedup_mixed_vs_fp64")}
+    if not a.no_cpu_baseline:
+        _log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(a.workload, min(a.iters, 3) if coupled else None)
+    print(json.dumps(out), flush=True)
+
+
+def run_workload(a, workload, arms, steps, max_iter, nroof):
+    """Each arm's `steps` solves (instances 0..steps-1, capped at max_iter outer iterations) one at a time on one
+    context, then as independent solves in flight on `lanes` lanes of kot_solve_batched; the rates reported are
+    the lanes pass's whole-job throughput.  With nroof > 0 a pass of nroof solves per arm on one stream times
+    every launch with HIP events (outside the timed runs) for the roofline."""
+    import numpy as np
+    import torch
+    from paper_2310_14087_amd import kotssn
+    from paper_2310_14087_amd.inputs import make_problem
+
+    dev = torch.device("cuda:0")
+    _log(f"generating {steps} {workload} instances")
+    probs = [make_problem(workload, s) for s in range(steps)]
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     dev_inputs = [(t(p.xs), t(p.ys), t(p.xf), t(p.yf)) for p in probs]
     torch.cuda.synchronize()
-
     ctx = kotssn.Context(0)
-    base = [dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol) for p in probs]
-    arms = ["fp64", "warm", "mixed32", "mixed16", "mixed"] if a.arm == "all" else [a.arm]
+    base = [dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, max_iter=max_iter) for p in probs]
     theta_dev, H = None, 0
     if any(x != "fp64" for x in arms):
         from paper_2310_14087_amd import warmstart
@@ -277,131 +385,112 @@ def main():
         return kotssn.default_params(**kw)
 
     def run_arm(arm):
-        """The arm's `steps` solves one after another on the main context (`overlap` as given), then, with
-        lanes > 1, the same solves again through kot_solve_batched: independent instances on `lanes` child
-        contexts, each with its own stream and host thread.  Returns (sequential results, seconds), and the
-        lanes' (results, seconds) or None."""
         for w in range(a.warmup):
-            _log(f"{arm} warmup {w}")
-            ctx.solve(*dev_inputs[w % n_inst], params(w % n_inst, arm))
+            _log(f"{workload} {arm} warmup {w}")
+            ctx.solve(*dev_inputs[w % steps], params(w % steps, arm))
         torch.cuda.synchronize()
         results = []
         t0 = time.perf_counter()
-        for k in range(a.steps):
-            i = k % n_inst
-            _, _, r = ctx.solve(*dev_inputs[i], params(i, arm))
+        for k in range(steps):
+            _, _, r = ctx.solve(*dev_inputs[k], params(k, arm))
             results.append(r)
-            _log(f"{arm} step {k}: instance {i} status={r.status} iters={r.iters} warm_used={r.warm_used} "
-                 f"residual={r.residual:.2e} ot={r.ot:.10g} device_ms={r.time_ms:.1f}")
+            _log(f"{workload} {arm} step {k}: status={r.status} iters={r.iters} warm_used={r.warm_used} "
+                 f"residual={r.residual:.3e} ot={r.ot:.10g} |alpha|={r.alpha_last} lowp={r.lowp_directions} "
+                 f"device_ms={r.time_ms:.1f}")
         torch.cuda.synchronize()
         seq = (results, time.perf_counter() - t0)
         if a.lanes <= 1:
             return seq, None
-        idx = [k % n_inst for k in range(a.steps)]
-        batch_in = [dev_inputs[i] for i in idx]
-        batch_prm = [params(i, arm) for i in idx]
-        nw = min(a.lanes, a.steps)
+        batch_prm = [params(i, arm) for i in range(steps)]
+        nw = min(a.lanes, steps)
         for w in range(a.warmup):  # every lane gets a solve: its workspace and GEMM unit lists exist before timing
-            ctx.solve_batched(batch_in[:nw], batch_prm[:nw], lanes=a.lanes)
+            ctx.solve_batched(dev_inputs[:nw], batch_prm[:nw], lanes=a.lanes)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = ctx.solve_batched(batch_in, batch_prm, lanes=a.lanes)
+        out = ctx.solve_batched(dev_inputs, batch_prm, lanes=a.lanes)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         lres = [r for _, r in out]
         for k, r in enumerate(lres):
-            _log(f"{arm} lanes solve {k}: instance {idx[k]} status={r.status} iters={r.iters} "
-                 f"residual={r.residual:.2e} ot={r.ot:.10g}")
+            _log(f"{workload} {arm} lanes solve {k}: status={r.status} iters={r.iters} residual={r.residual:.3e} "
+                 f"ot={r.ot:.10g}")
         return seq, (lres, el)
 
     def roofline_pass(arm):
-        """Per-class launch timing with HIP events around every launch, outside the timed loop and on one
-        stream (overlap=0), so that each launch's duration is its own and no event lands in the timed run."""
         ctx.profile_start()
         t0 = time.perf_counter()
-        for k in range(a.roofline_solves):
-            i = k % n_inst
-            prm = params(i, arm)
+        for k in range(nroof):
+            prm = params(k % steps, arm)
             prm.overlap = 0
-            ctx.solve(*dev_inputs[i], prm)
+            ctx.solve(*dev_inputs[k % steps], prm)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return ctx.profile_stop(), wall
 
     out_arms = {}
-    prof = None
-    elapsed = None
+    profs = {}
     for arm in arms:
         (sres, sel), lan = run_arm(arm)
         results, el = lan if lan else (sres, sel)
-        ok = lambda rs: sum(1 for r in rs if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
-        conv = ok(results)
-        out_arms[arm] = dict(solves_per_s=a.steps / el, ms_per_solve=1e3 * el / a.steps, converged=conv,
-                             iters=[r.iters for r in results], eig_sweeps=[r.eig_sweeps_total for r in results],
+        conv = sum(1 for r in results if r.status == kotssn.KOT_OK and r.residual <= 1e-6)
+        its = sum(r.iters for r in results)
+        out_arms[arm] = dict(solves_per_s=steps / el, iterations_per_s=its / el, ms_per_solve=1e3 * el / steps,
+                             converged=conv, iters=[r.iters for r in results],
+                             residual=[float(f"{r.residual:.4e}") for r in results],
+                             eig_sweeps=[r.eig_sweeps_total for r in results],
                              cg_iters=[r.cg_iters_total for r in results],
-                             lowp_directions=[r.lowp_directions for r in results], ot=[r.ot for r in results])
+                             alpha_last=[r.alpha_last for r in results],
+                             lowp_directions=[r.lowp_directions for r in results],
+                             warm_used=[r.warm_used for r in results], ot=[r.ot for r in results])
         if lan:
             out_arms[arm]["sequential"] = dict(
-                solves_per_s=a.steps / sel, ms_per_solve=1e3 * sel / a.steps, converged=ok(sres),
+                solves_per_s=steps / sel, iterations_per_s=sum(r.iters for r in sres) / sel,
+                ms_per_solve=1e3 * sel / steps,
                 ot_max_abs_diff_vs_lanes=max(abs(x.ot - y.ot) for x, y in zip(sres, results)))
-        if arm == arms[-1]:
-            elapsed, final = el, arm
-            if not a.no_profile:
-                _log(f"{arm}: roofline pass ({a.roofline_solves} solves, one stream, events on every launch)")
-                prof, prof_wall = roofline_pass(arm)
-        _log(f"{arm}: {a.steps / el:.2f} solves/s, {conv}/{a.steps} converged"
-             + (f" ({a.lanes} lanes; one at a time {a.steps / sel:.2f} solves/s)" if lan else ""))
+        if nroof > 0 and not a.no_profile:
+            _log(f"{workload} {arm}: roofline pass ({nroof} solves, one stream, events on every launch)")
+            profs[arm] = roofline_pass(arm)
+        _log(f"{workload} {arm}: {steps / el:.3f} solves/s, {its / el:.2f} iterations/s, {conv}/{steps} converged"
+             + (f" ({a.lanes} lanes; one at a time {steps / sel:.3f} solves/s)" if lan else ""))
     ctx.close()
     if "fp64" in out_arms:
         for arm in ("warm", "mixed32", "mixed16", "mixed"):
             if arm in out_arms:
                 out_arms[arm]["ot_rel_dev_vs_fp64"] = max(
                     abs(x - y) / abs(y) for x, y in zip(out_arms[arm]["ot"], out_arms["fp64"]["ot"]))
-                out_arms[f"speedup_{arm}_vs_fp64"] = out_arms[arm]["solves_per_s"] / out_arms["fp64"]["solves_per_s"]
-    value = a.steps / elapsed
-    out = {
-        "metric": "SSN solves/s to residual<=1e-6 at l=1000: plain FP64 vs warm-start+mixed",
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": 1e3 * elapsed / a.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{a.workload}: n=5000/side, d=10, two 4-component mixtures, l=1000, "
-                               f"sigma^2=0.005 on unit-cube data, lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
-                   "arm": final, "instances": n_inst, "lanes": max(1, a.lanes), "overlap": a.overlap,
-                   "precond": a.precond,
-                   "arms": out_arms},
-    }
-    if prof:
-        dom = max(prof, key=lambda c: prof[c]["ms"])
-        pc = prof[dom]
-        bound, peak, unit = CLASS_ROOF[dom]
-        sec = pc["ms"] * 1e-3
-        if bound == "hbm":
-            ach = pc["bytes"] / sec / 1e9 if sec > 0 else 0.0
-        else:
-            ach = pc["flops"] / sec / 1e12 if sec > 0 else 0.0
-        nl = max(1, pc["launches"])
-        out["roofline"] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-                           "traffic": gemm_traffic() if dom == "gemm_f64" else None,
-                           "traffic_unit": "HBM bytes per call", "kernel": dom, "launches": pc["launches"],
-                           "avg_launch_us": 1e6 * sec / nl, "flops_per_launch": pc["flops"] / nl,
-                           "algorithmic_bytes_per_launch": pc["bytes"] / nl, "share_of_pass": sec / prof_wall,
-                           "measured_on": f"{a.roofline_solves} solves of the {final} arm after the timed run, "
-                                          "one stream, HIP events around each launch"}
-        out["profile"] = {c: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                              "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0}
-                          for c, v in prof.items()}
-    if not a.no_cpu_baseline:
-        _log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(a.workload)
-    print(json.dumps(out), flush=True)
+                key = "iterations_per_s" if max_iter < 200 else "solves_per_s"
+                out_arms[f"speedup_{arm}_vs_fp64"] = out_arms[arm][key] / out_arms["fp64"][key]
+    res = {"arms": out_arms}
+    final = arms[-1]
+    if final in profs:
+        prof, wall = profs[final]
+        res["roofline"] = roofline_entry(prof, max(prof, key=lambda c: prof[c]["ms"]), wall,
+                                         f"{nroof} solves of the {final} arm after the timed run, one stream, HIP "
+                                         "events around each launch")
+        chain = {}
+        for arm, cls in (("fp64", "chain_f64"), ("mixed32", "gemm_f32"), ("mixed16", "gemm_bf16"),
+                         ("mixed", "gemm_bf16")):
+            if arm in profs and profs[arm][0][cls]["launches"] > 0:
+                chain[f"{arm}:{cls}"] = roofline_entry(profs[arm][0], cls, profs[arm][1],
+                                                       f"{nroof} solves of the {arm} arm, one stream")
+        res["roofline_chain"] = chain
+        res["profile"] = {arm: {c: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                                    "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0}
+                                for c, v in pr.items()} for arm, (pr, _) in profs.items()}
+    return res
+
+
+def roofline_entry(prof, cls, wall, how):
+    pc = prof[cls]
+    bound, peak, unit = CLASS_ROOF[cls]
+    sec = pc["ms"] * 1e-3
+    ach = (pc["bytes"] / sec / 1e9 if bound == "hbm" else pc["flops"] / sec / 1e12) if sec > 0 else 0.0
+    nl = max(1, pc["launches"])
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": class_traffic(cls), "traffic_unit": "HBM bytes per launch", "kernel": cls,
+            "launches": pc["launches"], "avg_launch_us": 1e6 * sec / nl, "flops_per_launch": pc["flops"] / nl,
+            "algorithmic_bytes_per_launch": pc["bytes"] / nl, "share_of_pass": sec / wall if wall > 0 else 0.0,
+            "measured_on": how}
 
 
 if __name__ == "__main__":

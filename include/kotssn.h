@@ -96,6 +96,8 @@ typedef struct kot_params {
                           lower precision and the FP64 CG runs instead (default 64; 0 = always) */
   int precond;         /* kot_precond of the Schur-system solver (default KOT_PRECOND_NONE) */
   int schur_solver;    /* a kot_schur_solver value; default KOT_SCHUR_CG */
+  int eig_inner_sweeps; /* cap on the cyclic Jacobi sweeps a 16x16 block-pair subproblem gets per visit of the
+                           eigensolver (default 1; a visit also ends after a sweep that rotated nothing) */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:

@@ -54,6 +54,12 @@ __device__ __forceinline__ void circle16(int r, int k, int& a, int& b) {
 }
 
 // With an explicit list, pairs k >= kact only complete the partition of the blocks: they rotate nothing.
+// One wavefront per pair runs cyclic Jacobi on the 16x16 subproblem S (circle ordering: 8 disjoint rotations
+// per sub-round).  A sub-round takes two barriers: lanes 0-7 form the rotations J_k = [[c, s], [-s, c]] of
+// their index pairs (a_k < b_k), then every lane applies S <- J^T S J to one 2x2 block (rows of pair lane/8,
+// columns of pair lane%8; the blocks are disjoint, so the two-sided update is one read and one write of each
+// entry) and U <- U J to two 2-column row segments.  The annihilated entries of the diagonal blocks are set
+// to zero exactly.  Inner sweeps stop after a sweep that rotated nothing, or after max_inner sweeps.
 __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __restrict__ A, int round, int nb,
                                                         const int2* __restrict__ list, int kact,
                                                         double* __restrict__ Uout, int* __restrict__ flag,
@@ -66,13 +72,14 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
   __shared__ double S[SLOT][SLOT + 1];
   __shared__ double U[SLOT][SLOT + 1];
   __shared__ double cs[8][2];
+  __shared__ int ab[8][2];
   __shared__ int idx[SLOT];
-  __shared__ int any_rot;
+  __shared__ int rot_sweep[2];
   const int k = blockIdx.x;
   const int2 pq = get_pair(round, nb, list, k);
   const int lane = threadIdx.x;
   if (lane < SLOT) idx[lane] = pair_slot_index(pq.x, pq.y, lane, l);
-  if (lane == 0) any_rot = 0;
+  if (lane < 2) rot_sweep[lane] = 0;
   __syncthreads();
   // the four loads of a lane are issued together (register buffer), then staged
   double sv[4];
@@ -89,176 +96,171 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
     U[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
+  const int k1 = lane >> 3, k2 = lane & 7;      // this lane's 2x2 block of S
+  const int ur = lane >> 2, uk = (lane & 3) * 2;  // this lane's U row and first of its two pairs
+  bool rotated_any = false;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
-    // largest off-diagonal magnitude of the subproblem
-    double mx = 0.0;
-    for (int u = lane; u < SLOT * SLOT; u += 64) {
-      const int i = u >> 4, j = u & 15;
-      if (i != j) mx = fmax(mx, fabs(S[i][j]));
-    }
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    if (mx <= thresh) break;
+    const int par = sweep & 1;
     for (int r = 0; r < 15; ++r) {
       if (lane < 8) {
         int a, b;
         circle16(r, lane, a, b);
         if (a > b) { const int t = a; a = b; b = t; }
         const double apq = S[a][b];
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         if (fabs(apq) > thresh) {
           const double theta = (S[b][b] - S[a][a]) / (2.0 * apq);
           const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
-          any_rot = 1;
+          sn = t * c;
+          rot_sweep[par] = 1;
         }
         cs[lane][0] = c;
-        cs[lane][1] = s;
+        cs[lane][1] = sn;
+        ab[lane][0] = a;
+        ab[lane][1] = b;
       }
       __syncthreads();
-      // columns: S <- S J, U <- U J   (16 rows x 8 pairs, 2 tasks per lane)
-      for (int u = lane; u < 128; u += 64) {
-        const int row = u >> 3, pk = u & 7;
-        int a, b;
-        circle16(r, pk, a, b);
-        if (a > b) { const int t = a; a = b; b = t; }
-        const double c = cs[pk][0], s = cs[pk][1];
-        if (s != 0.0) {
-          const double x = S[row][a], y = S[row][b];
-          S[row][a] = c * x - s * y;
-          S[row][b] = s * x + c * y;
-          const double ux = U[row][a], uy = U[row][b];
-          U[row][a] = c * ux - s * uy;
-          U[row][b] = s * ux + c * uy;
+      {
+        const int a1 = ab[k1][0], b1 = ab[k1][1], a2 = ab[k2][0], b2 = ab[k2][1];
+        const double c1 = cs[k1][0], s1 = cs[k1][1], c2 = cs[k2][0], s2 = cs[k2][1];
+        if (s1 != 0.0 || s2 != 0.0) {
+          const double xaa = S[a1][a2], xab = S[a1][b2], xba = S[b1][a2], xbb = S[b1][b2];
+          // rows: J1^T x
+          const double yaa = c1 * xaa - s1 * xba, yab = c1 * xab - s1 * xbb;
+          const double yba = s1 * xaa + c1 * xba, ybb = s1 * xab + c1 * xbb;
+          // columns: (J1^T x) J2
+          double zaa = c2 * yaa - s2 * yab, zab = s2 * yaa + c2 * yab;
+          double zba = c2 * yba - s2 * ybb, zbb = s2 * yba + c2 * ybb;
+          if (k1 == k2 && s1 != 0.0) { zab = 0.0; zba = 0.0; }
+          S[a1][a2] = zaa; S[a1][b2] = zab; S[b1][a2] = zba; S[b1][b2] = zbb;
         }
-      }
-      __syncthreads();
-      // rows: S <- J^T S; the annihilated pair (a, b), (b, a) is set to zero exactly
-      for (int u = lane; u < 128; u += 64) {
-        const int col = u >> 3, pk = u & 7;
-        int a, b;
-        circle16(r, pk, a, b);
-        if (a > b) { const int t = a; a = b; b = t; }
-        const double c = cs[pk][0], s = cs[pk][1];
-        if (s != 0.0) {
-          const double x = S[a][col], y = S[b][col];
-          S[a][col] = (col == b) ? 0.0 : c * x - s * y;
-          S[b][col] = (col == a) ? 0.0 : s * x + c * y;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kk = uk + h;
+          const double c = cs[kk][0], sn = cs[kk][1];
+          if (sn != 0.0) {
+            const int a = ab[kk][0], b = ab[kk][1];
+            const double ux = U[ur][a], uy = U[ur][b];
+            U[ur][a] = c * ux - sn * uy;
+            U[ur][b] = sn * ux + c * uy;
+          }
         }
       }
       __syncthreads();
     }
+    // rot_sweep[par] was last written before the barrier above; the other slot is cleared for the next sweep
+    const bool any = rot_sweep[par] != 0;
+    if (lane == 0) rot_sweep[par ^ 1] = 0;
+    __syncthreads();
+    if (!any) break;
+    rotated_any = true;
   }
   double* Uk = Uout + (long long)k * SLOT * SLOT;
   for (int u = lane; u < SLOT * SLOT; u += 64) Uk[u] = U[u >> 4][u & 15];
-  if (lane == 0) flag[k] = any_rot;
+  if (lane == 0) flag[k] = rotated_any ? 1 : 0;
 }
 
-// A_PQ <- U_P^T A_PQ U_Q for the pair-block tile (P, Q); a pair without rotations (flag 0) acts as the
-// identity, so its U is not read.
-__device__ __forceinline__ void apply_A_tile(int l, double* __restrict__ A, int round, int nb, const int2* __restrict__ list,
-                                             const double* __restrict__ Ub, const int* __restrict__ flag, int P, int Qb) {
-  const bool fP = flag[P] != 0, fQ = flag[Qb] != 0;
-  if (!fP && !fQ) return;
-  __shared__ double M[SLOT][SLOT + 1];
-  __shared__ double T[SLOT][SLOT + 1];
-  __shared__ int ip[SLOT], iq[SLOT];
-  const int lane = threadIdx.x;
-  const int2 pp = get_pair(round, nb, list, P), qq = get_pair(round, nb, list, Qb);
+// One launch per round for both updates (A and V are separate arrays).  Workgroup (x, y) has four wavefronts;
+// wavefront w takes item i = 4 x + w of pair row P = y: for i < np the A tile (P, Q = i),
+//   A_PQ <- U_P^T A_PQ U_Q,
+// for np <= i < np + nslab the 16-row slab r0 = 16 (i - np) of V,
+//   V[r0.., idx_P] <- V[r0.., idx_P] U_P.
+// A pair without rotations (flag 0) acts as the identity, so its U is not read; an item with nothing to rotate
+// does no loads.  Each 16x16 product is four v_mfma_f64_16x16x4f64 steps (accumulator lane L holds rows
+// L/16 + 4v, v = 0..3, of column L%16).  The barriers are uniform over the four wavefronts.
+__global__ __launch_bounds__(256) void apply_kernel(int l, int np, int nslab, double* __restrict__ A,
+                                                    double* __restrict__ V, int round, int nb,
+                                                    const int2* __restrict__ list, const double* __restrict__ Ub,
+                                                    const int* __restrict__ flag) {
+  __shared__ double Ms[4][SLOT][SLOT + 1];
+  __shared__ double Ts[4][SLOT][SLOT + 1];
+  __shared__ int ips[4][SLOT], iqs[4][SLOT];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int P = blockIdx.y;
+  const int item = (int)blockIdx.x * 4 + wv;
+  const bool isA = item < np, isV = !isA && item < np + nslab;
+  const bool fP = flag[P] != 0;
+  const bool fQ = isA && flag[item] != 0;
+  const bool act = isA ? (fP || fQ) : (isV && fP);
+  double (*M)[SLOT + 1] = Ms[wv];
+  double (*T)[SLOT + 1] = Ts[wv];
+  int* ip = ips[wv];
+  int* iq = iqs[wv];
+  const int2 pp = get_pair(round, nb, list, P);
   if (lane < SLOT) {
     ip[lane] = pair_slot_index(pp.x, pp.y, lane, l);
-    iq[lane] = pair_slot_index(qq.x, qq.y, lane, l);
+    if (isA) {
+      const int2 qq = get_pair(round, nb, list, item);
+      iq[lane] = pair_slot_index(qq.x, qq.y, lane, l);
+    }
   }
   __syncthreads();
-  double mv[4];
+  const int r0 = isV ? (item - np) * SLOT : 0;
+  if (act) {
+    double mv[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int u = lane + 64 * q, i = u >> 4, j = u & 15;
-    const int gi = ip[i], gj = iq[j];
-    mv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
-  }
+    for (int q = 0; q < 4; ++q) {
+      const int u = lane + 64 * q, i = u >> 4, j = u & 15;
+      if (isA) {
+        const int gi = ip[i], gj = iq[j];
+        mv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
+      } else {
+        const int gj = ip[j];
+        mv[q] = (r0 + i < l && gj >= 0) ? V[(long long)(r0 + i) * l + gj] : 0.0;
+      }
+    }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int u = lane + 64 * q;
-    M[u >> 4][u & 15] = mv[q];
+    for (int q = 0; q < 4; ++q) {
+      const int u = lane + 64 * q;
+      M[u >> 4][u & 15] = mv[q];
+    }
   }
   __syncthreads();
-  const double* UP = Ub + (long long)P * SLOT * SLOT;
-  const double* UQ = Ub + (long long)Qb * SLOT * SLOT;
   const int r16 = lane & 15, k4 = lane >> 4;
-  if (fQ) {
+  const double* UP = Ub + (long long)P * SLOT * SLOT;
+  if (act && isA) {
+    if (fQ) {
+      const double* UQ = Ub + (long long)item * SLOT * SLOT;
+      dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < SLOT; ks += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UQ[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = acc[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = M[k4 + 4 * v][r16];
+    }
+  } else if (act) {  // V slab: one product
     dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < SLOT; ks += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UQ[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UP[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = acc[v];
-  } else {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = M[k4 + 4 * v][r16];
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + k4 + 4 * v, gj = ip[r16];
+      if (row < l && gj >= 0) V[(long long)row * l + gj] = acc[v];
+    }
   }
   __syncthreads();
-  dbl4 acc2;
-  if (fP) {
-    acc2 = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (act && isA) {
+    dbl4 acc2;
+    if (fP) {
+      acc2 = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ks = 0; ks < SLOT; ks += 4)
-      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(UP[(ks + k4) * SLOT + r16], T[ks + k4][r16], acc2, 0, 0, 0);
-  } else {
+      for (int ks = 0; ks < SLOT; ks += 4)
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(UP[(ks + k4) * SLOT + r16], T[ks + k4][r16], acc2, 0, 0, 0);
+    } else {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc2[v] = T[k4 + 4 * v][r16];
+      for (int v = 0; v < 4; ++v) acc2[v] = T[k4 + 4 * v][r16];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = ip[k4 + 4 * v], gj = iq[r16];
+      if (gi >= 0 && gj >= 0) A[(long long)gi * l + gj] = acc2[v];
+    }
   }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int gi = ip[k4 + 4 * v], gj = iq[r16];
-    if (gi >= 0 && gj >= 0) A[(long long)gi * l + gj] = acc2[v];
-  }
-}
-
-// V[R, idx_P] <- V[R, idx_P] U_P for the 16-row slab R starting at r0.
-__device__ __forceinline__ void apply_V_slab(int l, double* __restrict__ V, int round, int nb, const int2* __restrict__ list,
-                                             const double* __restrict__ Ub, const int* __restrict__ flag, int P, int r0) {
-  if (!flag[P]) return;
-  __shared__ double M[SLOT][SLOT + 1];
-  __shared__ int ip[SLOT];
-  const int lane = threadIdx.x;
-  const int2 pp = get_pair(round, nb, list, P);
-  if (lane < SLOT) ip[lane] = pair_slot_index(pp.x, pp.y, lane, l);
-  __syncthreads();
-  double mv[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int u = lane + 64 * q, i = u >> 4, j = u & 15;
-    const int gj = ip[j];
-    mv[q] = (r0 + i < l && gj >= 0) ? V[(long long)(r0 + i) * l + gj] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int u = lane + 64 * q;
-    M[u >> 4][u & 15] = mv[q];
-  }
-  __syncthreads();
-  const double* UP = Ub + (long long)P * SLOT * SLOT;
-  const int r16 = lane & 15, k4 = lane >> 4;
-  dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int ks = 0; ks < SLOT; ks += 4)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UP[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = r0 + k4 + 4 * v, gj = ip[r16];
-    if (row < l && gj >= 0) V[(long long)row * l + gj] = acc[v];
-  }
-}
-
-// One launch per round for both updates (A and V are separate arrays): workgroups x < np take the A tiles
-// (P = y, Q = x), the rest take the 16-row slabs of V for pair y.
-__global__ __launch_bounds__(64) void apply_kernel(int l, int np, double* __restrict__ A, double* __restrict__ V,
-                                                   int round, int nb, const int2* __restrict__ list,
-                                                   const double* __restrict__ Ub, const int* __restrict__ flag) {
-  const int P = blockIdx.y;
-  if ((int)blockIdx.x < np) apply_A_tile(l, A, round, nb, list, Ub, flag, P, blockIdx.x);
-  else apply_V_slab(l, V, round, nb, list, Ub, flag, P, ((int)blockIdx.x - np) * SLOT);
 }
 
 // Sums of squares of A over the BSZ x BSZ blocks (b1, b2 >= b1): off-diagonal entries (boff), all entries,
@@ -408,6 +410,7 @@ struct EigWork {
   int lmax = 0;
   // one captured full-tournament sweep (all rounds) per (l, A/V buffers); replayed with hipGraphLaunch
   int graph_l = -1;
+  int graph_inner = -1;
   const double* graph_tmp = nullptr;
   hipGraphExec_t graph = nullptr;
   bool graph_failed = false;
@@ -570,7 +573,8 @@ static bool threshold_schedule(EigWork* w, int nb, double tau2) {
 }
 
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
-                       int max_sweeps, double tol, int* sweeps, double* rel_off, int* npos, hipStream_t st) {
+                       int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off, int* npos,
+                       hipStream_t st) {
   if (l > w->lmax) return hipErrorInvalidValue;
   double* A = tmp;
   double* V = tmp + (long long)l * l;
@@ -630,9 +634,10 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   const double thresh_rel = 1e-18;
   auto launch_round = [&](hipStream_t s_, int r, const int2* list, int kact) -> hipError_t {
     hipLaunchKernelGGL(pair_solve_kernel, dim3(np), dim3(64), 0, s_, l, A, r, nb, list, kact, w->U, w->flag,
-                       w->up, 8);
+                       w->up, inner_sweeps);
     KOT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(apply_kernel, dim3(np + nslab, np), dim3(64), 0, s_, l, np, A, V, r, nb, list, w->U, w->flag);
+    hipLaunchKernelGGL(apply_kernel, dim3((np + nslab + 3) / 4, np), dim3(256), 0, s_, l, np, nslab, A, V, r, nb, list,
+                       w->U, w->flag);
     return hipGetLastError();
   };
   auto launch_sweep = [&](hipStream_t s_) -> hipError_t {
@@ -651,17 +656,19 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     if (threshold_schedule(w, nb, tau2)) {
       const int R = (int)w->round_k.size();
       KOT_HIP_TRY(vec_copy(2 + R * np, w->hup_dev, w->up, st));  // threshold and pair lists
-      double fl = 0.0;
+      double fl = 0.0, by = 0.0;
       for (int r = 0; r < R; ++r) {
         const double k = w->round_k[r];
         fl += 8192.0 * (2.0 * k * k + 2.0 * k * (np - k) + k * nslab);
+        by += 4096.0 * ((double)np * np - (np - k) * (np - k) + k * nslab);  // tiles read and written
       }
-      if (pf) pf->begin(st, PROF_EIG_ROUND, fl, 0.0);
+      if (pf) pf->begin(st, PROF_EIG_ROUND, fl, by);
       for (int r = 0; r < R; ++r) KOT_HIP_TRY(launch_round(st, 0, w->list + (size_t)r * np, w->round_k[r]));
       if (pf) pf->end(st);
     } else {
       KOT_HIP_TRY(vec_copy(2, w->hup_dev, w->up, st));  // threshold
-      if (!w->graph_failed && (w->graph == nullptr || w->graph_l != l || w->graph_tmp != tmp)) {
+      if (!w->graph_failed &&
+          (w->graph == nullptr || w->graph_l != l || w->graph_tmp != tmp || w->graph_inner != inner_sweeps)) {
         if (w->graph) { hipGraphExecDestroy(w->graph); w->graph = nullptr; }
         hipGraph_t gr = nullptr;
         bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
@@ -684,6 +691,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
         } else {
           w->graph_l = l;
           w->graph_tmp = tmp;
+          w->graph_inner = inner_sweeps;
         }
       }
       if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, 32.0 * l * (double)l * (nb - 1));

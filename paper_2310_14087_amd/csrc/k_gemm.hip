@@ -588,7 +588,9 @@ hipEvent_t Profiler::get() {
   }
   return pool[next++];
 }
+thread_local int g_prof_chain = 0;
 void Profiler::begin(hipStream_t st, int cls, double flops, double bytes) {
+  if (g_prof_chain && cls == PROF_GEMM_F64) cls = PROF_CHAIN_F64;
   Rec r{cls, flops, bytes, get(), get()};
   if (r.a) hipEventRecord(r.a, st);
   recs.push_back(r);

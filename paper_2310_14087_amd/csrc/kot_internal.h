@@ -8,8 +8,10 @@
 namespace kot {
 
 // ---- optional launch profiler (events around kernel launches on the issuing stream) -----------------------
+// PROF_CHAIN_F64: the FP64 GEMMs of the Schur matvec's eigen-row chain (counted apart from the other FP64
+// GEMMs while g_prof_chain is set on the issuing thread).
 enum ProfClass { PROF_GEMM_F64 = 0, PROF_EIG_ROUND = 1, PROF_GEMV_F64 = 2, PROF_GEMM_F32 = 3, PROF_GEMM_BF16 = 4,
-                 PROF_POTENTIAL = 5, PROF_NCLASS = 6 };
+                 PROF_POTENTIAL = 5, PROF_CHAIN_F64 = 6, PROF_NCLASS = 7 };
 struct Profiler {
   bool on = false;
   struct Rec { int cls; double flops; double bytes; hipEvent_t a, b; };
@@ -24,6 +26,7 @@ struct Profiler {
   ~Profiler();
 };
 extern thread_local Profiler* g_prof;
+extern thread_local int g_prof_chain;
 
 // ---- GEMM (FP64 MFMA): C = alpha * op(A) * diag(s) * op(B) + beta * C, row-major --------------------------
 // Batched over grid.z with element strides sA, sB, sS, sC (0 for a shared operand).  lower != 0: only the
@@ -95,7 +98,8 @@ void eig_work_destroy(EigWork* w);
 // of positive eigenvalues through *npos (may be null); the host has synchronized with the stream on return.
 // tmp: workspace of at least 2*l*l doubles.
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
-                       int max_sweeps, double tol, int* sweeps, double* rel_off, int* npos, hipStream_t st);
+                       int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off, int* npos,
+                       hipStream_t st);
 
 // ---- vector kernels -----------------------------------------------------------------------------------------
 hipError_t vec_fill(int n, double v, double* x, hipStream_t st);

@@ -43,7 +43,7 @@ class KotParams(C.Structure):
                 ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int), ("lift_x0", C.c_int), ("ws_F", C.c_int),
                 ("ws_H", C.c_int), ("ws_theta", C.c_void_p), ("overlap", C.c_int),
                 ("lowp_min_rows", C.c_int), ("precond", C.c_int),
-                ("schur_solver", C.c_int)]
+                ("schur_solver", C.c_int), ("eig_inner_sweeps", C.c_int)]
 
 
 class KotProblem(C.Structure):
@@ -376,7 +376,7 @@ class Context:
                                             _ptr(u), _ptr(v), _ptr(T)))
         return u, v, T
 
-    PROFILE_CLASSES = ("gemm_f64", "eig_sweep", "gemv_f64", "gemm_f32", "gemm_bf16", "potential")
+    PROFILE_CLASSES = ("gemm_f64", "eig_sweep", "gemv_f64", "gemm_f32", "gemm_bf16", "potential", "chain_f64")
 
     def profile_start(self):
         self._check(self.lib.kot_profile(self.h, 1, None, 0))

@@ -48,12 +48,33 @@ def test_params_default_host_only(lib):
     assert p.schur_solver == kotssn.KOT_SCHUR_CG
 
 
-def test_struct_layouts_match_header():
-    """ctypes mirrors of the C structs have the sizes the header implies (field order / padding)."""
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the C structs have the size and every field offset that a C compiler gives the header."""
+    import shutil
+    import subprocess
     from paper_2310_14087_amd import kotssn
-    assert C.sizeof(kotssn.KotParams) == 8 * 5 + 4 * 2 + 8 * 11 + 4 * 8 + 8 + 8 + 8  # precond, schur_solver
-    assert C.sizeof(kotssn.KotProblem) == 16 + 4 * 8
-    assert C.sizeof(kotssn.KotResult) == 8 * 4 + 8 + 8 + 8 + 4 * 8 + 8
+    gcc = shutil.which("gcc") or shutil.which("cc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"kot_params": kotssn.KotParams, "kot_problem": kotssn.KotProblem, "kot_result": kotssn.KotResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kotssn.h"', "int main(void) {"]
+    for cname, ct in mirrors.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in ct._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, ct in mirrors.items():
+        assert got[(cname, "sizeof")] == C.sizeof(ct), cname
+        for fname, _ in ct._fields_:
+            assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)
 
 
 def test_null_arguments_are_rejected_without_a_device(lib):

@@ -123,6 +123,46 @@ def test_eigh(gpu_ctx, l):
     assert np.abs(P.T @ P - np.eye(l)).max() <= 1e-13 * max(1, l ** 0.5)
 
 
+def _coupled_z(l, n):
+    """A dense Z of the hot path: the median-bandwidth workload's Z = X - Phi*(gamma) - lambda1 I at the first
+    regularized Newton trial from the cold start (mixed signs, a cluster of eigenvalues near zero)."""
+    p = make_problem("mix1000_median", 0, l=l, n=n)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    g = np.zeros(core.l)
+    X = np.zeros((core.l, core.l))
+    r1, r2, rn, eig = ko.residual(core, g, X)
+    dg, dX, _ = ko.ssn_direction(core, r1, r2, eig, rn, ko.Params())
+    g, X = g + dg, X + dX
+    return X - ko.phi_star(core.R, g) - core.lam1 * np.eye(core.l)
+
+
+@pytest.mark.parametrize("kind,l,inner", [("random", 500, 8), ("random", 1000, 8), ("random", 1000, 1),
+                                          ("coupled", 1000, 8), ("coupled", 1000, 2)])
+def test_eigh_dense_large(gpu_ctx, kind, l, inner):
+    """Dense symmetric matrices at the hot path's size: a Gaussian random matrix and the median-bandwidth
+    workload's Z; eigenvalues against numpy's eigvalsh, the eigen-residual |Z P - P diag(w)| and the
+    orthogonality of P, with the block-pair subproblems' inner sweeps capped at `inner`."""
+    from paper_2310_14087_amd import kotssn
+    _case(f"kot_eigh dense {kind} l={l} inner={inner}")
+    if kind == "random":
+        rng = np.random.default_rng(l + 11)
+        A = rng.standard_normal((l, l))
+        Z = A + A.T
+    else:
+        Z = _coupled_z(l, 5 * l)
+        Z = 0.5 * (Z + Z.T)
+    w, P = gpu_ctx.eigh(_t(Z), kotssn.default_params(eig_inner_sweeps=inner))
+    w, P = _n(w), _n(P)
+    wref = np.linalg.eigvalsh(Z)
+    scale = np.abs(wref).max()
+    assert np.all(np.diff(w) >= 0)
+    np.testing.assert_allclose(w, wref, atol=1e-13 * scale * l ** 0.5)
+    assert np.abs(Z @ P - P * w).max() <= 1e-13 * scale * l ** 0.5
+    assert np.abs(P.T @ P - np.eye(l)).max() <= 1e-13 * l ** 0.5
+    if kind == "coupled":
+        assert (wref > 0).sum() == (w > 0).sum()     # |alpha| is the same integer
+
+
 @pytest.mark.parametrize("l,nc", [(77, 3), (300, 6), (1000, 40), (1000, 0)])
 def test_eigh_sparse(gpu_ctx, l, nc):
     """Diagonal plus a few coupled clusters (the structure of the SSN matrices when the filling points are
