@@ -185,6 +185,17 @@ kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z,
  * Jacobi sweeps do not reach the off-diagonal tolerance within prm->eig_max_sweeps (P, w still written). */
 kot_status kot_eigh(kot_ctx* ctx, int l, const double* Z, double* P, double* w, const kot_params* prm);
 
+/* kot_eigh for callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): no context, no hipMalloc/hipFree.  Its working storage is a static device
+ * array of each GPU the library runs on (4.2 MiB, held until the process ends), so l is limited to
+ * 1 <= l <= 512 (KOT_ERR_ARG beyond, with a message from kot_last_error(NULL)).  device: HIP device index
+ * (made current for the call, the previous device restored); hip_stream: a hipStream_t on that device
+ * (NULL = its default stream), synchronized before return.  Z, P (l x l) and w (l) are device pointers as in
+ * kot_eigh; the cold-start Jacobi sweeps are full tournaments.  Every call on a GPU shares that GPU's array and
+ * leaves the last call's contents in it: calls that overlap on one GPU (other threads or streams) race. */
+kot_status kot_eigh_noalloc(int device, void* hip_stream, int l, const double* Z, double* P, double* w,
+                            const kot_params* prm);
+
 /* Residual map Eq. (4.2) at w = (gamma, X): r1 = (Q gamma - z)/(2 lambda2) - Phi(X),
  * r2 = X - Pi(X - Phi*(gamma) - lambda1 I), with Phi(X)_i = R[:,i]^T X R[:,i], Phi*(gamma) = R diag(gamma) R^T.
  * Q, z, R, gamma, X, r1, r2 are device pointers; norms (host, 3 entries) receives |r1|_2, |r2|_F and

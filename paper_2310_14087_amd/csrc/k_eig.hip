@@ -16,6 +16,7 @@
 #include "kot_internal.h"
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace kot {
@@ -408,6 +409,10 @@ __global__ void permute_cols_kernel(int l, const double* __restrict__ V, const i
 
 struct EigWork {
   int lmax = 0;
+  // set for the allocation-free entry point: every device buffer below lies in the static scratch array, hb is
+  // plain host memory filled by a copy after each block-norm pass, the threshold goes up by a fill kernel, and
+  // sweeps are always full tournaments launched directly (no graph, no threshold schedule)
+  bool noalloc = false;
   // one captured full-tournament sweep (all rounds) per (l, A/V buffers); replayed with hipGraphLaunch
   int graph_l = -1;
   int graph_inner = -1;
@@ -483,6 +488,8 @@ static hipError_t block_norms(EigWork* w, int l, int nb, const double* A, hipStr
   hipLaunchKernelGGL(block_norm_kernel, dim3((nb * BSZ + 255) / 256, nb), dim3(256), 0, st, l, nb, A, w->boff,
                      w->boff + nb2, w->boff + 2 * nb2, w->dg);
   KOT_HIP_TRY(hipGetLastError());
+  if (w->noalloc)
+    KOT_HIP_TRY(hipMemcpyAsync(w->hb, w->boff, sizeof(double) * (2 * nb2 + nb), hipMemcpyDeviceToHost, st));
   KOT_HIP_TRY(hipStreamSynchronize(st));
   double so = 0.0, sa = 0.0, sp = 0.0;
   for (int b1 = 0; b1 < nb; ++b1) {
@@ -575,7 +582,7 @@ static bool threshold_schedule(EigWork* w, int nb, double tau2) {
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
                        int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off, int* npos,
                        hipStream_t st) {
-  if (l > w->lmax) return hipErrorInvalidValue;
+  if (l > w->lmax || (w->noalloc && P0)) return hipErrorInvalidValue;  // the no-alloc path has no warm start
   double* A = tmp;
   double* V = tmp + (long long)l * l;
   const long long nn = (long long)l * l;
@@ -648,12 +655,17 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * nslab * np);
   const double npairs = 0.5 * nb * (nb + 1.0);
   while (off > tol * all && s < max_sweeps) {
-    w->hup[0] = thresh_rel * all;  // the stream is idle here (block_norms synchronized it)
+    if (!w->noalloc) w->hup[0] = thresh_rel * all;  // the stream is idle here (block_norms synchronized it)
     Profiler* pf = (g_prof && g_prof->on) ? g_prof : nullptr;
     // threshold sweep over the block pairs above tau; if every pair is at or below tau, then
     // off(A)^2 <= npairs tau^2 = (tol |A|_F / 2)^2, so the stopping test is met
     const double tau2 = 0.25 * tol * tol * all * all / npairs;
-    if (threshold_schedule(w, nb, tau2)) {
+    if (w->noalloc) {
+      KOT_HIP_TRY(vec_fill(1, thresh_rel * all, w->up, st));
+      if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, 32.0 * l * (double)l * (nb - 1));
+      KOT_HIP_TRY(launch_sweep(st));
+      if (pf) pf->end(st);
+    } else if (threshold_schedule(w, nb, tau2)) {
       const int R = (int)w->round_k.size();
       KOT_HIP_TRY(vec_copy(2 + R * np, w->hup_dev, w->up, st));  // threshold and pair lists
       double fl = 0.0, by = 0.0;
@@ -706,6 +718,68 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   *rel_off = (all > 0.0) ? off / all : 0.0;
   if (npos) *npos = pos;
   return finish(V);
+}
+
+// ---- allocation-free eigendecomposition ---------------------------------------------------------------------
+// Scratch for eigh_jacobi_noalloc: one static array per device (each GPU the library runs on holds its own copy
+// until the process ends), sized for l <= kNoAllocMaxL.  Host code never uses the array's name as an address:
+// the device address comes from hipGetSymbolAddress, once per device, with that device current.
+namespace {
+constexpr int kNoAllocMaxNb = kNoAllocMaxL / BSZ;            // 64 blocks of 8
+constexpr int kNoAllocMaxNp = kNoAllocMaxNb / 2;
+constexpr size_t kNoAllocDoubles =
+    2 * (size_t)kNoAllocMaxL * kNoAllocMaxL                    // A, V
+    + (size_t)kNoAllocMaxNp * SLOT * SLOT                      // U
+    + (size_t)kNoAllocMaxL                                     // dg
+    + 2 * (size_t)kNoAllocMaxNb * kNoAllocMaxNb + kNoAllocMaxNb  // block norms
+    + 32                                                       // threshold slot (up)
+    + (size_t)kNoAllocMaxNp + kNoAllocMaxL;                    // flags and ranks (ints, two per double)
+constexpr int kNoAllocMaxDevices = 64;
+double g_noalloc_hb[2 * kNoAllocMaxNb * kNoAllocMaxNb + kNoAllocMaxNb];  // host copy of the block norms
+double* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+std::mutex g_noalloc_mu;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+size_t eigh_noalloc_scratch_bytes() { return sizeof(double) * kNoAllocDoubles; }
+
+// The calling thread's current device must be `device`.
+static hipError_t noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* ptr = nullptr;
+    KOT_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_noalloc_ptr[device];
+  return hipSuccess;
+}
+
+hipError_t eigh_jacobi_noalloc(int device, int l, const double* Z, double* P, double* wv, int max_sweeps,
+                               int inner_sweeps, double tol, int* sweeps, double* rel_off, hipStream_t st) {
+  if (l < 1 || l > kNoAllocMaxL) return hipErrorInvalidValue;
+  double* base = nullptr;
+  KOT_HIP_TRY(noalloc_scratch(device, &base));
+  const size_t ll = (size_t)kNoAllocMaxL * kNoAllocMaxL;
+  double* A = base;                      // A then V (eigh_jacobi's tmp layout: V = tmp + l*l)
+  double* cur = base + 2 * ll;
+  EigWork w;
+  w.noalloc = true;
+  w.graph_failed = true;
+  w.lmax = kNoAllocMaxL;
+  w.U = cur;    cur += (size_t)kNoAllocMaxNp * SLOT * SLOT;
+  w.dg = cur;   cur += kNoAllocMaxL;
+  w.boff = cur; cur += 2 * (size_t)kNoAllocMaxNb * kNoAllocMaxNb + kNoAllocMaxNb;
+  w.up = cur;   cur += 32;
+  w.flag = reinterpret_cast<int*>(cur);
+  w.perm = w.flag + kNoAllocMaxNp;
+  w.hb = g_noalloc_hb;
+  // symmetrized input straight into A's slot; eigh_jacobi's copy of Z into A is then in place
+  KOT_HIP_TRY(form_z(l, Z, 0.0, Z, 0.0, A, st));
+  int npos = 0;
+  return eigh_jacobi(&w, l, A, nullptr, P, wv, A, max_sweeps, inner_sweeps, tol, sweeps, rel_off, &npos, st);
 }
 
 }  // namespace kot

@@ -1290,7 +1290,46 @@ kot_status kot_destroy(kot_ctx* ctx) {
   return KOT_OK;
 }
 
-const char* kot_last_error(const kot_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+// Message of the calling thread's last failed context-free call (kot_eigh_noalloc), else "null context".
+static thread_local char g_free_err[512] = "null context";
+
+const char* kot_last_error(const kot_ctx* ctx) { return ctx ? ctx->err.c_str() : g_free_err; }
+
+static kot_status free_fail(kot_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_free_err, sizeof(g_free_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+kot_status kot_eigh_noalloc(int device, void* hip_stream, int l, const double* Z, double* P, double* w,
+                            const kot_params* p) {
+  if (!Z || !P || !w || !p) return free_fail(KOT_ERR_ARG, "kot_eigh_noalloc: null argument");
+  if (l < 1 || l > kNoAllocMaxL)
+    return free_fail(KOT_ERR_ARG, "kot_eigh_noalloc: l = %d is outside 1..%d (the size its static scratch holds)",
+                     l, kNoAllocMaxL);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return free_fail(KOT_ERR_ARG, "kot_eigh_noalloc: no HIP device %d", device);
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return free_fail(KOT_ERR_HIP, "kot_eigh_noalloc: hipGetDevice failed");
+  if (hipSetDevice(device) != hipSuccess) return free_fail(KOT_ERR_HIP, "kot_eigh_noalloc: hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int max_sw = p->eig_max_sweeps > 0 ? p->eig_max_sweeps : 30;
+  const int inner = p->eig_inner_sweeps > 0 ? p->eig_inner_sweeps : 1;
+  int sw = 0;
+  double rel = 0.0;
+  hipError_t e = eigh_jacobi_noalloc(device, l, Z, P, w, max_sw, inner, 1e-14, &sw, &rel, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return free_fail(KOT_ERR_HIP, "kot_eigh_noalloc: %s", hipGetErrorString(e));
+  if (!(rel <= 1e-14)) {
+    if (!std::isfinite(rel)) return free_fail(KOT_ERR_NUMERIC, "kot_eigh_noalloc: non-finite matrix");
+    return free_fail(KOT_ERR_EIG, "kot_eigh_noalloc: Jacobi did not converge in %d sweeps (off/norm = %.3e)", sw, rel);
+  }
+  return KOT_OK;
+}
 
 kot_status kot_setup(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, double* Q, double* z, double* R,
                      double* wsum, double* q2) {

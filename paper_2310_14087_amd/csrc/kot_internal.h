@@ -91,6 +91,13 @@ hipError_t cholesky_upper(int l, const double* A, double eps, double* R, double*
 
 // ---- symmetric eigensolver (block Jacobi) ------------------------------------------------------------------
 struct EigWork;
+// Largest l of the allocation-free eigendecomposition (its scratch is a static device array).
+constexpr int kNoAllocMaxL = 512;
+size_t eigh_noalloc_scratch_bytes();
+// Cold-start eigendecomposition of (Z + Z^T)/2 without allocating: full Jacobi sweeps in the static scratch
+// array of `device` (which must be current); the scratch is shared by every call on that device.
+hipError_t eigh_jacobi_noalloc(int device, int l, const double* Z, double* P, double* wv, int max_sweeps,
+                               int inner_sweeps, double tol, int* sweeps, double* rel_off, hipStream_t st);
 EigWork* eig_work_create(int lmax);
 void eig_work_destroy(EigWork* w);
 // Z (l x l) -> P (columns eigenvectors), wv ascending.  If P0 is non-null, starts from the basis P0

@@ -30,7 +30,7 @@ EXPORTED = ["kot_params_default", "kot_create", "kot_destroy", "kot_last_error",
             "kot_solve_core", "kot_eigh", "kot_residual", "kot_ssn_direction", "kot_eg_step", "kot_cholesky",
             "kot_gemm", "kot_profile", "kot_mlp_params", "kot_features", "kot_mlp_forward", "kot_mlp_loss_grad",
             "kot_mlp_adam", "kot_warmstart", "kot_solve_batched", "kot_autotune", "kot_autotune_load",
-            "kot_potentials"]
+            "kot_potentials", "kot_eigh_noalloc"]
 
 
 class KotParams(C.Structure):
@@ -82,6 +82,7 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
         "kot_solve": (i, [vp, P(KotProblem), P(KotParams), vp, P(KotResult)]),
         "kot_solve_core": (i, [vp, i, vp, vp, vp, d, vp, P(KotParams), vp, P(KotResult)]),
         "kot_eigh": (i, [vp, i, vp, vp, vp, P(KotParams)]),
+        "kot_eigh_noalloc": (i, [i, vp, i, vp, vp, vp, P(KotParams)]),
         "kot_residual": (i, [vp, i, vp, vp, vp, vp, vp, P(KotParams), vp, vp, P(d)]),
         "kot_ssn_direction": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp, P(d)]),
         "kot_eg_step": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp]),
@@ -122,6 +123,21 @@ def default_params(**kw) -> KotParams:
             raise AttributeError(f"unknown parameter {k}")
         setattr(p, k, v)
     return p
+
+
+def eigh_noalloc(Z, prm: KotParams, P=None, w=None):
+    """kot_eigh_noalloc on Z's device and torch's current stream there (no context; l <= 512).  P and w may be
+    given (preallocated outputs) so that the call itself allocates nothing."""
+    import torch
+    l = Z.shape[0]
+    P = torch.empty_like(Z) if P is None else P
+    w = torch.empty(l, device=Z.device, dtype=torch.float64) if w is None else w
+    lib = load()
+    st = lib.kot_eigh_noalloc(Z.device.index or 0, torch.cuda.current_stream(Z.device).cuda_stream, l, _ptr(Z),
+                              _ptr(P), _ptr(w), C.byref(prm))
+    if st != KOT_OK:
+        raise KotError(st, lib.kot_last_error(None).decode())
+    return w, P
 
 
 def _ptr(t, dtype=None) -> int | None:
