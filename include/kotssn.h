@@ -211,6 +211,17 @@ kot_status kot_ssn_direction(kot_ctx* ctx, int l, const double* Q, const double*
                              const double* gamma, const double* X, double mu, const kot_params* prm,
                              double* dgamma, double* dX, double* info);
 
+/* The Schur operator of Algorithm 1 at w = (gamma, X) with regularization mu (Lemma 4.3):
+ * y = (Q/(2 lambda2) + mu I + Phi T Phi*) v, T from the spectral data of Z = X - Phi*(gamma) - lambda1 I
+ * (Section 4.3), applied through the eigen-row chain with B = P^T R in the precision prm->precision
+ * (FP64; FP32; BF16 or split BF16 on the matrix cores with FP32 accumulation).  v, y (l) and Q, z, R, gamma,
+ * X as in kot_ssn_direction (device).  The product runs `reps` times on the same v (reps >= 1, for timing; y
+ * is overwritten each time).  info (host, 4 entries): |alpha|, the chain's row count
+ * min(|alpha|, l - |alpha|), 1 if the complement form ran, and the mean milliseconds per product. */
+kot_status kot_schur_matvec(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R,
+                            const double* gamma, const double* X, double mu, const kot_params* prm, int reps,
+                            const double* v, double* y, double* info);
+
 /* One extragradient step (Section 4.4) on the min-max form Eq. (4.1) with step eta: (gamma, X) ->
  * (gamma_out, X_out), projection onto R^l x S^l_+.  All arrays device pointers. */
 kot_status kot_eg_step(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R,

@@ -87,6 +87,8 @@ struct kot_ctx {
   // vectors (cap)
   double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *cdinv, *qd, *qe, *qs, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
   float *Bf = nullptr, *Cf = nullptr, *Ef = nullptr;  // reduced-precision chain operands
+  // BF16 chain: bfloat16 B, B^T (hi and lo) and H (hi and lo), each ldp x ldp (ldp = chain_ldp(cap))
+  unsigned short *Bh = nullptr, *BhT = nullptr, *Bl = nullptr, *BlT = nullptr, *Hh = nullptr, *Hl = nullptr;
   State S[4];  // 0: w, 1: trial, 2: v, 3: scratch
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   Profiler prof;
@@ -156,7 +158,8 @@ void free_ws(kot_ctx* c) {
 kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   HIPCHK(hipSetDevice(ctx->device));
   const size_t need_part = std::max<size_t>({(size_t)2 * kRedBlocks, (size_t)kDiagParts * l + 64, (size_t)nmax + 64,
-                                             (size_t)l + 64, nmax > 0 ? mean_gram_part_size(nmax) : (size_t)0});
+                                             (size_t)l + 64, nmax > 0 ? mean_gram_part_size(nmax) : (size_t)0,
+                                             (size_t)((l + 31) / 32) * l + 64});  // BF16 chain column dots
   if (l <= ctx->cap && need_part <= ctx->part_cap) return KOT_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   free_ws(ctx);
@@ -190,6 +193,12 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   if (!(ctx->gemm_ws = alloc(16 * mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   if (!(ctx->Bf = (float*)alloc(mm / 2)) || !(ctx->Cf = (float*)alloc(mm / 2)) || !(ctx->Ef = (float*)alloc(mm / 2)))
     return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  {
+    const size_t lp = (size_t)chain_ldp(cap), hb = lp * lp * sizeof(unsigned short);
+    unsigned short** hbufs[] = {&ctx->Bh, &ctx->BhT, &ctx->Bl, &ctx->BlT, &ctx->Hh, &ctx->Hl};
+    for (unsigned short** b : hbufs)
+      if (!(*b = (unsigned short*)alloc(hb))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
+  }
   ctx->gemm_ws_cap = 16 * (size_t)cap * cap;
   g_gemm_ws = ctx->gemm_ws;
   g_gemm_ws_cap = ctx->gemm_ws_cap;
@@ -421,10 +430,18 @@ kot_status schur_dinv(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, double*
 kot_status schur_matvec_lowp(kot_ctx* ctx, const CoreView& cv, const TPlan& tp, const double* v, double* y, int mode) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
-  HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / (2.0 * cv.lam2), cv.Q, l, nullptr, v, 1, 0.0, y, 1));
-  HIPCHK(vec_axpby(l, tp.mu, v, 1.0, y, st));
-  if (tp.comp) HIPCHK(mm(st, 0, 0, l, 1, l, 1.0 / tp.mu, cv.KK, l, nullptr, v, 1, 1.0, y, 1));
+  // y = Q v / (2 lam2) + mu v (+ (1/mu) (K o K) v in the complement form), FP64, one pass
+  HIPCHK(gemv2(l, cv.Q, 1.0 / (2.0 * cv.lam2), tp.comp ? cv.KK : nullptr, 1.0 / tp.mu, v, tp.mu, y, st));
   if (tp.m == 0) return KOT_OK;
+  if (mode != 0) {  // BF16 or split BF16 on the gfx950 BF16 matrix cores (operands prepared in ssn_direction)
+    ChainArgs c{};
+    c.m = tp.m; c.l = l; c.ldp = chain_ldp(l); c.r0 = tp.r0; c.v = v;
+    c.Bh = ctx->Bh; c.BhT = ctx->BhT; c.Bl = ctx->Bl; c.BlT = ctx->BlT; c.Hh = ctx->Hh; c.Hl = ctx->Hl;
+    c.a = tp.a; c.mu = tp.mu; c.w = tp.w; c.complement = tp.comp ? 1 : 0; c.diag_scale = 1.0; c.off_scale = 2.0;
+    c.D = ctx->Bf + (long long)tp.r0 * l; c.ldd = l; c.alpha = tp.comp ? -1.0 : 1.0; c.part = ctx->part; c.y = y;
+    HIPCHK(chain_bf16(c, mode == 2, st));
+    return KOT_OK;
+  }
   const float* Bs = ctx->Bf + (long long)tp.r0 * l;
   LowpArgs g{};
   g.m = tp.m; g.n = l; g.k = l; g.A = Bs; g.lda = l; g.s = v; g.B = ctx->Bf; g.ldb = l; g.transb = 1;
@@ -507,6 +524,9 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
     const int mode = p->precision == KOT_MIXED_BF16 ? 1 : (p->precision == KOT_MIXED_BF16X3 ? 2 : 0);
     const double inner_rel = mode == 1 ? 1e-2 : 1e-4;
     HIPCHK(f64_to_f32((long long)l * l, ctx->Bm, ctx->Bf, st));
+    if (mode != 0)
+      HIPCHK(chain_prep(l, chain_ldp(l), ctx->Bm, ctx->Bh, ctx->BhT, mode == 2 ? ctx->Bl : nullptr,
+                        mode == 2 ? ctx->BlT : nullptr, st));
     HIPCHK(vec_fill(l, 0.0, x, st));
     HIPCHK(vec_copy(l, ctx->a1, r, st));
     double xx = 0.0;
@@ -1440,6 +1460,48 @@ kot_status kot_ssn_direction(kot_ctx* ctx, int l, const double* Q, const double*
   info[1] = di.cg_res;
   info[2] = s.a;
   info[3] = s.rn;
+  return KOT_OK;
+}
+
+kot_status kot_schur_matvec(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R,
+                            const double* gamma, const double* X, double mu, const kot_params* p, int reps,
+                            const double* v, double* y, double* info) {
+  KCHK(check_ctx(ctx));
+  KCHK(check_params(ctx, p, false));
+  if (l < 1 || l > 4096 || !Q || !z || !R || !gamma || !X || !v || !y || !info || !(mu > 0.0) || reps < 1)
+    return fail(ctx, KOT_ERR_ARG, "invalid argument");
+  KCHK(ensure_ws(ctx, l, 0));
+  KCHK(check_upper(ctx, l, R));
+  CoreView cv;
+  cv.l = l; cv.Q = Q; cv.z = z; cv.R = R; cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
+  KCHK(prepare_core(ctx, cv));
+  State& s = ctx->S[0];
+  HIPCHK(vec_copy(l, gamma, s.g, ctx->stream));
+  HIPCHK(vec_copy(l * l, X, s.X, ctx->stream));
+  KCHK(residual_state(ctx, cv, s, nullptr, p, nullptr));
+  hipStream_t st = ctx->stream;
+  TPlan tp = make_tplan(l, s.a, mu, s.P, s.s);
+  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, s.P, l, nullptr, cv.R, l, 0.0, ctx->Bm, l, TRI_B_UPPER));
+  const int mode = p->precision == KOT_MIXED_BF16 ? 1 : (p->precision == KOT_MIXED_BF16X3 ? 2 : 0);
+  if (p->precision != KOT_FP64) {
+    HIPCHK(f64_to_f32((long long)l * l, ctx->Bm, ctx->Bf, st));
+    if (mode != 0)
+      HIPCHK(chain_prep(l, chain_ldp(l), ctx->Bm, ctx->Bh, ctx->BhT, mode == 2 ? ctx->Bl : nullptr,
+                        mode == 2 ? ctx->BlT : nullptr, st));
+  }
+  HIPCHK(hipEventRecord(ctx->ev0, st));
+  for (int r = 0; r < reps; ++r) {
+    if (p->precision == KOT_FP64) KCHK(schur_matvec(ctx, cv, tp, v, y));
+    else KCHK(schur_matvec_lowp(ctx, cv, tp, v, y, mode));
+  }
+  HIPCHK(hipEventRecord(ctx->ev1, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  info[0] = s.a;
+  info[1] = tp.m;
+  info[2] = tp.comp ? 1.0 : 0.0;
+  info[3] = ms / reps;
   return KOT_OK;
 }
 

@@ -237,6 +237,28 @@ struct LowpArgs {
 // mode: 0 FP32 products, 1 BF16, 2 split BF16 (three products); FP32 accumulation
 hipError_t gemm_lowp(const LowpArgs& g, int mode, bool psi, hipStream_t st);
 hipError_t f64_to_f32(long long n, const double* x, float* y, hipStream_t st);
+// BF16 chain of the Schur matvec (gfx950 MFMA, see k_lowp.hip): operands rounded once per Newton direction.
+struct ChainArgs {
+  int m, l, ldp, r0;                       // chain rows, size, padded leading dimension, first eigen-row
+  const double* v;                         // matvec input (length l)
+  const unsigned short *Bh, *BhT, *Bl, *BlT;  // bf16 B and B^T (hi, lo), ldp x ldp, zero padded
+  unsigned short *Hh, *Hl;                 // bf16 H (hi, lo), m x ldp
+  // Psi epilogue (see psi_hadamard)
+  int a;
+  double mu;
+  const double* w;
+  int complement;
+  double diag_scale, off_scale;
+  // column-dot epilogue: y[j] += alpha sum_r D[r][j] (H B)[r][j]
+  const float* D; int ldd;
+  double alpha;
+  double* part;                            // >= ceil(m / 32) * l doubles
+  double* y;
+};
+int chain_ldp(int l);
+hipError_t chain_prep(int l, int ldp, const double* B, unsigned short* Bh, unsigned short* BhT, unsigned short* Bl,
+                      unsigned short* BlT, hipStream_t st);
+hipError_t chain_bf16(const ChainArgs& g, bool split, hipStream_t st);
 // y[j] += alpha * sum_{r < m} A[r][j] B[r][j]; part >= 16 n doubles
 hipError_t diag_dot_lowp(int m, int n, double alpha, const float* A, int lda, const float* B, int ldb, double* y,
                          double* part, hipStream_t st);

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "KOT_OK", 1: "KOT_NOT_CONVERGED", -1: "KOT_ERR_ARG", -2: "KOT
                 -4: "KOT_ERR_FACTOR", -5: "KOT_ERR_NUMERIC", -6: "KOT_ERR_EIG"}
 
 EXPORTED = ["kot_params_default", "kot_create", "kot_destroy", "kot_last_error", "kot_setup", "kot_solve",
-            "kot_solve_core", "kot_eigh", "kot_residual", "kot_ssn_direction", "kot_eg_step", "kot_cholesky",
+            "kot_solve_core", "kot_eigh", "kot_residual", "kot_ssn_direction", "kot_schur_matvec", "kot_eg_step",
+            "kot_cholesky",
             "kot_gemm", "kot_profile", "kot_mlp_params", "kot_features", "kot_mlp_forward", "kot_mlp_loss_grad",
             "kot_mlp_adam", "kot_warmstart", "kot_solve_batched", "kot_autotune", "kot_autotune_load",
             "kot_potentials", "kot_eigh_noalloc"]
@@ -85,6 +86,7 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
         "kot_eigh_noalloc": (i, [i, vp, i, vp, vp, vp, P(KotParams)]),
         "kot_residual": (i, [vp, i, vp, vp, vp, vp, vp, P(KotParams), vp, vp, P(d)]),
         "kot_ssn_direction": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp, P(d)]),
+        "kot_schur_matvec": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), i, vp, vp, P(d)]),
         "kot_eg_step": (i, [vp, i, vp, vp, vp, vp, vp, d, P(KotParams), vp, vp]),
         "kot_cholesky": (i, [vp, i, vp, d, vp, vp]),
         "kot_gemm": (i, [vp, i, i, i, i, i, d, vp, i, vp, vp, i, d, vp, i, i, i]),
@@ -318,6 +320,15 @@ class Context:
         self._check(self.lib.kot_ssn_direction(self.h, l, _ptr(Q), _ptr(z), _ptr(R), _ptr(gamma), _ptr(X),
                                                float(mu), C.byref(prm), _ptr(dg), _ptr(dX), info))
         return dg, dX, dict(cg_iters=int(info[0]), cg_res=info[1], alpha=int(info[2]), res=info[3])
+
+    def schur_matvec(self, Q, z, R, gamma, X, mu, v, prm: KotParams, reps=1):
+        import torch
+        l = Q.shape[0]
+        y = torch.empty(l, device=Q.device, dtype=torch.float64)
+        info = (C.c_double * 4)()
+        self._check(self.lib.kot_schur_matvec(self.h, l, _ptr(Q), _ptr(z), _ptr(R), _ptr(gamma), _ptr(X), float(mu),
+                                              C.byref(prm), int(reps), _ptr(v), _ptr(y), info))
+        return y, dict(alpha=int(info[0]), m=int(info[1]), complement=bool(info[2]), ms=info[3])
 
     def eg_step(self, Q, z, R, gamma, X, eta, prm: KotParams):
         import torch

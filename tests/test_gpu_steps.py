@@ -392,3 +392,50 @@ def test_ssn_direction_reduced_precision(gpu_ctx, precision, name, l, n, mu):
     odg, odX, _ = ko.ssn_direction(core, o1, o2, eig, mu, ko.Params(cg_max_iter=400, tau=1e-13, kappa=1e-13))
     np.testing.assert_allclose(_n(dg), odg, atol=1e-6 * np.abs(odg).max())
     np.testing.assert_allclose(_n(dX), odX, atol=1e-6 * np.abs(odX).max())
+
+
+def _first_trial(name, l, n):
+    """Data of the hot path at the first regularized Newton trial from the cold start (its (gamma, X) and mu)."""
+    p, core = _core_case(name, l, n)
+    g = np.zeros(core.l)
+    X = np.zeros((core.l, core.l))
+    r1, r2, rn, eig = ko.residual(core, g, X)
+    dg, dX, _ = ko.ssn_direction(core, r1, r2, eig, rn, ko.Params())
+    g, X = g + dg, X + dX
+    _, _, rn2, _ = ko.residual(core, g, X)
+    return p, core, g, X, rn2
+
+
+# normwise error bounds per precision (FP64 relative to the operator, the others relative to the chain term
+# Phi T Phi* v): bfloat16 operands carry 8 significant bits (relative rounding 2^-9), split BF16 about 16
+_CHAIN_TOL = {0: 1e-12, 1: 1e-5, 2: 3e-2, 3: 1e-4}
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
+@pytest.mark.parametrize("name,l,n", [("mix1000_median", 300, 1500), ("mix1000_median", 1000, 5000),
+                                      ("mix256", 100, 300)])
+def test_schur_matvec_precisions(gpu_ctx, precision, name, l, n):
+    """The Schur operator's eigen-row chain (Algorithm 1, Lemma 4.3) in each precision against the oracle's
+    plain dense operator Q v/(2 lambda2) + mu v + Phi(T[Phi*(v)]) at the hot path's first Newton trial (the
+    coupled workload: about l/2 chain rows in the complement form)."""
+    from paper_2310_14087_amd import kotssn
+    if name == "mix256":
+        p, core = _core_case(name, l, n)
+        g, X = _random_iterate(core.l, 31)
+        mu = 0.3
+    else:
+        p, core, g, X, mu = _first_trial(name, l, n)
+    _case(f"kot_schur_matvec precision={precision} {name} l={core.l} mu={mu:.3g}")
+    v = np.random.default_rng(7).standard_normal(core.l)
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2, precision=precision)
+    y, info = gpu_ctx.schur_matvec(_t(core.Q), _t(core.z), _t(core.R), _t(g), _t(X), mu, _t(v), prm)
+    _, _, _, (s, P) = ko.residual(core, g, X)
+    Psi = ko.psi_matrix(s, mu)
+    yo = ko.schur_matvec(core, P, Psi, mu, v)
+    chain = yo - core.Q @ v / (2.0 * core.lam2) - mu * v
+    assert info["alpha"] == int(np.sum(s > 0)) and info["m"] == min(info["alpha"], core.l - info["alpha"])
+    if name != "mix256":
+        assert info["m"] >= core.l // 4          # the coupled workload's chain is about l/2 rows
+    # FP64 against the whole operator; reduced precision against the chain term (its Q and mu terms are FP64)
+    err = np.linalg.norm(_n(y) - yo) / np.linalg.norm(yo if precision == 0 else chain)
+    assert err <= _CHAIN_TOL[precision], err
