@@ -537,11 +537,13 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
       rr = ctx->hsc[SL_RR];
       xx = ctx->hsc[SL_XX];
       const double thr = p->tau * std::min(1.0, kr * std::sqrt(xx));
-      if (std::sqrt(rr) <= thr || sweeps >= 8 || it >= 4 * std::max(1, p->cg_max_iter)) break;
+      // the inner iterations of all sweeps share the CG cap of Remark 4.5 (cg_max_iter per direction)
+      const int budget = std::max(1, p->cg_max_iter);
+      if (std::sqrt(rr) <= thr || sweeps >= 8 || it >= budget) break;
       // inner CG from d = 0 on the reduced-precision operator, to a fixed threshold
       const double stop_in = std::max(inner_rel * std::sqrt(rr), 0.5 * thr);
       KCHK(run_cg([&](const double* v, double* y) { return schur_matvec_lowp(ctx, cv, tp, v, y, mode); }, r,
-                  ctx->lx, ctx->lr, ctx->lp, ctx->lAp, stop_in, std::max(1, p->cg_max_iter)));
+                  ctx->lx, ctx->lr, ctx->lp, ctx->lAp, stop_in, budget - it));
       it += (int)hcs[kCgIt];
       HIPCHK(vec_axpby(l, 1.0, ctx->lx, 1.0, x, st));
       KCHK(schur_matvec(ctx, cv, tp, x, Ap));                 // FP64 residual
