@@ -54,6 +54,27 @@ __device__ __forceinline__ void circle16(int r, int k, int& a, int& b) {
   else { a = (r + k) % 15; b = (r - k + 15) % 15; }
 }
 
+// Index pair (a < b) that lane k (0..7) rotates in sub-round r of one visit of a block pair (slots 0-7: block
+// p, 8-15: block q).  With `within`, sub-rounds 0-6 rotate the pairs inside each block (circle method on 8 indices:
+// lanes 0-3 block p, lanes 4-7 block q) and sub-rounds 7-14 the cross pairs; otherwise the 8 sub-rounds rotate the
+// cross pairs only: sub-round r pairs slot k with slot 8 + (k + r) mod 8.  A tournament sweep visits each block
+// pair once and runs `within` in its first round only (where every block appears once), so every index pair is
+// rotated exactly once per sweep: a cyclic Jacobi sweep in a parallel ordering.
+__device__ __forceinline__ void pair_of_subround(int r, int k, int within, int& a, int& b) {
+  if (within && r < 7) {
+    const int kk = k & 3, off = (k < 4) ? 0 : 8;
+    int x, y;
+    if (kk == 0) { x = 7; y = r; }
+    else { x = (r + kk) % 7; y = (r - kk + 7) % 7; }
+    a = off + (x < y ? x : y);
+    b = off + (x < y ? y : x);
+  } else {
+    const int rc = within ? r - 7 : r;
+    a = k;
+    b = 8 + (k + rc) % 8;
+  }
+}
+
 // With an explicit list, pairs k >= kact only complete the partition of the blocks: they rotate nothing.
 // One wavefront per pair runs cyclic Jacobi on the 16x16 subproblem S (circle ordering: 8 disjoint rotations
 // per sub-round).  A sub-round takes two barriers: lanes 0-7 form the rotations J_k = [[c, s], [-s, c]] of
@@ -61,10 +82,31 @@ __device__ __forceinline__ void circle16(int r, int k, int& a, int& b) {
 // columns of pair lane%8; the blocks are disjoint, so the two-sided update is one read and one write of each
 // entry) and U <- U J to two 2-column row segments.  The annihilated entries of the diagonal blocks are set
 // to zero exactly.  Inner sweeps stop after a sweep that rotated nothing, or after max_inner sweeps.
+// V <- V G of the previous round, in the same launch (it does not feed this round's pair solves): workgroups
+// from npb on take four (pair, 16-row slab) items each, with the previous round's rotations.
+struct VPrev {
+  int active;          // 0 at a sweep's first round
+  int round;           // previous round (tournament), or its explicit pair list below
+  const int2* list;
+  const double* U;
+  const int* flag;
+  double* V;
+  int nslab;
+};
+
+__device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, int item, int np);
+
 __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __restrict__ A, int round, int nb,
-                                                        const int2* __restrict__ list, int kact,
+                                                        const int2* __restrict__ list, int kact, int npb,
                                                         double* __restrict__ Uout, int* __restrict__ flag,
-                                                        const double* __restrict__ thresh_ptr, int max_inner) {
+                                                        const double* __restrict__ thresh_ptr, int max_inner,
+                                                        int within, VPrev vp, int np) {
+  if ((int)blockIdx.x >= npb) {
+    const int base = ((int)blockIdx.x - npb) * 4;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) v_slab_update(l, nb, vp, base + q, np);
+    return;
+  }
   if (list && (int)blockIdx.x >= kact) {
     if (threadIdx.x == 0) flag[blockIdx.x] = 0;
     return;
@@ -102,11 +144,11 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
   bool rotated_any = false;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     const int par = sweep & 1;
-    for (int r = 0; r < 15; ++r) {
+    const int nsub = within ? 15 : 8;
+    for (int r = 0; r < nsub; ++r) {
       if (lane < 8) {
         int a, b;
-        circle16(r, lane, a, b);
-        if (a > b) { const int t = a; a = b; b = t; }
+        pair_of_subround(r, lane, within, a, b);
         const double apq = S[a][b];
         double c = 1.0, sn = 0.0;
         if (fabs(apq) > thresh) {
@@ -162,16 +204,52 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
   if (lane == 0) flag[k] = rotated_any ? 1 : 0;
 }
 
-// One launch per round for both updates (A and V are separate arrays).  Workgroup (x, y) has four wavefronts;
-// wavefront w takes item i = 4 x + w of pair row P = y: for i < np the A tile (P, Q = i),
-//   A_PQ <- U_P^T A_PQ U_Q,
-// for np <= i < np + nslab the 16-row slab r0 = 16 (i - np) of V,
-//   V[r0.., idx_P] <- V[r0.., idx_P] U_P.
-// A pair without rotations (flag 0) acts as the identity, so its U is not read; an item with nothing to rotate
-// does no loads.  Each 16x16 product is four v_mfma_f64_16x16x4f64 steps (accumulator lane L holds rows
-// L/16 + 4v, v = 0..3, of column L%16).  The barriers are uniform over the four wavefronts.
-__global__ __launch_bounds__(256) void apply_kernel(int l, int np, int nslab, double* __restrict__ A,
-                                                    double* __restrict__ V, int round, int nb,
+// Item i = P * nslab + slab of the previous round: V[r0.., idx_P] <- V[r0.., idx_P] U_P on a 16-row slab (a
+// pair without rotations is skipped).  The whole workgroup (one wavefront) takes the item; the barriers are
+// uniform over it.
+__device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, int item, int np) {
+  if (!vp.active || item >= np * vp.nslab) return;
+  const int P = item / vp.nslab, r0 = (item % vp.nslab) * SLOT;
+  if (!vp.flag[P]) return;
+  __shared__ double M[SLOT][SLOT + 1];
+  __shared__ int ip[SLOT];
+  const int lane = threadIdx.x;
+  const int2 pp = get_pair(vp.round, nb, vp.list, P);
+  __syncthreads();  // the previous item's reads of M and ip are done
+  if (lane < SLOT) ip[lane] = pair_slot_index(pp.x, pp.y, lane, l);
+  __syncthreads();
+  double mv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q, i = u >> 4, j = u & 15;
+    const int gj = ip[j];
+    mv[q] = (r0 + i < l && gj >= 0) ? vp.V[(long long)(r0 + i) * l + gj] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int u = lane + 64 * q;
+    M[u >> 4][u & 15] = mv[q];
+  }
+  __syncthreads();
+  const double* UP = vp.U + (long long)P * SLOT * SLOT;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < SLOT; ks += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UP[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = r0 + k4 + 4 * v, gj = ip[r16];
+    if (row < l && gj >= 0) vp.V[(long long)row * l + gj] = acc[v];
+  }
+}
+
+// A <- G^T A G for one round.  Workgroup (x, y) has four wavefronts; wavefront w takes the A tile (P = y,
+// Q = 4 x + w): A_PQ <- U_P^T A_PQ U_Q.  A pair without rotations (flag 0) acts as the identity, so its U is not
+// read; a tile with nothing to rotate does no loads.  Each 16x16 product is four v_mfma_f64_16x16x4f64 steps
+// (accumulator lane L holds rows L/16 + 4v, v = 0..3, of column L%16).  The barriers are uniform over the
+// four wavefronts.  (V's update runs in the next round's pair-solve launch.)
+__global__ __launch_bounds__(256) void apply_kernel(int l, int np, double* __restrict__ A, int round, int nb,
                                                     const int2* __restrict__ list, const double* __restrict__ Ub,
                                                     const int* __restrict__ flag) {
   __shared__ double Ms[4][SLOT][SLOT + 1];
@@ -180,10 +258,10 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, int nslab, do
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int P = blockIdx.y;
   const int item = (int)blockIdx.x * 4 + wv;
-  const bool isA = item < np, isV = !isA && item < np + nslab;
+  const bool isA = item < np;
   const bool fP = flag[P] != 0;
   const bool fQ = isA && flag[item] != 0;
-  const bool act = isA ? (fP || fQ) : (isV && fP);
+  const bool act = isA && (fP || fQ);
   double (*M)[SLOT + 1] = Ms[wv];
   double (*T)[SLOT + 1] = Ts[wv];
   int* ip = ips[wv];
@@ -197,19 +275,13 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, int nslab, do
     }
   }
   __syncthreads();
-  const int r0 = isV ? (item - np) * SLOT : 0;
   if (act) {
     double mv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int u = lane + 64 * q, i = u >> 4, j = u & 15;
-      if (isA) {
-        const int gi = ip[i], gj = iq[j];
-        mv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
-      } else {
-        const int gj = ip[j];
-        mv[q] = (r0 + i < l && gj >= 0) ? V[(long long)(r0 + i) * l + gj] : 0.0;
-      }
+      const int gi = ip[i], gj = iq[j];
+      mv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -220,7 +292,7 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, int nslab, do
   __syncthreads();
   const int r16 = lane & 15, k4 = lane >> 4;
   const double* UP = Ub + (long long)P * SLOT * SLOT;
-  if (act && isA) {
+  if (act) {
     if (fQ) {
       const double* UQ = Ub + (long long)item * SLOT * SLOT;
       dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -233,19 +305,9 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, int nslab, do
 #pragma unroll
       for (int v = 0; v < 4; ++v) T[k4 + 4 * v][r16] = M[k4 + 4 * v][r16];
     }
-  } else if (act) {  // V slab: one product
-    dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < SLOT; ks += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(M[r16][ks + k4], UP[(ks + k4) * SLOT + r16], acc, 0, 0, 0);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = r0 + k4 + 4 * v, gj = ip[r16];
-      if (row < l && gj >= 0) V[(long long)row * l + gj] = acc[v];
-    }
   }
   __syncthreads();
-  if (act && isA) {
+  if (act) {
     dbl4 acc2;
     if (fP) {
       acc2 = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -419,8 +481,8 @@ struct EigWork {
   const double* graph_tmp = nullptr;
   hipGraphExec_t graph = nullptr;
   bool graph_failed = false;
-  double* U = nullptr;        // device [npairs_max * 256]
-  int* flag = nullptr;        // device [npairs_max]
+  double* U = nullptr;        // device [2][npairs_max * 256]: rotations of even and odd rounds
+  int* flag = nullptr;        // device [2][npairs_max]
   int* perm = nullptr;        // device [lmax]
   double* dg = nullptr;       // device [lmax]: the diagonal of A at the last block-norm pass
   double* hb = nullptr;       // block norms: off-diagonal part [nbmax^2], all entries [nbmax^2], positive diagonal
@@ -451,8 +513,8 @@ EigWork* eig_work_create(int lmax) {
   const int npm = nbmax / 2;
   const size_t nb2 = (size_t)nbmax * nbmax;
   const size_t nlist = (size_t)(nbmax - 1) * npm;
-  bool ok = hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256) == hipSuccess &&
-            hipMalloc(&w->flag, sizeof(int) * (size_t)npm) == hipSuccess &&
+  bool ok = hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256 * 2) == hipSuccess &&
+            hipMalloc(&w->flag, sizeof(int) * (size_t)npm * 2) == hipSuccess &&
             hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess &&
             hipMalloc(&w->dg, sizeof(double) * (size_t)lmax) == hipSuccess &&
             hipHostMalloc(&w->hb, sizeof(double) * (2 * nb2 + nbmax), hipHostMallocMapped | hipHostMallocCoherent) ==
@@ -639,17 +701,36 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all, &pos));
   int s = 0;
   const double thresh_rel = 1e-18;
-  auto launch_round = [&](hipStream_t s_, int r, const int2* list, int kact) -> hipError_t {
-    hipLaunchKernelGGL(pair_solve_kernel, dim3(np), dim3(64), 0, s_, l, A, r, nb, list, kact, w->U, w->flag,
-                       w->up, inner_sweeps);
+  // Round q of a sweep (rotations in buffer q & 1): the pair solves of round q together with V's update by
+  // round q - 1, then A's update by round q; after the last round, V's update by it.
+  const int nvwg = (np * nslab + 3) / 4;
+  double* Ub[2] = {w->U, w->U + (size_t)(block_count(w->lmax) / 2) * SLOT * SLOT};
+  int* Fb[2] = {w->flag, w->flag + block_count(w->lmax) / 2};
+  auto vprev = [&](int q, int r_prev, const int2* list_prev) {
+    VPrev vp{};
+    vp.active = q > 0 ? 1 : 0;
+    vp.round = r_prev; vp.list = list_prev; vp.U = Ub[(q - 1) & 1]; vp.flag = Fb[(q - 1) & 1]; vp.V = V;
+    vp.nslab = nslab;
+    return vp;
+  };
+  auto launch_round = [&](hipStream_t s_, int q, int r, const int2* list, int kact, int r_prev,
+                          const int2* list_prev) -> hipError_t {
+    const int within = (list != nullptr || r == 0) ? 1 : 0;
+    hipLaunchKernelGGL(pair_solve_kernel, dim3(np + (q > 0 ? nvwg : 0)), dim3(64), 0, s_, l, A, r, nb, list, kact,
+                       np, Ub[q & 1], Fb[q & 1], w->up, inner_sweeps, within, vprev(q, r_prev, list_prev), np);
     KOT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(apply_kernel, dim3((np + nslab + 3) / 4, np), dim3(256), 0, s_, l, np, nslab, A, V, r, nb, list,
-                       w->U, w->flag);
+    hipLaunchKernelGGL(apply_kernel, dim3((np + 3) / 4, np), dim3(256), 0, s_, l, np, A, r, nb, list, Ub[q & 1],
+                       Fb[q & 1]);
+    return hipGetLastError();
+  };
+  auto launch_v_tail = [&](hipStream_t s_, int q_last, int r_last, const int2* list_last) -> hipError_t {
+    hipLaunchKernelGGL(pair_solve_kernel, dim3(nvwg), dim3(64), 0, s_, l, A, 0, nb, nullptr, 0, 0, Ub[0], Fb[0],
+                       w->up, inner_sweeps, 1, vprev(q_last + 1, r_last, list_last), np);
     return hipGetLastError();
   };
   auto launch_sweep = [&](hipStream_t s_) -> hipError_t {
-    for (int r = 0; r < nb - 1; ++r) KOT_HIP_TRY(launch_round(s_, r, nullptr, np));
-    return hipSuccess;
+    for (int r = 0; r < nb - 1; ++r) KOT_HIP_TRY(launch_round(s_, r, r, nullptr, np, r - 1, nullptr));
+    return launch_v_tail(s_, nb - 2, nb - 2, nullptr);
   };
   // flops of one full sweep: per round 2 x 2 x 16^3 per A tile and 2 x 16^3 per V tile
   const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * nslab * np);
@@ -675,7 +756,10 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
         by += 4096.0 * ((double)np * np - (np - k) * (np - k) + k * nslab);  // tiles read and written
       }
       if (pf) pf->begin(st, PROF_EIG_ROUND, fl, by);
-      for (int r = 0; r < R; ++r) KOT_HIP_TRY(launch_round(st, 0, w->list + (size_t)r * np, w->round_k[r]));
+      for (int r = 0; r < R; ++r)
+        KOT_HIP_TRY(launch_round(st, r, 0, w->list + (size_t)r * np, w->round_k[r], 0,
+                                 r > 0 ? w->list + (size_t)(r - 1) * np : nullptr));
+      KOT_HIP_TRY(launch_v_tail(st, R - 1, 0, w->list + (size_t)(R - 1) * np));
       if (pf) pf->end(st);
     } else {
       KOT_HIP_TRY(vec_copy(2, w->hup_dev, w->up, st));  // threshold
@@ -729,11 +813,11 @@ constexpr int kNoAllocMaxNb = kNoAllocMaxL / BSZ;            // 64 blocks of 8
 constexpr int kNoAllocMaxNp = kNoAllocMaxNb / 2;
 constexpr size_t kNoAllocDoubles =
     2 * (size_t)kNoAllocMaxL * kNoAllocMaxL                    // A, V
-    + (size_t)kNoAllocMaxNp * SLOT * SLOT                      // U
+    + 2 * (size_t)kNoAllocMaxNp * SLOT * SLOT                  // U (two rounds)
     + (size_t)kNoAllocMaxL                                     // dg
     + 2 * (size_t)kNoAllocMaxNb * kNoAllocMaxNb + kNoAllocMaxNb  // block norms
     + 32                                                       // threshold slot (up)
-    + (size_t)kNoAllocMaxNp + kNoAllocMaxL;                    // flags and ranks (ints, two per double)
+    + (size_t)kNoAllocMaxNp + kNoAllocMaxL;                    // flags (two rounds) and ranks (ints, two per double)
 constexpr int kNoAllocMaxDevices = 64;
 double g_noalloc_hb[2 * kNoAllocMaxNb * kNoAllocMaxNb + kNoAllocMaxNb];  // host copy of the block norms
 double* g_noalloc_ptr[kNoAllocMaxDevices] = {};
@@ -769,12 +853,12 @@ hipError_t eigh_jacobi_noalloc(int device, int l, const double* Z, double* P, do
   w.noalloc = true;
   w.graph_failed = true;
   w.lmax = kNoAllocMaxL;
-  w.U = cur;    cur += (size_t)kNoAllocMaxNp * SLOT * SLOT;
+  w.U = cur;    cur += 2 * (size_t)kNoAllocMaxNp * SLOT * SLOT;
   w.dg = cur;   cur += kNoAllocMaxL;
   w.boff = cur; cur += 2 * (size_t)kNoAllocMaxNb * kNoAllocMaxNb + kNoAllocMaxNb;
   w.up = cur;   cur += 32;
   w.flag = reinterpret_cast<int*>(cur);
-  w.perm = w.flag + kNoAllocMaxNp;
+  w.perm = w.flag + 2 * kNoAllocMaxNp;
   w.hb = g_noalloc_hb;
   // symmetrized input straight into A's slot; eigh_jacobi's copy of Z into A is then in place
   KOT_HIP_TRY(form_z(l, Z, 0.0, Z, 0.0, A, st));
