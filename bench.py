@@ -107,7 +107,6 @@ def _cpu_model():
 
 # committed counter summaries per profiler class: (summary file, source file whose hash it was taken on)
 TRAFFIC = {
-    "gemm_f64": ("gemm_f64_mix1000_traffic.md", "k_gemm.hip"),
     "eig_sweep": ("eig_jacobi_mix1000_median_traffic.md", "k_eig.hip"),
 }
 
