@@ -17,7 +17,8 @@ Each arm's K solves run twice: one at a time on one context, then as independent
 L lanes of ``kot_solve_batched`` (child contexts with a stream and a host thread each; default 8).  The rates
 reported are those of the lanes pass (whole-job throughput); the one-at-a-time rate is kept beside them.
 
-Arms: ``fp64`` cold start, FP64 everywhere; ``warm`` learned warm start, FP64; ``mixed32``, ``mixed16`` and
+Arms: ``fp64`` cold start, FP64 everywhere; ``closed`` the closed-form start gamma0_i = max(z_i/Q_ii, -lambda1)
+(lifted like the learned one, no network), FP64; ``warm`` learned warm start, FP64; ``mixed32``, ``mixed16`` and
 ``mixed``: learned warm start with the CG matvec chain in FP32, BF16 and split BF16 (three BF16 products per
 FP32 product) on the matrix cores, FP32 accumulation, inside FP64 iterative refinement.  ``value`` is the rate
 of the last arm run (``mixed`` by default); every arm's rate is in ``config.arms``.  ``roofline`` covers the
@@ -192,6 +193,45 @@ def sweep_bench(a):
                       "rows": rows}), flush=True)
 
 
+def egcompare_bench(a):
+    """Appendix F's comparison, SSN side and pure extragradient side: residual |R(w_k)| against time on the
+    Section 5 setup in d = 10 (3- vs 5-Gaussian mixtures, Sobol filling, sigma^2 = 0.005, lambda1 = 1/n,
+    lambda2 = 1/sqrt(n), n filling points = n samples per side), n in {50, 100, 200, 500, 1000, 2000}; pure EG
+    with the paper's fixed step 0.01, Algorithm 2 with its defaults; both to |R| < 0.005.  Times are the solves'
+    device times; the history's k-th entry is placed at k/iters of it (iterations of one method cost alike)."""
+    import numpy as np
+    import torch
+    from paper_2310_14087_amd import kotssn
+    from paper_2310_14087_amd.inputs import make_problem
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    ctx = kotssn.Context(0)
+    rows = []
+    for n in (50, 100, 200, 500, 1000, 2000):
+        p = make_problem("sweep_d10", 0, l=n, n=n)
+        args = (t(p.xs), t(p.ys), t(p.xf), t(p.yf))
+        row = dict(n=n)
+        eg_cap = 3000 if n <= 500 else 1000  # pure EG is capped so that the mode stays a few minutes long
+        for meth, kw in (("ssn", dict()), ("eg", dict(safeguard=kotssn.KOT_SAFEGUARD_EG_ONLY, eg_step=0.01,
+                                                         max_iter=eg_cap))):
+            prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=0.005, **kw)
+            ctx.solve(*args, prm, hist_cap=4)  # warm-up (workspace sizing)
+            _, _, r = ctx.solve(*args, prm, hist_cap=eg_cap + 1)
+            k = r.iters
+            idx = sorted(set([0, k] + [int(round(x)) for x in np.geomspace(1, max(1, k), 24)]))
+            row[meth] = dict(status=r.status, iters=k, ms=r.time_ms, residual=r.residual,
+                             curve=[(round(r.time_ms * i / max(1, k), 3), float(f"{r.res_hist[i]:.4e}"))
+                                    for i in idx if i <= k])
+            _log(f"egcompare n={n} {meth}: status={r.status} iters={k} {r.time_ms:.1f} ms residual={r.residual:.3e}")
+        rows.append(row)
+    ctx.close()
+    print(json.dumps({"metric": "time to |R(w)| < 0.005: Algorithm 2 vs pure extragradient (step 0.01), d = 10",
+                      "unit": "ms", "higher_is_better": False, "data": "synthetic",
+                      "config": {"workload": "sweep_d10: mixtures of 3 vs 5 Gaussians, Sobol filling, "
+                                             "sigma^2=0.005, lambda1=1/n, lambda2=1/sqrt(n), l = n samples per side"},
+                      "rows": rows}), flush=True)
+
+
 def batch_bench(a):
     """Uneven batch (n ~ U{200..2000}, l ~ U{100..400}, d ~ U{2..10}): solves/s through kot_solve_batched with
     `lanes` concurrent streams vs one lane; FP32 CG chain, FP64 projections."""
@@ -248,11 +288,12 @@ def main():
                     help="outer iterations per solve on mix1000_median (Algorithm 2 does not reach 1e-6 there)")
     ap.add_argument("--workload", default="mix1000_median",
                     help="mix1000_median (the metric line: fixed outer-iteration solves, iterations/s), mix1000 "
-                         "(decoupled: solves to 1e-6, solves/s) or sweep (Section 5's synthetic sweep)")
+                         "(decoupled: solves to 1e-6, solves/s), sweep (Section 5's synthetic sweep) or egcompare "
+                         "(Appendix F: Algorithm 2 against pure extragradient, residual against time)")
     ap.add_argument("--no-decoupled", action="store_true",
                     help="skip the decoupled mix1000 secondary that runs after the mix1000_median line")
     ap.add_argument("--decoupled-steps", type=int, default=24)
-    ap.add_argument("--arm", default="all", choices=["fp64", "warm", "mixed32", "mixed16", "mixed", "all"])
+    ap.add_argument("--arm", default="all", choices=["fp64", "closed", "warm", "mixed32", "mixed16", "mixed", "all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the roofline pass")
     ap.add_argument("--roofline-solves", type=int, default=0,
@@ -284,12 +325,14 @@ def main():
         return batch_bench(a)
     if a.workload == "sweep":
         return sweep_bench(a)
+    if a.workload == "egcompare":
+        return egcompare_bench(a)
     if a.copy_calibrate > 0:
         return copy_calibrate(a.copy_calibrate)
     if a.workload not in WORKLOAD_TEXT:
         raise SystemExit(f"unknown workload {a.workload}")
     coupled = a.workload == "mix1000_median"
-    arms = ["fp64", "warm", "mixed32", "mixed16", "mixed"] if a.arm == "all" else [a.arm]
+    arms = ["fp64", "closed", "warm", "mixed32", "mixed16", "mixed"] if a.arm == "all" else [a.arm]
     steps = a.steps or (4 if coupled else 24)
     nroof = a.roofline_solves or (1 if coupled else 3)
     main_res = run_workload(a, a.workload, arms, steps, a.iters if coupled else 200, nroof)
@@ -331,14 +374,16 @@ def main():
         out["profile"] = main_res["profile"]
     if coupled and not a.no_decoupled:
         _log("decoupled secondary: mix1000 solves to 1e-6")
-        dec_arms = ["fp64", "mixed"] if a.arm == "all" else arms
+        dec_arms = ["fp64", "closed", "warm", "mixed"] if a.arm == "all" else arms
         dec = run_workload(a, "mix1000", dec_arms, a.decoupled_steps, 200, 0)
         out["config"]["decoupled"] = {
             "workload": WORKLOAD_TEXT["mix1000"], "metric": "SSN solves/s to residual<=1e-6 (decoupled)",
             "arms": {k: {q: v[q] for q in ("solves_per_s", "ms_per_solve", "converged", "iters",
                                           "lowp_directions", "warm_used") if q in v}
                      for k, v in dec["arms"].items() if isinstance(v, dict)},
-            "speedup_mixed_vs_fp64": dec["arms"].get("speedup_mixed_vs_fp64")}
+            "speedup_mixed_vs_fp64": dec["arms"].get("speedup_mixed_vs_fp64"),
+            "speedup_closed_vs_fp64": dec["arms"].get("speedup_closed_vs_fp64"),
+            "speedup_warm_vs_fp64": dec["arms"].get("speedup_warm_vs_fp64")}
     if not a.no_cpu_baseline:
         _log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(a.workload, min(a.iters, 3) if coupled else None)
@@ -364,7 +409,7 @@ def run_workload(a, workload, arms, steps, max_iter, nroof):
     ctx = kotssn.Context(0)
     base = [dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, max_iter=max_iter) for p in probs]
     theta_dev, H = None, 0
-    if any(x != "fp64" for x in arms):
+    if any(x not in ("fp64", "closed") for x in arms):
         from paper_2310_14087_amd import warmstart
         theta, F, H, meta = warmstart.load()
         theta_dev = torch.from_numpy(theta).to(dev)
@@ -373,7 +418,9 @@ def run_workload(a, workload, arms, steps, max_iter, nroof):
         jac = a.precond == "jacobi" or (a.precond == "auto" and arm != "fp64")
         kw = dict(base[i], overlap=a.overlap,
                   precond=kotssn.KOT_PRECOND_JACOBI if jac else kotssn.KOT_PRECOND_NONE)
-        if arm != "fp64":
+        if arm == "closed":
+            kw.update(closed_start=1)
+        elif arm != "fp64":
             kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
         if arm == "mixed":
             kw.update(precision=kotssn.KOT_MIXED_BF16X3)
@@ -453,7 +500,7 @@ def run_workload(a, workload, arms, steps, max_iter, nroof):
              + (f" ({a.lanes} lanes; one at a time {steps / sel:.3f} solves/s)" if lan else ""))
     ctx.close()
     if "fp64" in out_arms:
-        for arm in ("warm", "mixed32", "mixed16", "mixed"):
+        for arm in ("closed", "warm", "mixed32", "mixed16", "mixed"):
             if arm in out_arms:
                 out_arms[arm]["ot_rel_dev_vs_fp64"] = max(
                     abs(x - y) / abs(y) for x, y in zip(out_arms[arm]["ot"], out_arms["fp64"]["ot"]))

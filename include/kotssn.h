@@ -98,6 +98,9 @@ typedef struct kot_params {
   int schur_solver;    /* a kot_schur_solver value; default KOT_SCHUR_CG */
   int eig_inner_sweeps; /* cap on the cyclic Jacobi sweeps a 16x16 block-pair subproblem gets per visit of the
                            eigensolver (default 1; a visit also ends after a sweep that rotated nothing) */
+  int closed_start;    /* 1: without gamma0 and without ws_theta, start from gamma0_i = max(z_i / Q_ii, -lambda1),
+                          the minimizer of Eq. (3.4) for diagonal Q and orthogonal R (the LMI is then the box
+                          gamma >= -lambda1), lifted and kept or dropped like any start (default 0) */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:

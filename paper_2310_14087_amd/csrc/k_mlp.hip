@@ -323,7 +323,21 @@ __global__ __launch_bounds__(256) void lift_threshold_kernel(int l, int nb, cons
     if (d[i] < thr) d[i] = 0.0;
 }
 
+__global__ void closed_start_kernel(int l, const double* __restrict__ Q, const double* __restrict__ z, double lam1,
+                                    double* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < l) g[i] = fmax(z[i] / Q[(long long)i * l + i], -lam1);
+}
+
 }  // namespace
+
+// gamma0_i = max(z_i / Q_ii, -lambda1): the minimizer of Eq. (3.4) when Q is diagonal and R orthogonal (the LMI
+// is then the box gamma >= -lambda1), i.e. lambda1 times the network's first input feature, clipped.
+hipError_t closed_start(int l, const double* Q, const double* z, double lam1, double* g, hipStream_t st) {
+  hipLaunchKernelGGL(closed_start_kernel, dim3((l + 255) / 256), dim3(256), 0, st, l, Q, z, lam1, g);
+  return hipGetLastError();
+}
+
 
 hipError_t gemm_f32(const GemmF32Args& g, hipStream_t st) {
   if (g.m <= 0 || g.n <= 0 || g.k <= 0) return hipErrorInvalidValue;

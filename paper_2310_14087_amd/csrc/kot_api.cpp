@@ -936,13 +936,16 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   const bool eta_default = !(eta > 0.0);
   if (!pre) {
     if (eta_default) KCHK(default_eta_launch(ctx, cv));       // read with the first residual's norms
-    if (gamma0 || p->ws_theta) HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + SL_ZZ, ctx->part, st));
+    if (gamma0 || p->ws_theta || p->closed_start) HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + SL_ZZ, ctx->part, st));
   }
   State* W = &ctx->S[0];
   State* T = &ctx->S[1];
   State* V = &ctx->S[2];
   if (p->ws_theta && !gamma0) {  // learned start
     if (!pre) KCHK(predict_gamma0(ctx, cv, ctx->Kb, p->ws_F, p->ws_H, p->ws_theta, ctx->S[1].g));
+    gamma0 = ctx->S[1].g;
+  } else if (p->closed_start && !gamma0) {  // closed-form start (the diagonal, orthogonal-factor minimizer)
+    HIPCHK(closed_start(l, cv.Q, cv.z, cv.lam1, ctx->S[1].g, st));
     gamma0 = ctx->S[1].g;
   }
   if (gamma0) HIPCHK(vec_copy(l, gamma0, W->g, st));
@@ -1253,6 +1256,7 @@ void kot_params_default(kot_params* p) {
   p->null_step = 0;
   p->eig_max_sweeps = 30;
   p->eig_inner_sweeps = 1;
+  p->closed_start = 0;
   p->warm_eig = 1;
   p->lift_x0 = 1;
   p->ws_F = 0;
@@ -1374,7 +1378,7 @@ kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, c
   cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
   // the lifted start needs R^-T: the factorization forms it beside R (the buffer is free until the first
   // extragradient step)
-  double* Linv = (gamma0 || p->ws_theta) && p->lift_x0 ? ctx->Xh : nullptr;
+  double* Linv = (gamma0 || p->ws_theta || p->closed_start) && p->lift_x0 ? ctx->Xh : nullptr;
   cv.Linv = Linv;
   if (overlap_ok(ctx, p, pb->l)) {
     Prelude pre;

@@ -205,6 +205,7 @@ hipError_t f32_to_f64_scaled(int n, const float* x, double s, double* y, hipStre
 hipError_t trtri_upper(int l, const double* R, double* Y, double* T, hipStream_t st);
 // d = ((Q g - z)/(2 lam2)) on predicted-active points (g_i <= -0.9 lambda1), zeroed below frac * mean of the
 // positive entries; part: >= 128 doubles.
+hipError_t closed_start(int l, const double* Q, const double* z, double lam1, double* g, hipStream_t st);
 hipError_t lift_diag(int l, const double* Qg, const double* z, const double* g, double lam1, double lam2, double frac,
                      double* d, double* part, hipStream_t st);
 

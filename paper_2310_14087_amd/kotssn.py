@@ -44,7 +44,7 @@ class KotParams(C.Structure):
                 ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int), ("lift_x0", C.c_int), ("ws_F", C.c_int),
                 ("ws_H", C.c_int), ("ws_theta", C.c_void_p), ("overlap", C.c_int),
                 ("lowp_min_rows", C.c_int), ("precond", C.c_int),
-                ("schur_solver", C.c_int), ("eig_inner_sweeps", C.c_int)]
+                ("schur_solver", C.c_int), ("eig_inner_sweeps", C.c_int), ("closed_start", C.c_int)]
 
 
 class KotProblem(C.Structure):

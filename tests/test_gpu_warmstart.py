@@ -117,6 +117,44 @@ def test_learned_warm_start_gain(gpu_ctx):
     assert np.mean(warm_it) < 0.7 * np.mean(cold_it)
 
 
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_learned_start_against_closed_form_start_256(gpu_ctx):
+    """256 held-out problems (seeds never used in training): outer iterations from the cold start, from the
+    closed-form start gamma0_i = max(z_i/Q_ii, -lambda1) (the network's first feature times lambda1, same lift,
+    no network) and from the network's start; every run reaches the same estimate.  The learned start needs
+    fewer iterations than the cold start; what the network adds over the closed-form start is printed (and
+    recorded in the design notes)."""
+    import torch
+    from paper_2310_14087_amd import kotssn, warmstart
+    theta, F, H, meta = warmstart.load(WEIGHTS)
+    th = torch.from_numpy(theta).to("cuda:0")
+    its = {"cold": [], "closed": [], "learned": []}
+    used = {"closed": 0, "learned": 0}
+    print("[case] cold / closed-form / learned starts on 256 held-out mix256 problems", flush=True)
+    for s in range(100000, 100256):
+        p = make_problem("mix256", s)
+        args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+        base = dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+        _, _, rc = gpu_ctx.solve(*args, kotssn.default_params(**base))
+        _, _, rz = gpu_ctx.solve(*args, kotssn.default_params(closed_start=1, **base))
+        _, _, rw = gpu_ctx.solve(*args, kotssn.default_params(ws_F=F, ws_H=H, ws_theta=th.data_ptr(), **base))
+        for r in (rc, rz, rw):
+            assert r.status == kotssn.KOT_OK, (s, r)
+            assert abs(r.ot - rc.ot) <= 1e-6 * abs(rc.ot)
+        its["cold"].append(rc.iters)
+        its["closed"].append(rz.iters)
+        its["learned"].append(rw.iters)
+        used["closed"] += rz.warm_used
+        used["learned"] += rw.warm_used
+    m = {k: float(np.mean(v)) for k, v in its.items()}
+    print(f"mean outer iterations over 256 held-out problems: cold {m['cold']:.3f}, closed-form start "
+          f"{m['closed']:.3f} (kept {used['closed']}/256), learned start {m['learned']:.3f} (kept "
+          f"{used['learned']}/256); learned better than closed-form on "
+          f"{sum(a < b for a, b in zip(its['learned'], its['closed']))}, worse on "
+          f"{sum(a > b for a, b in zip(its['learned'], its['closed']))}")
+    assert m["learned"] < 0.7 * m["cold"]
+
+
 @pytest.mark.parametrize("name,l,n,seed", [("mix256", 70, 200, 11), ("tiny", None, None, 0), ("mix256", 200, 300, 5)])
 def test_lifted_start_matrix(gpu_ctx, name, l, n, seed):
     """max_iter = 0 returns the start point: X0 = R^-T diag(y) R^-1 with the lift's rule, checked with numpy
