@@ -32,6 +32,17 @@ __device__ __forceinline__ int pair_slot_index(int p, int q, int s, int l) {
   return (g < l) ? g : -1;
 }
 
+// Index of slot s (0..15) of block pair (x, y) in the block-padded range (slots past l included).
+__device__ __forceinline__ int slot_index(int2 pq, int s) { return (s < BSZ) ? pq.x * BSZ + s : pq.y * BSZ + (s - BSZ); }
+
+// Blocked storage of the working matrices A and V during the sweeps: the 8x8 block (bi, bj) of the L x L matrix
+// (L = 8 nb) occupies 64 consecutive doubles at (bi nb + bj) 64, row-major inside, so that a 16x16 tile of a
+// block pair is four 512-byte runs.  Entries past l are zero and stay zero: no rotation involves an index past l
+// (its entries of A are zero), so the U of every pair is the identity on such slots.
+__host__ __device__ __forceinline__ long long blk(int nb, int i, int j) {
+  return ((long long)(i >> 3) * nb + (j >> 3)) * 64 + (i & 7) * 8 + (j & 7);
+}
+
 // Round-robin tournament over nb (even) blocks, circle method: in round r < nb - 1, pair 0 = (nb-1, r) and
 // pair k = ((r + k) mod (nb-1), (r - k) mod (nb-1)); every pair of blocks meets once in nb - 1 rounds.
 __device__ __forceinline__ int2 round_pair(int r, int k, int nb) {
@@ -76,12 +87,11 @@ __device__ __forceinline__ void pair_of_subround(int r, int k, int within, int& 
 }
 
 // With an explicit list, pairs k >= kact only complete the partition of the blocks: they rotate nothing.
-// One wavefront per pair runs cyclic Jacobi on the 16x16 subproblem S (circle ordering: 8 disjoint rotations
-// per sub-round).  A sub-round takes two barriers: lanes 0-7 form the rotations J_k = [[c, s], [-s, c]] of
-// their index pairs (a_k < b_k), then every lane applies S <- J^T S J to one 2x2 block (rows of pair lane/8,
-// columns of pair lane%8; the blocks are disjoint, so the two-sided update is one read and one write of each
-// entry) and U <- U J to two 2-column row segments.  The annihilated entries of the diagonal blocks are set
-// to zero exactly.  Inner sweeps stop after a sweep that rotated nothing, or after max_inner sweeps.
+// One wavefront per pair runs cyclic Jacobi on the 16x16 subproblem S (8 disjoint rotations per sub-round,
+// jacobi16): every lane applies S <- J^T S J to one 2x2 block (rows of pair lane/8, columns of pair lane%8; the
+// blocks are disjoint, so the two-sided update is one read and one write of each entry) and U <- U J to two
+// row segments.  The annihilated entries of the diagonal blocks are set to zero exactly.  Inner sweeps stop
+// after a sweep that rotated nothing, or after max_inner sweeps.
 // V <- V G of the previous round, in the same launch (it does not feed this round's pair solves): workgroups
 // from npb on take four (pair, 16-row slab) items each, with the previous round's rotations.
 struct VPrev {
@@ -94,17 +104,27 @@ struct VPrev {
   int nslab;
 };
 
-__device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, int item, int np);
+__device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, int item, int np,
+                                              double (*M)[SLOT + 1], int* ip);
+
+// Cyclic Jacobi on the 16x16 subproblem S staged in LDS (one wavefront; U starts as the identity).  Returns
+// whether any rotation was applied.
+__device__ __forceinline__ bool jacobi16(double (*S)[SLOT + 1], double (*U)[SLOT + 1], double2* cs, double thresh,
+                                         int max_inner, int within);
 
 __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __restrict__ A, int round, int nb,
                                                         const int2* __restrict__ list, int kact, int npb,
                                                         double* __restrict__ Uout, int* __restrict__ flag,
                                                         const double* __restrict__ thresh_ptr, int max_inner,
                                                         int within, VPrev vp, int np) {
+  __shared__ double S[SLOT][SLOT + 1];
+  __shared__ double U[SLOT][SLOT + 1];
+  __shared__ double2 cs[8];
+  __shared__ int idx[SLOT];
   if ((int)blockIdx.x >= npb) {
     const int base = ((int)blockIdx.x - npb) * 4;
 #pragma unroll 1
-    for (int q = 0; q < 4; ++q) v_slab_update(l, nb, vp, base + q, np);
+    for (int q = 0; q < 4; ++q) v_slab_update(l, nb, vp, base + q, np, S, idx);
     return;
   }
   if (list && (int)blockIdx.x >= kact) {
@@ -112,17 +132,10 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
     return;
   }
   const double thresh = *thresh_ptr;
-  __shared__ double S[SLOT][SLOT + 1];
-  __shared__ double U[SLOT][SLOT + 1];
-  __shared__ double cs[8][2];
-  __shared__ int ab[8][2];
-  __shared__ int idx[SLOT];
-  __shared__ int rot_sweep[2];
   const int k = blockIdx.x;
   const int2 pq = get_pair(round, nb, list, k);
   const int lane = threadIdx.x;
   if (lane < SLOT) idx[lane] = pair_slot_index(pq.x, pq.y, lane, l);
-  if (lane < 2) rot_sweep[lane] = 0;
   __syncthreads();
   // the four loads of a lane are issued together (register buffer), then staged
   double sv[4];
@@ -130,7 +143,7 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
   for (int q = 0; q < 4; ++q) {
     const int u = lane + 64 * q, i = u >> 4, j = u & 15;
     const int gi = idx[i], gj = idx[j];
-    sv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
+    sv[q] = (gi >= 0 && gj >= 0) ? A[blk(nb, gi, gj)] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -139,80 +152,122 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
     U[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int k1 = lane >> 3, k2 = lane & 7;      // this lane's 2x2 block of S
-  const int ur = lane >> 2, uk = (lane & 3) * 2;  // this lane's U row and first of its two pairs
-  bool rotated_any = false;
-  for (int sweep = 0; sweep < max_inner; ++sweep) {
-    const int par = sweep & 1;
-    const int nsub = within ? 15 : 8;
-    for (int r = 0; r < nsub; ++r) {
-      if (lane < 8) {
-        int a, b;
-        pair_of_subround(r, lane, within, a, b);
-        const double apq = S[a][b];
-        double c = 1.0, sn = 0.0;
-        if (fabs(apq) > thresh) {
-          const double theta = (S[b][b] - S[a][a]) / (2.0 * apq);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          sn = t * c;
-          rot_sweep[par] = 1;
-        }
-        cs[lane][0] = c;
-        cs[lane][1] = sn;
-        ab[lane][0] = a;
-        ab[lane][1] = b;
-      }
-      __syncthreads();
-      {
-        const int a1 = ab[k1][0], b1 = ab[k1][1], a2 = ab[k2][0], b2 = ab[k2][1];
-        const double c1 = cs[k1][0], s1 = cs[k1][1], c2 = cs[k2][0], s2 = cs[k2][1];
-        if (s1 != 0.0 || s2 != 0.0) {
-          const double xaa = S[a1][a2], xab = S[a1][b2], xba = S[b1][a2], xbb = S[b1][b2];
-          // rows: J1^T x
-          const double yaa = c1 * xaa - s1 * xba, yab = c1 * xab - s1 * xbb;
-          const double yba = s1 * xaa + c1 * xba, ybb = s1 * xab + c1 * xbb;
-          // columns: (J1^T x) J2
-          double zaa = c2 * yaa - s2 * yab, zab = s2 * yaa + c2 * yab;
-          double zba = c2 * yba - s2 * ybb, zbb = s2 * yba + c2 * ybb;
-          if (k1 == k2 && s1 != 0.0) { zab = 0.0; zba = 0.0; }
-          S[a1][a2] = zaa; S[a1][b2] = zab; S[b1][a2] = zba; S[b1][b2] = zbb;
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int kk = uk + h;
-          const double c = cs[kk][0], sn = cs[kk][1];
-          if (sn != 0.0) {
-            const int a = ab[kk][0], b = ab[kk][1];
-            const double ux = U[ur][a], uy = U[ur][b];
-            U[ur][a] = c * ux - sn * uy;
-            U[ur][b] = sn * ux + c * uy;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    // rot_sweep[par] was last written before the barrier above; the other slot is cleared for the next sweep
-    const bool any = rot_sweep[par] != 0;
-    if (lane == 0) rot_sweep[par ^ 1] = 0;
-    __syncthreads();
-    if (!any) break;
-    rotated_any = true;
-  }
+  const bool rotated_any = jacobi16(S, U, cs, thresh, max_inner, within);
+  __syncthreads();
   double* Uk = Uout + (long long)k * SLOT * SLOT;
   for (int u = lane; u < SLOT * SLOT; u += 64) Uk[u] = U[u >> 4][u & 15];
   if (lane == 0) flag[k] = rotated_any ? 1 : 0;
 }
 
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by one third-order step,
+// y0 (1 + e/2 + 3 e^2/8) with e = 1 - x y0^2, and y0 (1 + e + e^2) with e = 1 - x y0.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y0, y0, 1.0);
+  return fma(y0 * e, fma(0.375, e, 0.5), y0);
+}
+__device__ __forceinline__ double rcp_refined(double x) {
+  const double y0 = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y0, 1.0);
+  return fma(y0, fma(e, e, e), y0);
+}
+// 1/sqrt(x) to within about half an ulp: a Newton step from rsqrt_refined with the residual 1 - x y^2 formed
+// from the exact split of y^2 (y y = hi + lo), so its rounding errors carry no bias (a biased c would make the
+// columns of V drift in norm over thousands of rotations).
+__device__ __forceinline__ double rsqrt_accurate(double x) {
+  const double y = rsqrt_refined(x);
+  const double hi = y * y;
+  const double lo = fma(y, y, -hi);
+  const double e = fma(-x, lo, fma(-x, hi, 1.0));
+  return fma(0.5 * y, e, y);
+}
+
+// Rotation J = [[c, s], [-s, c]] that annihilates apq in the 2x2 [[app, apq], [apq, aqq]] (J^T S J), the identity
+// when |apq| <= thresh: t = tan of the angle is the root of t^2 + 2 theta t - 1 = 0 (theta = d / (2 apq),
+// d = aqq - app) of smaller magnitude, t = 2 apq sgn(d) / (|d| + sqrt(d^2 + 4 apq^2)), c = 1/sqrt(1 + t^2),
+// s = t c.  The square root and the reciprocals come from refined hardware estimates (c to about half an ulp);
+// when d^2 + 4 apq^2 leaves the normal range the same root is formed with IEEE division and square root from
+// theta.
+__device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, double thresh, double& c, double& sn) {
+  c = 1.0;
+  sn = 0.0;
+  if (fabs(apq) > thresh) {
+    const double d = aqq - app;
+    const double h = fma(d, d, 4.0 * apq * apq);
+    double t;
+    if (h > 1e-290 && h < 1e290) {
+      const double r = h * rsqrt_refined(h);
+      t = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) * rcp_refined(fabs(d) + r);
+    } else {
+      const double theta = d / (2.0 * apq);
+      t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    }
+    c = rsqrt_accurate(fma(t, t, 1.0));
+    sn = t * c;
+  }
+}
+
+// One wavefront, no barriers.  Lane (k1, k2) = (lane / 8, lane % 8) forms the rotation J_k2 of sub-round pair k2
+// (the eight lanes with the same k2 compute the same one from the same entries); the lanes with k1 == k2 publish
+// theirs in cs, from which every lane takes J_k1.  The lane then applies S <- J^T S J to the 2x2 block (rows of
+// pair k1, columns of pair k2) and U <- U J_k1 to rows 2 k2, 2 k2 + 1.  A sub-round issues its LDS reads of S
+// and U before its writes; the LDS operations of one wavefront complete in issue order, so every read sees the
+// previous sub-round's writes and none sees this one's, and the compiler barriers keep that order in the code.
+__device__ __forceinline__ bool jacobi16(double (*S)[SLOT + 1], double (*U)[SLOT + 1], double2* cs, double thresh,
+                                         int max_inner, int within) {
+  const int lane = threadIdx.x;
+  const int k1 = lane >> 3, k2 = lane & 7;
+  const int ur = 2 * k2;
+  bool rotated_any = false;
+  for (int sweep = 0; sweep < max_inner; ++sweep) {
+    bool act = false;
+    const int nsub = within ? 15 : 8;
+    for (int r = 0; r < nsub; ++r) {
+      int a1, b1, a2, b2;
+      pair_of_subround(r, k1, within, a1, b1);
+      pair_of_subround(r, k2, within, a2, b2);
+      const double p2 = S[a2][b2], d2a = S[a2][a2], d2b = S[b2][b2];
+      const double xaa = S[a1][a2], xab = S[a1][b2], xba = S[b1][a2], xbb = S[b1][b2];
+      const double u0a = U[ur][a1], u0b = U[ur][b1], u1a = U[ur + 1][a1], u1b = U[ur + 1][b1];
+      asm volatile("" ::: "memory");
+      double c2, s2;
+      jacobi_rot(d2a, d2b, p2, thresh, c2, s2);
+      act = act || fabs(p2) > thresh;
+      if (k1 == k2) cs[k2] = make_double2(c2, s2);
+      asm volatile("" ::: "memory");
+      const double2 j1 = cs[k1];
+      const double c1 = j1.x, s1 = j1.y;
+      if (s1 != 0.0 || s2 != 0.0) {
+        // rows: J1^T x, then columns: (J1^T x) J2
+        const double yaa = c1 * xaa - s1 * xba, yab = c1 * xab - s1 * xbb;
+        const double yba = s1 * xaa + c1 * xba, ybb = s1 * xab + c1 * xbb;
+        double zaa = c2 * yaa - s2 * yab, zab = s2 * yaa + c2 * yab;
+        double zba = c2 * yba - s2 * ybb, zbb = s2 * yba + c2 * ybb;
+        if (k1 == k2 && s1 != 0.0) { zab = 0.0; zba = 0.0; }
+        S[a1][a2] = zaa; S[a1][b2] = zab; S[b1][a2] = zba; S[b1][b2] = zbb;
+      }
+      if (s1 != 0.0) {
+        U[ur][a1] = c1 * u0a - s1 * u0b;
+        U[ur][b1] = s1 * u0a + c1 * u0b;
+        U[ur + 1][a1] = c1 * u1a - s1 * u1b;
+        U[ur + 1][b1] = s1 * u1a + c1 * u1b;
+      }
+      asm volatile("" ::: "memory");
+    }
+    if (!__any(act)) break;
+    rotated_any = true;
+  }
+  return rotated_any;
+}
+
 // Item i = P * nslab + slab of the previous round: V[r0.., idx_P] <- V[r0.., idx_P] U_P on a 16-row slab (a
 // pair without rotations is skipped).  The whole workgroup (one wavefront) takes the item; the barriers are
 // uniform over it.
-__device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, int item, int np) {
+__device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, int item, int np,
+                                              double (*M)[SLOT + 1], int* ip) {
   if (!vp.active || item >= np * vp.nslab) return;
   const int P = item / vp.nslab, r0 = (item % vp.nslab) * SLOT;
   if (!vp.flag[P]) return;
-  __shared__ double M[SLOT][SLOT + 1];
-  __shared__ int ip[SLOT];
   const int lane = threadIdx.x;
   const int2 pp = get_pair(vp.round, nb, vp.list, P);
   __syncthreads();  // the previous item's reads of M and ip are done
@@ -223,7 +278,7 @@ __device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, in
   for (int q = 0; q < 4; ++q) {
     const int u = lane + 64 * q, i = u >> 4, j = u & 15;
     const int gj = ip[j];
-    mv[q] = (r0 + i < l && gj >= 0) ? vp.V[(long long)(r0 + i) * l + gj] : 0.0;
+    mv[q] = (r0 + i < l && gj >= 0) ? vp.V[blk(nb, r0 + i, gj)] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -240,7 +295,7 @@ __device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, in
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = r0 + k4 + 4 * v, gj = ip[r16];
-    if (row < l && gj >= 0) vp.V[(long long)row * l + gj] = acc[v];
+    if (row < l && gj >= 0) vp.V[blk(nb, row, gj)] = acc[v];
   }
 }
 
@@ -281,7 +336,7 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, double* __res
     for (int q = 0; q < 4; ++q) {
       const int u = lane + 64 * q, i = u >> 4, j = u & 15;
       const int gi = ip[i], gj = iq[j];
-      mv[q] = (gi >= 0 && gj >= 0) ? A[(long long)gi * l + gj] : 0.0;
+      mv[q] = (gi >= 0 && gj >= 0) ? A[blk(nb, gi, gj)] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -321,7 +376,220 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, double* __res
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gi = ip[k4 + 4 * v], gj = iq[r16];
-      if (gi >= 0 && gj >= 0) A[(long long)gi * l + gj] = acc2[v];
+      if (gi >= 0 && gj >= 0) A[blk(nb, gi, gj)] = acc2[v];
+    }
+  }
+}
+
+// ---- one launch per round (full tournament sweeps) -------------------------------------------------------------
+// (pair index, half) of block b in tournament round r: the inverse of round_pair.
+__device__ __forceinline__ int2 pair_of_block(int r, int b, int nb) {
+  const int m = nb - 1, np = nb / 2;
+  if (b == m) return make_int2(0, 0);
+  if (b == r) return make_int2(0, 1);
+  int d = b - r;
+  if (d < 0) d += m;  // 1 .. m - 1
+  return d <= np - 1 ? make_int2(d, 0) : make_int2(m - d, 1);
+}
+
+// Launch q of a sweep with A double-buffered.  Ain holds A before the rotations G of round q - 1 (prev; none at
+// the sweep's first round), and the launch
+//   * solves the pairs of round q (workgroups [0, npw)) on the subproblems of A' = G^T Ain G: the 16 indices of
+//     a new pair come from two blocks, each the half (ha, hb) of a pair Pa, Pb of round q - 1, so with the 32
+//     indices of Pa and Pb and W (32 x 16) holding U_Pa's columns of half ha and U_Pb's of half hb,
+//     S = W^T (M W), M = Ain on those 32 indices;
+//   * writes A' into Aout tile by tile (workgroups [npw, npw + naw), 2 x 2 tiles each: tile (P, Q) <-
+//     U_P^T Ain_PQ U_Q, copied when neither pair rotated; Aout == Ain only when there are no pair solves, and
+//     then such tiles are skipped and each tile reads its own entries);
+//   * applies V <- V G (the remaining workgroups, one (pair, 64-row slab) item each).
+// None of the three reads what another writes, so a round costs one launch instead of two.  Every workgroup is
+// one wavefront.  Every pair solve writes its U (the identity when it rotated nothing), so the products need no
+// flags, and with the block padding in storage no access needs a guard: the loads and stores are unconditional
+// (edge tiles of an odd pair count aside).  The products run on v_mfma_f64_16x16x4f64 with operands loaded straight from memory: the
+// A operand of step ks on lane (k4 = L/16, r16 = L%16) is X[r16][ks + k4], the B operand Y[ks + k4][r16], and
+// the accumulator's v-th value is D[k4 + 4 v][r16], which is exactly the B operand of step ks = 4 v of a second
+// product, so T = X Y feeds Z^T T without leaving registers.  Reads of A out of place use its symmetry
+// (X[r][c] = A[c][r]), so that the 16 lanes of one k4 read row segments.
+struct RoundArgs {
+  int l, nb, np;
+  int round, npw;  // this round's pair solves (npw = 0: none)
+  int prev, naw;   // the previous round (-1: none) and the apply workgroups (ceil(np / 2)^2, or 0)
+  int nvw;         // V items (np * ceil(8 nb / 64), or 0)
+  const double* Ain;
+  double* Aout;
+  const double* Uprev;
+  double* Uout;
+  double* V;
+  const double* thresh_ptr;
+  int max_inner, within;
+};
+
+__global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
+  const int lane = threadIdx.x;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  int wg = blockIdx.x;
+  if (wg < a.npw) {
+    // ---- pair solve
+    __shared__ double S[SLOT][SLOT + 1];
+    __shared__ double U[SLOT][SLOT + 1];
+    __shared__ double2 cs[8];
+    const int k = wg;
+    const int2 pq = round_pair(a.round, k, a.nb);
+    if (a.prev < 0) {
+      double sv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int u = lane + 64 * q, i = u >> 4, j = u & 15;
+        sv[q] = a.Ain[blk(a.nb, slot_index(pq, i), slot_index(pq, j))];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int u = lane + 64 * q;
+        S[u >> 4][u & 15] = sv[q];
+      }
+    } else {
+      const int2 ea = pair_of_block(a.prev, pq.x, a.nb), eb = pair_of_block(a.prev, pq.y, a.nb);
+      const int2 pa = round_pair(a.prev, ea.x, a.nb), pb = round_pair(a.prev, eb.x, a.nb);
+      const double* Ua = a.Uprev + (long long)ea.x * SLOT * SLOT;
+      const double* Ub = a.Uprev + (long long)eb.x * SLOT * SLOT;
+      // W[4 ks + k4][r16]: the B operand of T = M W and the A operand of S = W^T T
+      double wv[8];
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const int c = 4 * ks + k4;
+        double v = 0.0;
+        if (ks < 4) {
+          if (r16 < 8) v = Ua[c * SLOT + ea.y * 8 + r16];
+        } else {
+          if (r16 >= 8) v = Ub[(c - SLOT) * SLOT + eb.y * 8 + r16 - 8];
+        }
+        wv[ks] = v;
+      }
+      // M[c][c'] over source indices c < 16 from Pa, c >= 16 from Pb; lane reads M[rb 16 + r16][4 ks + k4]
+      double mv[2][8];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int gj = rb == 0 ? slot_index(pa, r16) : slot_index(pb, r16);
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          const int c = 4 * ks + k4;
+          const int gi = ks < 4 ? slot_index(pa, c) : slot_index(pb, c - SLOT);
+          mv[rb][ks] = a.Ain[blk(a.nb, gi, gj)];
+        }
+      }
+      dbl4 t[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        t[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) t[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(mv[rb][ks], wv[ks], t[rb], 0, 0, 0);
+      }
+      // S = W^T T: step ks takes T's rows 4 ks .. 4 ks + 3, held as t[ks / 4][ks % 4]
+      dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[ks], t[ks >> 2][ks & 3], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[k4 + 4 * v][r16] = acc[v];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int u = lane + 64 * q, i = u >> 4, j = u & 15;
+      U[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi16(S, U, cs, *a.thresh_ptr, a.max_inner, a.within);
+    __syncthreads();
+    double* Uk = a.Uout + (long long)k * SLOT * SLOT;
+    for (int u = lane; u < SLOT * SLOT; u += 64) Uk[u] = U[u >> 4][u & 15];
+    return;
+  }
+  wg -= a.npw;
+  if (wg < a.naw) {
+    // ---- tiles (P0 + i, Q0 + j), i, j < 2, of the previous round's pairs: U_P and U_Q are loaded once for two tiles
+    const int ng = (a.np + 1) / 2;
+    const int P0 = 2 * (wg / ng), Q0 = 2 * (wg % ng);
+    // in place (the tail) every tile reads its own entries only: tile (Q, P), which holds A[iq][ip], is being
+    // rewritten by another wavefront
+    const bool inplace = a.Aout == a.Ain;
+    int2 pp[2], qq[2];
+    bool lp[2], lq[2];
+    double up[2][4], uq[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      lp[i] = P0 + i < a.np;
+      lq[i] = Q0 + i < a.np;
+      const int P = lp[i] ? P0 + i : P0, Q = lq[i] ? Q0 + i : Q0;
+      pp[i] = round_pair(a.prev, P, a.nb);
+      qq[i] = round_pair(a.prev, Q, a.nb);
+      const double* UP = a.Uprev + (long long)P * SLOT * SLOT;
+      const double* UQ = a.Uprev + (long long)Q * SLOT * SLOT;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        up[i][s4] = UP[(4 * s4 + k4) * SLOT + r16];
+        uq[i][s4] = UQ[(4 * s4 + k4) * SLOT + r16];
+      }
+    }
+    double mv[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ipr = slot_index(pp[i], r16);  // row r16 of the tile
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int gi = slot_index(qq[j], 4 * s4 + k4);  // column 4 s4 + k4 of the tile
+          mv[i][j][s4] = a.Ain[inplace ? blk(a.nb, ipr, gi) : blk(a.nb, gi, ipr)];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        dbl4 t = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) t = __builtin_amdgcn_mfma_f64_16x16x4f64(mv[i][j][s4], uq[j][s4], t, 0, 0, 0);
+        dbl4 y = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) y = __builtin_amdgcn_mfma_f64_16x16x4f64(up[i][s4], t[s4], y, 0, 0, 0);
+        if (lp[i] && lq[j]) {
+          const int gj = slot_index(qq[j], r16);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) a.Aout[blk(a.nb, slot_index(pp[i], k4 + 4 * v), gj)] = y[v];
+        }
+      }
+    return;
+  }
+  wg -= a.naw;
+  if (wg < a.nvw) {
+    // ---- V[r0 .. r0 + 63, idx_P] <- V[r0 .., idx_P] U_P (rows past the padded size are not touched)
+    const int L = a.nb * BSZ;
+    const int ns = (L + 63) / 64;
+    const int P = wg / ns, r0 = (wg % ns) * 64;
+    const int2 pp = round_pair(a.prev, P, a.nb);
+    const double* UP = a.Uprev + (long long)P * SLOT * SLOT;
+    double u[4], mv[4][4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      u[s4] = UP[(4 * s4 + k4) * SLOT + r16];
+      const int gc = slot_index(pp, 4 * s4 + k4);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const int row = min(r0 + 16 * rb + r16, L - 1);
+        mv[rb][s4] = a.V[blk(a.nb, row, gc)];
+      }
+    }
+    const int gj = slot_index(pp, r16);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(mv[rb][s4], u[s4], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * rb + k4 + 4 * v;
+        if (row < L) a.V[blk(a.nb, row, gj)] = acc[v];
+      }
     }
   }
 }
@@ -375,7 +643,7 @@ __global__ __launch_bounds__(256) void block_norm_kernel(int l, int nb, const do
 #pragma unroll
   for (int r = 0; r < BSZ; ++r) {
     const int i = b1 * BSZ + r;
-    v[r] = (need && i < l && j < l) ? A[(long long)i * l + j] : 0.0;
+    v[r] = (need && i < l && j < l) ? A[blk(nb, i, j)] : 0.0;
   }
   double off = 0.0, all = 0.0, pos = 0.0;
 #pragma unroll
@@ -400,12 +668,6 @@ __global__ __launch_bounds__(256) void block_norm_kernel(int l, int nb, const do
     ball[(long long)b1 * nb + b2] = (b1 < b2 ? 2.0 : 1.0) * all;
     if (b1 == b2) bpos[b1] = pos;
   }
-}
-
-__global__ void eye_kernel(int l, double* __restrict__ V) {
-  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= (long long)l * l) return;
-  V[u] = ((u / l) == (u % l)) ? 1.0 : 0.0;
 }
 
 // Ascending order of the diagonal dg by ranks: element i goes to position #{j : k_j < k_i, or k_j == k_i and
@@ -465,6 +727,28 @@ __global__ void permute_cols_kernel(int l, const double* __restrict__ V, const i
   if (u >= (long long)l * l) return;
   const int i = (int)(u / l), j = (int)(u % l);
   P[u] = V[(long long)i * l + perm[j]];
+}
+
+// P[i][j] = V[i][perm[j]] with V in blocked storage.
+__global__ void permute_cols_blocked_kernel(int l, int nb, const double* __restrict__ V, const int* __restrict__ perm,
+                                            double* __restrict__ P) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)l * l) return;
+  const int i = (int)(u / l), j = (int)(u % l);
+  P[u] = V[blk(nb, i, perm[j])];
+}
+
+// Blocked storage of the row-major l x l X (ld l), zeros past l (X null: the identity).  One thread per stored
+// entry, in storage order.
+__global__ void to_blocked_kernel(int l, int nb, const double* __restrict__ X, double* __restrict__ B) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)nb * nb * 64) return;
+  const long long b = u >> 6;
+  const int e = (int)(u & 63);
+  const int i = (int)(b / nb) * 8 + (e >> 3), j = (int)(b % nb) * 8 + (e & 7);
+  double v = 0.0;
+  if (i < l && j < l) v = X ? X[(long long)i * l + j] : (i == j ? 1.0 : 0.0);
+  B[u] = v;
 }
 
 }  // namespace
@@ -641,24 +925,36 @@ static bool threshold_schedule(EigWork* w, int nb, double tau2) {
   return true;
 }
 
+size_t eig_mat_doubles(int l) {
+  const size_t L = (size_t)block_count(l) * BSZ;
+  return L * L;
+}
+
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
-                       int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off, int* npos,
-                       hipStream_t st) {
-  if (l > w->lmax || (w->noalloc && P0)) return hipErrorInvalidValue;  // the no-alloc path has no warm start
-  double* A = tmp;
-  double* V = tmp + (long long)l * l;
+                       int tmp_mats, int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off,
+                       int* npos, hipStream_t st) {
+  if (l > w->lmax || (w->noalloc && P0) || tmp_mats < 2 || (P0 && tmp_mats < 3)) return hipErrorInvalidValue;
+  const int nb = block_count(l);
+  const long long mat = (long long)eig_mat_doubles(l);
+  double* A = tmp;                                    // blocked A
+  double* V = tmp + mat;                              // blocked V (row-major staging before the sweeps)
+  double* A2 = tmp_mats >= 3 ? tmp + 2 * mat : nullptr;  // second blocked A (row-major staging before the sweeps)
   const long long nn = (long long)l * l;
   const int eb = (int)((nn + 255) / 256);
-  // ascending eigenvalues from w->dg and the columns of src (the basis) permuted to match into P
+  const int ebb = (int)((mat + 255) / 256);
+  // ascending eigenvalues from w->dg and the columns of the basis permuted to match into P: src row-major, or
+  // the blocked V when src is null
   auto finish = [&](const double* src) -> hipError_t {
     if (l > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 15) / 16), dim3(256), 0, st, l, w->dg, wv, w->perm);
     KOT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, src, w->perm, P);
+    if (src) hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, src, w->perm, P);
+    else hipLaunchKernelGGL(permute_cols_blocked_kernel, dim3(eb), dim3(256), 0, st, l, nb, V, w->perm, P);
     return hipGetLastError();
   };
   if (P0) {
-    // A = P0^T Z P0 (Z P0 staged in V; P0 may alias the output P), then V = P0
+    // A = P0^T Z P0 (Z P0 staged row-major in V's region, the product row-major in A2's; P0 may alias the output
+    // P), then both to blocked storage: A from the product, V from P0
     GemmArgs g{};
     g.transa = 0; g.transb = 0; g.m = l; g.n = l; g.k = l; g.alpha = 1.0; g.beta = 0.0;
     g.A = Z; g.lda = l; g.B = P0; g.ldb = l; g.C = V; g.ldc = l; g.batch = 1;
@@ -684,16 +980,20 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
         return finish(P0 == P ? V : P0);
       }
     }
-    g.transa = 1; g.A = P0; g.B = V; g.C = A;
+    g.transa = 1; g.A = P0; g.B = V; g.C = A2;
     g.lower = 1; g.mirror = 1;  // symmetric result: lower tiles, mirrored
     KOT_HIP_TRY(gemm_f64(g, st));
-    KOT_HIP_TRY(vec_copy((int)nn, P0, V, st));
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, A2, A);
+    KOT_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, P0, V);
+    KOT_HIP_TRY(hipGetLastError());
   } else {
-    KOT_HIP_TRY(vec_copy((int)nn, Z, A, st));
-    hipLaunchKernelGGL(eye_kernel, dim3(eb), dim3(256), 0, st, l, V);
+    // Z may lie in V's region (the allocation-free path stages it there): it is read before V is written
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, Z, A);
+    KOT_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, nullptr, V);
     KOT_HIP_TRY(hipGetLastError());
   }
-  const int nb = block_count(l);
   const int np = nb / 2;
   const int nslab = (l + SLOT - 1) / SLOT;
   double off = 0.0, all = 0.0;
@@ -728,7 +1028,33 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
                        w->up, inner_sweeps, 1, vprev(q_last + 1, r_last, list_last), np);
     return hipGetLastError();
   };
+  // With a second buffer for A, round q's pair solves, A's update by round q - 1 (Ain = buffer (q - 1) & 1 ->
+  // buffer q & 1) and V's update by round q - 1 share launch q (round_kernel); a tail launch applies the last
+  // round to A (into the first buffer, in place when that is where A is) and to V.
+  auto launch_sweep_fused = [&](hipStream_t s_) -> hipError_t {
+    const int R = nb - 1;
+    double* Abuf[2] = {A, A2};
+    for (int q = 0; q <= R; ++q) {
+      RoundArgs ra{};
+      ra.l = l; ra.nb = nb; ra.np = np;
+      ra.round = q; ra.npw = q < R ? np : 0;
+      ra.prev = q - 1; ra.naw = q > 0 ? ((np + 1) / 2) * ((np + 1) / 2) : 0;
+      ra.Ain = q > 0 ? Abuf[(q - 1) & 1] : A;
+      ra.Aout = q < R ? Abuf[q & 1] : A;
+      ra.Uprev = Ub[(q + 1) & 1];
+      ra.Uout = Ub[q & 1];
+      ra.nvw = q > 0 ? np * ((nb * BSZ + 63) / 64) : 0;
+      ra.V = V;
+      ra.thresh_ptr = w->up;
+      ra.max_inner = inner_sweeps; ra.within = q == 0 ? 1 : 0;
+      const int grid = ra.npw + ra.naw + ra.nvw;
+      hipLaunchKernelGGL(round_kernel, dim3(grid), dim3(64), 0, s_, ra);
+      KOT_HIP_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+  };
   auto launch_sweep = [&](hipStream_t s_) -> hipError_t {
+    if (A2) return launch_sweep_fused(s_);
     for (int r = 0; r < nb - 1; ++r) KOT_HIP_TRY(launch_round(s_, r, r, nullptr, np, r - 1, nullptr));
     return launch_v_tail(s_, nb - 2, nb - 2, nullptr);
   };
@@ -801,7 +1127,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   *sweeps = s;
   *rel_off = (all > 0.0) ? off / all : 0.0;
   if (npos) *npos = pos;
-  return finish(V);
+  return finish(nullptr);
 }
 
 // ---- allocation-free eigendecomposition ---------------------------------------------------------------------
@@ -847,7 +1173,7 @@ hipError_t eigh_jacobi_noalloc(int device, int l, const double* Z, double* P, do
   double* base = nullptr;
   KOT_HIP_TRY(noalloc_scratch(device, &base));
   const size_t ll = (size_t)kNoAllocMaxL * kNoAllocMaxL;
-  double* A = base;                      // A then V (eigh_jacobi's tmp layout: V = tmp + l*l)
+  double* A = base;                      // A then V (eigh_jacobi's tmp layout: V = tmp + eig_mat_doubles(l))
   double* cur = base + 2 * ll;
   EigWork w;
   w.noalloc = true;
@@ -860,10 +1186,11 @@ hipError_t eigh_jacobi_noalloc(int device, int l, const double* Z, double* P, do
   w.flag = reinterpret_cast<int*>(cur);
   w.perm = w.flag + 2 * kNoAllocMaxNp;
   w.hb = g_noalloc_hb;
-  // symmetrized input straight into A's slot; eigh_jacobi's copy of Z into A is then in place
-  KOT_HIP_TRY(form_z(l, Z, 0.0, Z, 0.0, A, st));
+  // the symmetrized input is staged row-major in V's region, from which eigh_jacobi forms the blocked A
+  double* Zs = A + eig_mat_doubles(l);
+  KOT_HIP_TRY(form_z(l, Z, 0.0, Z, 0.0, Zs, st));
   int npos = 0;
-  return eigh_jacobi(&w, l, A, nullptr, P, wv, A, max_sweeps, inner_sweeps, tol, sweeps, rel_off, &npos, st);
+  return eigh_jacobi(&w, l, Zs, nullptr, P, wv, A, 2, max_sweeps, inner_sweeps, tol, sweeps, rel_off, &npos, st);
 }
 
 }  // namespace kot

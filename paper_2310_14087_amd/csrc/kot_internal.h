@@ -103,10 +103,12 @@ void eig_work_destroy(EigWork* w);
 // Z (l x l) -> P (columns eigenvectors), wv ascending.  If P0 is non-null, starts from the basis P0
 // (columns orthonormal).  Returns the sweep count through *sweeps, off/norm through *rel_off and the number
 // of positive eigenvalues through *npos (may be null); the host has synchronized with the stream on return.
-// tmp: workspace of at least 2*l*l doubles.
+// tmp: workspace of tmp_mats >= 2 matrices of eig_mat_doubles(l) doubles each (blocked A and V); with a third
+// (required for a warm start) a full sweep runs one launch per round instead of two.
+size_t eig_mat_doubles(int l);
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
-                       int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off, int* npos,
-                       hipStream_t st);
+                       int tmp_mats, int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off,
+                       int* npos, hipStream_t st);
 
 // ---- vector kernels -----------------------------------------------------------------------------------------
 hipError_t vec_fill(int n, double v, double* x, hipStream_t st);
