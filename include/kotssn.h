@@ -101,6 +101,10 @@ typedef struct kot_params {
   int closed_start;    /* 1: without gamma0 and without ws_theta, start from gamma0_i = max(z_i / Q_ii, -lambda1),
                           the minimizer of Eq. (3.4) for diagonal Q and orthogonal R (the LMI is then the box
                           gamma >= -lambda1), lifted and kept or dropped like any start (default 0) */
+  double kdiag_tol;    /* sparsity of K (Remark 4.5): when every off-diagonal entry of K + eps I is at most kdiag_tol
+                          times its largest diagonal entry, the setup drops them, so R = diag(sqrt(K_ii + eps))
+                          without the factorization, and the solve's products with R (Phi, Phi*, P^T R, the
+                          lifted start) become diagonal scalings (default 1e-12; 0 = always factor) */
 } kot_params;
 
 /* Samples and filling points (Section 3).  All four arrays are device pointers, row-major:
@@ -134,6 +138,7 @@ typedef struct kot_result {
   int warm_used;       /* 1 if the start from gamma0 was kept (it had |R(w0)| <= |R(0,0)|), else 0 */
   int lowp_directions; /* Newton directions computed with the reduced-precision chain (see lowp_min_rows) */
   double time_ms;      /* wall time of the solve on the device stream */
+  int kdiag;           /* 1 if the setup took K as diagonal (kdiag_tol), else 0 */
 } kot_result;
 
 /* Fills *p with the defaults listed above (sigma, lambda1, lambda2 set to 1, 1e-3, 1e-3). */
@@ -148,7 +153,8 @@ const char* kot_last_error(const kot_ctx* ctx);
 
 /* Dual data of Eq. (3.4) (Section 3): Q = K_X + K_Y (l x l), z (l), the upper-triangular factor R with
  * R^T R = K + eps I where K = K_X o K_Y (l x l), wsum = w_mu + w_nu at the filling points (l), and q2
- * (host scalar).  Q, z, R, wsum are device pointers; R's strictly lower triangle is written as 0.
+ * (host scalar).  Q, z, R, wsum are device pointers; R's strictly lower triangle is written as 0.  When
+ * K + eps I is diagonal to prm->kdiag_tol, its off-diagonal entries are dropped and R = diag(sqrt(K_ii + eps)).
  * Returns KOT_ERR_FACTOR if the Cholesky factorization meets a non-positive pivot. */
 kot_status kot_setup(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm,
                      double* Q, double* z, double* R, double* wsum, double* q2);

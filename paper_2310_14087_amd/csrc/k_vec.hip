@@ -618,6 +618,88 @@ __global__ void scale_cols_kernel(int rows, int cols, const double* __restrict__
   out[(long long)i * ldo + j] = A[(long long)i * lda + j] * s[j];
 }
 
+// ---- diagonal kernel factor (Remark 4.5: sparsity of K) ------------------------------------------------------
+// out[0] = max_{i != j} |A_ij|, out[1] = max_i |A_ii|; out must hold zeros on entry (atomic max on the bit
+// patterns of non-negative doubles, which order like the values).  One row per workgroup.
+__global__ __launch_bounds__(256) void offdiag_absmax_kernel(int l, const double* __restrict__ A, double* out) {
+  const int i = blockIdx.x;
+  double m = 0.0, dm = 0.0;
+  for (int j = threadIdx.x; j < l; j += 256) {
+    const double v = fabs(A[(long long)i * l + j]);
+    if (j == i) dm = v;
+    else m = fmax(m, v);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m = fmax(m, __shfl_xor(m, o));
+    dm = fmax(dm, __shfl_xor(dm, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(m));
+    atomicMax(reinterpret_cast<unsigned long long*>(out + 1), (unsigned long long)__double_as_longlong(dm));
+  }
+}
+
+// R = diag(sqrt(K_ii)) (dense l x l, zeros off the diagonal), rd_i = R_ii, Linv = R^-T when non-null; info = 0,
+// then (diag_check_kernel) an index (1-based) with K_ii <= 0, if any.
+__global__ void diag_factor_kernel(int l, const double* __restrict__ K, double* __restrict__ R, double* __restrict__ rd,
+                                   double* __restrict__ Linv, int* __restrict__ info) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u == 0) *info = 0;
+  if (u >= (long long)l * l) return;
+  const int i = (int)(u / l), j = (int)(u % l);
+  double r = 0.0, ri = 0.0;
+  if (i == j) {
+    const double k = K[u];
+    r = sqrt(k);
+    ri = 1.0 / r;
+    rd[i] = r;
+  }
+  R[u] = r;
+  if (Linv) Linv[u] = ri;
+}
+__global__ void diag_check_kernel(int l, const double* __restrict__ K, int* __restrict__ info) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < l && !(K[(long long)i * l + i] > 0.0)) atomicCAS(info, 0, i + 1);
+}
+
+// out = diag(rd_i^2 g_i) (power 2) or diag(g_i / rd_i^2) (power -2), dense l x l.
+__global__ void diag_gram_kernel(int l, const double* __restrict__ rd, int power, const double* __restrict__ g,
+                                 double* __restrict__ out) {
+  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (long long)l * l) return;
+  const int i = (int)(u / l), j = (int)(u % l);
+  double v = 0.0;
+  if (i == j) v = power > 0 ? rd[i] * rd[i] * g[i] : g[i] / (rd[i] * rd[i]);
+  out[u] = v;
+}
+
+// y_i = alpha rd_i^2 X_ii + beta y_i (beta = 0: y is not read).
+__global__ void phi_diag_kernel(int l, const double* __restrict__ rd, const double* __restrict__ X, double alpha,
+                                double beta, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= l) return;
+  const double v = alpha * rd[i] * rd[i] * X[(long long)i * l + i];
+  y[i] = beta != 0.0 ? v + beta * y[i] : v;
+}
+
+// B = P^T diag(rd): B_ij = P_ji rd_j, through 32 x 32 LDS tiles (coalesced reads and writes).
+__global__ __launch_bounds__(256) void transpose_scale_kernel(int l, const double* __restrict__ P,
+                                                              const double* __restrict__ rd, double* __restrict__ B) {
+  __shared__ double T[32][33];
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;  // the B tile (rows bi.., columns bj..)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {  // P rows bj + r, columns bi + tx
+    const int pr = bj + r, pc = bi + tx;
+    T[r][tx] = (pr < l && pc < l) ? P[(long long)pr * l + pc] * rd[pr] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int br = bi + r, bc = bj + tx;
+    if (br < l && bc < l) B[(long long)br * l + bc] = T[tx][r];
+  }
+}
+
 inline int nblk(long long n, int b = 256) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -649,6 +731,29 @@ hipError_t vec_axpby(int n, double a, const double* x, double b, double* y, hipS
 hipError_t vec_lincomb(int n, double a, const double* x, double b, const double* y, double* z, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n)), dim3(256), 0, st, (long long)n, a, x, b, y, z);
+  return hipGetLastError();
+}
+hipError_t offdiag_absmax(int l, const double* A, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, st, 2LL, 0.0, out);
+  hipLaunchKernelGGL(offdiag_absmax_kernel, dim3(l), dim3(256), 0, st, l, A, out);
+  return hipGetLastError();
+}
+hipError_t diag_factor(int l, const double* K, double* R, double* rd, double* Linv, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(diag_factor_kernel, dim3(nblk((long long)l * l)), dim3(256), 0, st, l, K, R, rd, Linv, info);
+  hipLaunchKernelGGL(diag_check_kernel, dim3(nblk(l)), dim3(256), 0, st, l, K, info);
+  return hipGetLastError();
+}
+hipError_t diag_gram(int l, const double* rd, int power, const double* g, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(diag_gram_kernel, dim3(nblk((long long)l * l)), dim3(256), 0, st, l, rd, power, g, out);
+  return hipGetLastError();
+}
+hipError_t phi_diag(int l, const double* rd, const double* X, double alpha, double beta, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(phi_diag_kernel, dim3(nblk(l)), dim3(256), 0, st, l, rd, X, alpha, beta, y);
+  return hipGetLastError();
+}
+hipError_t transpose_scale(int l, const double* P, const double* rd, double* B, hipStream_t st) {
+  const int t = (l + 31) / 32;
+  hipLaunchKernelGGL(transpose_scale_kernel, dim3(t, t), dim3(256), 0, st, l, P, rd, B);
   return hipGetLastError();
 }
 hipError_t add_diag(int l, double a, double* X, hipStream_t st) {

@@ -26,9 +26,10 @@ constexpr int kScalarDoubles = 64, kScalarInts = 16;
 constexpr size_t kScalarBytes = kScalarDoubles * sizeof(double) + kScalarInts * sizeof(int);
 // scalar slots: 0-3 per-call temporaries; residual norms (|r1|^2, |r2|^2) of the EG point 4-5 and of the trial
 // 6-7; the theta-rule dots 8-11; inputs of the default EG step 12-13; |z|^2 14; refinement scalars 16-19;
+// the largest off-diagonal and diagonal entries of K + eps I 20-21;
 // pooled feature statistics 24-25; the device-resident CG / QMR state 32-38
 enum : int { SL_TMP = 0, SL_VN = 4, SL_TN = 6, SL_THETA = 8, SL_ETA = 12, SL_ZZ = 14, SL_RR = 16, SL_PAP = 17,
-             SL_XX = 18, SL_POOL = 24, SL_CG = 32 };
+             SL_XX = 18, SL_KD = 20, SL_POOL = 24, SL_CG = 32 };
 
 struct State {  // an iterate w = (gamma, X) with its residual and the spectral data of Z
   double* g = nullptr;
@@ -52,6 +53,7 @@ struct CoreView {  // dual data of Eq. (3.4) on the device
   double lam1 = 0.0, lam2 = 0.0;
   double* KK = nullptr;  // (R^T R) o (R^T R)
   const double* Linv = nullptr;  // R^-T when the factorization produced it (else the lift inverts R itself)
+  const double* rd = nullptr;    // non-null: R is diagonal (kdiag_tol), rd its diagonal; products with R scale
   int kb_state = 0;      // the context's K buffer: 0 unrelated, 1 holds R^T R = K + eps I, 2 and KK is formed
 };
 
@@ -85,7 +87,7 @@ struct kot_ctx {
   // matrices (cap x cap)
   double *Qb, *Rb, *Kb, *KKb, *Z, *T1, *T2, *T3, *T4, *Bm, *dX, *Mr, *eigtmp, *Pe1, *Pe2, *Xh;
   // vectors (cap)
-  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *cdinv, *qd, *qe, *qs, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
+  double *zb, *wsumb, *wmu, *wnu, *dg, *a1, *cx, *cr, *cp, *cAp, *cdinv, *rdb, *qd, *qe, *qs, *vtmp, *gh, *s_e1, *s_e2, *r1h, *lx, *lr, *lp, *lAp;
   float *Bf = nullptr, *Cf = nullptr, *Ef = nullptr;  // reduced-precision chain operands
   // BF16 chain: bfloat16 B, B^T (hi and lo) and H (hi and lo), each ldp x ldp (ldp = chain_ldp(cap))
   unsigned short *Bh = nullptr, *BhT = nullptr, *Bl = nullptr, *BlT = nullptr, *Hh = nullptr, *Hl = nullptr;
@@ -180,7 +182,7 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
   if (!(ctx->eigtmp = alloc(3 * eig_mat_doubles(cap) * sizeof(double))))
     return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   double** vecs[] = {&ctx->zb, &ctx->wsumb, &ctx->wmu, &ctx->wnu, &ctx->dg, &ctx->a1, &ctx->cx, &ctx->cr, &ctx->cp,
-                     &ctx->cAp, &ctx->cdinv, &ctx->qd, &ctx->qe, &ctx->qs, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
+                     &ctx->cAp, &ctx->cdinv, &ctx->rdb, &ctx->qd, &ctx->qe, &ctx->qs, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
                      &ctx->lAp};
   for (double** v : vecs)
     if (!(*v = alloc(vv))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
@@ -258,6 +260,10 @@ hipError_t mm_coldot(hipStream_t st, int ta, int tb, int m, int n, int k, double
 // out = Phi*(g) = R diag(g) R^T  (R upper: the k-th term touches only rows and columns <= k)
 kot_status phi_star(kot_ctx* ctx, const CoreView& cv, const double* g, double* out) {
   const int l = cv.l;
+  if (cv.rd) {
+    HIPCHK(diag_gram(l, cv.rd, 2, g, out, ctx->stream));
+    return KOT_OK;
+  }
   HIPCHK(mm(ctx->stream, 0, 1, l, l, l, 1.0, cv.R, l, g, cv.R, l, 0.0, out, l, TRI_A_UPPER | TRI_B_LOWER, true));
   return KOT_OK;
 }
@@ -265,6 +271,10 @@ kot_status phi_star(kot_ctx* ctx, const CoreView& cv, const double* g, double* o
 // y = alpha*Phi(X) + beta*y, Phi(X)_i = R[:,i]^T X R[:,i] = sum_r R_ri (X R)_ri (X R never written out)
 kot_status phi_op(kot_ctx* ctx, const CoreView& cv, const double* X, double alpha, double beta, double* y) {
   const int l = cv.l;
+  if (cv.rd) {
+    HIPCHK(phi_diag(l, cv.rd, X, alpha, beta, y, ctx->stream));
+    return KOT_OK;
+  }
   HIPCHK(mm_coldot(ctx->stream, 0, 0, l, l, l, 1.0, X, l, nullptr, cv.R, l, TRI_B_UPPER, cv.R, l, alpha, beta, y));
   return KOT_OK;
 }
@@ -471,7 +481,8 @@ kot_status ssn_direction(kot_ctx* ctx, const CoreView& cv, const State& s, doubl
   hipStream_t st = ctx->stream;
   TPlan tp = make_tplan(l, s.a, mu, s.P, s.s);
   // B = P^T R
-  HIPCHK(mm(st, 1, 0, l, l, l, 1.0, s.P, l, nullptr, cv.R, l, 0.0, ctx->Bm, l, TRI_B_UPPER));
+  if (cv.rd) HIPCHK(transpose_scale(l, s.P, cv.rd, ctx->Bm, st));
+  else HIPCHK(mm(st, 1, 0, l, l, l, 1.0, s.P, l, nullptr, cv.R, l, 0.0, ctx->Bm, l, TRI_B_UPPER));
   // M = r2 + T[r2]  (kept in Mr), a1 = -r1 - Phi(M)/(mu+1)
   KCHK(t_apply(ctx, tp, s.r2, ctx->T1));
   HIPCHK(vec_lincomb(l * l, 1.0, s.r2, 1.0, ctx->T1, ctx->Mr, st));
@@ -955,10 +966,12 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   if (gamma0 && p->lift_x0) {
     // X0 = R^-T diag(y) R^-1 with y = (Q gamma0 - z)/(2 lam2) (stationarity's value of Phi(X)) on the
     // constraints predicted active, small entries dropped, so that Phi(X0) = y
-    if (!cv.Linv) KCHK(trtri_cached(ctx, l, cv.R, ctx->T1, ctx->T2));
+    if (!cv.Linv && !cv.rd) KCHK(trtri_cached(ctx, l, cv.R, ctx->T1, ctx->T2));
     HIPCHK(mm(st, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, W->g, 1, 0.0, ctx->vtmp, 1));
     HIPCHK(lift_diag(l, ctx->vtmp, cv.z, W->g, cv.lam1, cv.lam2, 0.02, ctx->dg, ctx->part, st));
-    if (cv.Linv)
+    if (cv.rd)
+      HIPCHK(diag_gram(l, cv.rd, -2, ctx->dg, W->X, st));
+    else if (cv.Linv)
       HIPCHK(mm(st, 0, 1, l, l, l, 1.0, cv.Linv, l, ctx->dg, cv.Linv, l, 0.0, W->X, l, TRI_A_LOWER | TRI_B_UPPER,
                 true));
     else
@@ -1123,19 +1136,36 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   return status;
 }
 
-// Linv (optional): receives R^-T from the factorization.
+// Whether K + eps I (in ctx->Kb) is diagonal to kdiag_tol relative to its largest diagonal entry (a host
+// synchronization); if so R = diag(sqrt(K_ii + eps)) (rd: its diagonal; Linv: R^-T) replaces the factorization.
+kot_status kdiag_factor(kot_ctx* ctx, int l, const kot_params* p, double* R, double* rd, double* Linv, bool* diag) {
+  *diag = false;
+  if (!(p->kdiag_tol > 0.0) || !rd) return KOT_OK;
+  HIPCHK(offdiag_absmax(l, ctx->Kb, ctx->dsc + SL_KD, ctx->stream));
+  KCHK(sync_read(ctx));
+  if (!(ctx->hsc[SL_KD] <= p->kdiag_tol * ctx->hsc[SL_KD + 1])) return KOT_OK;
+  HIPCHK(diag_factor(l, ctx->Kb, R, rd, Linv, ctx->dint, ctx->stream));
+  *diag = true;
+  return KOT_OK;
+}
+
+// Linv (optional): receives R^-T from the factorization.  rd (optional): with kdiag_tol, the diagonal of a
+// diagonal R (*diag set when taken).
 kot_status setup_impl(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, double* Q, double* z, double* R,
-                      double* wsum, double* q2, double* Linv = nullptr) {
+                      double* wsum, double* q2, double* Linv = nullptr, double* rd = nullptr, bool* diag = nullptr) {
   const int l = pb->l, d = pb->d;
   hipStream_t st = ctx->stream;
   HIPCHK(gram_build(l, d, pb->xf, pb->yf, p->sigma, Q, ctx->Kb, st));
   HIPCHK(add_diag(l, p->eps_jitter, ctx->Kb, st));  // K + eps I = R^T R from here on
+  bool dg = false;
+  KCHK(kdiag_factor(ctx, l, p, R, rd, Linv, &dg));
+  if (diag) *diag = dg;
   HIPCHK(mean_embedding(pb->n_src, l, d, pb->xs, pb->xf, p->sigma, ctx->wmu, st));
   HIPCHK(mean_embedding(pb->n_tgt, l, d, pb->ys, pb->yf, p->sigma, ctx->wnu, st));
   HIPCHK(mean_gram(pb->n_src, d, pb->xs, p->sigma, ctx->dsc + 0, ctx->part, st));
   HIPCHK(mean_gram(pb->n_tgt, d, pb->ys, p->sigma, ctx->dsc + 1, ctx->part, st));
   HIPCHK(build_z(l, d, pb->xf, pb->yf, ctx->wmu, ctx->wnu, p->lambda2, z, wsum, st));
-  HIPCHK(cholesky_upper(l, ctx->Kb, 0.0, R, ctx->T1, ctx->dint, st, Linv));
+  if (!dg) HIPCHK(cholesky_upper(l, ctx->Kb, 0.0, R, ctx->T1, ctx->dint, st, Linv));
   KCHK(sync_read(ctx, 2, 1));
   *q2 = ctx->hsc[0] + ctx->hsc[1];
   if (ctx->hint[0] != 0)
@@ -1175,14 +1205,15 @@ kot_status setup_side(kot_ctx* ctx, kot_ctx* own, const kot_problem* pb, const k
 // setup_impl with the factorization on the calling stream and setup_side beside it; the core buffers of ctx
 // hold Q, z, R, w_mu + w_nu, K + eps I and KK on return (and Linv, when given, R^-T).
 kot_status setup_overlapped(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, bool predict, Prelude* pre,
-                            double* Linv) {
+                            double* Linv, double* rd, bool* diag) {
   const int l = pb->l, d = pb->d;
   hipStream_t st = ctx->stream;
   KCHK(side_ensure(ctx, l, std::max(pb->n_src, pb->n_tgt)));
   HIPCHK(gram_build(l, d, pb->xf, pb->yf, p->sigma, ctx->Qb, ctx->Kb, st));
   HIPCHK(add_diag(l, p->eps_jitter, ctx->Kb, st));  // K + eps I = R^T R from here on; read-only below
+  KCHK(kdiag_factor(ctx, l, p, ctx->Rb, rd, Linv, diag));
   KCHK(side_post(ctx, [ctx, pb, p, predict, pre]() { return setup_side(ctx->side->c, ctx, pb, p, predict, pre); }));
-  const hipError_t e = cholesky_upper(l, ctx->Kb, 0.0, ctx->Rb, ctx->T1, ctx->dint, st, Linv);
+  const hipError_t e = *diag ? hipSuccess : cholesky_upper(l, ctx->Kb, 0.0, ctx->Rb, ctx->T1, ctx->dint, st, Linv);
   const kot_status rc = e != hipSuccess ? fail(ctx, KOT_ERR_HIP, "cholesky_upper: %s", hipGetErrorString(e))
                                         : sync_read(ctx);
   const kot_status rs = side_join(ctx);  // joined even when the factorization failed
@@ -1259,6 +1290,7 @@ void kot_params_default(kot_params* p) {
   p->eig_max_sweeps = 30;
   p->eig_inner_sweeps = 1;
   p->closed_start = 0;
+  p->kdiag_tol = 1e-12;
   p->warm_eig = 1;
   p->lift_x0 = 1;
   p->ws_F = 0;
@@ -1366,7 +1398,7 @@ kot_status kot_setup(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, d
   KCHK(check_params(ctx, p, true));
   if (!Q || !z || !R || !wsum || !q2) return fail(ctx, KOT_ERR_ARG, "null output");
   KCHK(ensure_ws(ctx, pb->l, std::max(pb->n_src, pb->n_tgt)));
-  return setup_impl(ctx, pb, p, Q, z, R, wsum, q2);
+  return setup_impl(ctx, pb, p, Q, z, R, wsum, q2, nullptr, ctx->rdb);
 }
 
 kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, const double* gamma0, kot_result* res) {
@@ -1382,19 +1414,26 @@ kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, c
   // extragradient step)
   double* Linv = (gamma0 || p->ws_theta || p->closed_start) && p->lift_x0 ? ctx->Xh : nullptr;
   cv.Linv = Linv;
+  bool diag = false;
   if (overlap_ok(ctx, p, pb->l)) {
     Prelude pre;
-    KCHK(setup_overlapped(ctx, pb, p, p->ws_theta && !gamma0, &pre, Linv));
+    KCHK(setup_overlapped(ctx, pb, p, p->ws_theta && !gamma0, &pre, Linv, ctx->rdb, &diag));
     cv.q2 = pre.q2;
     cv.kb_state = 2;
     cv.KK = ctx->KKb;
-    return run_alg2(ctx, cv, p, gamma0, res, &pre);
+    cv.rd = diag ? ctx->rdb : nullptr;
+    const kot_status s = run_alg2(ctx, cv, p, gamma0, res, &pre);
+    res->kdiag = diag ? 1 : 0;
+    return s;
   }
   double q2 = 0.0;
-  KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2, Linv));
+  KCHK(setup_impl(ctx, pb, p, ctx->Qb, ctx->zb, ctx->Rb, ctx->wsumb, &q2, Linv, ctx->rdb, &diag));
   cv.q2 = q2;
   cv.kb_state = 1;
-  return run_alg2(ctx, cv, p, gamma0, res);
+  cv.rd = diag ? ctx->rdb : nullptr;
+  const kot_status s = run_alg2(ctx, cv, p, gamma0, res);
+  res->kdiag = diag ? 1 : 0;
+  return s;
 }
 
 kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z, const double* R, double q2,

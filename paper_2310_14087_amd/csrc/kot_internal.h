@@ -120,6 +120,15 @@ hipError_t vec_axpby(int n, double a, const double* x, double b, double* y, hipS
 hipError_t vec_lincomb(int n, double a, const double* x, double b, const double* y, double* z, hipStream_t st);
 // X += a * I  (l x l)
 hipError_t add_diag(int l, double a, double* X, hipStream_t st);
+// Diagonal kernel factor (the sparsity of Remark 4.5): out[0..1] = max off-diagonal and max diagonal |A_ij|;
+// R = diag(sqrt(K_ii)) as a dense matrix with rd its diagonal and Linv = R^-T (optional), info = 0 or the first
+// non-positive K_ii (1-based); out = diag(rd^power g) for power +-2; y = alpha diag(rd^2) diag(X) + beta y;
+// B = P^T diag(rd).
+hipError_t offdiag_absmax(int l, const double* A, double* out, hipStream_t st);
+hipError_t diag_factor(int l, const double* K, double* R, double* rd, double* Linv, int* info, hipStream_t st);
+hipError_t diag_gram(int l, const double* rd, int power, const double* g, double* out, hipStream_t st);
+hipError_t phi_diag(int l, const double* rd, const double* X, double alpha, double beta, double* y, hipStream_t st);
+hipError_t transpose_scale(int l, const double* P, const double* rd, double* B, hipStream_t st);
 // Z = 0.5 * (Z + Z^T)
 hipError_t symmetrize(int l, double* Z, hipStream_t st);
 // Deterministic reductions: out[0] = sum x*y; partials in part (>= 2 kRedBlocks doubles).  dot2 forms one or

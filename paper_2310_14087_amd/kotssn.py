@@ -44,7 +44,8 @@ class KotParams(C.Structure):
                 ("eig_max_sweeps", C.c_int), ("warm_eig", C.c_int), ("lift_x0", C.c_int), ("ws_F", C.c_int),
                 ("ws_H", C.c_int), ("ws_theta", C.c_void_p), ("overlap", C.c_int),
                 ("lowp_min_rows", C.c_int), ("precond", C.c_int),
-                ("schur_solver", C.c_int), ("eig_inner_sweeps", C.c_int), ("closed_start", C.c_int)]
+                ("schur_solver", C.c_int), ("eig_inner_sweeps", C.c_int), ("closed_start", C.c_int),
+                ("kdiag_tol", C.c_double)]
 
 
 class KotProblem(C.Structure):
@@ -57,7 +58,7 @@ class KotResult(C.Structure):
                 ("hist_cap", C.c_int), ("ot", C.c_double), ("residual", C.c_double), ("iters", C.c_int),
                 ("cg_iters_total", C.c_int), ("eg_accepts", C.c_int), ("null_steps", C.c_int),
                 ("eig_sweeps_total", C.c_int), ("alpha_last", C.c_int), ("warm_used", C.c_int),
-                ("lowp_directions", C.c_int), ("time_ms", C.c_double)]
+                ("lowp_directions", C.c_int), ("time_ms", C.c_double), ("kdiag", C.c_int)]
 
 
 _lib = None
@@ -182,6 +183,7 @@ class SolveResult:
     time_ms: float
     res_hist: np.ndarray
     res_v_hist: np.ndarray
+    kdiag: int = 0
 
 
 class Context:
@@ -250,7 +252,7 @@ class Context:
         n = min(res.iters + 1, len(rh))
         return SolveResult(st, res.ot, res.residual, res.iters, res.cg_iters_total, res.eg_accepts, res.null_steps,
                            res.eig_sweeps_total, res.alpha_last, res.warm_used, res.lowp_directions, res.time_ms, rh[:n].copy(),
-                           rvh[:n].copy())
+                           rvh[:n].copy(), kdiag=res.kdiag)
 
     def solve(self, xs, ys, xf, yf, prm: KotParams, gamma0=None, want_X=False, hist_cap=1024):
         l, dd = xf.shape
