@@ -398,9 +398,9 @@ __device__ __forceinline__ int2 pair_of_block(int r, int b, int nb) {
 //     a new pair come from two blocks, each the half (ha, hb) of a pair Pa, Pb of round q - 1, so with the 32
 //     indices of Pa and Pb and W (32 x 16) holding U_Pa's columns of half ha and U_Pb's of half hb,
 //     S = W^T (M W), M = Ain on those 32 indices;
-//   * writes A' into Aout tile by tile (workgroups [npw, npw + naw), 2 x 2 tiles each: tile (P, Q) <-
-//     U_P^T Ain_PQ U_Q, copied when neither pair rotated; Aout == Ain only when there are no pair solves, and
-//     then such tiles are skipped and each tile reads its own entries);
+//   * writes A' into Aout tile by tile (workgroups [npw, npw + naw), 2 x 2 tiles each, P >= Q: tile (P, Q) <-
+//     U_P^T Ain_PQ U_Q and its mirror; Aout == Ain only when there are no pair solves, and then each tile
+//     reads its own entries);
 //   * applies V <- V G (the remaining workgroups, one (pair, 64-row slab) item each).
 // None of the three reads what another writes, so a round costs one launch instead of two.  Every workgroup is
 // one wavefront.  Every pair solve writes its U (the identity when it rotated nothing), so the products need no
@@ -413,7 +413,7 @@ __device__ __forceinline__ int2 pair_of_block(int r, int b, int nb) {
 struct RoundArgs {
   int l, nb, np;
   int round, npw;  // this round's pair solves (npw = 0: none)
-  int prev, naw;   // the previous round (-1: none) and the apply workgroups (ceil(np / 2)^2, or 0)
+  int prev, naw;   // the previous round (-1: none) and the apply workgroups (g (g + 1) / 2, g = ceil(np / 2); or 0)
   int nvw;         // V items (np * ceil(8 nb / 64), or 0)
   const double* Ain;
   double* Aout;
@@ -508,9 +508,14 @@ __global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
   wg -= a.npw;
   for (int d = 0; d < a.delay; ++d) __builtin_amdgcn_s_sleep(1);
   if (wg < a.naw) {
-    // ---- tiles (P0 + i, Q0 + j), i, j < 2, of the previous round's pairs: U_P and U_Q are loaded once for two tiles
-    const int ng = (a.np + 1) / 2;
-    const int P0 = 2 * (wg / ng), Q0 = 2 * (wg % ng);
+    // ---- tiles (P0 + i, Q0 + j), i, j < 2, of the previous round's pairs with P >= Q (group (gp, gq), gp >= gq,
+    // of the lower triangle of 2 x 2 tile groups): U_P and U_Q are loaded once for two tiles, and each result Y is
+    // written to tile (P, Q) and, mirrored, to tile (Q, P), so A is read once and stays exactly symmetric
+    int gp = (int)((sqrt(8.0 * wg + 1.0) - 1.0) * 0.5);
+    while ((gp + 1) * (gp + 2) / 2 <= wg) ++gp;
+    while (gp * (gp + 1) / 2 > wg) --gp;
+    const int gq = wg - gp * (gp + 1) / 2;
+    const int P0 = 2 * gp, Q0 = 2 * gq;
     // in place (the tail) every tile reads its own entries only: tile (Q, P), which holds A[iq][ip], is being
     // rewritten by another wavefront
     const bool inplace = a.Aout == a.Ain;
@@ -533,16 +538,19 @@ __global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
       }
     }
     double mv[2][2][4];
+    bool run[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int ipr = slot_index(pp[i], r16);  // row r16 of the tile
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j) {
+        run[i][j] = lp[i] && lq[j] && P0 + i >= Q0 + j;
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           const int gi = slot_index(qq[j], 4 * s4 + k4);  // column 4 s4 + k4 of the tile
-          mv[i][j][s4] = a.Ain[inplace ? blk(a.nb, ipr, gi) : blk(a.nb, gi, ipr)];
+          mv[i][j][s4] = run[i][j] ? a.Ain[inplace ? blk(a.nb, ipr, gi) : blk(a.nb, gi, ipr)] : 0.0;
         }
+      }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -554,10 +562,13 @@ __global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
         dbl4 y = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) y = __builtin_amdgcn_mfma_f64_16x16x4f64(up[i][s4], t[s4], y, 0, 0, 0);
-        if (lp[i] && lq[j]) {
+        if (run[i][j]) {
           const int gj = slot_index(qq[j], r16);
 #pragma unroll
           for (int v = 0; v < 4; ++v) a.Aout[blk(a.nb, slot_index(pp[i], k4 + 4 * v), gj)] = y[v];
+          if (P0 + i != Q0 + j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a.Aout[blk(a.nb, gj, slot_index(pp[i], k4 + 4 * v))] = y[v];
         }
       }
     return;
@@ -1040,7 +1051,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       RoundArgs ra{};
       ra.l = l; ra.nb = nb; ra.np = np;
       ra.round = q; ra.npw = q < R ? np : 0;
-      ra.prev = q - 1; ra.naw = q > 0 ? ((np + 1) / 2) * ((np + 1) / 2) : 0;
+      ra.prev = q - 1; ra.naw = q > 0 ? ((np + 1) / 2) * ((np + 1) / 2 + 1) / 2 : 0;
       ra.Ain = q > 0 ? Abuf[(q - 1) & 1] : A;
       ra.Aout = q < R ? Abuf[q & 1] : A;
       ra.Uprev = Ub[(q + 1) & 1];
