@@ -37,8 +37,9 @@ __device__ __forceinline__ int slot_index(int2 pq, int s) { return (s < BSZ) ? p
 
 // Blocked storage of the working matrices A and V during the sweeps: the 8x8 block (bi, bj) of the L x L matrix
 // (L = 8 nb) occupies 64 consecutive doubles at (bi nb + bj) 64, row-major inside, so that a 16x16 tile of a
-// block pair is four 512-byte runs.  Entries past l are zero and stay zero: no rotation involves an index past l
-// (its entries of A are zero), so the U of every pair is the identity on such slots.
+// block pair is four 512-byte runs.  V is kept transposed (V^T in the same storage).  Entries past l are zero and
+// stay zero: no rotation involves an index past l (its entries of A are zero), so the U of every pair is the
+// identity on such slots.
 __host__ __device__ __forceinline__ long long blk(int nb, int i, int j) {
   return ((long long)(i >> 3) * nb + (j >> 3)) * 64 + (i & 7) * 8 + (j & 7);
 }
@@ -278,7 +279,7 @@ __device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, in
   for (int q = 0; q < 4; ++q) {
     const int u = lane + 64 * q, i = u >> 4, j = u & 15;
     const int gj = ip[j];
-    mv[q] = (r0 + i < l && gj >= 0) ? vp.V[blk(nb, r0 + i, gj)] : 0.0;
+    mv[q] = (r0 + i < l && gj >= 0) ? vp.V[blk(nb, gj, r0 + i)] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -295,7 +296,7 @@ __device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, in
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = r0 + k4 + 4 * v, gj = ip[r16];
-    if (row < l && gj >= 0) vp.V[blk(nb, row, gj)] = acc[v];
+    if (row < l && gj >= 0) vp.V[blk(nb, gj, row)] = acc[v];
   }
 }
 
@@ -401,7 +402,8 @@ __device__ __forceinline__ int2 pair_of_block(int r, int b, int nb) {
 //   * writes A' into Aout tile by tile (workgroups [npw, npw + naw), 2 x 2 tiles each, P >= Q: tile (P, Q) <-
 //     U_P^T Ain_PQ U_Q and its mirror; Aout == Ain only when there are no pair solves, and then each tile
 //     reads its own entries);
-//   * applies V <- V G (the remaining workgroups, one (pair, 64-row slab) item each).
+//   * applies V <- V G (the remaining workgroups, one (pair, 64-column slab of V^T) item each: V is stored
+//     transposed, so that the update reads and writes row segments of 16 columns).
 // None of the three reads what another writes, so a round costs one launch instead of two.  Every workgroup is
 // one wavefront.  Every pair solve writes its U (the identity when it rotated nothing), so the products need no
 // flags, and with the block padding in storage no access needs a guard: the loads and stores are unconditional
@@ -575,34 +577,33 @@ __global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
   }
   wg -= a.naw;
   if (wg < a.nvw) {
-    // ---- V[r0 .. r0 + 63, idx_P] <- V[r0 .., idx_P] U_P (rows past the padded size are not touched)
+    // ---- V <- V G on rows idx_P of V^T (stored transposed): V^T[idx_P, c0 .. c0 + 63] <- U_P^T V^T[idx_P, c0 ..]
+    //      (columns past the padded size are not touched)
     const int L = a.nb * BSZ;
     const int ns = (L + 63) / 64;
-    const int P = wg / ns, r0 = (wg % ns) * 64;
+    const int P = wg / ns, c0 = (wg % ns) * 64;
     const int2 pp = round_pair(a.prev, P, a.nb);
     const double* UP = a.Uprev + (long long)P * SLOT * SLOT;
     double u[4], mv[4][4];
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       u[s4] = UP[(4 * s4 + k4) * SLOT + r16];
-      const int gc = slot_index(pp, 4 * s4 + k4);
+      const int gr = slot_index(pp, 4 * s4 + k4);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        const int row = min(r0 + 16 * rb + r16, L - 1);
-        mv[rb][s4] = a.V[blk(a.nb, row, gc)];
+      for (int cb = 0; cb < 4; ++cb) {
+        const int col = min(c0 + 16 * cb + r16, L - 1);
+        mv[cb][s4] = a.V[blk(a.nb, gr, col)];
       }
     }
-    const int gj = slot_index(pp, r16);
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    for (int cb = 0; cb < 4; ++cb) {
       dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(mv[rb][s4], u[s4], acc, 0, 0, 0);
+      for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(u[s4], mv[cb][s4], acc, 0, 0, 0);
+      const int col = c0 + 16 * cb + r16;
+      if (col < L)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * rb + k4 + 4 * v;
-        if (row < L) a.V[blk(a.nb, row, gj)] = acc[v];
-      }
+        for (int v = 0; v < 4; ++v) a.V[blk(a.nb, slot_index(pp, k4 + 4 * v), col)] = acc[v];
     }
   }
 }
@@ -742,25 +743,34 @@ __global__ void permute_cols_kernel(int l, const double* __restrict__ V, const i
   P[u] = V[(long long)i * l + perm[j]];
 }
 
-// P[i][j] = V[i][perm[j]] with V in blocked storage.
-__global__ void permute_cols_blocked_kernel(int l, int nb, const double* __restrict__ V, const int* __restrict__ perm,
-                                            double* __restrict__ P) {
-  const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= (long long)l * l) return;
-  const int i = (int)(u / l), j = (int)(u % l);
-  P[u] = V[blk(nb, i, perm[j])];
+// P[i][j] = V[i][perm[j]] = Vt[perm[j]][i] with Vt = V^T in blocked storage: 32 x 32 tiles of P through LDS
+// (row segments of Vt in, row segments of P out).
+__global__ __launch_bounds__(256) void permute_cols_blocked_kernel(int l, int nb, const double* __restrict__ Vt,
+                                                                   const int* __restrict__ perm, double* __restrict__ P) {
+  __shared__ double T[32][33];
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int jj = ty; jj < 32; jj += 8) {
+    const int j = j0 + jj, i = i0 + tx;
+    T[jj][tx] = (j < l && i < l) ? Vt[blk(nb, perm[j], i)] : 0.0;
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 32; ii += 8) {
+    const int i = i0 + ii, j = j0 + tx;
+    if (i < l && j < l) P[(long long)i * l + j] = T[tx][ii];
+  }
 }
 
-// Blocked storage of the row-major l x l X (ld l), zeros past l (X null: the identity).  One thread per stored
-// entry, in storage order.
-__global__ void to_blocked_kernel(int l, int nb, const double* __restrict__ X, double* __restrict__ B) {
+// Blocked storage of the row-major l x l X (ld l), or of X^T with trans, zeros past l (X null: the identity).
+// One thread per stored entry, in storage order.
+__global__ void to_blocked_kernel(int l, int nb, const double* __restrict__ X, int trans, double* __restrict__ B) {
   const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= (long long)nb * nb * 64) return;
   const long long b = u >> 6;
   const int e = (int)(u & 63);
   const int i = (int)(b / nb) * 8 + (e >> 3), j = (int)(b % nb) * 8 + (e & 7);
   double v = 0.0;
-  if (i < l && j < l) v = X ? X[(long long)i * l + j] : (i == j ? 1.0 : 0.0);
+  if (i < l && j < l) v = X ? (trans ? X[(long long)j * l + i] : X[(long long)i * l + j]) : (i == j ? 1.0 : 0.0);
   B[u] = v;
 }
 
@@ -950,7 +960,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   const int nb = block_count(l);
   const long long mat = (long long)eig_mat_doubles(l);
   double* A = tmp;                                    // blocked A
-  double* V = tmp + mat;                              // blocked V (row-major staging before the sweeps)
+  double* V = tmp + mat;                              // blocked V^T (row-major staging before the sweeps)
   double* A2 = tmp_mats >= 3 ? tmp + 2 * mat : nullptr;  // second blocked A (row-major staging before the sweeps)
   const long long nn = (long long)l * l;
   const int eb = (int)((nn + 255) / 256);
@@ -962,7 +972,8 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     hipLaunchKernelGGL(rank_sort_kernel, dim3((l + 15) / 16), dim3(256), 0, st, l, w->dg, wv, w->perm);
     KOT_HIP_TRY(hipGetLastError());
     if (src) hipLaunchKernelGGL(permute_cols_kernel, dim3(eb), dim3(256), 0, st, l, src, w->perm, P);
-    else hipLaunchKernelGGL(permute_cols_blocked_kernel, dim3(eb), dim3(256), 0, st, l, nb, V, w->perm, P);
+    else hipLaunchKernelGGL(permute_cols_blocked_kernel, dim3((l + 31) / 32, (l + 31) / 32), dim3(256), 0, st, l, nb,
+                            V, w->perm, P);
     return hipGetLastError();
   };
   if (P0) {
@@ -996,15 +1007,15 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     g.transa = 1; g.A = P0; g.B = V; g.C = A2;
     g.lower = 1; g.mirror = 1;  // symmetric result: lower tiles, mirrored
     KOT_HIP_TRY(gemm_f64(g, st));
-    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, A2, A);
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, A2, 0, A);
     KOT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, P0, V);
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, P0, 1, V);
     KOT_HIP_TRY(hipGetLastError());
   } else {
     // Z may lie in V's region (the allocation-free path stages it there): it is read before V is written
-    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, Z, A);
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, Z, 0, A);
     KOT_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, nullptr, V);
+    hipLaunchKernelGGL(to_blocked_kernel, dim3(ebb), dim3(256), 0, st, l, nb, nullptr, 0, V);
     KOT_HIP_TRY(hipGetLastError());
   }
   const int np = nb / 2;
