@@ -188,72 +188,79 @@ __device__ __forceinline__ double rsqrt_accurate(double x) {
 // d = aqq - app) of smaller magnitude, t = 2 apq sgn(d) / (|d| + sqrt(d^2 + 4 apq^2)), c = 1/sqrt(1 + t^2),
 // s = t c.  The square root and the reciprocals come from refined hardware estimates (c to about half an ulp);
 // when d^2 + 4 apq^2 leaves the normal range the same root is formed with IEEE division and square root from
-// theta.
+// theta.  The threshold is applied by selection, so the common path has no branch.
 __device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, double thresh, double& c, double& sn) {
-  c = 1.0;
-  sn = 0.0;
-  if (fabs(apq) > thresh) {
-    const double d = aqq - app;
-    const double h = fma(d, d, 4.0 * apq * apq);
-    double t;
-    if (h > 1e-290 && h < 1e290) {
-      const double r = h * rsqrt_refined(h);
-      t = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) * rcp_refined(fabs(d) + r);
-    } else {
-      const double theta = d / (2.0 * apq);
-      t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-    }
-    c = rsqrt_accurate(fma(t, t, 1.0));
-    sn = t * c;
+  const bool act = fabs(apq) > thresh;
+  const double d = aqq - app;
+  const double h = fma(d, d, 4.0 * apq * apq);
+  const bool normal = h > 1e-290 && h < 1e290;
+  double t;
+  if (normal || !act) {
+    const double hh = normal ? h : 1.0;
+    const double r = hh * rsqrt_refined(hh);
+    t = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) * rcp_refined(fabs(d) + r);
+  } else {
+    const double theta = d / (2.0 * apq);
+    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
   }
+  const double cc = rsqrt_accurate(fma(t, t, 1.0));
+  c = act ? cc : 1.0;
+  sn = act ? t * cc : 0.0;
 }
 
 // One wavefront, no barriers.  Lane (k1, k2) = (lane / 8, lane % 8) forms the rotation J_k2 of sub-round pair k2
 // (the eight lanes with the same k2 compute the same one from the same entries); the lanes with k1 == k2 publish
 // theirs in cs, from which every lane takes J_k1.  The lane then applies S <- J^T S J to the 2x2 block (rows of
-// pair k1, columns of pair k2) and U <- U J_k1 to rows 2 k2, 2 k2 + 1.  A sub-round issues its LDS reads of S
-// and U before its writes; the LDS operations of one wavefront complete in issue order, so every read sees the
-// previous sub-round's writes and none sees this one's, and the compiler barriers keep that order in the code.
+// pair k1, columns of pair k2) and U <- U J_k1 to rows 2 k2, 2 k2 + 1; an identity rotation leaves the entries
+// exactly as they are, so the updates run unconditionally.  A sub-round issues its LDS reads of S and U before
+// its writes; the LDS operations of one wavefront complete in issue order, so every read sees the previous
+// sub-round's writes and none sees this one's, and the compiler barriers keep that order in the code.  Cross
+// visits (no within-block rotations: every round of a sweep but its first) run an unrolled 8-sub-round loop
+// whose pair indices are k and 8 + (k + r) mod 8.
 __device__ __forceinline__ bool jacobi16(double (*S)[SLOT + 1], double (*U)[SLOT + 1], double2* cs, double thresh,
                                          int max_inner, int within) {
   const int lane = threadIdx.x;
   const int k1 = lane >> 3, k2 = lane & 7;
   const int ur = 2 * k2;
   bool rotated_any = false;
+  auto subround = [&](int a1, int b1, int a2, int b2, bool& act) {
+    const double p2 = S[a2][b2], d2a = S[a2][a2], d2b = S[b2][b2];
+    const double xaa = S[a1][a2], xab = S[a1][b2], xba = S[b1][a2], xbb = S[b1][b2];
+    const double u0a = U[ur][a1], u0b = U[ur][b1], u1a = U[ur + 1][a1], u1b = U[ur + 1][b1];
+    asm volatile("" ::: "memory");
+    double c2, s2;
+    jacobi_rot(d2a, d2b, p2, thresh, c2, s2);
+    act = act || fabs(p2) > thresh;
+    if (k1 == k2) cs[k2] = make_double2(c2, s2);
+    asm volatile("" ::: "memory");
+    const double2 j1 = cs[k1];
+    const double c1 = j1.x, s1 = j1.y;
+    // rows: J1^T x, then columns: (J1^T x) J2
+    const double yaa = c1 * xaa - s1 * xba, yab = c1 * xab - s1 * xbb;
+    const double yba = s1 * xaa + c1 * xba, ybb = s1 * xab + c1 * xbb;
+    const double zaa = c2 * yaa - s2 * yab, zbb = s2 * yba + c2 * ybb;
+    const bool annihilate = k1 == k2 && s1 != 0.0;
+    const double zab = annihilate ? 0.0 : s2 * yaa + c2 * yab;
+    const double zba = annihilate ? 0.0 : c2 * yba - s2 * ybb;
+    S[a1][a2] = zaa; S[a1][b2] = zab; S[b1][a2] = zba; S[b1][b2] = zbb;
+    U[ur][a1] = c1 * u0a - s1 * u0b;
+    U[ur][b1] = s1 * u0a + c1 * u0b;
+    U[ur + 1][a1] = c1 * u1a - s1 * u1b;
+    U[ur + 1][b1] = s1 * u1a + c1 * u1b;
+    asm volatile("" ::: "memory");
+  };
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     bool act = false;
-    const int nsub = within ? 15 : 8;
-    for (int r = 0; r < nsub; ++r) {
-      int a1, b1, a2, b2;
-      pair_of_subround(r, k1, within, a1, b1);
-      pair_of_subround(r, k2, within, a2, b2);
-      const double p2 = S[a2][b2], d2a = S[a2][a2], d2b = S[b2][b2];
-      const double xaa = S[a1][a2], xab = S[a1][b2], xba = S[b1][a2], xbb = S[b1][b2];
-      const double u0a = U[ur][a1], u0b = U[ur][b1], u1a = U[ur + 1][a1], u1b = U[ur + 1][b1];
-      asm volatile("" ::: "memory");
-      double c2, s2;
-      jacobi_rot(d2a, d2b, p2, thresh, c2, s2);
-      act = act || fabs(p2) > thresh;
-      if (k1 == k2) cs[k2] = make_double2(c2, s2);
-      asm volatile("" ::: "memory");
-      const double2 j1 = cs[k1];
-      const double c1 = j1.x, s1 = j1.y;
-      if (s1 != 0.0 || s2 != 0.0) {
-        // rows: J1^T x, then columns: (J1^T x) J2
-        const double yaa = c1 * xaa - s1 * xba, yab = c1 * xab - s1 * xbb;
-        const double yba = s1 * xaa + c1 * xba, ybb = s1 * xab + c1 * xbb;
-        double zaa = c2 * yaa - s2 * yab, zab = s2 * yaa + c2 * yab;
-        double zba = c2 * yba - s2 * ybb, zbb = s2 * yba + c2 * ybb;
-        if (k1 == k2 && s1 != 0.0) { zab = 0.0; zba = 0.0; }
-        S[a1][a2] = zaa; S[a1][b2] = zab; S[b1][a2] = zba; S[b1][b2] = zbb;
+    if (!within) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) subround(k1, 8 + ((k1 + r) & 7), k2, 8 + ((k2 + r) & 7), act);
+    } else {
+      for (int r = 0; r < 15; ++r) {
+        int a1, b1, a2, b2;
+        pair_of_subround(r, k1, within, a1, b1);
+        pair_of_subround(r, k2, within, a2, b2);
+        subround(a1, b1, a2, b2, act);
       }
-      if (s1 != 0.0) {
-        U[ur][a1] = c1 * u0a - s1 * u0b;
-        U[ur][b1] = s1 * u0a + c1 * u0b;
-        U[ur + 1][a1] = c1 * u1a - s1 * u1b;
-        U[ur + 1][b1] = s1 * u1a + c1 * u1b;
-      }
-      asm volatile("" ::: "memory");
     }
     if (!__any(act)) break;
     rotated_any = true;
@@ -1071,9 +1078,9 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       ra.V = V;
       ra.thresh_ptr = w->up;
       ra.max_inner = inner_sweeps; ra.within = q == 0 ? 1 : 0;
-      // the update wavefronts hold back about 1.7 us so that the pair solves' loads (the round's critical path)
-      // are not queued behind theirs: 11.5 instead of 12.5 us per round at l = 1000
-      ra.delay = ra.npw > 0 ? 64 : 0;
+      // the update wavefronts hold back about 0.9 us so that the pair solves' loads (the round's critical path)
+      // are not queued behind theirs: 8.2 instead of 8.5 us per round at l = 1000
+      ra.delay = ra.npw > 0 ? 32 : 0;
       const int grid = ra.npw + ra.naw + ra.nvw;
       hipLaunchKernelGGL(round_kernel, dim3(grid), dim3(64), 0, s_, ra);
       KOT_HIP_TRY(hipGetLastError());
