@@ -1094,6 +1094,9 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   };
   // flops of one full sweep: per round 2 x 2 x 16^3 per A tile and 2 x 16^3 per V tile
   const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * nslab * np);
+  // algorithmic bytes of a full sweep: per round A's lower triangle (A is symmetric) and V read and written once,
+  // 8 l^2 + 16 l^2
+  const double sweep_bytes = 24.0 * l * (double)l * (nb - 1);
   const double npairs = 0.5 * nb * (nb + 1.0);
   while (off > tol * all && s < max_sweeps) {
     if (!w->noalloc) w->hup[0] = thresh_rel * all;  // the stream is idle here (block_norms synchronized it)
@@ -1103,7 +1106,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     const double tau2 = 0.25 * tol * tol * all * all / npairs;
     if (w->noalloc) {
       KOT_HIP_TRY(vec_fill(1, thresh_rel * all, w->up, st));
-      if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, 32.0 * l * (double)l * (nb - 1));
+      if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, sweep_bytes);
       KOT_HIP_TRY(launch_sweep(st));
       if (pf) pf->end(st);
     } else if (threshold_schedule(w, nb, tau2)) {
@@ -1113,7 +1116,8 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       for (int r = 0; r < R; ++r) {
         const double k = w->round_k[r];
         fl += 8192.0 * (2.0 * k * k + 2.0 * k * (np - k) + k * nslab);
-        by += 4096.0 * ((double)np * np - (np - k) * (np - k) + k * nslab);  // tiles read and written
+        // the active tiles of A (half of them, by symmetry) and V's active slabs, read and written
+        by += 2048.0 * ((double)np * np - (np - k) * (np - k)) + 4096.0 * k * nslab;
       }
       if (pf) pf->begin(st, PROF_EIG_ROUND, fl, by);
       for (int r = 0; r < R; ++r)
@@ -1150,7 +1154,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
           w->graph_inner = inner_sweeps;
         }
       }
-      if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, 32.0 * l * (double)l * (nb - 1));
+      if (pf) pf->begin(st, PROF_EIG_ROUND, sweep_flops, sweep_bytes);
       if (w->graph) KOT_HIP_TRY(hipGraphLaunch(w->graph, st));
       else KOT_HIP_TRY(launch_sweep(st));
       if (pf) pf->end(st);
