@@ -10,7 +10,8 @@ Algorithm 2 does not reach residual 1e-6 in any affordable number of iterations,
 decoupled ``mix1000`` workload (the same draw on unit-cube data with sigma^2 = 0.005, where K is the identity to
 1e-14) is timed as solves to 1e-6 (solves/s), as a labelled secondary.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--iters N] [--workload mix1000_median|mix1000|sweep]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--iters N]
+                    [--workload mix1000_median|mix1000|sweep|egcompare|eigcompare]
                     [--arm fp64|warm|mixed32|mixed16|mixed|all] [--lanes L] [--no-decoupled] [--no-cpu-baseline]
 
 Each arm's K solves run twice: one at a time on one context, then as independent solves in flight together on
@@ -232,6 +233,70 @@ def egcompare_bench(a):
                       "rows": rows}), flush=True)
 
 
+def eigcompare_bench(a):
+    """Eq. (4.4)'s symmetric eigendecomposition from a cold start: the block Jacobi eigensolver (kot_eigh) against
+    the vendor's tridiagonal path (torch.linalg.eigh, rocSOLVER) on the same dense matrices, l in {500, 1000, 2000}:
+    a Gaussian random symmetric matrix and one with a clustered spectrum (half in [-1, -1e-3], 40 % in [0, 1e-6],
+    the rest in [1, 2]: the shape of the SSN's Z near the PSD boundary).  Median wall time of 3 calls each,
+    the Jacobi sweeps from its profiler class, and each result's accuracy against the other's eigenvalues."""
+    import numpy as np
+    import torch
+    from paper_2310_14087_amd import kotssn
+    dev = torch.device("cuda:0")
+    ctx = kotssn.Context(0)
+    rows = []
+    for l in (500, 1000, 2000):
+        for kind in ("random", "clustered"):
+            rng = np.random.default_rng(7 * l + (kind == "clustered"))
+            if kind == "random":
+                A = rng.standard_normal((l, l))
+                Z = A + A.T
+            else:
+                Qm, _ = np.linalg.qr(rng.standard_normal((l, l)))
+                h, f = l // 2, (2 * l) // 5
+                d = np.concatenate([rng.uniform(-1, -1e-3, h), rng.uniform(0, 1e-6, f), rng.uniform(1, 2, l - h - f)])
+                Z = (Qm * d) @ Qm.T
+                Z = 0.5 * (Z + Z.T)
+            Zt = torch.from_numpy(Z).to(dev)
+            prm = kotssn.default_params()
+            ctx.eigh(Zt, prm)
+            torch.linalg.eigh(Zt)
+            torch.cuda.synchronize()
+            # wall time around each synchronized call (kot_eigh runs on its context's stream and returns
+            # synchronized; its host work between sweeps is part of the method)
+            ms_k, ms_t = [], []
+            ctx.profile_start()
+            for _ in range(3):
+                t0 = time.perf_counter()
+                w, P = ctx.eigh(Zt, prm)
+                torch.cuda.synchronize()
+                ms_k.append(1e3 * (time.perf_counter() - t0))
+            sweeps = ctx.profile_stop()["eig_sweep"]["launches"] / 3.0
+            for _ in range(3):
+                t0 = time.perf_counter()
+                wt, Pt = torch.linalg.eigh(Zt)
+                torch.cuda.synchronize()
+                ms_t.append(1e3 * (time.perf_counter() - t0))
+            sc = float(wt.abs().max())
+            eye = torch.eye(l, device=dev, dtype=torch.float64)
+            acc = lambda ww, PP: dict(
+                eig_err=float((ww - wt).abs().max()) / sc,
+                residual=float((Zt @ PP - PP * ww).abs().max()) / sc,
+                orth=float((PP.T @ PP - eye).abs().max()))
+            row = dict(l=l, kind=kind, jacobi_ms=float(np.median(ms_k)), jacobi_sweeps=sweeps,
+                       rocsolver_ms=float(np.median(ms_t)), jacobi_acc=acc(w, P), rocsolver_acc=acc(wt, Pt))
+            rows.append(row)
+            _log(f"eigcompare l={l} {kind}: jacobi {row['jacobi_ms']:.2f} ms ({sweeps:.0f} sweeps), "
+                 f"rocsolver {row['rocsolver_ms']:.2f} ms; residual {row['jacobi_acc']['residual']:.1e} / "
+                 f"{row['rocsolver_acc']['residual']:.1e}")
+    ctx.close()
+    print(json.dumps({"metric": "cold symmetric eigendecomposition time: block Jacobi (kot_eigh) vs "
+                                "torch.linalg.eigh (rocSOLVER tridiagonal)", "unit": "ms",
+                      "higher_is_better": False, "data": "synthetic", "dtype": "f64",
+                      "config": {"workload": "dense symmetric l x l: Gaussian random, and clustered spectrum"},
+                      "rows": rows}), flush=True)
+
+
 def batch_bench(a):
     """Uneven batch (n ~ U{200..2000}, l ~ U{100..400}, d ~ U{2..10}): solves/s through kot_solve_batched with
     `lanes` concurrent streams vs one lane; FP32 CG chain, FP64 projections."""
@@ -288,8 +353,9 @@ def main():
                     help="outer iterations per solve on mix1000_median (Algorithm 2 does not reach 1e-6 there)")
     ap.add_argument("--workload", default="mix1000_median",
                     help="mix1000_median (the metric line: fixed outer-iteration solves, iterations/s), mix1000 "
-                         "(decoupled: solves to 1e-6, solves/s), sweep (Section 5's synthetic sweep) or egcompare "
-                         "(Appendix F: Algorithm 2 against pure extragradient, residual against time)")
+                         "(decoupled: solves to 1e-6, solves/s), sweep (Section 5's synthetic sweep), egcompare "
+                         "(Appendix F: Algorithm 2 against pure extragradient, residual against time) or "
+                         "eigcompare (cold eigendecomposition: block Jacobi against the vendor's tridiagonal path)")
     ap.add_argument("--no-decoupled", action="store_true",
                     help="skip the decoupled mix1000 secondary that runs after the mix1000_median line")
     ap.add_argument("--decoupled-steps", type=int, default=24)
@@ -327,6 +393,8 @@ def main():
         return sweep_bench(a)
     if a.workload == "egcompare":
         return egcompare_bench(a)
+    if a.workload == "eigcompare":
+        return eigcompare_bench(a)
     if a.copy_calibrate > 0:
         return copy_calibrate(a.copy_calibrate)
     if a.workload not in WORKLOAD_TEXT:
