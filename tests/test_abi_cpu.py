@@ -46,6 +46,7 @@ def test_params_default_host_only(lib):
     assert p.null_step == 0 and p.safeguard == kotssn.KOT_SAFEGUARD_EG and p.precision == kotssn.KOT_FP64
     assert p.overlap == 1 and p.lowp_min_rows == 64 and p.precond == kotssn.KOT_PRECOND_NONE
     assert p.schur_solver == kotssn.KOT_SCHUR_CG
+    assert p.eig_inner_sweeps == 1 and p.closed_start == 0 and p.kdiag_tol == 1e-12
 
 
 def test_struct_layouts_match_header(tmp_path):
