@@ -37,11 +37,16 @@ __device__ __forceinline__ int slot_index(int2 pq, int s) { return (s < BSZ) ? p
 
 // Blocked storage of the working matrices A and V during the sweeps: the 8x8 block (bi, bj) of the L x L matrix
 // (L = 8 nb) occupies 64 consecutive doubles at (bi nb + bj) 64, row-major inside, so that a 16x16 tile of a
-// block pair is four 512-byte runs.  V is kept transposed (V^T in the same storage).  Entries past l are zero and
+// block pair is four 512-byte runs.  Of the symmetric A only the lower blocks are kept (sym); V is kept
+// transposed (V^T in the same storage).  Entries past l are zero and
 // stay zero: no rotation involves an index past l (its entries of A are zero), so the U of every pair is the
 // identity on such slots.
 __host__ __device__ __forceinline__ long long blk(int nb, int i, int j) {
   return ((long long)(i >> 3) * nb + (j >> 3)) * 64 + (i & 7) * 8 + (j & 7);
+}
+// A is symmetric and only its lower blocks (bi >= bj) are kept: entry (i, j) lives at (i, j) or at (j, i).
+__device__ __forceinline__ long long sym(int nb, int i, int j) {
+  return ((i >> 3) >= (j >> 3)) ? blk(nb, i, j) : blk(nb, j, i);
 }
 
 // Round-robin tournament over nb (even) blocks, circle method: in round r < nb - 1, pair 0 = (nb-1, r) and
@@ -144,7 +149,7 @@ __global__ __launch_bounds__(64) void pair_solve_kernel(int l, const double* __r
   for (int q = 0; q < 4; ++q) {
     const int u = lane + 64 * q, i = u >> 4, j = u & 15;
     const int gi = idx[i], gj = idx[j];
-    sv[q] = (gi >= 0 && gj >= 0) ? A[blk(nb, gi, gj)] : 0.0;
+    sv[q] = (gi >= 0 && gj >= 0) ? A[sym(nb, gi, gj)] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -308,7 +313,7 @@ __device__ __forceinline__ void v_slab_update(int l, int nb, const VPrev& vp, in
 }
 
 // A <- G^T A G for one round.  Workgroup (x, y) has four wavefronts; wavefront w takes the A tile (P = y,
-// Q = 4 x + w): A_PQ <- U_P^T A_PQ U_Q.  A pair without rotations (flag 0) acts as the identity, so its U is not
+// Q = 4 x + w) when Q <= P: A_PQ <- U_P^T A_PQ U_Q (on the lower storage).  A pair without rotations (flag 0) acts as the identity, so its U is not
 // read; a tile with nothing to rotate does no loads.  Each 16x16 product is four v_mfma_f64_16x16x4f64 steps
 // (accumulator lane L holds rows L/16 + 4v, v = 0..3, of column L%16).  The barriers are uniform over the
 // four wavefronts.  (V's update runs in the next round's pair-solve launch.)
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, double* __res
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int P = blockIdx.y;
   const int item = (int)blockIdx.x * 4 + wv;
-  const bool isA = item < np;
+  const bool isA = item <= P && item < np;  // tiles Q <= P: their transposes hold the same stored entries
   const bool fP = flag[P] != 0;
   const bool fQ = isA && flag[item] != 0;
   const bool act = isA && (fP || fQ);
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, double* __res
     for (int q = 0; q < 4; ++q) {
       const int u = lane + 64 * q, i = u >> 4, j = u & 15;
       const int gi = ip[i], gj = iq[j];
-      mv[q] = (gi >= 0 && gj >= 0) ? A[blk(nb, gi, gj)] : 0.0;
+      mv[q] = (gi >= 0 && gj >= 0) ? A[sym(nb, gi, gj)] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -384,7 +389,8 @@ __global__ __launch_bounds__(256) void apply_kernel(int l, int np, double* __res
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gi = ip[k4 + 4 * v], gj = iq[r16];
-      if (gi >= 0 && gj >= 0) A[blk(nb, gi, gj)] = acc2[v];
+      // each stored entry belongs to one tile: (P, Q) with P > Q, or the diagonal tile's lower blocks
+      if (gi >= 0 && gj >= 0 && (P != item || (gi >> 3) >= (gj >> 3))) A[sym(nb, gi, gj)] = acc2[v];
     }
   }
 }
@@ -407,8 +413,7 @@ __device__ __forceinline__ int2 pair_of_block(int r, int b, int nb) {
 //     indices of Pa and Pb and W (32 x 16) holding U_Pa's columns of half ha and U_Pb's of half hb,
 //     S = W^T (M W), M = Ain on those 32 indices;
 //   * writes A' into Aout tile by tile (workgroups [npw, npw + naw), 2 x 2 tiles each, P >= Q: tile (P, Q) <-
-//     U_P^T Ain_PQ U_Q and its mirror; Aout == Ain only when there are no pair solves, and then each tile
-//     reads its own entries);
+//     U_P^T Ain_PQ U_Q on A's stored lower blocks; Aout == Ain only when there are no pair solves);
 //   * applies V <- V G (the remaining workgroups, one (pair, 64-column slab of V^T) item each: V is stored
 //     transposed, so that the update reads and writes row segments of 16 columns).
 // None of the three reads what another writes, so a round costs one launch instead of two.  Every workgroup is
@@ -417,8 +422,7 @@ __device__ __forceinline__ int2 pair_of_block(int r, int b, int nb) {
 // (edge tiles of an odd pair count aside).  The products run on v_mfma_f64_16x16x4f64 with operands loaded straight from memory: the
 // A operand of step ks on lane (k4 = L/16, r16 = L%16) is X[r16][ks + k4], the B operand Y[ks + k4][r16], and
 // the accumulator's v-th value is D[k4 + 4 v][r16], which is exactly the B operand of step ks = 4 v of a second
-// product, so T = X Y feeds Z^T T without leaving registers.  Reads of A out of place use its symmetry
-// (X[r][c] = A[c][r]), so that the 16 lanes of one k4 read row segments.
+// product, so T = X Y feeds Z^T T without leaving registers.
 struct RoundArgs {
   int l, nb, np;
   int round, npw;  // this round's pair solves (npw = 0: none)
@@ -437,10 +441,10 @@ struct RoundArgs {
 };
 
 // Tiles (P0 + i, Q0 + j), i, j < G, of the previous round's pairs with P >= Q (group (gp, gq), gp >= gq, of the
-// lower triangle of G x G tile groups): U_P and U_Q are loaded once for G tiles, and each result Y is written to
-// tile (P, Q) and, mirrored, to tile (Q, P), so A is read once and stays exactly symmetric.  In place (the tail)
-// every tile reads its own entries only: tile (Q, P), which holds A[iq][ip], is being rewritten by another
-// wavefront.
+// lower triangle of G x G tile groups): U_P and U_Q are loaded once for G tiles.  With only A's lower blocks
+// stored, tile (P, Q), P > Q, owns the stored copies of all its entries (its transpose is not computed) and a
+// diagonal tile its lower blocks, so every stored entry is read and written once, by one wavefront (also in place,
+// in the tail).
 template <int G>
 __device__ __forceinline__ void apply_tiles(const RoundArgs& a, int wg, int r16, int k4) {
   int gp = (int)((sqrt(8.0 * wg + 1.0) - 1.0) * 0.5);
@@ -448,7 +452,6 @@ __device__ __forceinline__ void apply_tiles(const RoundArgs& a, int wg, int r16,
   while (gp * (gp + 1) / 2 > wg) --gp;
   const int gq = wg - gp * (gp + 1) / 2;
   const int P0 = G * gp, Q0 = G * gq;
-  const bool inplace = a.Aout == a.Ain;
   int2 pp[G], qq[G];
   bool lp[G], lq[G];
   double up[G][4], uq[G][4];
@@ -478,7 +481,7 @@ __device__ __forceinline__ void apply_tiles(const RoundArgs& a, int wg, int r16,
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int gi = slot_index(qq[j], 4 * s4 + k4);  // column 4 s4 + k4 of the tile
-        mv[i][j][s4] = run[i][j] ? a.Ain[inplace ? blk(a.nb, ipr, gi) : blk(a.nb, gi, ipr)] : 0.0;
+        mv[i][j][s4] = run[i][j] ? a.Ain[sym(a.nb, gi, ipr)] : 0.0;
       }
     }
   }
@@ -494,11 +497,12 @@ __device__ __forceinline__ void apply_tiles(const RoundArgs& a, int wg, int r16,
       for (int s4 = 0; s4 < 4; ++s4) y = __builtin_amdgcn_mfma_f64_16x16x4f64(up[i][s4], t[s4], y, 0, 0, 0);
       if (run[i][j]) {
         const int gj = slot_index(qq[j], r16);
+        const bool diag = P0 + i == Q0 + j;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) a.Aout[blk(a.nb, slot_index(pp[i], k4 + 4 * v), gj)] = y[v];
-        if (P0 + i != Q0 + j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) a.Aout[blk(a.nb, gj, slot_index(pp[i], k4 + 4 * v))] = y[v];
+        for (int v = 0; v < 4; ++v) {
+          const int gr = slot_index(pp[i], k4 + 4 * v);
+          if (!diag || (gr >> 3) >= (gj >> 3)) a.Aout[sym(a.nb, gr, gj)] = y[v];
+        }
       }
     }
 }
@@ -520,7 +524,7 @@ __global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int u = lane + 64 * q, i = u >> 4, j = u & 15;
-        sv[q] = a.Ain[blk(a.nb, slot_index(pq, i), slot_index(pq, j))];
+        sv[q] = a.Ain[sym(a.nb, slot_index(pq, i), slot_index(pq, j))];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -554,7 +558,7 @@ __global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
         for (int ks = 0; ks < 8; ++ks) {
           const int c = 4 * ks + k4;
           const int gi = ks < 4 ? slot_index(pa, c) : slot_index(pb, c - SLOT);
-          mv[rb][ks] = a.Ain[blk(a.nb, gi, gj)];
+          mv[rb][ks] = a.Ain[sym(a.nb, gi, gj)];
         }
       }
       dbl4 t[2];
@@ -673,7 +677,7 @@ __global__ __launch_bounds__(256) void block_norm_kernel(int l, int nb, const do
 #pragma unroll
   for (int r = 0; r < BSZ; ++r) {
     const int i = b1 * BSZ + r;
-    v[r] = (need && i < l && j < l) ? A[blk(nb, i, j)] : 0.0;
+    v[r] = (need && i < l && j < l) ? A[sym(nb, i, j)] : 0.0;
   }
   double off = 0.0, all = 0.0, pos = 0.0;
 #pragma unroll
