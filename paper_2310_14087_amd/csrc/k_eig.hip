@@ -428,11 +428,14 @@ struct RoundArgs {
   int round, npw;  // this round's pair solves (npw = 0: none)
   int prev, naw;   // the previous round (-1: none) and the apply workgroups (g (g + 1) / 2, g = ceil(np / 2); or 0)
   int nvw;         // V items (np * ceil(8 nb / 64), or 0)
+  int vmode;       // V's update: 1 by the previous round, 2 by the two previous rounds at once (Uprev2, Uprev)
   const double* Ain;
   double* Aout;
   const double* Uprev;
+  const double* Uprev2;  // rotations of round prev - 1 (vmode 2)
   double* Uout;
-  double* V;
+  const double* Vin;     // V^T before the update and after it (equal only with vmode 1)
+  double* Vout;
   const double* thresh_ptr;
   int max_inner, within;
   int delay;  // s_sleep periods (64 clocks each) before the update workgroups start (see launch_sweep_fused)
@@ -597,33 +600,88 @@ __global__ __launch_bounds__(64) void round_kernel(RoundArgs a) {
   }
   wg -= a.naw;
   if (wg < a.nvw) {
-    // ---- V <- V G on rows idx_P of V^T (stored transposed): V^T[idx_P, c0 .. c0 + 63] <- U_P^T V^T[idx_P, c0 ..]
-    //      (columns past the padded size are not touched)
     const int L = a.nb * BSZ;
     const int ns = (L + 63) / 64;
-    const int P = wg / ns, c0 = (wg % ns) * 64;
-    const int2 pp = round_pair(a.prev, P, a.nb);
-    const double* UP = a.Uprev + (long long)P * SLOT * SLOT;
-    double u[4], mv[4][4];
+    const int K = wg / ns, c0 = (wg % ns) * 64;
+    if (a.vmode == 1) {
+      // ---- V <- V G on rows idx_K of V^T (stored transposed): V^T[idx_K, c0 .. c0 + 63] <- U_K^T V^T[idx_K, c0 ..]
+      //      (columns past the padded size are not touched)
+      const int2 pp = round_pair(a.prev, K, a.nb);
+      const double* UP = a.Uprev + (long long)K * SLOT * SLOT;
+      double u[4], mv[4][4];
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      u[s4] = UP[(4 * s4 + k4) * SLOT + r16];
-      const int gr = slot_index(pp, 4 * s4 + k4);
+      for (int s4 = 0; s4 < 4; ++s4) {
+        u[s4] = UP[(4 * s4 + k4) * SLOT + r16];
+        const int gr = slot_index(pp, 4 * s4 + k4);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const int col = min(c0 + 16 * cb + r16, L - 1);
+          mv[cb][s4] = a.Vin[blk(a.nb, gr, col)];
+        }
+      }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        const int col = min(c0 + 16 * cb + r16, L - 1);
-        mv[cb][s4] = a.V[blk(a.nb, gr, col)];
+        dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(u[s4], mv[cb][s4], acc, 0, 0, 0);
+        const int col = c0 + 16 * cb + r16;
+        if (col < L)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) a.Vout[blk(a.nb, slot_index(pp, k4 + 4 * v), col)] = acc[v];
       }
-    }
+    } else {
+      // ---- V <- V G_b G_c for rounds b = prev - 1 and c = prev at once, out of place.  The two blocks x, x' of
+      //      pair K of round c were halves hx, hx' of pairs Px, Px' of round b, so with the 32 rows of Px and Px'
+      //      and W (32 x 16) holding U_Px's columns of half hx and U_Px''s of half hx' (as in the pair solves),
+      //      V^T[idx_K, :] <- C^T V^T[idx_Px u idx_Px', :] with C = W U_K.  C's accumulator is the A operand of
+      //      C^T's steps as it stands (step ks takes C's rows 4 ks .. 4 ks + 3).  Each block of V^T is read by
+      //      the two pairs of round c that hold its round-b pair's blocks, and written once.
+      const int b = a.prev - 1;
+      const int2 pk = round_pair(a.prev, K, a.nb);
+      const int2 ea = pair_of_block(b, pk.x, a.nb), eb = pair_of_block(b, pk.y, a.nb);
+      const int2 pa = round_pair(b, ea.x, a.nb), pb = round_pair(b, eb.x, a.nb);
+      const double* Ua = a.Uprev2 + (long long)ea.x * SLOT * SLOT;
+      const double* Ub = a.Uprev2 + (long long)eb.x * SLOT * SLOT;
+      const double* UK = a.Uprev + (long long)K * SLOT * SLOT;
+      // W[16 rb + r16][4 s4 + k4] is nonzero for rb = 0, s4 < 2 (U_Px) and rb = 1, s4 >= 2 (U_Px')
+      double w0[2], w1[2], uk[4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int s4 = 0; s4 < 2; ++s4) {
+        w0[s4] = Ua[r16 * SLOT + ea.y * 8 + 4 * s4 + k4];
+        w1[s4] = Ub[r16 * SLOT + eb.y * 8 + 4 * s4 + k4];
+      }
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(u[s4], mv[cb][s4], acc, 0, 0, 0);
-      const int col = c0 + 16 * cb + r16;
-      if (col < L)
+      for (int s4 = 0; s4 < 4; ++s4) uk[s4] = UK[(4 * s4 + k4) * SLOT + r16];
+      dbl4 c[2];
+      c[0] = dbl4{0.0, 0.0, 0.0, 0.0};
+      c[1] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) a.V[blk(a.nb, slot_index(pp, k4 + 4 * v), col)] = acc[v];
+      for (int s4 = 0; s4 < 2; ++s4) {
+        c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(w0[s4], uk[s4], c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(w1[s4], uk[2 + s4], c[1], 0, 0, 0);
+      }
+      double mv[4][8];
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const int cr = 4 * ks + k4;
+        const int gr = ks < 4 ? slot_index(pa, cr) : slot_index(pb, cr - SLOT);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const int col = min(c0 + 16 * cb + r16, L - 1);
+          mv[cb][ks] = a.Vin[blk(a.nb, gr, col)];
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(c[ks >> 2][ks & 3], mv[cb][ks], acc, 0, 0, 0);
+        const int col = c0 + 16 * cb + r16;
+        if (col < L)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) a.Vout[blk(a.nb, slot_index(pk, k4 + 4 * v), col)] = acc[v];
+      }
     }
   }
 }
@@ -808,7 +866,8 @@ struct EigWork {
   const double* graph_tmp = nullptr;
   hipGraphExec_t graph = nullptr;
   bool graph_failed = false;
-  double* U = nullptr;        // device [2][npairs_max * 256]: rotations of even and odd rounds
+  double* U = nullptr;        // device [3][npairs_max * 256]: rotations of the last rounds (round q in q mod 2 or
+                              // q mod 3)
   int* flag = nullptr;        // device [2][npairs_max]
   int* perm = nullptr;        // device [lmax]
   double* dg = nullptr;       // device [lmax]: the diagonal of A at the last block-norm pass
@@ -840,7 +899,7 @@ EigWork* eig_work_create(int lmax) {
   const int npm = nbmax / 2;
   const size_t nb2 = (size_t)nbmax * nbmax;
   const size_t nlist = (size_t)(nbmax - 1) * npm;
-  bool ok = hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256 * 2) == hipSuccess &&
+  bool ok = hipMalloc(&w->U, sizeof(double) * (size_t)npm * 256 * 3) == hipSuccess &&
             hipMalloc(&w->flag, sizeof(int) * (size_t)npm * 2) == hipSuccess &&
             hipMalloc(&w->perm, sizeof(int) * (size_t)lmax) == hipSuccess &&
             hipMalloc(&w->dg, sizeof(double) * (size_t)lmax) == hipSuccess &&
@@ -982,6 +1041,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   double* A = tmp;                                    // blocked A
   double* V = tmp + mat;                              // blocked V^T (row-major staging before the sweeps)
   double* A2 = tmp_mats >= 3 ? tmp + 2 * mat : nullptr;  // second blocked A (row-major staging before the sweeps)
+  double* V2 = tmp_mats >= 4 ? tmp + 3 * mat : nullptr;  // second V^T: V's update by two rounds at once
   const long long nn = (long long)l * l;
   const int eb = (int)((nn + 255) / 256);
   const int ebb = (int)((mat + 255) / 256);
@@ -1075,9 +1135,21 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   // With a second buffer for A, round q's pair solves, A's update by round q - 1 (Ain = buffer (q - 1) & 1 ->
   // buffer q & 1) and V's update by round q - 1 share launch q (round_kernel); a tail launch applies the last
   // round to A (into the first buffer, in place when that is where A is) and to V.
+  // V's update: with a second V buffer, even launches q = 2, 4, .. apply rounds q - 2 and q - 1 at once (out of
+  // place, V^T read twice and written once per two rounds) and the tail the rounds left; otherwise launch q
+  // applies round q - 1 in place.  V ends every sweep in its first buffer (an odd number of buffer flips is
+  // undone by an out-of-place tail, or by a copy).
   auto launch_sweep_fused = [&](hipStream_t s_) -> hipError_t {
     const int R = nb - 1;
     double* Abuf[2] = {A, A2};
+    double* Vb[2] = {V, V2};
+    double* Ub3[3] = {w->U, w->U + (size_t)(block_count(w->lmax) / 2) * SLOT * SLOT,
+                      w->U + 2 * (size_t)(block_count(w->lmax) / 2) * SLOT * SLOT};
+    const bool pairs2 = V2 != nullptr;
+    int cur = 0;
+    int flips_left = 0;  // two-round updates still to come in this sweep
+    if (pairs2)
+      for (int q = 2; q <= R; q += 2) ++flips_left;
     for (int q = 0; q <= R; ++q) {
       RoundArgs ra{};
       ra.l = l; ra.nb = nb; ra.np = np;
@@ -1090,10 +1162,29 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       ra.prev = q - 1; ra.naw = q > 0 ? ng * (ng + 1) / 2 : 0;
       ra.Ain = q > 0 ? Abuf[(q - 1) & 1] : A;
       ra.Aout = q < R ? Abuf[q & 1] : A;
-      ra.Uprev = Ub[(q + 1) & 1];
-      ra.Uout = Ub[q & 1];
-      ra.nvw = q > 0 ? np * ((nb * BSZ + 63) / 64) : 0;
-      ra.V = V;
+      if (pairs2) {
+        ra.Uprev = Ub3[(q + 2) % 3];
+        ra.Uprev2 = Ub3[(q + 1) % 3];
+        ra.Uout = Ub3[q % 3];
+      } else {
+        ra.Uprev = Ub[(q + 1) & 1];
+        ra.Uout = Ub[q & 1];
+      }
+      ra.vmode = 0;
+      if (!pairs2) {
+        if (q > 0) ra.vmode = 1;
+        ra.Vin = V; ra.Vout = V;
+      } else if (q >= 2 && (q & 1) == 0) {
+        ra.vmode = 2;  // rounds q - 2, q - 1
+        ra.Vin = Vb[cur]; ra.Vout = Vb[cur ^ 1];
+        cur ^= 1;
+        --flips_left;
+      } else if (q == R) {
+        ra.vmode = 1;  // round R - 1 (R odd); out of place when that returns V to its first buffer
+        ra.Vin = Vb[cur]; ra.Vout = Vb[0];
+        cur = 0;
+      }
+      ra.nvw = ra.vmode ? np * ((nb * BSZ + 63) / 64) : 0;
       ra.thresh_ptr = w->up;
       ra.max_inner = inner_sweeps; ra.within = q == 0 ? 1 : 0;
       // the update wavefronts hold back about 0.9 us so that the pair solves' loads (the round's critical path)
@@ -1103,6 +1194,8 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       hipLaunchKernelGGL(round_kernel, dim3(grid), dim3(64), 0, s_, ra);
       KOT_HIP_TRY(hipGetLastError());
     }
+    if (cur != 0) KOT_HIP_TRY(vec_copy((int)mat, Vb[cur], V, s_));
+    (void)flips_left;
     return hipSuccess;
   };
   auto launch_sweep = [&](hipStream_t s_) -> hipError_t {
@@ -1112,9 +1205,9 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
   };
   // flops of one full sweep: per round 2 x 2 x 16^3 per A tile and 2 x 16^3 per V tile
   const double sweep_flops = (double)(nb - 1) * (4.0 * 4096.0 * np * np + 2.0 * 4096.0 * nslab * np);
-  // algorithmic bytes of a full sweep: per round A's lower triangle (A is symmetric) and V read and written once,
-  // 8 l^2 + 16 l^2
-  const double sweep_bytes = 24.0 * l * (double)l * (nb - 1);
+  // algorithmic bytes of a full sweep: per round A's lower triangle (A is symmetric) read and written once, 8 l^2,
+  // and V read and written once per round (16 l^2) or, with the two-round update, once per two rounds (8 l^2)
+  const double sweep_bytes = (A2 && V2 ? 16.0 : 24.0) * l * (double)l * (nb - 1);
   const double npairs = 0.5 * nb * (nb + 1.0);
   while (off > tol * all && s < max_sweeps) {
     if (!w->noalloc) w->hup[0] = thresh_rel * all;  // the stream is idle here (block_norms synchronized it)

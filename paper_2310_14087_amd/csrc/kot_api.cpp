@@ -178,8 +178,8 @@ kot_status ensure_ws(kot_ctx* ctx, int l, int nmax) {
                      &ctx->Bm, &ctx->dX, &ctx->Mr, &ctx->Pe1, &ctx->Pe2, &ctx->Xh};
   for (double** m : mats)
     if (!(*m = alloc(mm))) return fail(ctx, KOT_ERR_OOM, "workspace allocation failed (l=%d)", cap);
-  // the eigensolver's blocked A, V and second A (each over the block-padded size)
-  if (!(ctx->eigtmp = alloc(3 * eig_mat_doubles(cap) * sizeof(double))))
+  // the eigensolver's blocked A, V, second A and second V (each over the block-padded size)
+  if (!(ctx->eigtmp = alloc(4 * eig_mat_doubles(cap) * sizeof(double))))
     return fail(ctx, KOT_ERR_OOM, "workspace allocation failed");
   double** vecs[] = {&ctx->zb, &ctx->wsumb, &ctx->wmu, &ctx->wnu, &ctx->dg, &ctx->a1, &ctx->cx, &ctx->cr, &ctx->cp,
                      &ctx->cAp, &ctx->cdinv, &ctx->rdb, &ctx->qd, &ctx->qe, &ctx->qs, &ctx->vtmp, &ctx->gh, &ctx->s_e1, &ctx->s_e2, &ctx->r1h, &ctx->lx, &ctx->lr, &ctx->lp,
@@ -297,7 +297,7 @@ kot_status eig_run(kot_ctx* ctx, int l, const double* Z, const double* P0, doubl
   double rel = 0.0;
   const int max_sw = p->eig_max_sweeps > 0 ? p->eig_max_sweeps : 30;
   const int inner = p->eig_inner_sweeps > 0 ? p->eig_inner_sweeps : 1;
-  HIPCHK(eigh_jacobi(ctx->eig, l, Z, P0, P, w, ctx->eigtmp, 3, max_sw, inner, 1e-14, &sw, &rel, npos, ctx->stream));
+  HIPCHK(eigh_jacobi(ctx->eig, l, Z, P0, P, w, ctx->eigtmp, 4, max_sw, inner, 1e-14, &sw, &rel, npos, ctx->stream));
   if (sweeps_acc) *sweeps_acc += sw;
   if (!(rel <= 1e-14)) {
     if (!std::isfinite(rel)) return fail(ctx, KOT_ERR_NUMERIC, "non-finite matrix in eigensolver");

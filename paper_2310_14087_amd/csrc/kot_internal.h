@@ -104,7 +104,8 @@ void eig_work_destroy(EigWork* w);
 // (columns orthonormal).  Returns the sweep count through *sweeps, off/norm through *rel_off and the number
 // of positive eigenvalues through *npos (may be null); the host has synchronized with the stream on return.
 // tmp: workspace of tmp_mats >= 2 matrices of eig_mat_doubles(l) doubles each (blocked A and V); with a third
-// (required for a warm start) a full sweep runs one launch per round instead of two.
+// (required for a warm start) a full sweep runs one launch per round instead of two, and with a fourth V is
+// updated by two rounds at once.
 size_t eig_mat_doubles(int l);
 hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, double* P, double* wv, double* tmp,
                        int tmp_mats, int max_sweeps, int inner_sweeps, double tol, int* sweeps, double* rel_off,
