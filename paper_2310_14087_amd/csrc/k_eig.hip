@@ -1146,10 +1146,7 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     double* Ub3[3] = {w->U, w->U + (size_t)(block_count(w->lmax) / 2) * SLOT * SLOT,
                       w->U + 2 * (size_t)(block_count(w->lmax) / 2) * SLOT * SLOT};
     const bool pairs2 = V2 != nullptr;
-    int cur = 0;
-    int flips_left = 0;  // two-round updates still to come in this sweep
-    if (pairs2)
-      for (int q = 2; q <= R; q += 2) ++flips_left;
+    int cur = 0;  // the V buffer holding V before launch q
     for (int q = 0; q <= R; ++q) {
       RoundArgs ra{};
       ra.l = l; ra.nb = nb; ra.np = np;
@@ -1178,7 +1175,6 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
         ra.vmode = 2;  // rounds q - 2, q - 1
         ra.Vin = Vb[cur]; ra.Vout = Vb[cur ^ 1];
         cur ^= 1;
-        --flips_left;
       } else if (q == R) {
         ra.vmode = 1;  // round R - 1 (R odd); out of place when that returns V to its first buffer
         ra.Vin = Vb[cur]; ra.Vout = Vb[0];
@@ -1195,7 +1191,6 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
       KOT_HIP_TRY(hipGetLastError());
     }
     if (cur != 0) KOT_HIP_TRY(vec_copy((int)mat, Vb[cur], V, s_));
-    (void)flips_left;
     return hipSuccess;
   };
   auto launch_sweep = [&](hipStream_t s_) -> hipError_t {

@@ -106,8 +106,10 @@ def test_setup(gpu_ctx, name, l, n):
     np.testing.assert_allclose(Rg, core.R, atol=1e-9)
 
 
-@pytest.mark.parametrize("l", [1, 2, 7, 16, 33, 64, 100, 257])
+@pytest.mark.parametrize("l", [1, 2, 7, 16, 30, 33, 64, 100, 127, 257])
 def test_eigh(gpu_ctx, l):
+    """Random dense matrices whose block-padded sizes give tournaments of 1, 3, 5, 7, 13, 15 and 33 rounds: the
+    update of V by two rounds at a time ends with the last round alone after each of these."""
     from paper_2310_14087_amd import kotssn
     _case(f"kot_eigh random symmetric l={l}")
     rng = np.random.default_rng(l)
