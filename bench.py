@@ -359,7 +359,8 @@ def main():
     ap.add_argument("--no-decoupled", action="store_true",
                     help="skip the decoupled mix1000 secondary that runs after the mix1000_median line")
     ap.add_argument("--decoupled-steps", type=int, default=24)
-    ap.add_argument("--arm", default="all", choices=["fp64", "closed", "warm", "mixed32", "mixed16", "mixed", "all"])
+    ap.add_argument("--arm", default="all",
+                    choices=["fp64", "closed", "warm", "mixed32", "mixed16", "mixed_fallback", "mixed", "all"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the roofline pass")
     ap.add_argument("--roofline-solves", type=int, default=0,
@@ -400,7 +401,8 @@ def main():
     if a.workload not in WORKLOAD_TEXT:
         raise SystemExit(f"unknown workload {a.workload}")
     coupled = a.workload == "mix1000_median"
-    arms = ["fp64", "closed", "warm", "mixed32", "mixed16", "mixed"] if a.arm == "all" else [a.arm]
+    arms = (["fp64", "closed", "warm", "mixed32", "mixed16", "mixed_fallback", "mixed"] if a.arm == "all"
+            else [a.arm])
     steps = a.steps or (4 if coupled else 24)
     nroof = a.roofline_solves or (1 if coupled else 3)
     main_res = run_workload(a, a.workload, arms, steps, a.iters if coupled else 200, nroof)
@@ -489,8 +491,12 @@ def run_workload(a, workload, arms, steps, max_iter, nroof):
         if arm == "closed":
             kw.update(closed_start=1)
         elif arm != "fp64":
+            # the learned start, dropped for the cold start when it fails the fallback test; in the
+            # mixed_fallback arm the closed-form start replaces it first (closed_start = 2)
             kw.update(ws_F=kotssn.N_FEATURES, ws_H=H, ws_theta=theta_dev.data_ptr())
-        if arm == "mixed":
+            if arm == "mixed_fallback":
+                kw.update(closed_start=2)
+        if arm in ("mixed", "mixed_fallback"):
             kw.update(precision=kotssn.KOT_MIXED_BF16X3)
         elif arm == "mixed16":
             kw.update(precision=kotssn.KOT_MIXED_BF16)
@@ -568,7 +574,7 @@ def run_workload(a, workload, arms, steps, max_iter, nroof):
              + (f" ({a.lanes} lanes; one at a time {steps / sel:.3f} solves/s)" if lan else ""))
     ctx.close()
     if "fp64" in out_arms:
-        for arm in ("closed", "warm", "mixed32", "mixed16", "mixed"):
+        for arm in ("closed", "warm", "mixed32", "mixed16", "mixed_fallback", "mixed"):
             if arm in out_arms:
                 out_arms[arm]["ot_rel_dev_vs_fp64"] = max(
                     abs(x - y) / abs(y) for x, y in zip(out_arms[arm]["ot"], out_arms["fp64"]["ot"]))

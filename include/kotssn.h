@@ -98,9 +98,12 @@ typedef struct kot_params {
   int schur_solver;    /* a kot_schur_solver value; default KOT_SCHUR_CG */
   int eig_inner_sweeps; /* cap on the cyclic Jacobi sweeps a 16x16 block-pair subproblem gets per visit of the
                            eigensolver (default 1; a visit also ends after a sweep that rotated nothing) */
-  int closed_start;    /* 1: without gamma0 and without ws_theta, start from gamma0_i = max(z_i / Q_ii, -lambda1),
-                          the minimizer of Eq. (3.4) for diagonal Q and orthogonal R (the LMI is then the box
-                          gamma >= -lambda1), lifted and kept or dropped like any start (default 0) */
+  int closed_start;    /* the closed-form start gamma0_i = max(z_i / Q_ii, -lambda1), the minimizer of Eq. (3.4)
+                          for diagonal Q and orthogonal R (the LMI is then the box gamma >= -lambda1), lifted and
+                          kept or dropped like any start: 1 = the start when neither gamma0 nor ws_theta is given;
+                          2 = the replacement of a start (gamma0 or the network's) that fails the fallback test,
+                          itself kept only if it passes that test; 0 (default) = not used.  Other values are
+                          rejected with KOT_ERR_ARG. */
   double kdiag_tol;    /* sparsity of K (Remark 4.5): when every off-diagonal entry of K + eps I is at most kdiag_tol
                           times its largest diagonal entry, the setup drops them, so R = diag(sqrt(K_ii + eps))
                           without the factorization, and the solve's products with R (Phi, Phi*, P^T R, the
@@ -135,7 +138,8 @@ typedef struct kot_result {
   int null_steps;      /* iterations that kept w_k */
   int eig_sweeps_total;
   int alpha_last;      /* number of positive eigenvalues of Z at the returned iterate */
-  int warm_used;       /* 1 if the start from gamma0 was kept (it had |R(w0)| <= |R(0,0)|), else 0 */
+  int warm_used;       /* 1 if the start from gamma0 (given or the network's) was kept (it had |R(w0)| <= |R(0,0)|),
+                          2 if it was not and the closed-form start replacing it was (closed_start = 2), else 0 */
   int lowp_directions; /* Newton directions computed with the reduced-precision chain (see lowp_min_rows) */
   double time_ms;      /* wall time of the solve on the device stream */
   int kdiag;           /* 1 if the setup took K as diagonal (kdiag_tol), else 0 */
@@ -159,8 +163,11 @@ const char* kot_last_error(const kot_ctx* ctx);
 kot_status kot_setup(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm,
                      double* Q, double* z, double* R, double* wsum, double* q2);
 
-/* Full solve: setup (as kot_setup) then Algorithm 2 from gamma0 (device, length l; NULL = cold start
- * gamma = 0), X0 = 0. */
+/* Full solve: setup (as kot_setup) then Algorithm 2 from a start w0 = (gamma0, X0): gamma0 (device, length
+ * l) if given, else the network's prediction when prm->ws_theta is set, else the closed-form start when
+ * prm->closed_start = 1, else the cold start (0, 0); X0 lifted from gamma0 (lift_x0) or 0.  A start is kept
+ * only if |R(w0)| <= |R(0, 0)| (the fallback test); a given or predicted start that fails it is replaced by
+ * the closed-form start when prm->closed_start = 2 (if that passes), else by (0, 0); res->warm_used says which. */
 kot_status kot_solve(kot_ctx* ctx, const kot_problem* prob, const kot_params* prm, const double* gamma0,
                      kot_result* res);
 

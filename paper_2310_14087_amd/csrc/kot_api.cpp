@@ -665,6 +665,7 @@ kot_status check_params(kot_ctx* ctx, const kot_params* p, bool need_sigma) {
     return fail(ctx, KOT_ERR_ARG, "precond must be KOT_PRECOND_NONE or KOT_PRECOND_JACOBI");
   if (p->schur_solver != KOT_SCHUR_CG && p->schur_solver != KOT_SCHUR_SQMR)
     return fail(ctx, KOT_ERR_ARG, "schur_solver must be KOT_SCHUR_CG or KOT_SCHUR_SQMR");
+  if (p->closed_start < 0 || p->closed_start > 2) return fail(ctx, KOT_ERR_ARG, "closed_start must be 0, 1 or 2");
   return KOT_OK;
 }
 
@@ -949,7 +950,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   const bool eta_default = !(eta > 0.0);
   if (!pre) {
     if (eta_default) KCHK(default_eta_launch(ctx, cv));       // read with the first residual's norms
-    if (gamma0 || p->ws_theta || p->closed_start) HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + SL_ZZ, ctx->part, st));
+    if (gamma0 || p->ws_theta || p->closed_start == 1) HIPCHK(dot(l, cv.z, cv.z, ctx->dsc + SL_ZZ, ctx->part, st));
   }
   State* W = &ctx->S[0];
   State* T = &ctx->S[1];
@@ -957,15 +958,20 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   if (p->ws_theta && !gamma0) {  // learned start
     if (!pre) KCHK(predict_gamma0(ctx, cv, ctx->Kb, p->ws_F, p->ws_H, p->ws_theta, ctx->S[1].g));
     gamma0 = ctx->S[1].g;
-  } else if (p->closed_start && !gamma0) {  // closed-form start (the diagonal, orthogonal-factor minimizer)
+  } else if (p->closed_start == 1 && !gamma0) {  // closed-form start (the diagonal, orthogonal-factor minimizer)
     HIPCHK(closed_start(l, cv.Q, cv.z, cv.lam1, ctx->S[1].g, st));
     gamma0 = ctx->S[1].g;
   }
   if (gamma0) HIPCHK(vec_copy(l, gamma0, W->g, st));
   else HIPCHK(vec_fill(l, 0.0, W->g, st));
-  if (gamma0 && p->lift_x0) {
-    // X0 = R^-T diag(y) R^-1 with y = (Q gamma0 - z)/(2 lam2) (stationarity's value of Phi(X)) on the
-    // constraints predicted active, small entries dropped, so that Phi(X0) = y
+  // X0 for the start in W->g: with lift_x0, X0 = R^-T diag(y) R^-1 with y = (Q gamma0 - z)/(2 lam2)
+  // (stationarity's value of Phi(X)) on the constraints predicted active, small entries dropped, so that
+  // Phi(X0) = y; else X0 = 0
+  auto start_x = [&]() -> kot_status {
+    if (!p->lift_x0) {
+      HIPCHK(vec_fill(l * l, 0.0, W->X, st));
+      return KOT_OK;
+    }
     if (!cv.Linv && !cv.rd) KCHK(trtri_cached(ctx, l, cv.R, ctx->T1, ctx->T2));
     HIPCHK(mm(st, 0, 0, l, 1, l, 1.0, cv.Q, l, nullptr, W->g, 1, 0.0, ctx->vtmp, 1));
     HIPCHK(lift_diag(l, ctx->vtmp, cv.z, W->g, cv.lam1, cv.lam2, 0.02, ctx->dg, ctx->part, st));
@@ -977,22 +983,33 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     else
       HIPCHK(mm(st, 1, 0, l, l, l, 1.0, ctx->T1, l, ctx->dg, ctx->T1, l, 0.0, W->X, l, TRI_A_LOWER | TRI_B_UPPER,
                 true));
-  } else {
-    HIPCHK(vec_fill(l * l, 0.0, W->X, st));
-  }
+    return KOT_OK;
+  };
+  if (gamma0) KCHK(start_x());
+  else HIPCHK(vec_fill(l * l, 0.0, W->X, st));
   int sweeps = 0;
   KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
   if (eta_default) eta = pre ? pre->eta : default_eta_read(ctx, cv);
   res->warm_used = 0;
   if (gamma0) {
-    // fallback: the cold start w = (0, 0) has |R| = |z|/(2 lam2) (Pi(-lambda1 I) = 0); keep the better one
+    // fallback: the cold start w = (0, 0) has |R| = |z|/(2 lam2) (Pi(-lambda1 I) = 0); keep the better one.
+    // With closed_start = 2 a rejected start (the network's or the caller's) is first replaced by the
+    // closed-form start, which is kept on the same test.
     const double cold = std::sqrt(pre ? pre->zz : ctx->hsc[SL_ZZ]) / (2.0 * cv.lam2);
-    if (!(W->rn <= cold)) {
-      HIPCHK(vec_fill(l, 0.0, W->g, st));
-      HIPCHK(vec_fill(l * l, 0.0, W->X, st));
-      KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
-    } else {
+    if (W->rn <= cold) {
       res->warm_used = 1;
+    } else {
+      if (p->closed_start == 2) {
+        HIPCHK(closed_start(l, cv.Q, cv.z, cv.lam1, W->g, st));
+        KCHK(start_x());
+        KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+        if (W->rn <= cold) res->warm_used = 2;
+      }
+      if (res->warm_used == 0) {
+        HIPCHK(vec_fill(l, 0.0, W->g, st));
+        HIPCHK(vec_fill(l * l, 0.0, W->X, st));
+        KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+      }
     }
   }
   const bool use_eg = p->safeguard == KOT_SAFEGUARD_EG;
@@ -1412,7 +1429,7 @@ kot_status kot_solve(kot_ctx* ctx, const kot_problem* pb, const kot_params* p, c
   cv.lam1 = p->lambda1; cv.lam2 = p->lambda2;
   // the lifted start needs R^-T: the factorization forms it beside R (the buffer is free until the first
   // extragradient step)
-  double* Linv = (gamma0 || p->ws_theta || p->closed_start) && p->lift_x0 ? ctx->Xh : nullptr;
+  double* Linv = (gamma0 || p->ws_theta || p->closed_start == 1) && p->lift_x0 ? ctx->Xh : nullptr;
   cv.Linv = Linv;
   bool diag = false;
   if (overlap_ok(ctx, p, pb->l)) {

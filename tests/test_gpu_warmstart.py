@@ -107,7 +107,7 @@ def test_learned_warm_start_gain(gpu_ctx):
         prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
         _, _, rc = gpu_ctx.solve(*args, prm)
         prw = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, ws_F=F, ws_H=H,
-                                    ws_theta=th.data_ptr())
+                                    ws_theta=th.data_ptr(), closed_start=0)
         _, _, rw = gpu_ctx.solve(*args, prw)
         assert rc.status == kotssn.KOT_OK and rw.status == kotssn.KOT_OK
         assert abs(rw.ot - rc.ot) <= 1e-6 * abs(rc.ot)
@@ -137,7 +137,8 @@ def test_learned_start_against_closed_form_start_256(gpu_ctx):
         base = dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
         _, _, rc = gpu_ctx.solve(*args, kotssn.default_params(**base))
         _, _, rz = gpu_ctx.solve(*args, kotssn.default_params(closed_start=1, **base))
-        _, _, rw = gpu_ctx.solve(*args, kotssn.default_params(ws_F=F, ws_H=H, ws_theta=th.data_ptr(), **base))
+        _, _, rw = gpu_ctx.solve(*args, kotssn.default_params(ws_F=F, ws_H=H, ws_theta=th.data_ptr(), closed_start=0,
+                                                              **base))
         for r in (rc, rz, rw):
             assert r.status == kotssn.KOT_OK, (s, r)
             assert abs(r.ot - rc.ot) <= 1e-6 * abs(rc.ot)
@@ -165,7 +166,8 @@ def test_lifted_start_matrix(gpu_ctx, name, l, n, seed):
     core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
     rng = np.random.default_rng(1)
     g0 = -p.lam1 * (1.0 + 0.3 * rng.standard_normal(p.l))
-    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=1e-300, max_iter=0)
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=1e-300, max_iter=0,
+                                closed_start=0)
     g, X, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm, gamma0=_t(g0), want_X=True)
     y = (core.Q @ g0 - core.z) / (2 * p.lam2)
     y = np.where((g0 <= -0.9 * p.lam1) & (y > 0), y, 0.0)
@@ -178,3 +180,70 @@ def test_lifted_start_matrix(gpu_ctx, name, l, n, seed):
         np.testing.assert_allclose(ko.phi(core.R, _n(X)), y, atol=1e-8 * max(1.0, y.max()))
     else:  # the start was worse than the cold start: (0, 0) is returned
         assert np.all(_n(X) == 0) and np.all(_n(g) == 0)
+
+
+def _same_solve(a, b):
+    """a reached b's start after rejecting another one: the same iterates, histories and counters, and at least
+    b's sweeps (the rejected start's residual took its own)."""
+    (ga, Xa, ra), (gb, Xb, rb) = a, b
+    k = ra.iters + 1
+    assert (ra.status, ra.iters, ra.cg_iters_total, ra.eg_accepts) == (rb.status, rb.iters, rb.cg_iters_total,
+                                                                         rb.eg_accepts)
+    assert ra.eig_sweeps_total >= rb.eig_sweeps_total
+    np.testing.assert_array_equal(ra.res_hist[:k], rb.res_hist[:k])
+    assert ra.ot == rb.ot
+    assert np.array_equal(_n(ga), _n(gb)) and np.array_equal(_n(Xa), _n(Xb))
+
+
+def test_rejected_start_replaced_by_closed_form_start(gpu_ctx):
+    """A given start worse than the cold one (gamma0 = +10 lambda1 everywhere): with closed_start = 2 the
+    closed-form start replaces it (warm_used = 2) and the solve is the closed_start = 1 solve bit for bit; with
+    closed_start = 0 (the default) it is the cold solve bit for bit (warm_used = 0)."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem("mix256", 3, l=90, n=300)
+    print(f"[case] rejected given start, closed-form fallback, mix256 l={p.l}", flush=True)
+    args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+    bad = _t(np.full(p.l, 10.0 * p.lam1))
+    base = dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+    fb = gpu_ctx.solve(*args, kotssn.default_params(closed_start=2, **base), gamma0=bad, want_X=True, hist_cap=256)
+    cl = gpu_ctx.solve(*args, kotssn.default_params(closed_start=1, **base), want_X=True, hist_cap=256)
+    assert cl[2].warm_used == 1 and fb[2].warm_used == 2
+    assert fb[2].status == kotssn.KOT_OK
+    _same_solve(fb, cl)
+    nf = gpu_ctx.solve(*args, kotssn.default_params(closed_start=0, **base), gamma0=bad, want_X=True, hist_cap=256)
+    cd = gpu_ctx.solve(*args, kotssn.default_params(closed_start=0, **base), want_X=True, hist_cap=256)
+    assert nf[2].warm_used == 0
+    _same_solve(nf, cd)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_learned_start_fallback_on_coupled_workload(gpu_ctx):
+    """The median-bandwidth workload at full size (l = 1000, n = 5000), 2 outer iterations: the network's start
+    fails the fallback test there (it was trained on decoupled problems); with closed_start = 2 the closed-form
+    start replaces it (warm_used = 2), and the solve is then the closed_start = 1 solve bit for bit."""
+    import torch
+    from paper_2310_14087_amd import kotssn, warmstart
+    theta, F, H, meta = warmstart.load(WEIGHTS)
+    th = torch.from_numpy(theta).to("cuda:0")
+    p = make_problem("mix1000_median", 0)
+    print(f"[case] learned start with closed-form fallback, mix1000_median l={p.l}", flush=True)
+    args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+    base = dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, max_iter=2)
+    lw = dict(ws_F=F, ws_H=H, ws_theta=th.data_ptr())
+    only = gpu_ctx.solve(*args, kotssn.default_params(closed_start=0, **lw, **base))
+    assert only[2].warm_used == 0
+    fb = gpu_ctx.solve(*args, kotssn.default_params(closed_start=2, **lw, **base), want_X=True, hist_cap=16)
+    cl = gpu_ctx.solve(*args, kotssn.default_params(closed_start=1, **base), want_X=True, hist_cap=16)
+    assert cl[2].warm_used == 1 and fb[2].warm_used == 2
+    _same_solve(fb, cl)
+
+
+def test_closed_start_value_checked(gpu_ctx):
+    import torch
+    from paper_2310_14087_amd import kotssn
+    print("[case] kot_solve rejects closed_start=3", flush=True)
+    p = make_problem("mix256", 0, l=20, n=40)
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, closed_start=3)
+    with pytest.raises(kotssn.KotError) as e:
+        gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm)
+    assert e.value.status == kotssn.KOT_ERR_ARG
