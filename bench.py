@@ -308,8 +308,8 @@ def batch_bench(a):
     probs = [make_problem("batch", s) for s in range(a.batch)]
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     inputs = [(t(p.xs), t(p.ys), t(p.xf), t(p.yf)) for p in probs]
-    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=1, max_iter=60)
-            for p in probs]
+    prms = [kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, precision=1, max_iter=60,
+                                  closed_start=a.batch_closed_start) for p in probs]
     ctx = kotssn.Context(0)
     if a.tune:
         if os.path.exists(a.tune):
@@ -330,6 +330,7 @@ def batch_bench(a):
         _log(f"lanes={lanes}: {len(probs) / dt:.2f} solves/s, {conv}/{len(probs)} converged")
     ctx.close()
     print(json.dumps({"metric": "batched SSN solves/s (uneven problems)", "problems": len(probs),
+                      "start": "closed-form" if a.batch_closed_start else "cold",
                       "sizes": {"l": [p.l for p in probs], "n": [p.n_src for p in probs], "d": [p.d for p in probs]},
                       "results": res}), flush=True)
 
@@ -373,6 +374,8 @@ def main():
                          "plain fp64 arm, jacobi on the accelerated arms")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the metric line: time kot_solve_batched on this many 'batch' problems")
+    ap.add_argument("--batch-closed-start", type=int, default=0, choices=[0, 1],
+                    help="with --batch: 1 = every problem starts from the closed-form start (closed_start = 1)")
     ap.add_argument("--lanes", type=int, default=8,
                     help="independent solves in flight (kot_solve_batched lanes, one stream and host thread each); "
                          "1: one solve at a time on the main context")
