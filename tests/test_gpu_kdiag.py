@@ -123,3 +123,20 @@ def test_setup_returns_the_diagonal_factor(gpu_ctx):
     assert np.all(Rg == np.diag(np.diag(Rg)))
     np.testing.assert_allclose(np.diag(Rg) ** 2, np.diag(core.extra["K"]) + 1e-10, rtol=1e-15)
     np.testing.assert_allclose(Rg, core.R, atol=1e-12)
+
+
+def test_closed_form_fallback_on_diagonal_path(gpu_ctx):
+    """closed_start = 2 on the diagonal path: a rejected given start is replaced by the closed-form start, whose
+    lift is the diagonal diag(y / r^2); the solve is the closed_start = 1 solve bit for bit."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem("mix1000", 2, l=150, n=600)
+    print("[case] kot_solve mix1000 l=150 diagonal path, rejected start replaced by the closed-form start", flush=True)
+    args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+    base = dict(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+    bad = _t(np.full(p.l, 100.0 * p.lam1))
+    gf, Xf, rf = gpu_ctx.solve(*args, kotssn.default_params(closed_start=2, **base), gamma0=bad, want_X=True)
+    gc, Xc, rc = gpu_ctx.solve(*args, kotssn.default_params(closed_start=1, **base), want_X=True)
+    assert rf.kdiag == 1 and rc.kdiag == 1
+    assert rf.warm_used == 2 and rc.warm_used == 1
+    assert rf.status == kotssn.KOT_OK and (rf.iters, rf.ot) == (rc.iters, rc.ot)
+    assert np.array_equal(_n(gf), _n(gc)) and np.array_equal(_n(Xf), _n(Xc))
