@@ -32,7 +32,7 @@ typedef enum {
   KOT_ERR_HIP = -2,        /* HIP runtime error */
   KOT_ERR_OOM = -3,        /* workspace allocation failed */
   KOT_ERR_FACTOR = -4,     /* K + eps I is not numerically positive definite */
-  KOT_ERR_NUMERIC = -5,    /* NaN/Inf in the residual */
+  KOT_ERR_NUMERIC = -5,    /* NaN/Inf in the residual, or in a matrix given to the eigensolver */
   KOT_ERR_EIG = -6         /* eigensolver did not reach its off-diagonal tolerance */
 } kot_status;
 
@@ -197,7 +197,8 @@ kot_status kot_solve_core(kot_ctx* ctx, int l, const double* Q, const double* z,
                           const double* wsum, const kot_params* prm, const double* gamma0, kot_result* res);
 
 /* Symmetric eigendecomposition (Eq. 4.4): Z = P diag(w) P^T with w ascending.  Z, P (l x l) and w (l) are
- * device pointers; P's columns are the eigenvectors.  Z is not modified.  Returns KOT_ERR_EIG if the
+ * device pointers; P's columns are the eigenvectors.  Z is not modified.  Returns KOT_ERR_NUMERIC if Z has a
+ * non-finite entry (P, w then hold no result) and KOT_ERR_EIG if the
  * Jacobi sweeps do not reach the off-diagonal tolerance within prm->eig_max_sweeps (P, w still written). */
 kot_status kot_eigh(kot_ctx* ctx, int l, const double* Z, double* P, double* w, const kot_params* prm);
 

@@ -1269,7 +1269,10 @@ hipError_t eigh_jacobi(EigWork* w, int l, const double* Z, const double* P0, dou
     KOT_HIP_TRY(block_norms(w, l, nb, A, st, &off, &all, &pos));
   }
   *sweeps = s;
-  *rel_off = (all > 0.0) ? off / all : 0.0;
+  // a non-finite entry (NaN, or an infinity and the NaNs its rotations make) leaves a non-finite norm: report
+  // it as a non-finite ratio, so that the caller does not take the sweeps' output for converged
+  if (!std::isfinite(off) || !std::isfinite(all)) *rel_off = NAN;
+  else *rel_off = (all > 0.0) ? off / all : 0.0;
   if (npos) *npos = pos;
   return finish(nullptr);
 }

@@ -185,6 +185,27 @@ def test_eigh_sparse(gpu_ctx, l, nc):
     assert np.abs(P.T @ P - np.eye(l)).max() <= 1e-13 * l ** 0.5
 
 
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_eigh_non_finite_entry_reported(gpu_ctx, bad):
+    """A NaN or an infinity in Z is reported as KOT_ERR_NUMERIC (kot_eigh and kot_eigh_noalloc), and the
+    context still decomposes the next matrix."""
+    from paper_2310_14087_amd import kotssn
+    _case(f"kot_eigh with a {bad} entry (expects KOT_ERR_NUMERIC)")
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((40, 40))
+    Z = A + A.T
+    Zb = Z.copy()
+    Zb[3, 7] = Zb[7, 3] = bad
+    with pytest.raises(kotssn.KotError) as e:
+        gpu_ctx.eigh(_t(Zb), kotssn.default_params())
+    assert e.value.status == kotssn.KOT_ERR_NUMERIC
+    with pytest.raises(kotssn.KotError) as e:
+        kotssn.eigh_noalloc(_t(Zb), kotssn.default_params())
+    assert e.value.status == kotssn.KOT_ERR_NUMERIC
+    w, P = gpu_ctx.eigh(_t(Z), kotssn.default_params())
+    np.testing.assert_allclose(_n(w), np.linalg.eigvalsh(Z), atol=1e-12 * np.abs(Z).sum())
+
+
 def test_eigh_degenerate(gpu_ctx):
     """Repeated and zero eigenvalues: invariants still hold."""
     from paper_2310_14087_amd import kotssn
