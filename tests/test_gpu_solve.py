@@ -246,3 +246,24 @@ def test_invalid_sizes_rejected(gpu_ctx, l, n, d):
     with pytest.raises(kotssn.KotError) as e:
         gpu_ctx.solve(z(n), z(n), z(l), z(l), prm)
     assert e.value.status == kotssn.KOT_ERR_ARG
+
+
+@pytest.mark.parametrize("where", ["sample", "filling_point"])
+def test_non_finite_input_reported(gpu_ctx, where):
+    """A NaN in a sample (it reaches z and q^2) or in a filling point (it reaches K) ends kot_solve with an
+    error status (KOT_ERR_NUMERIC, or KOT_ERR_FACTOR when the factorization meets it), and the context still
+    solves the next problem."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem("mix256", 4, l=40, n=80)
+    print(f"[case] kot_solve with a NaN {where} (expects an error status)", flush=True)
+    xs, xf = p.xs.copy(), p.xf.copy()
+    if where == "sample":
+        xs[5, 1] = np.nan
+    else:
+        xf[7, 0] = np.nan
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+    with pytest.raises(kotssn.KotError) as e:
+        gpu_ctx.solve(_t(xs), _t(p.ys), _t(xf), _t(p.yf), prm)
+    assert e.value.status in (kotssn.KOT_ERR_NUMERIC, kotssn.KOT_ERR_FACTOR)
+    _, _, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm)
+    assert r.status == kotssn.KOT_OK and r.residual <= p.tol
