@@ -8,7 +8,7 @@ pairwise distance): the kernel is dense, the eigen-row chain of the Schur matvec
 Algorithm 2 does not reach residual 1e-6 in any affordable number of iterations, so every solve is capped at
 ``--iters`` outer iterations and the line reports outer iterations/s (with each solve's residual).  After it, the
 decoupled ``mix1000`` workload (the same draw on unit-cube data with sigma^2 = 0.005, where K is the identity to
-1e-14) is timed as solves to 1e-6 (solves/s), as a labelled secondary.  Prints one JSON line.
+about 1e-14) is timed as solves to 1e-6 (solves/s), as a labelled secondary.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--iters N]
                     [--workload mix1000_median|mix1000|sweep|egcompare|eigcompare]
@@ -340,7 +340,7 @@ WORKLOAD_TEXT = {
                       "l=1000 filling points uniform in the per-side bounding boxes, raw coordinates, sigma = median "
                       "pooled pairwise distance (dense, coupled kernel), lambda1=1/l, lambda2=1/sqrt(n)",
     "mix1000": "mix1000 (decoupled): the same draw mapped to the unit cube with sigma^2=0.005 (the kernel K is the "
-               "identity to 1e-14, so the SDP nearly decouples), lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
+               "identity to about 1e-14, so the SDP nearly decouples), lambda1=1/l, lambda2=1/sqrt(n), tol 1e-6",
 }
 
 
