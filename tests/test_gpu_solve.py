@@ -267,3 +267,75 @@ def test_non_finite_input_reported(gpu_ctx, where):
     assert e.value.status in (kotssn.KOT_ERR_NUMERIC, kotssn.KOT_ERR_FACTOR)
     _, _, r = gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm)
     assert r.status == kotssn.KOT_OK and r.residual <= p.tol
+
+
+@pytest.mark.parametrize("name,l,n,seed", [("mix1000", 150, 600, 0), ("mix256", 64, 300, 2)])
+def test_solve_core_on_oracle_dual_data(gpu_ctx, name, l, n, seed):
+    """kot_solve_core on the oracle's own dual data (its Q, z, upper Cholesky factor R, w_mu + w_nu and q^2):
+    Algorithm 2 reaches the tolerance at the oracle's minimizer and estimate."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem(name, seed, l=l, n=n)
+    print(f"[case] kot_solve_core {name} seed={seed} l={p.l} on the oracle's dual data", flush=True)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=p.tol))
+    assert ref["status"] == "converged"
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2, tol=p.tol)
+    gamma, X, r = gpu_ctx.solve_core(_t(core.Q), _t(core.z), _t(core.R), core.q2, _t(core.wsum), prm, want_X=True)
+    assert r.status == kotssn.KOT_OK and r.residual <= p.tol, r
+    assert abs(r.ot - ref["ot"]) <= 1e-6 * abs(ref["ot"])
+    g = _n(gamma)
+    np.testing.assert_allclose(g, ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
+    _, _, rn, _ = ko.residual(core, g, _n(X))
+    assert rn <= 1.01 * p.tol
+
+
+def test_solve_core_tiny_fixed_iterations(gpu_ctx):
+    """kot_solve_core on the dense 'tiny' dual data: the first four iterations follow the oracle's (converged
+    inner solves, as in the kot_solve test of the same workload)."""
+    from paper_2310_14087_amd import kotssn
+    p = make_problem("tiny", 0)
+    print("[case] kot_solve_core tiny fixed 4 iterations", flush=True)
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    ref = ko.solve(core, ko.Params(tol=p.tol, max_iter=4, cg_max_iter=400, tau=1e-13, kappa=1e-13))
+    prm = kotssn.default_params(lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, max_iter=4, cg_max_iter=400,
+                                tau=1e-13, kappa=1e-13)
+    gamma, _, r = gpu_ctx.solve_core(_t(core.Q), _t(core.z), _t(core.R), core.q2, _t(core.wsum), prm)
+    assert r.status == kotssn.KOT_NOT_CONVERGED and r.iters == 4
+    np.testing.assert_allclose(r.res_hist, [h["res"] for h in ref["history"]], rtol=1e-6)
+    np.testing.assert_allclose(_n(gamma), ref["gamma"], atol=1e-6 * np.abs(ref["gamma"]).max())
+
+
+@pytest.mark.parametrize("start", [0, 1])
+def test_solve_core_diagonal_instance_closed_form(gpu_ctx, start):
+    """Diagonal Q and R = I (an orthogonal factor): Eq. 3.4 separates into l one-dimensional problems whose
+    minimizer is gamma_i = max(z_i / Q_ii, -lambda1), and OT = (q^2 - gamma . wsum) / (2 lambda2).  Reached from
+    the cold start, and kept at once from the closed-form start (closed_start = 1)."""
+    from paper_2310_14087_amd import kotssn
+    print(f"[case] kot_solve_core diagonal instance l=50 closed_start={start}", flush=True)
+    rng = np.random.default_rng(9)
+    l, lam1, lam2 = 50, 0.1, 0.5
+    q = rng.uniform(1.0, 3.0, l)
+    z = rng.uniform(-1.0, 0.5, l)
+    wsum = rng.uniform(0.0, 1.0, l)
+    q2 = 1.7
+    g_star = np.maximum(z / q, -lam1)
+    assert 5 < np.sum(g_star == -lam1) < l - 5          # both kinds of coordinates occur
+    prm = kotssn.default_params(lambda1=lam1, lambda2=lam2, tol=1e-10, closed_start=start)
+    gamma, _, r = gpu_ctx.solve_core(_t(np.diag(q)), _t(z), _t(np.eye(l)), q2, _t(wsum), prm)
+    assert r.status == kotssn.KOT_OK and r.residual <= 1e-10, r
+    np.testing.assert_allclose(_n(gamma), g_star, rtol=0, atol=1e-9)
+    assert abs(r.ot - (q2 - g_star @ wsum) / (2 * lam2)) <= 1e-9 * max(1.0, abs(r.ot))
+    if start:
+        assert r.warm_used == 1 and r.iters <= 1
+
+
+def test_solve_core_rejects_non_triangular_factor(gpu_ctx):
+    from paper_2310_14087_amd import kotssn
+    print("[case] kot_solve_core with an entry below R's diagonal (expects KOT_ERR_ARG)", flush=True)
+    l = 12
+    R = np.eye(l)
+    R[5, 2] = 0.3
+    prm = kotssn.default_params(lambda1=0.1, lambda2=0.5)
+    with pytest.raises(kotssn.KotError) as e:
+        gpu_ctx.solve_core(_t(2 * np.eye(l)), _t(np.ones(l)), _t(R), 1.0, _t(np.zeros(l)), prm)
+    assert e.value.status == kotssn.KOT_ERR_ARG
