@@ -339,3 +339,28 @@ def test_solve_core_rejects_non_triangular_factor(gpu_ctx):
     with pytest.raises(kotssn.KotError) as e:
         gpu_ctx.solve_core(_t(2 * np.eye(l)), _t(np.ones(l)), _t(R), 1.0, _t(np.zeros(l)), prm)
     assert e.value.status == kotssn.KOT_ERR_ARG
+
+
+def test_profile_counts_sweeps_and_leaves_results_unchanged(gpu_ctx):
+    """kot_profile: with event timing on, one eig_sweep entry per Jacobi sweep of the solve (one stream), with
+    positive time and algorithmic bytes no more than 24 l^2 per round on average (a full sweep counts 16 l^2 per
+    round: A's lower triangle, and V once per two rounds; a threshold sweep's active tiles of A and V, V read and
+    written every round), and the same iterates as without it."""
+    import torch
+    from paper_2310_14087_amd import kotssn
+    p = make_problem("mix1000_median", 0, l=200, n=1000)
+    print(f"[case] kot_profile around a mix1000_median l={p.l} solve (3 iterations, one stream)", flush=True)
+    args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=p.tol, max_iter=3, overlap=0)
+    g0, _, r0 = gpu_ctx.solve(*args, prm)
+    gpu_ctx.profile_start()
+    g1, _, r1 = gpu_ctx.solve(*args, prm)
+    prof = gpu_ctx.profile_stop()
+    assert torch.equal(g0, g1) and r1.eig_sweeps_total == r0.eig_sweeps_total
+    e = prof["eig_sweep"]
+    assert e["launches"] == r1.eig_sweeps_total > 0
+    assert e["ms"] > 0
+    nb = -(-p.l // 8)
+    nb += nb & 1
+    assert 0 < e["bytes"] <= e["launches"] * 24.0 * p.l * p.l * (nb - 1)
+    assert prof["gemm_f64"]["launches"] > 0 and prof["gemm_f64"]["flops"] > 0

@@ -247,3 +247,28 @@ def test_closed_start_value_checked(gpu_ctx):
     with pytest.raises(kotssn.KotError) as e:
         gpu_ctx.solve(_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf), prm)
     assert e.value.status == kotssn.KOT_ERR_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_kot_warmstart_prediction(gpu_ctx):
+    """kot_warmstart: gamma0 = lambda1 * f(features) with the trained network, against the network evaluated in
+    FP64 on the CPU (oracle/mlp.py) on the library's features; kot_solve with the same network and max_iter = 0
+    returns that start (kept on this held-out decoupled problem)."""
+    import torch
+    from paper_2310_14087_amd import kotssn, warmstart
+    theta, F, H, meta = warmstart.load(WEIGHTS)
+    th = torch.from_numpy(theta).to("cuda:0")
+    p = make_problem("mix256", 100003)
+    print(f"[case] kot_warmstart mix256 seed=100003 l={p.l}", flush=True)
+    args = (_t(p.xs), _t(p.ys), _t(p.xf), _t(p.yf))
+    prm = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=1e-300, max_iter=0)
+    g0 = _n(gpu_ctx.warmstart(*args, prm, th, H))
+    core = ko.setup(p.xs, p.ys, p.xf, p.yf, p.sigma, p.lam1, p.lam2)
+    X = _n(gpu_ctx.features(_t(core.Q), _t(core.z), _t(core.R), _t(core.wsum), core.q2, prm))
+    ref, _ = mlp.forward(theta.astype(np.float64), X.astype(np.float64), F, H)
+    np.testing.assert_allclose(g0, p.lam1 * ref, rtol=0, atol=1e-4 * p.lam1 * max(1.0, np.abs(ref).max()))
+    prw = kotssn.default_params(sigma=p.sigma, lambda1=p.lam1, lambda2=p.lam2, tol=1e-300, max_iter=0, ws_F=F,
+                                ws_H=H, ws_theta=th.data_ptr())
+    g, _, r = gpu_ctx.solve(*args, prw)
+    assert r.warm_used == 1
+    np.testing.assert_allclose(_n(g), g0, rtol=1e-6, atol=1e-9 * p.lam1)
