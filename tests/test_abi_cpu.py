@@ -117,3 +117,11 @@ def test_bench_refuses_more_than_one_gpu(argv, env):
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+@pytest.mark.parametrize("F,H", [(12, 512), (5, 64), (1, 1)])
+def test_mlp_params_count(lib, F, H):
+    """kot_mlp_params (host only): the length of theta in the documented layout, W1 (F x H), b1, W2 (H x H), b2,
+    w3 (H), b3 -- the count the oracle's network uses."""
+    from oracle import mlp
+    assert lib.kot_mlp_params(F, H) == F * H + H + H * H + H + H + 1 == mlp.n_params(F, H)
