@@ -72,6 +72,9 @@ def load(path: str | os.PathLike | None = None) -> C.CDLL:
     p = Path(path) if path else _LIBPATH
     if not p.exists():
         raise OSError(f"{p} not found: build it with `python -m paper_2310_14087_amd.build`")
+    # torch first: the library must bind to the HIP runtime that allocates the tensors it is handed (loaded
+    # first, it would pull in the system's copy, whose context does not see torch's device memory)
+    import torch  # noqa: F401
     lib = C.CDLL(str(p))
     vp, i, d = C.c_void_p, C.c_int, C.c_double
     P = C.POINTER
