@@ -65,12 +65,6 @@ __device__ __forceinline__ int2 get_pair(int round, int nb, const int2* __restri
   return list ? list[k] : round_pair(round, k, nb);
 }
 
-// 16-player circle ordering: in sub-round r, pair 0 = (15, r), pair k = ((r+k)%15, (r-k+15)%15).
-__device__ __forceinline__ void circle16(int r, int k, int& a, int& b) {
-  if (k == 0) { a = 15; b = r; }
-  else { a = (r + k) % 15; b = (r - k + 15) % 15; }
-}
-
 // Index pair (a < b) that lane k (0..7) rotates in sub-round r of one visit of a block pair (slots 0-7: block
 // p, 8-15: block q).  With `within`, sub-rounds 0-6 rotate the pairs inside each block (circle method on 8 indices:
 // lanes 0-3 block p, lanes 4-7 block q) and sub-rounds 7-14 the cross pairs; otherwise the 8 sub-rounds rotate the
