@@ -28,7 +28,7 @@ constexpr size_t kScalarBytes = kScalarDoubles * sizeof(double) + kScalarInts * 
 // 6-7; the theta-rule dots 8-11; inputs of the default EG step 12-13; |z|^2 14; refinement scalars 16-19;
 // the largest off-diagonal and diagonal entries of K + eps I 20-21;
 // pooled feature statistics 24-25; the device-resident CG / QMR state 32-38
-enum : int { SL_TMP = 0, SL_VN = 4, SL_TN = 6, SL_THETA = 8, SL_ETA = 12, SL_ZZ = 14, SL_RR = 16, SL_PAP = 17,
+enum : int { SL_TMP = 0, SL_R1 = 2, SL_VN = 4, SL_TN = 6, SL_THETA = 8, SL_ETA = 12, SL_ZZ = 14, SL_RR = 16, SL_PAP = 17,
              SL_XX = 18, SL_KD = 20, SL_POOL = 24, SL_CG = 32 };
 
 struct State {  // an iterate w = (gamma, X) with its residual and the spectral data of Z
@@ -988,30 +988,41 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
   if (gamma0) KCHK(start_x());
   else HIPCHK(vec_fill(l * l, 0.0, W->X, st));
   int sweeps = 0;
-  KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
-  if (eta_default) eta = pre ? pre->eta : default_eta_read(ctx, cv);
+  // Fallback test of a start w0: kept when |R(w0)| <= |R(0, 0)| = |z|/(2 lam2) (Pi(-lambda1 I) = 0), else the
+  // cold start is taken.  |R(w0)| >= |r1(w0)|, and r1 needs no eigendecomposition: a start whose r1 alone exceeds
+  // the bound (by more than the two norms' rounding) is dropped before its Z is decomposed, with the same outcome.
+  auto test_start = [&](bool* kept) -> kot_status {
+    KCHK(r1_op(ctx, cv, W->g, W->X, W->r1));
+    HIPCHK(dot(l, W->r1, W->r1, ctx->dsc + SL_R1, ctx->part, st));
+    KCHK(sync_read(ctx));
+    const double cold = std::sqrt(pre ? pre->zz : ctx->hsc[SL_ZZ]) / (2.0 * cv.lam2);
+    *kept = false;
+    if (!(std::sqrt(ctx->hsc[SL_R1]) <= cold * (1.0 + 1e-12))) return KOT_OK;
+    KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+    *kept = W->rn <= cold;
+    return KOT_OK;
+  };
   res->warm_used = 0;
+  bool kept = false;
   if (gamma0) {
-    // fallback: the cold start w = (0, 0) has |R| = |z|/(2 lam2) (Pi(-lambda1 I) = 0); keep the better one.
     // With closed_start = 2 a rejected start (the network's or the caller's) is first replaced by the
     // closed-form start, which is kept on the same test.
-    const double cold = std::sqrt(pre ? pre->zz : ctx->hsc[SL_ZZ]) / (2.0 * cv.lam2);
-    if (W->rn <= cold) {
+    KCHK(test_start(&kept));
+    if (kept) {
       res->warm_used = 1;
-    } else {
-      if (p->closed_start == 2) {
-        HIPCHK(closed_start(l, cv.Q, cv.z, cv.lam1, W->g, st));
-        KCHK(start_x());
-        KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
-        if (W->rn <= cold) res->warm_used = 2;
-      }
-      if (res->warm_used == 0) {
-        HIPCHK(vec_fill(l, 0.0, W->g, st));
-        HIPCHK(vec_fill(l * l, 0.0, W->X, st));
-        KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
-      }
+    } else if (p->closed_start == 2) {
+      HIPCHK(closed_start(l, cv.Q, cv.z, cv.lam1, W->g, st));
+      KCHK(start_x());
+      KCHK(test_start(&kept));
+      if (kept) res->warm_used = 2;
+    }
+    if (!kept) {
+      HIPCHK(vec_fill(l, 0.0, W->g, st));
+      HIPCHK(vec_fill(l * l, 0.0, W->X, st));
     }
   }
+  if (!kept) KCHK(residual_state(ctx, cv, *W, nullptr, p, &sweeps));
+  if (eta_default) eta = pre ? pre->eta : default_eta_read(ctx, cv);
   const bool use_eg = p->safeguard == KOT_SAFEGUARD_EG;
   const bool overlap = use_eg && overlap_ok(ctx, p, l);
   int side_sweeps = 0, side2_sweeps = 0;
