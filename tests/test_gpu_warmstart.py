@@ -214,6 +214,8 @@ def test_rejected_start_replaced_by_closed_form_start(gpu_ctx):
     cd = gpu_ctx.solve(*args, kotssn.default_params(closed_start=0, **base), want_X=True, hist_cap=256)
     assert nf[2].warm_used == 0
     _same_solve(nf, cd)
+    # |r1| of this start alone exceeds the cold start's residual: it is dropped before its Z is decomposed
+    assert fb[2].eig_sweeps_total == cl[2].eig_sweeps_total and nf[2].eig_sweeps_total == cd[2].eig_sweeps_total
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
@@ -236,6 +238,7 @@ def test_learned_start_fallback_on_coupled_workload(gpu_ctx):
     cl = gpu_ctx.solve(*args, kotssn.default_params(closed_start=1, **base), want_X=True, hist_cap=16)
     assert cl[2].warm_used == 1 and fb[2].warm_used == 2
     _same_solve(fb, cl)
+    assert fb[2].eig_sweeps_total == cl[2].eig_sweeps_total  # the network's start fails on |r1| alone
 
 
 def test_closed_start_value_checked(gpu_ctx):
