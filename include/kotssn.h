@@ -123,7 +123,9 @@ typedef struct kot_problem {
 
 /* Solver outputs.  gamma (device, length l) receives the dual vector; X (device, l x l, may be NULL)
  * receives the PSD multiplier; res_hist / res_v_hist (host, hist_cap entries each, may be NULL) receive
- * |R(w_k)| and |R(v_k)| for k = 0..iters; the scalars are filled on return. */
+ * |R(w_k)| and |R(v_k)| for k = 0..iters, where an iteration whose accept test was decided by the lower bound
+ * |R(v_k)| >= |r1(v_k)| (the trial's residual below it, so Z at v_k was not decomposed) records |r1(v_k)|; the
+ * scalars are filled on return. */
 typedef struct kot_result {
   double* gamma;
   double* X;

@@ -348,6 +348,14 @@ kot_status residual_state(kot_ctx* ctx, const CoreView& cv, State& s, const doub
   return KOT_OK;
 }
 
+// r1 of state s and its squared norm in the SL_VN slot of ctx's scalars; with sync, read back at once.
+kot_status r1_only(kot_ctx* ctx, const CoreView& cv, State& s, bool sync = true) {
+  KCHK(r1_op(ctx, cv, s.g, s.X, s.r1));
+  HIPCHK(dot(cv.l, s.r1, s.r1, ctx->dsc + SL_VN, ctx->part, ctx->stream));
+  if (sync) KCHK(sync_read(ctx));
+  return KOT_OK;
+}
+
 // ---- operator T (Section 4.3) via the G + G^T decomposition -----------------------------------------------
 struct TPlan {
   int l, a;
@@ -1033,6 +1041,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     V->a = W->a; V->r1n = W->r1n; V->r2n = W->r2n; V->rn = W->rn; V->has_eig = W->has_eig;
   }
   double theta = p->theta0;
+  bool v_basis = false;  // V->P holds an eigenbasis (written by a full residual at a v)
   int k = 0, cg_total = 0, eg_acc = 0, nulls = 0, lowp_dirs = 0;
   kot_status status = KOT_NOT_CONVERGED;
   bool warm_e = false;
@@ -1054,7 +1063,9 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     // (1) safeguard: one EG step on v, then R(v_{k+1}); on the side stream when overlapped
     // the extragradient step reads v_k (w_0 at k = 0) and its eigenbasis
     const State* Vs = k == 0 ? W : V;
-    const double* Pv = p->warm_eig ? Vs->P : nullptr;
+    // warm basis of the residual at v_{k+1} (when it is needed): V's own last eigenbasis once one has been
+    // computed, else w_k's (V's buffer holds no basis before the first full residual at a v)
+    const double* Pv = !p->warm_eig ? nullptr : (k > 0 && v_basis ? V->P : W->P);
     if (use_eg && overlap) {
       // gh on this stream, then the projection for Xn on the third stream and the rest of the branch (the
       // projection for Xh, gn, the residual at v_{k+1} once Xn is in) on the second
@@ -1067,7 +1078,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
         if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, KOT_ERR_HIP, "stream synchronization");
         return KOT_OK;
       }));
-      const kot_status rp = side_post(ctx, [ctx, &cv, Vs, V, H, Pv, eta, warm_v, p, &side_sweeps]() -> kot_status {
+      const kot_status rp = side_post(ctx, [ctx, &cv, Vs, V, H, eta, warm_v, p, &side_sweeps]() -> kot_status {
         kot_ctx* c = ctx->side->c;
         const int n = cv.l;
         const kot_status r0 = eg_proj(c, cv, Vs->g, Vs->X, eta, c->Pe1, c->s_e1, warm_v, c->Xh, p, &side_sweeps);
@@ -1079,7 +1090,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
         KCHK(r2);
         std::swap(H->g, V->g);
         std::swap(H->X, V->X);
-        return residual_state(c, cv, *V, Pv, p, &side_sweeps, SL_VN, false);
+        return r1_only(c, cv, *V);
       });
       if (rp < 0) {  // the third stream's job is already out: wait for it before returning
         (void)runner_join(ctx, ctx->side2);
@@ -1092,7 +1103,7 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
       warm_e = true;
       std::swap(H->g, V->g);
       std::swap(H->X, V->X);
-      KCHK(residual_state(ctx, cv, *V, Pv, p, &sweeps, SL_VN, true));
+      KCHK(r1_only(ctx, cv, *V, false));
     }
     // (2) regularized SSN trial
     const double mu = theta * W->rn;
@@ -1122,7 +1133,22 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
     }
     KCHK(rc_newton);
     finish_norms(ctx, *T, SL_TN);
-    if (use_eg && !overlap) finish_norms(ctx, *V, SL_VN);
+    if (use_eg) {
+      // |R(v_{k+1})| >= |r1(v_{k+1})|: when the trial's residual is below that bound (by more than the norms'
+      // rounding), the accept test below takes the trial (and the null-step variant's W->rn <= |R(v_{k+1})|
+      // holds whenever it is asked) whatever r2 is, so the eigendecomposition of Z at v_{k+1} is not needed:
+      // |R(v_{k+1})| is then recorded as that lower bound.  Otherwise the full residual is computed.
+      const double r1v = std::sqrt(overlap ? ctx->side->c->hsc[SL_VN] : ctx->hsc[SL_VN]);
+      if (T->rn <= r1v * (1.0 - 1e-12)) {
+        V->r1n = r1v;
+        V->r2n = 0.0;
+        V->rn = r1v;
+        V->has_eig = false;
+      } else {
+        KCHK(residual_state(ctx, cv, *V, Pv, p, &sweeps, SL_VN, false));
+        v_basis = true;
+      }
+    }
     const double rho = -(ctx->hsc[SL_THETA] + ctx->hsc[SL_THETA + 1]);
     const double dwn = std::sqrt(ctx->hsc[SL_THETA + 2]) + std::sqrt(ctx->hsc[SL_THETA + 3]);
     const double dw2 = dwn * dwn;
