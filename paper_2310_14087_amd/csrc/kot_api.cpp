@@ -606,12 +606,15 @@ kot_status eg_proj(kot_ctx* ctx, const CoreView& cv, const double* gs, const dou
 //   gh = g - eta r1(g, X),  Xh = Pi(X - eta (Phi*(g) + lam1 I)),  gn = g - eta r1(gh, Xh),
 //   Xn = Pi(X - eta (Phi*(gh) + lam1 I)).
 // The X-part of the operator depends on gamma alone, so Xn needs gh but not Xh: the two projections are
-// independent (the overlapped iteration runs them on two streams).
+// independent (the overlapped iteration runs them on two streams).  When warm, both start from the previous
+// step's bases, the first from the second's: X is then Pi of the matrix that basis diagonalizes, and the matrix
+// projected first differs from that one by its negative part (diagonal in the basis) and an eta-sized term.
 kot_status eg_step_impl(kot_ctx* ctx, const CoreView& cv, const double* g, const double* X, const double* r1,
                         double eta, double* gn, double* Xn, bool warm, const kot_params* p, int* sweeps_acc) {
   const int l = cv.l;
   hipStream_t st = ctx->stream;
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, r1, ctx->gh, st));
+  if (warm) HIPCHK(vec_copy(l * l, ctx->Pe2, ctx->Pe1, st));
   KCHK(eg_proj(ctx, cv, g, X, eta, ctx->Pe1, ctx->s_e1, warm, ctx->Xh, p, sweeps_acc));
   KCHK(r1_op(ctx, cv, ctx->gh, ctx->Xh, ctx->r1h));
   HIPCHK(vec_lincomb(l, 1.0, g, -eta, ctx->r1h, gn, st));
@@ -1072,6 +1075,9 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
       const bool warm_v = warm_e && p->warm_eig;
       State* H = &ctx->S[3];
       HIPCHK(vec_lincomb(l, 1.0, Vs->g, -eta, Vs->r1, ctx->gh, st));
+      // the first projection starts from the second's basis of the previous step, as in the one-stream order;
+      // copied on this stream, so before the third stream's job (ordered after it) overwrites that basis
+      if (warm_v) HIPCHK(vec_copy(l * l, ctx->side2->c->Pe2, ctx->side->c->Pe1, st));
       KCHK(runner_post(ctx, ctx->side2, [ctx, &cv, Vs, H, eta, warm_v, p, &side2_sweeps]() -> kot_status {
         kot_ctx* c = ctx->side2->c;
         KCHK(eg_proj(c, cv, ctx->gh, Vs->X, eta, c->Pe2, c->s_e2, warm_v, H->X, p, &side2_sweeps));
