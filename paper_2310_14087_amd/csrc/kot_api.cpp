@@ -1063,15 +1063,15 @@ kot_status run_alg2(kot_ctx* ctx, CoreView& cv, const kot_params* p, const doubl
       KCHK(residual_state(ctx, cv, *W, p->warm_eig ? W->P : nullptr, p, &sweeps));
       continue;
     }
-    // (1) safeguard: one EG step on v, then R(v_{k+1}); on the side stream when overlapped
-    // the extragradient step reads v_k (w_0 at k = 0) and its eigenbasis
+    // (1) safeguard: one EG step from v_k (w_0 at k = 0), then r1 at v_{k+1} (its full residual only if the
+    // accept test needs it, below); on the side streams when overlapped
     const State* Vs = k == 0 ? W : V;
     // warm basis of the residual at v_{k+1} (when it is needed): V's own last eigenbasis once one has been
     // computed, else w_k's (V's buffer holds no basis before the first full residual at a v)
     const double* Pv = !p->warm_eig ? nullptr : (k > 0 && v_basis ? V->P : W->P);
     if (use_eg && overlap) {
       // gh on this stream, then the projection for Xn on the third stream and the rest of the branch (the
-      // projection for Xh, gn, the residual at v_{k+1} once Xn is in) on the second
+      // projection for Xh, gn, r1 at v_{k+1} once Xn is in) on the second
       const bool warm_v = warm_e && p->warm_eig;
       State* H = &ctx->S[3];
       HIPCHK(vec_lincomb(l, 1.0, Vs->g, -eta, Vs->r1, ctx->gh, st));
