@@ -817,8 +817,16 @@ void side_loop(SideRunner* s) {
     kot_ctx* c = s->c;
     bind_thread(c);
     kot_status rc;
-    if (hipSetDevice(c->device) != hipSuccess || hipStreamWaitEvent(c->stream, s->ready, 0) != hipSuccess)
-      rc = fail(c, KOT_ERR_HIP, "could not order the side stream after the caller's stream");
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) {
+      e = hipStreamWaitEvent(c->stream, s->ready, 0);
+      if (e != hipSuccess) {  // a device-side wait that could not be queued: wait on the host (same ordering)
+        (void)hipGetLastError();
+        e = hipEventSynchronize(s->ready);
+      }
+    }
+    if (e != hipSuccess)
+      rc = fail(c, KOT_ERR_HIP, "could not order the side stream after the caller's stream (%s)", hipGetErrorString(e));
     else
       rc = s->job();
     s->rc = rc;
